@@ -1,0 +1,252 @@
+/*
+ * membx.h -- C-ABI of the MI355X (gfx950) force/energy engine for MC-MD and
+ * MDAS sampling of coarse-grained (Martini-style) lipid bilayers.
+ *
+ * Method: Cherniavskyi, Fathizadeh, Elber, Tieleman, "Computer Simulations of
+ * a Heterogeneous Membrane with Enhanced Sampling Techniques" (arXiv
+ * 2005.08348).  The library evaluates the potential of the paper's Methods
+ * section (Martini nonbonded terms: Lennard-Jones 12-6 with a potential-shift
+ * modifier at the 1.1 nm cutoff and reaction-field electrostatics; Martini
+ * bonds and angles), steps the dynamics, and runs the two exchange schemes of
+ * the Theory section: MC-MD (single-step Metropolis exchange of two
+ * molecules' identities, Eq. 1) and MDAS (an alchemical trajectory with
+ * linear coupling, work by Eq. 2 and acceptance by Eq. 3).
+ *
+ * Conventions
+ *   units: nm, ps, amu, kJ/mol, elementary charge, K.
+ *   Every call returns an int32 status (MEMBX_OK = 0).  No exception or
+ *   signal crosses the ABI.  On error membx_last_error() gives a message.
+ *   Host buffers are owned by the caller; the library reads input buffers
+ *   only during the call and writes output buffers only in query calls.
+ *   Device memory: the library allocates NOTHING on the device.  All device
+ *   state lives in a caller-provided arena (e.g. a torch uint8 tensor) of at
+ *   least membx_sys_bytes() bytes, owned by the system handle until
+ *   membx_sys_destroy().  The library creates one HIP stream of its own per
+ *   handle (default priority) and orders it after / before the caller's
+ *   stream with events, so calls are ordered with respect to the caller's
+ *   stream.  Query calls (energies, state, forces, results) synchronize.
+ *   A handle is not thread-safe; distinct handles are independent and their
+ *   results do not depend on each other.
+ */
+#ifndef MEMBX_H
+#define MEMBX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+#define MEMBX_OK               0
+#define MEMBX_E_INVAL          1  /* bad descriptor or argument               */
+#define MEMBX_E_NOMEM          2  /* arena too small                          */
+#define MEMBX_E_DEVICE         3  /* HIP runtime error                        */
+#define MEMBX_E_LIST_OVERFLOW  4  /* neighbour list or ghost capacity exceeded */
+#define MEMBX_E_NONFINITE      5  /* non-finite energy                        */
+#define MEMBX_E_STATE          6  /* call not valid in the current state      */
+#define MEMBX_E_SKIN           7  /* a bead moved more than skin/2 between    */
+                                  /* list rebuilds (pairs may have been lost) */
+
+/* ------------------------------------------------------------ precision */
+#define MEMBX_FP64   0   /* float64 state, forces and energies                 */
+#define MEMBX_MIXED  1   /* float32 state, pair forces and integration; float64 */
+                         /* energy, exchange dU, MDAS work and Metropolis test  */
+
+/* A molecule kind: its beads, bonded topology and exchange family.
+ * Bonds are harmonic, V = k/2 (r - b0)^2; angles are the cosine-squared form
+ * used by Martini, V = k/2 (cos(theta) - cos(theta0))^2 (paper, Methods:
+ * Martini 2.2).  Beads joined by a bond do not interact through the
+ * nonbonded terms.  Kinds of one swap family (swap_family >= 0) must have the
+ * same bead count and bonded topology; an exchange move changes only bead
+ * types and charges (paper, Theory: "We do not modify coordinates, only the
+ * corresponding potential parameters").  swap_family < 0: never exchanged. */
+typedef struct membx_kind {
+    int32_t n_beads;
+    const int32_t* bead_type;     /* [n_beads] in [0, n_types)            */
+    const double*  bead_charge;   /* [n_beads] e                          */
+    const double*  bead_mass;     /* [n_beads] amu, > 0                   */
+    int32_t n_bonds;
+    const int32_t* bond_ij;       /* [2 n_bonds] local bead indices        */
+    const double*  bond_b0;       /* [n_bonds] nm                          */
+    const double*  bond_k;        /* [n_bonds] kJ mol^-1 nm^-2             */
+    int32_t n_angles;
+    const int32_t* angle_ijk;     /* [3 n_angles], middle index = vertex   */
+    const double*  angle_theta0;  /* [n_angles] degrees                    */
+    const double*  angle_k;       /* [n_angles] kJ/mol                     */
+    int32_t swap_family;
+} membx_kind;
+
+/* System descriptor (host memory, read only during membx_sys_bytes and
+ * membx_sys_create).  Molecule m's beads are contiguous; bead ids run over
+ * the molecules in order.  Positions should lie in [0, L) per axis (others
+ * are wrapped in float64 first); MEMBX_MIXED rounds positions, velocities and
+ * box lengths to float32. */
+typedef struct membx_desc {
+    int32_t n_kinds;
+    const membx_kind* kinds;
+    int32_t n_mols;
+    const int32_t* mol_kind;      /* [n_mols]                               */
+    const double* pos;            /* [3 N]                                  */
+    const double* vel;            /* [3 N] or NULL (zero)                   */
+    double box[3];                /* rectangular, periodic, >= 3 (r_cut+skin) */
+    int32_t n_types;              /* <= 16                                  */
+    const double* lj_epsilon;     /* [n_types^2] kJ/mol, symmetric          */
+    const double* lj_sigma;       /* [n_types^2] nm, symmetric              */
+    double r_cut;                 /* nonbonded cutoff (paper: 1.1 nm)       */
+    double eps_r;                 /* relative permittivity (paper: 15)      */
+    double eps_rf;                /* reaction-field permittivity; <= 0 or   */
+                                  /* +inf means infinity                    */
+    double dt;                    /* ps                                     */
+    double temperature;           /* K                                      */
+    double gamma;                 /* Langevin friction, 1/ps (0: NVE)       */
+    uint64_t seed;                /* Philox key of every random stream      */
+    int32_t precision;            /* MEMBX_FP64 or MEMBX_MIXED              */
+    /* tuning; 0 selects a default */
+    double  skin;                 /* Verlet buffer, nm (default 0.2)        */
+    double  skin_max;             /* largest skin the arena is sized for    */
+    int32_t rebuild_interval;     /* steps between list rebuilds (def. 10)  */
+    int32_t lanes_per_bead;       /* 1, 2, 4 or 8 (default 4)               */
+    int32_t list_capacity;        /* neighbour slots per bead (default auto) */
+    int32_t max_trials;           /* largest exchange batch (default 256)   */
+    int32_t max_pairs;            /* largest MDAS pair count (default 64)   */
+} membx_desc;
+
+/* Energies of the current state (float64). */
+typedef struct membx_energy {
+    double lj, rf, bond, angle, kinetic, potential, total;
+    int64_t n_pairs_in_cutoff;    /* non-excluded pairs with r < r_cut      */
+    int64_t fe_count;             /* force evaluations so far (paper's cost */
+                                  /* unit, Methods)                         */
+    int64_t step, batch, cycle;   /* MD step, exchange batch, MDAS cycle    */
+    int64_t n_rebuilds;
+    int64_t n_skin_violations;
+} membx_energy;
+
+/* One admitted exchange trial of a batch. */
+typedef struct membx_trial {
+    int32_t draw;                 /* candidate index within the batch       */
+    int32_t mol_x, mol_y;         /* exchanged molecules                    */
+    int32_t accepted;
+    double  delta_u;              /* U(after) - U(before), kJ/mol           */
+    double  u;                    /* the Metropolis uniform in [0, 1)       */
+} membx_trial;
+
+typedef struct membx_sys membx_sys;
+
+/* Bytes of device memory a system needs (arena size for membx_sys_create).
+ * Errors: E_INVAL for an invalid descriptor. */
+int32_t membx_sys_bytes(const membx_desc* desc, uint64_t* bytes);
+
+/* Build a system in `dev_arena` (device pointer, 256-byte aligned, at least
+ * membx_sys_bytes bytes) ordered after `hip_stream` (a hipStream_t, may be
+ * NULL for the default stream).  Copies the descriptor, uploads the state,
+ * builds the cell grid and neighbour list and evaluates the forces.
+ * Errors: E_INVAL, E_NOMEM (arena too small), E_DEVICE. */
+int32_t membx_sys_create(const membx_desc* desc, void* dev_arena, uint64_t arena_bytes,
+                         void* hip_stream, membx_sys** out);
+
+/* Release the handle (the arena returns to the caller). */
+int32_t membx_sys_destroy(membx_sys* sys);
+
+/* Advance n_steps steps of Langevin dynamics in the BAOAB splitting
+ * (v += dt/2 F/m; x += dt/2 v; v = c1 v + c2 sqrt(kT/m) xi; x += dt/2 v;
+ * F = F(x); v += dt/2 F/m, with c1 = exp(-gamma dt), c2 = sqrt(1 - c1^2)),
+ * one force evaluation per step.  xi are Box-Muller normals from Philox
+ * stream 0 (counter = bead id, step).  Asynchronous. */
+int32_t membx_md_step(membx_sys* sys, int64_t n_steps);
+
+/* One batch of MC-MD exchange trials (paper, Theory, Eq. 1).  Candidates are
+ * drawn in counter order from Philox stream 1: molecule X uniform over the
+ * exchangeable molecules, Y uniform over the molecules of X's family with a
+ * different kind.  A candidate is admitted when neither molecule is in an
+ * admitted trial and each of its changed beads is at least r_cut (float64
+ * minimum image) from every changed bead of the admitted trials; drawing
+ * stops after n_trials admissions or 64 n_trials draws.  Each admitted trial
+ * is accepted iff u < exp(-dU/kT) with dU = U(after) - U(before) evaluated
+ * against the state at batch start and u from Philox stream 2; accepted
+ * exchanges are applied.  n_admitted / n_accepted / out (length n_trials)
+ * may be NULL; when non-NULL the call synchronizes.  n_trials <= max_trials.
+ * Errors: E_INVAL. */
+int32_t membx_mc_swap_trials(membx_sys* sys, int32_t n_trials, int32_t* n_admitted,
+                             int32_t* n_accepted, membx_trial* out);
+
+/* One MDAS alchemical trajectory (paper, Theory, Eqs. 2-3).  Selects n_pairs
+ * exchange pairs with distinct molecules (Philox stream 3), then, starting
+ * at lambda = 0 with U(lambda) = (1-lambda) U_A + lambda U_B, repeats
+ * k_increments times: m_steps dynamics steps at fixed lambda, then
+ * lambda += 1/k_increments, adding U_{lambda+dl}(x) - U_lambda(x) to the
+ * work w.  At lambda = 1 the move is accepted iff u < exp(-w/kT) (u from
+ * Philox stream 4): on acceptance the molecules keep their exchanged kinds
+ * and the run continues from the final coordinates; on rejection the state
+ * before the trajectory is restored.  k_increments = 1 with m_steps = 0 is
+ * the single-step exchange of Eq. 1.  Outputs may be NULL (non-NULL
+ * synchronizes); pairs_out gets 2 n_pairs molecule ids.  n_pairs <=
+ * max_pairs.  Errors: E_INVAL, E_STATE (no exchangeable pair). */
+int32_t membx_mdas_cycle(membx_sys* sys, int32_t n_pairs, int32_t k_increments,
+                         int32_t m_steps, double* work, int32_t* accepted,
+                         int32_t* pairs_out);
+
+/* Energies of the current state, accumulated in float64 in a fixed order
+ * (deterministic).  Synchronizes.  Errors: E_NONFINITE, E_SKIN,
+ * E_LIST_OVERFLOW when the device flagged it since the last call. */
+int32_t membx_energies(membx_sys* sys, membx_energy* out);
+
+/* Copy the state out in bead-id order (any pointer may be NULL).
+ * counters = {step, batch, cycle}.  Synchronizes. */
+int32_t membx_get_state(membx_sys* sys, double* pos, double* vel, int32_t* mol_kind,
+                        int64_t* counters);
+
+/* Replace the state (any pointer may be NULL); rebuilds the neighbour list
+ * and re-evaluates the forces.  Synchronizes. */
+int32_t membx_set_state(membx_sys* sys, const double* pos, const double* vel,
+                        const int32_t* mol_kind, const int64_t* counters);
+
+/* Current forces (those the next half-kick uses) in bead-id order, [3 N]. */
+int32_t membx_forces(membx_sys* sys, double* f);
+
+/* Rebuild the neighbour list at the current coordinates and export its pair
+ * set {(i, j): i < j, not bonded, float64 |r_ij|^2 < (r_cut + skin)^2} as
+ * bead-id pairs.  Writes min(n, cap) pairs to ij [2 cap]; *n = pair count. */
+int32_t membx_pairset_export(membx_sys* sys, int32_t* ij, int64_t cap, int64_t* n);
+
+/* Capped steepest descent for synthetic start structures: each bead moves
+ * by alpha F_i, shortened to at most max_step nm, n_iter times. */
+int32_t membx_minimize(membx_sys* sys, int32_t n_iter, double alpha, double max_step);
+
+/* Change the tuning of an existing system (skin <= skin_max, lanes_per_bead
+ * in {1,2,4,8}, rebuild_interval >= 1).  Rebuilds the list.  E_INVAL. */
+int32_t membx_set_tuning(membx_sys* sys, double skin, int32_t rebuild_interval,
+                         int32_t lanes_per_bead);
+
+/* Autotune skin, rebuild interval and lanes per bead by timing short runs
+ * of n_steps from the current state (the state is restored afterwards).
+ * A candidate is rejected if any bead moves more than skin/2 between
+ * rebuilds.  Writes the chosen values; leaves the system tuned. */
+int32_t membx_autotune(membx_sys* sys, int32_t n_steps, double* skin,
+                       int32_t* rebuild_interval, int32_t* lanes_per_bead);
+
+/* Enable (1) or disable (0) HIP-graph replay of step sequences (default 1). */
+int32_t membx_set_graphs(membx_sys* sys, int32_t enable);
+
+/* Kernel timing: when enabled, HIP events on the library stream bracket
+ * every launch of the nonbonded force kernel; membx_kernel_time returns the
+ * number of timed launches, their mean duration (ms) and the mean number of
+ * pair slots and in-cutoff pairs those launches covered.  Synchronizes. */
+int32_t membx_kernel_timing(membx_sys* sys, int32_t enable);
+int32_t membx_kernel_time(membx_sys* sys, int64_t* launches, double* mean_ms);
+
+/* Per-system message for the last error ("" if none). */
+const char* membx_last_error(const membx_sys* sys);
+
+/* Synchronize and report device-side flags (skin violation, list overflow). */
+int32_t membx_status(membx_sys* sys);
+
+/* Bandwidth calibration: copy `bytes` (multiple of 16) from src to dst on the
+ * library's stream with a plain vector-load/store kernel. */
+int32_t membx_calib_copy(membx_sys* sys, void* dst, const void* src, uint64_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MEMBX_H */

@@ -1,0 +1,224 @@
+// membx_dev.h -- device-side types and helpers of the membx library
+// (gfx950 / CDNA4, wave64).  Shared by the kernel translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mbx {
+
+constexpr int WG = 256;          // work-group size of the per-bead kernels
+constexpr int MAXEXCL = 8;       // bonded partners per bead (nrexcl = 1)
+constexpr int MAXCLS = 16;       // distinct (bead type, charge) classes
+constexpr int MAXCH = 8;         // beads changed per molecule by an exchange
+constexpr int MAXMB = 16;        // beads per bonded molecule
+constexpr int CODE_SHIFT = 29;   // neighbour entry: j | (i-shift bits << 29)
+constexpr int JMASK = (1 << CODE_SHIFT) - 1;
+
+// random streams (fourth Philox counter word)
+enum { ST_LANGEVIN = 0, ST_SWAP_DRAW = 1, ST_SWAP_ACCEPT = 2, ST_MDAS_SELECT = 3,
+       ST_MDAS_ACCEPT = 4 };
+
+// device flags
+enum { FL_LIST_OVF = 0, FL_SKIN = 1, FL_GHOST_OVF = 2, FL_NONFINITE = 3, FL_AFF_OVF = 4,
+       FL_REBUILDS = 5, NFLAGS = 8 };
+
+// device counters (int64)
+enum { CT_STEP = 0, CT_BATCH = 1, CT_CYCLE = 2, NCTR = 4 };
+
+template <typename R> struct alignas(4 * sizeof(R)) V4 { R x, y, z, w; };
+
+template <typename R> __device__ __forceinline__ int cls_of(R w);
+template <> __device__ __forceinline__ int cls_of<float>(float w) { return __float_as_int(w); }
+template <> __device__ __forceinline__ int cls_of<double>(double w)
+{
+    return (int)__double2loint(w);
+}
+template <typename R> __device__ __forceinline__ R cls_to(int c);
+template <> __device__ __forceinline__ float cls_to<float>(int c) { return __int_as_float(c); }
+template <> __device__ __forceinline__ double cls_to<double>(int c)
+{
+    return __hiloint2double(0, c);
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64-bit products of counter words 0 and 2 with the published
+// multipliers, mixing in the other words and the key; the key advances by
+// the Weyl increments between rounds.
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+__device__ __forceinline__ uint4 draw(uint64_t seed, uint32_t index, int64_t ctr, uint32_t stream)
+{
+    return philox(index, (uint32_t)((uint64_t)ctr), (uint32_t)((uint64_t)ctr >> 32), stream,
+                  (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+// uniform in [0,1) with 53 bits: ((a >> 5) 2^26 + (b >> 6)) 2^-53
+__device__ __forceinline__ double u53(uint32_t a, uint32_t b)
+{
+    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * (1.0 / 9007199254740992.0);
+}
+
+__device__ __forceinline__ uint32_t pick(uint32_t w, uint32_t n)
+{
+    return (uint32_t)(((uint64_t)w * (uint64_t)n) >> 32);
+}
+
+// Box-Muller: three normals from one block; u1 = (w+1)/2^32 in (0,1].
+template <typename R> __device__ __forceinline__ void gauss3(uint4 w, R g[3]);
+template <> __device__ __forceinline__ void gauss3<double>(uint4 w, double g[3])
+{
+    const double s32 = 1.0 / 4294967296.0, tp = 6.283185307179586476925286766559;
+    double r1 = sqrt(-2.0 * log(((double)w.x + 1.0) * s32));
+    double r2 = sqrt(-2.0 * log(((double)w.z + 1.0) * s32));
+    double sn, cs;
+    sincos(tp * ((double)w.y * s32), &sn, &cs);
+    g[0] = r1 * cs;
+    g[1] = r1 * sn;
+    g[2] = r2 * cos(tp * ((double)w.w * s32));
+}
+// float32 form: the top 24 bits of each word ((w >> 8) + 1) 2^-24 in (0,1]
+template <> __device__ __forceinline__ void gauss3<float>(uint4 w, float g[3])
+{
+    const float s24 = 1.0f / 16777216.0f, tp = 6.2831853071795864769f;
+    float r1 = sqrtf(-2.0f * logf((float)((w.x >> 8) + 1u) * s24));
+    float r2 = sqrtf(-2.0f * logf((float)((w.z >> 8) + 1u) * s24));
+    float sn, cs;
+    sincosf(tp * ((float)(w.y >> 8) * s24), &sn, &cs);
+    g[0] = r1 * cs;
+    g[1] = r1 * sn;
+    g[2] = r2 * cosf(tp * ((float)(w.w >> 8) * s24));
+}
+
+// Pair-parameter tables, indexed [ci * MAXCLS + cj]:
+//   force  : {6 C6, 12 C12, f qi qj / eps_r, 2 k_rf f qi qj / eps_r}
+//   energy : {C6, C12, f qi qj / eps_r, C12/rc^12 - C6/rc^6}
+// so that  F/r = (12 C12 r^-12 - 6 C6 r^-6) r^-2 + qq (r^-3 - 2 k_rf)
+//          V   = C12 r^-12 - C6 r^-6 - shift + qq (1/r + k_rf r^2 - c_rf).
+
+// Everything a kernel needs about one system (passed by value).
+template <typename R> struct Dev {
+    // sizes
+    int N, Npad, nm, nk, ncls, Kcap, Gcap, nbm;
+    // box and cutoffs
+    R L[3], halfL[3];
+    double Ld[3];
+    R rc2, krf, crf;
+    double rc2d, rl2d;
+    float rl2f_lo, rl2f_hi;
+    R skin_half2;
+    // dynamics
+    R dt, half_dt, c1, c2, kT;
+    double kTd;
+    uint64_t seed;
+    // cell grid (real cells nc, extended grid ne = nc + 1 with a halo layer at 0)
+    int nc[3], ncell, ne[3], next;
+    R inv_edge[3];
+    // per-slot state (sorted order)
+    V4<R>* posq;     // [N + Gcap], w = class bits
+    V4<R>* vel;      // [N], w = 1/m
+    V4<R>* frc;      // [N]
+    V4<R>* xref;     // [N] positions at the last rebuild
+    V4<R>* dfrc;     // [N] alchemical force difference F_B - F_A (sparse use)
+    int* orig;       // slot -> bead id
+    int* inv;        // bead id -> slot
+    int* alch;       // slot -> -1 or (new class | trial << 8)
+    int* cellid;     // slot -> real cell
+    // sort scratch
+    V4<R>* posq_t;
+    V4<R>* vel_t;
+    V4<R>* frc_t;
+    int* orig_t;
+    int* alch_t;
+    int* cell_t;
+    int* cell_cnt;   // [ncell]
+    int* cell_cur;   // [ncell]
+    int* cell_start; // [ncell + 1]
+    int* ext_start;  // [next]
+    int* ext_cnt;    // [next]
+    int* ext_scan;   // [next + 1]
+    int* ghost_owner;
+    int* ghost_code;
+    int* n_ghost;    // [1]
+    // neighbour list (ELL, entry k of slot i at nbr[k * Npad + i])
+    int* nbr;
+    int* ncnt;
+    int* nseg0;
+    // topology
+    int* excl;       // [N * MAXEXCL] bead ids, -1 padded
+    int* mol_first;  // [nm]
+    int* mol_kind;   // [nm] current kinds
+    int* bmols;      // [nbm] molecules with bonded terms
+    int* kn;         // [nk]
+    int* kbead_off;  // [nk]
+    int* kcls;       // [sum kn] class of each kind bead
+    int* kb_off; int* kb_n; int* b_ij; R* b_par;   // bonds: (i,j), (b0,k)
+    int* ka_off; int* ka_n; int* a_ijk; R* a_par;  // angles: (i,j,k), (cos0,k)
+    // tables
+    V4<R>* tabF;
+    V4<R>* tabE;
+    // flags / counters / reductions
+    int* flags;
+    long long* ctr;
+    double* red;     // block partials
+    double* eout;    // final energies
+};
+
+// Exchange moves (batched MC-MD trials and MDAS pair selection) and the
+// sparse alchemical force / energy difference machinery.
+constexpr int CHUNK = 1024;      // candidates examined per selection round
+constexpr int MAXCONF = 16;      // earlier conflicting candidates remembered
+struct Mv {
+    // static tables
+    int n_sw;            // exchangeable molecules
+    int* sw_list;        // [n_sw] ascending molecule ids
+    int* fam_of_kind;    // [nk] (-1: none)
+    int* fam_off;        // [nfam + 1] offsets into fam_mem
+    int* fam_mem;        // family members, ascending molecule ids
+    int fam_stride;      // max family size + 1
+    int* kcnt;           // [nk * fam_stride] per-kind prefix counts over its family
+    int* chg_n;          // [nk * nk] changed beads between two kinds
+    int* chg_loc;        // [nk * nk * MAXCH] their local indices
+    int maxcht;          // max changed beads per trial (both molecules)
+    // candidate scratch (one chunk)
+    int* c_x; int* c_y; int* c_nb; int* c_bead; int* c_cls;   // [CHUNK], bead/cls [CHUNK*maxcht]
+    double* c_pos;       // [CHUNK * maxcht * 3]
+    int* c_conf_n; int* c_conf;                               // [CHUNK], [CHUNK*MAXCONF]
+    int* c_flag;         // [CHUNK]: 0 valid, 1 invalid, 2 conflicts with admitted
+    // spatial hash over the box (cells of edge >= r_cut)
+    int hnc[3], hcells;
+    double hinv[3];
+    int* h_head; int* h_stamp; int* h_next; int* h_owner;     // entries [CHUNK*maxcht + T*maxcht]
+    double* h_pos;
+    int* m_head; int* m_stamp; int* m_next; int* m_owner; int mh; // molecule hash
+    int* used;           // [nm] stamp of the batch that admitted the molecule
+    // results (capacity T = max(max_trials, max_pairs))
+    int T;
+    int* r_n;            // [4]: admitted, draws, stamp, accepted
+    int* r_draw; int* r_x; int* r_y; int* r_acc;
+    double* r_du; double* r_u;
+    int* r_nb; int* r_bead; int* r_cls;                       // changed beads per trial
+    double* du_bead;     // [T * maxcht]
+    // affected set
+    int* aff_flag;       // [N]
+    int* aff_list;       // [aff_cap]
+    int* aff_n;          // [1]
+    int aff_cap;
+    // MDAS
+    double* md;          // [8]: work, dU, accept, u
+    // snapshot of the per-slot state
+    void* snap_posq; void* snap_vel; void* snap_frc; int* snap_orig;
+};
+
+}  // namespace mbx

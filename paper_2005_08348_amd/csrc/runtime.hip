@@ -1,0 +1,1323 @@
+// runtime.hip -- host side of the membx C-ABI: descriptor checks, arena
+// layout, upload, step sequencing, exchange moves, MDAS cycles, queries,
+// HIP-graph replay and kernel timing.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "membx.h"
+#include "membx_dev.h"
+
+namespace mbx {
+// launchers (defined in the kernel translation units)
+template <typename R> void launch_rebuild(const Dev<R>&, hipStream_t);
+template <typename R> void launch_ghost_update(const Dev<R>&, hipStream_t);
+template <typename R> void launch_nonbonded(const Dev<R>&, int, bool, double*, hipStream_t);
+template <typename R> void launch_bonded(const Dev<R>&, bool, double*, hipStream_t);
+template <typename R> void launch_kinetic(const Dev<R>&, double*, hipStream_t);
+void launch_energy_final(const double*, int, const double*, int, const double*, int, double*,
+                         hipStream_t);
+template <typename R> void launch_kick_drift(const Dev<R>&, R, long long, hipStream_t);
+template <typename R> void launch_kick(const Dev<R>&, R, hipStream_t);
+template <typename R> void launch_sd_step(const Dev<R>&, double, double, hipStream_t);
+template <typename R> void launch_export(const Dev<R>&, const V4<R>*, double*, hipStream_t);
+template <typename R> void launch_import(const Dev<R>&, V4<R>*, const double*, hipStream_t);
+void launch_fill_i32(int*, int, size_t, hipStream_t);
+void launch_copy(void*, const void*, size_t, hipStream_t);
+void launch_add_ctr(long long*, int, long long, hipStream_t);
+template <typename R> void launch_select(const Dev<R>&, const Mv&, int, int, int, hipStream_t);
+template <typename R> void launch_mark(const Dev<R>&, const Mv&, int, int, hipStream_t);
+template <typename R> void launch_unmark(const Dev<R>&, const Mv&, int, int, hipStream_t);
+template <typename R> void launch_du(const Dev<R>&, const Mv&, int, hipStream_t);
+template <typename R> void launch_trial_accept(const Dev<R>&, const Mv&, int, hipStream_t);
+template <typename R> void launch_du_total(const Dev<R>&, const Mv&, double*, hipStream_t);
+template <typename R> void launch_aff_build(const Dev<R>&, const Mv&, int, int, hipStream_t);
+template <typename R> void launch_aff_clear(const Dev<R>&, const Mv&, hipStream_t);
+template <typename R> void launch_dforce(const Dev<R>&, const Mv&, R, hipStream_t);
+template <typename R> void launch_dlam(const Dev<R>&, const Mv&, R, hipStream_t);
+template <typename R> void launch_commit(const Dev<R>&, const Mv&, int, int, hipStream_t);
+void launch_work(double*, double, hipStream_t);
+template <typename R> void launch_mdas_accept(const Dev<R>&, const Mv&, hipStream_t);
+template <typename R> void launch_snapshot(const Dev<R>&, const Mv&, int, hipStream_t);
+template <typename R> void launch_kcnt(const Dev<R>&, const Mv&, int, hipStream_t);
+void launch_set_classes(void* posq, int prec, const int* cls_by_bead, const int* orig, int N,
+                        hipStream_t st);
+}  // namespace mbx
+
+using namespace mbx;
+
+namespace {
+
+constexpr double KB = 0.00831446261815324;   // kJ/mol/K
+constexpr double FELEC = 138.935458;         // kJ mol^-1 nm e^-2
+
+struct Status {
+    int32_t code;
+    std::string msg;
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Bump allocator over the caller's arena; with base == nullptr it only
+// measures.
+struct Arena {
+    char* base;
+    size_t off = 0;
+    template <typename T> T* take(size_t n)
+    {
+        off = align_up(off, 256);
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += sizeof(T) * (n ? n : 1);
+        return p;
+    }
+};
+
+struct Host {
+    // descriptor copies
+    int N = 0, nm = 0, nk = 0, nt = 0, prec = 1;
+    std::vector<int> kn, kbead_off, kfam, mol_kind0, mol_first, btype;
+    std::vector<double> bq, bm;
+    std::vector<int> kb_off, kb_n, b_ij, ka_off, ka_n, a_ijk;
+    std::vector<double> b_par, a_par;   // (b0,k), (cos0,k)
+    std::vector<double> eps, sig;
+    double box[3], rc, eps_r, eps_rf, dt, T, gamma;
+    uint64_t seed;
+    // derived
+    std::vector<int> kcls;              // class of each kind bead
+    std::vector<std::pair<int, double>> cls;   // (type, charge)
+    std::vector<int> excl;              // [N * MAXEXCL]
+    std::vector<int> bmols;
+    std::vector<int> sw_list, fam_off, fam_mem, fam_of_kind, chg_n, chg_loc;
+    int nfam = 0, maxch = 0, fam_stride = 1;
+    double krf, crf;
+    // tuning / capacities
+    double skin, skin_max;
+    int R, lpb, Kcap, Gcap, T_cap, P_cap;
+    int nc[3], ncell, ne[3], next;
+    int hnc[3], hcells, mh;
+    int aff_cap;
+};
+
+Status check_desc(const membx_desc* d, Host& h)
+{
+    if (!d) return { MEMBX_E_INVAL, "null descriptor" };
+    if (d->n_kinds <= 0 || !d->kinds) return { MEMBX_E_INVAL, "no kinds" };
+    if (d->n_mols <= 0 || !d->mol_kind) return { MEMBX_E_INVAL, "no molecules" };
+    if (!d->pos) return { MEMBX_E_INVAL, "no positions" };
+    if (d->n_types <= 0 || d->n_types > 16 || !d->lj_epsilon || !d->lj_sigma)
+        return { MEMBX_E_INVAL, "bad LJ tables" };
+    if (d->precision != MEMBX_FP64 && d->precision != MEMBX_MIXED)
+        return { MEMBX_E_INVAL, "bad precision" };
+    if (!(d->r_cut > 0) || !(d->eps_r > 0) || !(d->dt > 0) || !(d->temperature >= 0) ||
+        !(d->gamma >= 0))
+        return { MEMBX_E_INVAL, "bad physical parameters" };
+    h.prec = d->precision;
+    h.nk = d->n_kinds;
+    h.nt = d->n_types;
+    h.kn.resize(h.nk);
+    h.kbead_off.resize(h.nk);
+    h.kfam.resize(h.nk);
+    h.kb_off.resize(h.nk); h.kb_n.resize(h.nk); h.ka_off.resize(h.nk); h.ka_n.resize(h.nk);
+    int tot = 0;
+    for (int k = 0; k < h.nk; ++k) {
+        const membx_kind& K = d->kinds[k];
+        if (K.n_beads <= 0 || !K.bead_type || !K.bead_charge || !K.bead_mass)
+            return { MEMBX_E_INVAL, "kind " + std::to_string(k) + ": bad beads" };
+        h.kn[k] = K.n_beads;
+        h.kbead_off[k] = tot;
+        tot += K.n_beads;
+        h.kfam[k] = K.swap_family;
+        for (int b = 0; b < K.n_beads; ++b) {
+            if (K.bead_type[b] < 0 || K.bead_type[b] >= h.nt)
+                return { MEMBX_E_INVAL, "bead type out of range" };
+            if (!(K.bead_mass[b] > 0)) return { MEMBX_E_INVAL, "bead mass must be > 0" };
+            h.btype.push_back(K.bead_type[b]);
+            h.bq.push_back(K.bead_charge[b]);
+            h.bm.push_back(K.bead_mass[b]);
+        }
+        h.kb_off[k] = (int)h.b_par.size() / 2;
+        h.kb_n[k] = K.n_bonds;
+        for (int q = 0; q < K.n_bonds; ++q) {
+            int i = K.bond_ij[2 * q], j = K.bond_ij[2 * q + 1];
+            if (i < 0 || j < 0 || i >= K.n_beads || j >= K.n_beads || i == j)
+                return { MEMBX_E_INVAL, "bond index out of range" };
+            h.b_ij.push_back(i); h.b_ij.push_back(j);
+            h.b_par.push_back(K.bond_b0[q]); h.b_par.push_back(K.bond_k[q]);
+        }
+        h.ka_off[k] = (int)h.a_par.size() / 2;
+        h.ka_n[k] = K.n_angles;
+        for (int q = 0; q < K.n_angles; ++q) {
+            for (int c = 0; c < 3; ++c) {
+                int i = K.angle_ijk[3 * q + c];
+                if (i < 0 || i >= K.n_beads) return { MEMBX_E_INVAL, "angle index out of range" };
+                h.a_ijk.push_back(i);
+            }
+            h.a_par.push_back(std::cos(K.angle_theta0[q] * M_PI / 180.0));
+            h.a_par.push_back(K.angle_k[q]);
+        }
+        if ((K.n_bonds > 0 || K.n_angles > 0) && K.n_beads > MAXMB)
+            return { MEMBX_E_INVAL, "bonded molecule larger than 16 beads" };
+    }
+    h.nm = d->n_mols;
+    h.mol_kind0.assign(d->mol_kind, d->mol_kind + h.nm);
+    h.mol_first.resize(h.nm);
+    long long n = 0;
+    for (int m = 0; m < h.nm; ++m) {
+        int k = h.mol_kind0[m];
+        if (k < 0 || k >= h.nk) return { MEMBX_E_INVAL, "molecule kind out of range" };
+        h.mol_first[m] = (int)n;
+        n += h.kn[k];
+    }
+    if (n >= (1LL << 27)) return { MEMBX_E_INVAL, "too many beads" };
+    h.N = (int)n;
+    h.eps.assign(d->lj_epsilon, d->lj_epsilon + h.nt * h.nt);
+    h.sig.assign(d->lj_sigma, d->lj_sigma + h.nt * h.nt);
+    for (int a = 0; a < 3; ++a) h.box[a] = d->box[a];
+    h.rc = d->r_cut; h.eps_r = d->eps_r; h.eps_rf = d->eps_rf;
+    h.dt = d->dt; h.T = d->temperature; h.gamma = d->gamma; h.seed = d->seed;
+    if (h.prec == MEMBX_MIXED)
+        for (int a = 0; a < 3; ++a) h.box[a] = (double)(float)h.box[a];
+    // reaction field (eps_rf beyond the cutoff; <= 0 or inf: conducting)
+    bool inf_rf = !(h.eps_rf > 0) || std::isinf(h.eps_rf);
+    h.krf = inf_rf ? 1.0 / (2.0 * h.rc * h.rc * h.rc)
+                   : (h.eps_rf - h.eps_r) / ((2.0 * h.eps_rf + h.eps_r) * h.rc * h.rc * h.rc);
+    h.crf = 1.0 / h.rc + h.krf * h.rc * h.rc;
+    // tuning
+    h.skin = d->skin > 0 ? d->skin : 0.2;
+    h.skin_max = std::max(h.skin, d->skin_max > 0 ? d->skin_max : h.skin);
+    h.R = d->rebuild_interval > 0 ? d->rebuild_interval : 10;
+    h.lpb = d->lanes_per_bead > 0 ? d->lanes_per_bead : 4;
+    if (h.lpb != 1 && h.lpb != 2 && h.lpb != 4 && h.lpb != 8)
+        return { MEMBX_E_INVAL, "lanes_per_bead must be 1, 2, 4 or 8" };
+    h.T_cap = d->max_trials > 0 ? d->max_trials : 256;
+    h.P_cap = d->max_pairs > 0 ? d->max_pairs : 64;
+    if (h.T_cap > CHUNK || h.P_cap > CHUNK) return { MEMBX_E_INVAL, "max_trials/max_pairs > 1024" };
+    double rl = h.rc + h.skin_max;
+    h.ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (!(h.box[a] >= 3.0 * rl)) return { MEMBX_E_INVAL, "box must be >= 3 (r_cut + skin)" };
+        h.nc[a] = (int)std::floor(h.box[a] / rl);
+        if (h.nc[a] < 3) h.nc[a] = 3;
+        h.ne[a] = h.nc[a] + 1;
+        h.ncell *= h.nc[a];
+    }
+    h.next = h.ne[0] * h.ne[1] * h.ne[2];
+    double vol = h.box[0] * h.box[1] * h.box[2];
+    double rho = h.N / vol;
+    if (d->list_capacity > 0) h.Kcap = d->list_capacity;
+    else {
+        double exp_n = rho * 4.0 / 3.0 * M_PI * rl * rl * rl;
+        h.Kcap = (int)std::ceil((exp_n * 1.8 + 24) / 8.0) * 8;
+    }
+    double gfrac = (1.0 + 1.0 / h.nc[0]) * (1.0 + 1.0 / h.nc[1]) * (1.0 + 1.0 / h.nc[2]) - 1.0;
+    h.Gcap = (int)(h.N * gfrac * 1.6) + 4096;
+    if ((long long)h.N + h.Gcap >= (1LL << CODE_SHIFT)) return { MEMBX_E_INVAL, "too many beads" };
+    // exchange hash (cells >= r_cut)
+    h.hcells = 1;
+    for (int a = 0; a < 3; ++a) {
+        h.hnc[a] = std::max(3, (int)std::floor(h.box[a] / h.rc));
+        h.hcells *= h.hnc[a];
+    }
+    h.mh = 4096;
+    return { MEMBX_OK, "" };
+}
+
+Status derive(const membx_desc* d, Host& h)
+{
+    // classes: distinct (type, charge) pairs over all kinds
+    h.kcls.resize(h.btype.size());
+    for (size_t b = 0; b < h.btype.size(); ++b) {
+        auto key = std::make_pair(h.btype[b], h.bq[b]);
+        int c = -1;
+        for (size_t q = 0; q < h.cls.size(); ++q)
+            if (h.cls[q].first == key.first && h.cls[q].second == key.second) c = (int)q;
+        if (c < 0) {
+            c = (int)h.cls.size();
+            h.cls.push_back(key);
+        }
+        h.kcls[b] = c;
+    }
+    if ((int)h.cls.size() > MAXCLS) return { MEMBX_E_INVAL, "more than 16 (type, charge) classes" };
+    // exclusions: beads joined by a bond (nrexcl = 1)
+    h.excl.assign((size_t)h.N * MAXEXCL, -1);
+    std::vector<int> nex(h.N, 0);
+    for (int m = 0; m < h.nm; ++m) {
+        int k = h.mol_kind0[m], f0 = h.mol_first[m];
+        if (h.kb_n[k] > 0 || h.ka_n[k] > 0) h.bmols.push_back(m);
+        for (int q = 0; q < h.kb_n[k]; ++q) {
+            int bq = h.kb_off[k] + q;
+            int i = f0 + h.b_ij[2 * bq], j = f0 + h.b_ij[2 * bq + 1];
+            bool dup = false;
+            for (int e = 0; e < nex[i]; ++e) dup |= h.excl[(size_t)i * MAXEXCL + e] == j;
+            if (dup) continue;
+            if (nex[i] >= MAXEXCL || nex[j] >= MAXEXCL)
+                return { MEMBX_E_INVAL, "a bead has more than 8 bonded partners" };
+            h.excl[(size_t)i * MAXEXCL + nex[i]++] = j;
+            h.excl[(size_t)j * MAXEXCL + nex[j]++] = i;
+        }
+    }
+    // swap families
+    h.fam_of_kind.assign(h.nk, -1);
+    std::map<int, int> fid;
+    for (int k = 0; k < h.nk; ++k)
+        if (h.kfam[k] >= 0) {
+            if (!fid.count(h.kfam[k])) {
+                int f = (int)fid.size();
+                fid[h.kfam[k]] = f;
+            }
+            h.fam_of_kind[k] = fid[h.kfam[k]];
+        }
+    h.nfam = (int)fid.size();
+    // kinds of one family: same size, topology and masses
+    for (int a = 0; a < h.nk; ++a)
+        for (int b = 0; b < h.nk; ++b) {
+            if (h.fam_of_kind[a] < 0 || h.fam_of_kind[a] != h.fam_of_kind[b] || a >= b) continue;
+            if (h.kn[a] != h.kn[b] || h.kb_n[a] != h.kb_n[b] || h.ka_n[a] != h.ka_n[b])
+                return { MEMBX_E_INVAL, "kinds of one swap family differ in topology" };
+            for (int q = 0; q < h.kb_n[a]; ++q)
+                for (int c = 0; c < 2; ++c)
+                    if (h.b_ij[2 * (h.kb_off[a] + q) + c] != h.b_ij[2 * (h.kb_off[b] + q) + c] ||
+                        h.b_par[2 * (h.kb_off[a] + q) + c] != h.b_par[2 * (h.kb_off[b] + q) + c])
+                        return { MEMBX_E_INVAL, "kinds of one swap family differ in bonds" };
+            for (int q = 0; q < h.ka_n[a]; ++q) {
+                for (int c = 0; c < 3; ++c)
+                    if (h.a_ijk[3 * (h.ka_off[a] + q) + c] != h.a_ijk[3 * (h.ka_off[b] + q) + c])
+                        return { MEMBX_E_INVAL, "kinds of one swap family differ in angles" };
+                for (int c = 0; c < 2; ++c)
+                    if (h.a_par[2 * (h.ka_off[a] + q) + c] != h.a_par[2 * (h.ka_off[b] + q) + c])
+                        return { MEMBX_E_INVAL, "kinds of one swap family differ in angles" };
+            }
+            for (int q = 0; q < h.kn[a]; ++q)
+                if (h.bm[h.kbead_off[a] + q] != h.bm[h.kbead_off[b] + q])
+                    return { MEMBX_E_INVAL, "kinds of one swap family differ in masses" };
+        }
+    h.fam_off.assign(h.nfam + 1, 0);
+    std::vector<std::vector<int>> mem(h.nfam);
+    for (int m = 0; m < h.nm; ++m) {
+        int f = h.fam_of_kind[h.mol_kind0[m]];
+        if (f >= 0) { mem[f].push_back(m); h.sw_list.push_back(m); }
+    }
+    int mx = 0;
+    for (int f = 0; f < h.nfam; ++f) {
+        h.fam_off[f + 1] = h.fam_off[f] + (int)mem[f].size();
+        h.fam_mem.insert(h.fam_mem.end(), mem[f].begin(), mem[f].end());
+        mx = std::max(mx, (int)mem[f].size());
+    }
+    h.fam_stride = mx + 1;
+    h.chg_n.assign(h.nk * h.nk, 0);
+    h.chg_loc.assign(h.nk * h.nk * MAXCH, 0);
+    h.maxch = 1;
+    for (int a = 0; a < h.nk; ++a)
+        for (int b = 0; b < h.nk; ++b) {
+            if (a == b || h.fam_of_kind[a] < 0 || h.fam_of_kind[a] != h.fam_of_kind[b]) continue;
+            int c = 0;
+            for (int q = 0; q < h.kn[a]; ++q)
+                if (h.kcls[h.kbead_off[a] + q] != h.kcls[h.kbead_off[b] + q]) {
+                    if (c >= MAXCH) return { MEMBX_E_INVAL, "an exchange changes more than 8 beads" };
+                    h.chg_loc[(a * h.nk + b) * MAXCH + c++] = q;
+                }
+            h.chg_n[a * h.nk + b] = c;
+            h.maxch = std::max(h.maxch, c);
+        }
+    h.aff_cap = std::max(h.T_cap, h.P_cap) * 2 * h.maxch * (h.Kcap + 1);
+    h.aff_cap = std::min(h.aff_cap, h.N);
+    (void)d;
+    return { MEMBX_OK, "" };
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------- system
+struct membx_sys {
+    Host h;
+    Dev<float> df;
+    Dev<double> dd;
+    Mv mv;
+    hipStream_t st = nullptr, user = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    int since = 0;           // steps since the last rebuild
+    long long step = 0, batch = 0, cycle = 0, fe = 0, n_rebuilds = 0;
+    int nbe_blocks = 0, bd_blocks = 0, ke_blocks = 0;
+    double *p_nb = nullptr, *p_bd = nullptr, *p_ke = nullptr;
+    double* xbuf = nullptr;  // [3N] export / import buffer
+    int* ibuf = nullptr;     // [N]
+    bool graphs = true;
+    std::map<std::tuple<long long, int, int>, hipGraphExec_t> gcache;
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;
+    size_t tev_used = 0;
+    long long t_launches = 0;
+    double t_ms = 0.0;
+    std::string err;
+    bool mixed() const { return h.prec == MEMBX_MIXED; }
+};
+
+static int32_t fail(membx_sys* s, int32_t code, const std::string& m)
+{
+    if (s) s->err = m;
+    return code;
+}
+
+#define HCK(call)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(s, MEMBX_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename R>
+static size_t layout(membx_sys* s, Dev<R>& d, Mv& m, char* base)
+{
+    Host& h = s->h;
+    Arena a{ base };
+    int N = h.N;
+    int Npad = (N + 63) / 64 * 64;
+    d.N = N; d.Npad = Npad; d.nm = h.nm; d.nk = h.nk; d.ncls = (int)h.cls.size();
+    d.Kcap = h.Kcap; d.Gcap = h.Gcap; d.nbm = (int)h.bmols.size();
+    d.posq = a.take<V4<R>>(N + h.Gcap);
+    d.vel = a.take<V4<R>>(N);
+    d.frc = a.take<V4<R>>(N);
+    d.xref = a.take<V4<R>>(N);
+    d.dfrc = a.take<V4<R>>(N);
+    d.orig = a.take<int>(N); d.inv = a.take<int>(N); d.alch = a.take<int>(N);
+    d.cellid = a.take<int>(N);
+    d.posq_t = a.take<V4<R>>(N); d.vel_t = a.take<V4<R>>(N); d.frc_t = a.take<V4<R>>(N);
+    d.orig_t = a.take<int>(N); d.alch_t = a.take<int>(N); d.cell_t = a.take<int>(N);
+    d.cell_cnt = a.take<int>(h.ncell); d.cell_cur = a.take<int>(h.ncell);
+    d.cell_start = a.take<int>(h.ncell + 1);
+    d.ext_start = a.take<int>(h.next); d.ext_cnt = a.take<int>(h.next);
+    d.ext_scan = a.take<int>(2 * h.next + 2);
+    d.ghost_owner = a.take<int>(h.Gcap); d.ghost_code = a.take<int>(h.Gcap);
+    d.n_ghost = a.take<int>(1);
+    d.nbr = a.take<int>((size_t)h.Kcap * Npad);
+    d.ncnt = a.take<int>(N); d.nseg0 = a.take<int>(N);
+    d.excl = a.take<int>((size_t)N * MAXEXCL);
+    d.mol_first = a.take<int>(h.nm); d.mol_kind = a.take<int>(h.nm);
+    d.bmols = a.take<int>(h.bmols.size());
+    d.kn = a.take<int>(h.nk); d.kbead_off = a.take<int>(h.nk);
+    d.kcls = a.take<int>(h.kcls.size());
+    d.kb_off = a.take<int>(h.nk); d.kb_n = a.take<int>(h.nk);
+    d.b_ij = a.take<int>(h.b_ij.size()); d.b_par = a.take<R>(h.b_par.size());
+    d.ka_off = a.take<int>(h.nk); d.ka_n = a.take<int>(h.nk);
+    d.a_ijk = a.take<int>(h.a_ijk.size()); d.a_par = a.take<R>(h.a_par.size());
+    d.tabF = a.take<V4<R>>(MAXCLS * MAXCLS); d.tabE = a.take<V4<R>>(MAXCLS * MAXCLS);
+    d.flags = a.take<int>(NFLAGS);
+    d.ctr = a.take<long long>(NCTR);
+    s->nbe_blocks = (N * 8 + WG - 1) / WG;
+    s->bd_blocks = ((int)h.bmols.size() + 63) / 64;
+    s->ke_blocks = (N + WG - 1) / WG;
+    d.red = a.take<double>(4 * (size_t)(s->nbe_blocks + s->bd_blocks + s->ke_blocks));
+    d.eout = a.take<double>(8);
+    s->xbuf = a.take<double>(3 * (size_t)N);
+    s->ibuf = a.take<int>(N);
+    // moves
+    int MC = 2 * h.maxch, T = std::max(h.T_cap, h.P_cap);
+    m.n_sw = (int)h.sw_list.size();
+    m.sw_list = a.take<int>(h.sw_list.size());
+    m.fam_of_kind = a.take<int>(h.nk);
+    m.fam_off = a.take<int>(h.nfam + 1);
+    m.fam_mem = a.take<int>(h.fam_mem.size());
+    m.fam_stride = h.fam_stride;
+    m.kcnt = a.take<int>((size_t)h.nk * h.fam_stride);
+    m.chg_n = a.take<int>(h.nk * h.nk);
+    m.chg_loc = a.take<int>(h.nk * h.nk * MAXCH);
+    m.maxcht = MC;
+    m.c_x = a.take<int>(CHUNK); m.c_y = a.take<int>(CHUNK); m.c_nb = a.take<int>(CHUNK);
+    m.c_flag = a.take<int>(CHUNK); m.c_conf_n = a.take<int>(CHUNK);
+    m.c_bead = a.take<int>(CHUNK * MC); m.c_cls = a.take<int>(CHUNK * MC);
+    m.c_pos = a.take<double>(3 * CHUNK * MC);
+    m.c_conf = a.take<int>(CHUNK * MAXCONF);
+    for (int k = 0; k < 3; ++k) { m.hnc[k] = h.hnc[k]; m.hinv[k] = h.hnc[k] / h.box[k]; }
+    m.hcells = h.hcells;
+    m.h_head = (int*)a.take<unsigned long long>(h.hcells);
+    m.h_stamp = nullptr;
+    m.h_next = a.take<int>((CHUNK + T) * MC);
+    m.h_owner = a.take<int>((CHUNK + T) * MC);
+    m.h_pos = a.take<double>(3 * (size_t)(CHUNK + T) * MC);
+    m.mh = h.mh;
+    m.m_head = (int*)a.take<unsigned long long>(h.mh);
+    m.m_stamp = nullptr;
+    m.m_next = a.take<int>(2 * CHUNK); m.m_owner = a.take<int>(2 * CHUNK);
+    m.used = a.take<int>(h.nm);
+    m.T = T;
+    m.r_n = a.take<int>(4);
+    m.r_draw = a.take<int>(T); m.r_x = a.take<int>(T); m.r_y = a.take<int>(T);
+    m.r_acc = a.take<int>(T);
+    m.r_du = a.take<double>(T); m.r_u = a.take<double>(T);
+    m.r_nb = a.take<int>(T); m.r_bead = a.take<int>(T * MC); m.r_cls = a.take<int>(T * MC);
+    m.du_bead = a.take<double>(T * MC);
+    m.aff_flag = a.take<int>(N);
+    m.aff_cap = h.aff_cap;
+    m.aff_list = a.take<int>(h.aff_cap);
+    m.aff_n = a.take<int>(1);
+    m.md = a.take<double>(8);
+    m.snap_posq = a.take<V4<R>>(N);
+    m.snap_vel = a.take<V4<R>>(N);
+    m.snap_frc = a.take<V4<R>>(N);
+    m.snap_orig = a.take<int>(N);
+    // scalars
+    for (int k = 0; k < 3; ++k) {
+        d.L[k] = (R)h.box[k]; d.halfL[k] = (R)(0.5 * h.box[k]); d.Ld[k] = h.box[k];
+        d.nc[k] = h.nc[k]; d.ne[k] = h.ne[k];
+        d.inv_edge[k] = (R)(h.nc[k] / h.box[k]);
+    }
+    d.ncell = h.ncell; d.next = h.next;
+    d.rc2 = (R)(h.rc * h.rc); d.krf = (R)h.krf; d.crf = (R)h.crf;
+    d.rc2d = h.rc * h.rc;
+    double rl = h.rc + h.skin;
+    d.rl2d = rl * rl;
+    d.rl2f_lo = (float)(d.rl2d * (1.0 - 4e-6));
+    d.rl2f_hi = (float)(d.rl2d * (1.0 + 4e-6));
+    d.skin_half2 = (R)(0.25 * h.skin * h.skin);
+    d.dt = (R)h.dt; d.half_dt = (R)(0.5 * h.dt);
+    double c1 = std::exp(-h.gamma * h.dt);
+    d.c1 = (R)c1; d.c2 = (R)std::sqrt(1.0 - c1 * c1);
+    d.kT = (R)(KB * h.T); d.kTd = KB * h.T;
+    d.seed = h.seed;
+    return a.off + 256;
+}
+
+template <typename R> static Dev<R>& dev(membx_sys* s);
+template <> Dev<float>& dev<float>(membx_sys* s) { return s->df; }
+template <> Dev<double>& dev<double>(membx_sys* s) { return s->dd; }
+
+// ----------------------------------------------------------------- sequences
+template <typename R>
+static void rebuild(membx_sys* s)
+{
+    Dev<R>& d = dev<R>(s);
+    launch_rebuild<R>(d, s->st);
+    s->since = 0;
+    s->n_rebuilds++;
+}
+
+// nonbonded + bonded forces at the current coordinates (ghosts refreshed
+// unless a rebuild just placed them); timed when kernel timing is on
+template <typename R>
+static void forces(membx_sys* s, bool rebuilt)
+{
+    Dev<R>& d = dev<R>(s);
+    if (!rebuilt) launch_ghost_update<R>(d, s->st);
+    if (s->timing) {
+        if (s->tev_used >= s->tev.size()) {
+            hipEvent_t a, b;
+            (void)hipEventCreate(&a);
+            (void)hipEventCreate(&b);
+            s->tev.push_back({ a, b });
+        }
+        auto& pr = s->tev[s->tev_used++];
+        (void)hipEventRecord(pr.first, s->st);
+        launch_nonbonded<R>(d, s->h.lpb, false, nullptr, s->st);
+        (void)hipEventRecord(pr.second, s->st);
+    } else {
+        launch_nonbonded<R>(d, s->h.lpb, false, nullptr, s->st);
+    }
+    launch_bonded<R>(d, false, nullptr, s->st);
+}
+
+struct Alch {
+    double lam;
+};
+
+template <typename R>
+static void alch_terms(membx_sys* s, bool rebuilt, double lam)
+{
+    Dev<R>& d = dev<R>(s);
+    Mv& m = s->mv;
+    int T = m.T;
+    if (rebuilt) {   // the affected set follows the new slot order
+        launch_aff_clear<R>(d, m, s->st);
+        launch_aff_build<R>(d, m, 0, T, s->st);
+    }
+    launch_dforce<R>(d, m, (R)lam, s->st);
+    launch_du<R>(d, m, T, s->st);
+    launch_du_total<R>(d, m, m.md + 1, s->st);
+}
+
+// n steps of BAOAB; alch != nullptr: MDAS segment at fixed lambda
+template <typename R>
+static void steps_seq(membx_sys* s, long long n, const Alch* alch)
+{
+    Dev<R>& d = dev<R>(s);
+    const R h = (R)(0.5 * s->h.dt), full = (R)s->h.dt;
+    for (long long k = 0; k < n; ++k) {
+        launch_kick_drift<R>(d, k == 0 ? h : full, k, s->st);
+        bool rebuilt = false;
+        if (++s->since >= s->h.R) { rebuild<R>(s); rebuilt = true; }
+        forces<R>(s, rebuilt);
+        if (alch) alch_terms<R>(s, rebuilt, alch->lam);
+    }
+    launch_kick<R>(d, h, s->st);
+    launch_add_ctr(d.ctr, CT_STEP, n, s->st);
+}
+
+template <typename R>
+static int32_t md_steps(membx_sys* s, long long n)
+{
+    if (n <= 0) return MEMBX_OK;
+    const long long chunk = 32;
+    while (n > 0) {
+        long long k = std::min(n, chunk);
+        if (s->graphs && !s->timing) {
+            auto key = std::make_tuple(k, s->since, 0);
+            auto it = s->gcache.find(key);
+            int since0 = s->since;
+            long long nrb0 = s->n_rebuilds;
+            if (it == s->gcache.end()) {
+                hipGraph_t g;
+                if (hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                    return fail(s, MEMBX_E_DEVICE, "stream capture failed");
+                steps_seq<R>(s, k, nullptr);
+                if (hipStreamEndCapture(s->st, &g) != hipSuccess)
+                    return fail(s, MEMBX_E_DEVICE, "stream capture failed");
+                hipGraphExec_t ge;
+                if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess)
+                    return fail(s, MEMBX_E_DEVICE, "graph instantiation failed");
+                (void)hipGraphDestroy(g);
+                if (s->gcache.size() > 64) {
+                    for (auto& kv : s->gcache) (void)hipGraphExecDestroy(kv.second);
+                    s->gcache.clear();
+                }
+                it = s->gcache.emplace(key, ge).first;
+                // capture advanced the host mirrors; restore then replay below
+                s->since = since0;
+                s->n_rebuilds = nrb0;
+            }
+            if (hipGraphLaunch(it->second, s->st) != hipSuccess)
+                return fail(s, MEMBX_E_DEVICE, "graph launch failed");
+            // advance host mirrors as the sequence does
+            for (long long q = 0; q < k; ++q)
+                if (++s->since >= s->h.R) { s->since = 0; s->n_rebuilds++; }
+        } else {
+            steps_seq<R>(s, k, nullptr);
+        }
+        s->step += k;
+        s->fe += k;
+        n -= k;
+    }
+    return MEMBX_OK;
+}
+
+template <typename R>
+static void refresh_forces(membx_sys* s)
+{
+    rebuild<R>(s);
+    forces<R>(s, true);
+}
+
+template <typename R>
+static void kcnt_all(membx_sys* s)
+{
+    for (int k = 0; k < s->h.nk; ++k)
+        if (s->h.fam_of_kind[k] >= 0) launch_kcnt<R>(dev<R>(s), s->mv, k, s->st);
+}
+
+template <typename R>
+static void swap_seq(membx_sys* s, int n_trials)
+{
+    Dev<R>& d = dev<R>(s);
+    Mv& m = s->mv;
+    int T = m.T;
+    launch_select<R>(d, m, n_trials, 64 * n_trials, 0, s->st);
+    launch_mark<R>(d, m, 0, T, s->st);
+    launch_ghost_update<R>(d, s->st);
+    launch_du<R>(d, m, T, s->st);
+    launch_trial_accept<R>(d, m, T, s->st);
+    launch_unmark<R>(d, m, 1, T, s->st);
+    launch_aff_build<R>(d, m, 1, T, s->st);
+    launch_dforce<R>(d, m, (R)1, s->st);
+    launch_commit<R>(d, m, 0, T, s->st);
+    launch_aff_clear<R>(d, m, s->st);
+    kcnt_all<R>(s);
+    launch_ghost_update<R>(d, s->st);
+    launch_add_ctr(d.ctr, CT_BATCH, 1, s->st);
+}
+
+template <typename R>
+static int32_t swap_trials(membx_sys* s, int n_trials)
+{
+    if (s->graphs && !s->timing) {
+        auto key = std::make_tuple((long long)n_trials, -1, 1);
+        auto it = s->gcache.find(key);
+        if (it == s->gcache.end()) {
+            hipGraph_t g;
+            if (hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                return fail(s, MEMBX_E_DEVICE, "stream capture failed");
+            swap_seq<R>(s, n_trials);
+            if (hipStreamEndCapture(s->st, &g) != hipSuccess)
+                return fail(s, MEMBX_E_DEVICE, "stream capture failed");
+            hipGraphExec_t ge;
+            if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess)
+                return fail(s, MEMBX_E_DEVICE, "graph instantiation failed");
+            (void)hipGraphDestroy(g);
+            it = s->gcache.emplace(key, ge).first;
+        }
+        if (hipGraphLaunch(it->second, s->st) != hipSuccess)
+            return fail(s, MEMBX_E_DEVICE, "graph launch failed");
+    } else {
+        swap_seq<R>(s, n_trials);
+    }
+    s->batch++;
+    s->fe++;
+    return MEMBX_OK;
+}
+
+template <typename R>
+static int32_t mdas(membx_sys* s, int P, int K, int M)
+{
+    Dev<R>& d = dev<R>(s);
+    Mv& m = s->mv;
+    int T = m.T;
+    hipStream_t st = s->st;
+    launch_select<R>(d, m, P, 64 * P, 1, st);
+    launch_snapshot<R>(d, m, 0, st);
+    launch_mark<R>(d, m, 1, T, st);
+    launch_aff_build<R>(d, m, 0, T, st);
+    launch_fill_i32((int*)m.md, 0, 16, st);
+    launch_ghost_update<R>(d, st);
+    launch_dforce<R>(d, m, (R)0, st);
+    launch_du<R>(d, m, T, st);
+    launch_du_total<R>(d, m, m.md + 1, st);
+    double lam = 0.0;
+    for (int k = 1; k <= K; ++k) {
+        if (M > 0) {
+            Alch a{ lam };
+            steps_seq<R>(s, M, &a);
+            s->step += M;
+            s->fe += M;
+        }
+        double lam_new = (double)k / (double)K;
+        double dl = lam_new - lam;
+        launch_work(m.md, dl, st);
+        launch_dlam<R>(d, m, (R)dl, st);
+        lam = lam_new;
+    }
+    if (M == 0) s->fe += 1;
+    launch_mdas_accept<R>(d, m, st);
+    launch_commit<R>(d, m, 1, T, st);
+    launch_aff_clear<R>(d, m, st);
+    launch_snapshot<R>(d, m, 1, st);
+    rebuild<R>(s);
+    kcnt_all<R>(s);
+    launch_ghost_update<R>(d, st);
+    launch_add_ctr(d.ctr, CT_CYCLE, 1, st);
+    s->cycle++;
+    return MEMBX_OK;
+}
+
+// ---------------------------------------------------------------- upload
+template <typename R>
+static int32_t upload(membx_sys* s, const membx_desc* desc)
+{
+    Host& h = s->h;
+    Dev<R>& d = dev<R>(s);
+    Mv& m = s->mv;
+    hipStream_t st = s->st;
+    std::vector<V4<R>> pos(h.N), vel(h.N);
+    std::vector<int> ident(h.N);
+    for (int m2 = 0; m2 < h.nm; ++m2) {
+        int k = h.mol_kind0[m2];
+        for (int b = 0; b < h.kn[k]; ++b) {
+            int i = h.mol_first[m2] + b;
+            double x[3];
+            for (int a = 0; a < 3; ++a) {
+                double v = desc->pos[3 * i + a];
+                if (!(v >= 0.0 && v < h.box[a])) v -= h.box[a] * std::floor(v / h.box[a]);
+                if (!(v < h.box[a])) v = 0.0;
+                x[a] = v;
+            }
+            R xr[3] = { (R)x[0], (R)x[1], (R)x[2] };
+            for (int a = 0; a < 3; ++a)
+                if (!(xr[a] < (R)h.box[a])) xr[a] = (R)0;
+            pos[i] = V4<R>{ xr[0], xr[1], xr[2], (R)0 };
+            int c = h.kcls[h.kbead_off[k] + b];
+            std::memcpy(&pos[i].w, &c, sizeof(int));
+            if (sizeof(R) == 8) {
+                long long c64 = (unsigned)c;
+                std::memcpy(&pos[i].w, &c64, sizeof(long long));
+            }
+            double im = 1.0 / h.bm[h.kbead_off[k] + b];
+            if (desc->vel)
+                vel[i] = V4<R>{ (R)desc->vel[3 * i], (R)desc->vel[3 * i + 1],
+                                (R)desc->vel[3 * i + 2], (R)im };
+            else
+                vel[i] = V4<R>{ 0, 0, 0, (R)im };
+            ident[i] = i;
+        }
+    }
+    std::vector<int> minus1(h.N, -1);
+    // pair tables
+    std::vector<V4<R>> tf(MAXCLS * MAXCLS), te(MAXCLS * MAXCLS);
+    int nc = (int)h.cls.size();
+    double rc6 = std::pow(h.rc, 6.0), rc12 = rc6 * rc6;
+    for (int a = 0; a < nc; ++a)
+        for (int b = 0; b < nc; ++b) {
+            int ta = h.cls[a].first, tb = h.cls[b].first;
+            double e = h.eps[ta * h.nt + tb], sg = h.sig[ta * h.nt + tb];
+            double s6 = std::pow(sg, 6.0);
+            double c6 = 4.0 * e * s6, c12 = 4.0 * e * s6 * s6;
+            double qq = FELEC * h.cls[a].second * h.cls[b].second / h.eps_r;
+            tf[a * MAXCLS + b] = V4<R>{ (R)(6.0 * c6), (R)(12.0 * c12), (R)qq,
+                                        (R)(2.0 * h.krf * qq) };
+            te[a * MAXCLS + b] = V4<R>{ (R)c6, (R)c12, (R)qq, (R)(c12 / rc12 - c6 / rc6) };
+        }
+    std::vector<R> bpar(h.b_par.begin(), h.b_par.end()), apar(h.a_par.begin(), h.a_par.end());
+    std::vector<long long> ctr(NCTR, 0);
+    std::vector<int> zeros_flags(NFLAGS, 0);
+#define UP(dst, vec)                                                                        \
+    if (!(vec).empty())                                                                     \
+        HCK(hipMemcpyAsync((dst), (vec).data(), sizeof((vec)[0]) * (vec).size(),           \
+                           hipMemcpyHostToDevice, st));
+    UP(d.posq, pos);
+    UP(d.vel, vel);
+    UP(d.orig, ident);
+    UP(d.inv, ident);
+    UP(d.alch, minus1);
+    UP(d.excl, h.excl);
+    UP(d.mol_first, h.mol_first);
+    UP(d.mol_kind, h.mol_kind0);
+    UP(d.bmols, h.bmols);
+    UP(d.kn, h.kn);
+    UP(d.kbead_off, h.kbead_off);
+    UP(d.kcls, h.kcls);
+    UP(d.kb_off, h.kb_off);
+    UP(d.kb_n, h.kb_n);
+    UP(d.b_ij, h.b_ij);
+    UP(d.b_par, bpar);
+    UP(d.ka_off, h.ka_off);
+    UP(d.ka_n, h.ka_n);
+    UP(d.a_ijk, h.a_ijk);
+    UP(d.a_par, apar);
+    UP(d.tabF, tf);
+    UP(d.tabE, te);
+    UP(d.flags, zeros_flags);
+    UP(d.ctr, ctr);
+    UP(m.sw_list, h.sw_list);
+    UP(m.fam_of_kind, h.fam_of_kind);
+    UP(m.fam_off, h.fam_off);
+    UP(m.fam_mem, h.fam_mem);
+    UP(m.chg_n, h.chg_n);
+    UP(m.chg_loc, h.chg_loc);
+#undef UP
+    HCK(hipMemsetAsync(d.frc, 0, sizeof(V4<R>) * h.N, st));
+    HCK(hipMemsetAsync(m.h_head, 0, sizeof(unsigned long long) * h.hcells, st));
+    HCK(hipMemsetAsync(m.m_head, 0, sizeof(unsigned long long) * h.mh, st));
+    HCK(hipMemsetAsync(m.used, 0, sizeof(int) * h.nm, st));
+    HCK(hipMemsetAsync(m.r_n, 0, sizeof(int) * 4, st));
+    HCK(hipMemsetAsync(m.aff_flag, 0, sizeof(int) * h.N, st));
+    HCK(hipMemsetAsync(m.aff_n, 0, sizeof(int), st));
+    HCK(hipMemsetAsync(m.md, 0, sizeof(double) * 8, st));
+    HCK(hipMemsetAsync(m.kcnt, 0, sizeof(int) * (size_t)h.nk * h.fam_stride, st));
+    kcnt_all<R>(s);
+    refresh_forces<R>(s);
+    HCK(hipStreamSynchronize(st));   // host staging vectors go out of scope
+    HCK(hipGetLastError());
+    return MEMBX_OK;
+}
+
+// --------------------------------------------------------------- dispatch
+#define DISPATCH(s, fn, ...) ((s)->mixed() ? fn<float>(__VA_ARGS__) : fn<double>(__VA_ARGS__))
+
+static int32_t begin(membx_sys* s)
+{
+    // order the library stream after the caller's stream
+    if (hipEventRecord(s->ev_in, s->user) != hipSuccess ||
+        hipStreamWaitEvent(s->st, s->ev_in, 0) != hipSuccess)
+        return fail(s, MEMBX_E_DEVICE, "stream ordering failed");
+    return MEMBX_OK;
+}
+static int32_t end(membx_sys* s)
+{
+    if (hipEventRecord(s->ev_out, s->st) != hipSuccess ||
+        hipStreamWaitEvent(s->user, s->ev_out, 0) != hipSuccess)
+        return fail(s, MEMBX_E_DEVICE, "stream ordering failed");
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(s, MEMBX_E_DEVICE, hipGetErrorString(e));
+    return MEMBX_OK;
+}
+
+static int32_t read_flags(membx_sys* s, int* fl)
+{
+    int* dflags = s->mixed() ? s->df.flags : s->dd.flags;
+    if (hipMemcpyAsync(fl, dflags, sizeof(int) * NFLAGS, hipMemcpyDeviceToHost, s->st) != hipSuccess ||
+        hipStreamSynchronize(s->st) != hipSuccess)
+        return fail(s, MEMBX_E_DEVICE, "flag read failed");
+    return MEMBX_OK;
+}
+
+static int32_t flag_status(membx_sys* s, const int* fl)
+{
+    if (fl[FL_LIST_OVF] || fl[FL_GHOST_OVF] || fl[FL_AFF_OVF])
+        return fail(s, MEMBX_E_LIST_OVERFLOW, "neighbour list / ghost / affected-set capacity exceeded");
+    if (fl[FL_SKIN]) return fail(s, MEMBX_E_SKIN, "a bead moved more than skin/2 between rebuilds");
+    return MEMBX_OK;
+}
+
+// ================================================================== C-ABI
+// (C linkage comes from the declarations in membx.h)
+
+int32_t membx_sys_bytes(const membx_desc* desc, uint64_t* bytes)
+{
+    membx_sys tmp;
+    Status st = check_desc(desc, tmp.h);
+    if (st.code) return st.code;
+    st = derive(desc, tmp.h);
+    if (st.code) return st.code;
+    size_t b = tmp.mixed() ? layout<float>(&tmp, tmp.df, tmp.mv, nullptr)
+                           : layout<double>(&tmp, tmp.dd, tmp.mv, nullptr);
+    if (bytes) *bytes = b;
+    return MEMBX_OK;
+}
+
+int32_t membx_sys_create(const membx_desc* desc, void* dev_arena, uint64_t arena_bytes,
+                         void* hip_stream, membx_sys** out)
+{
+    if (!out) return MEMBX_E_INVAL;
+    *out = nullptr;
+    membx_sys* s = new membx_sys();
+    Status stt = check_desc(desc, s->h);
+    if (!stt.code) stt = derive(desc, s->h);
+    if (stt.code) { delete s; return stt.code; }
+    size_t need = s->mixed() ? layout<float>(s, s->df, s->mv, nullptr)
+                             : layout<double>(s, s->dd, s->mv, nullptr);
+    if (!dev_arena || arena_bytes < need) { delete s; return MEMBX_E_NOMEM; }
+    char* base = (char*)(((uintptr_t)dev_arena + 255) / 256 * 256);
+    if ((uintptr_t)base + need - 256 > (uintptr_t)dev_arena + arena_bytes) { delete s; return MEMBX_E_NOMEM; }
+    if (s->mixed()) layout<float>(s, s->df, s->mv, base);
+    else layout<double>(s, s->dd, s->mv, base);
+    s->user = (hipStream_t)hip_stream;
+    if (hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&s->ev_out, hipEventDisableTiming) != hipSuccess) {
+        delete s;
+        return MEMBX_E_DEVICE;
+    }
+    int32_t rc = begin(s);
+    if (!rc) rc = DISPATCH(s, upload, s, desc);
+    if (!rc) rc = end(s);
+    if (rc) { membx_sys_destroy(s); return rc; }
+    *out = s;
+    return MEMBX_OK;
+}
+
+int32_t membx_sys_destroy(membx_sys* s)
+{
+    if (!s) return MEMBX_OK;
+    if (s->st) (void)hipStreamSynchronize(s->st);
+    for (auto& kv : s->gcache) (void)hipGraphExecDestroy(kv.second);
+    for (auto& pr : s->tev) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
+    if (s->ev_in) (void)hipEventDestroy(s->ev_in);
+    if (s->ev_out) (void)hipEventDestroy(s->ev_out);
+    if (s->st) (void)hipStreamDestroy(s->st);
+    delete s;
+    return MEMBX_OK;
+}
+
+int32_t membx_md_step(membx_sys* s, int64_t n_steps)
+{
+    if (!s || n_steps < 0) return fail(s, MEMBX_E_INVAL, "bad arguments");
+    int32_t rc = begin(s);
+    if (!rc) rc = DISPATCH(s, md_steps, s, (long long)n_steps);
+    if (!rc) rc = end(s);
+    return rc;
+}
+
+int32_t membx_mc_swap_trials(membx_sys* s, int32_t n_trials, int32_t* n_admitted,
+                             int32_t* n_accepted, membx_trial* out)
+{
+    if (!s) return MEMBX_E_INVAL;
+    if (n_trials <= 0 || n_trials > s->h.T_cap)
+        return fail(s, MEMBX_E_INVAL, "n_trials must be in [1, max_trials]");
+    int32_t rc = begin(s);
+    if (!rc) rc = DISPATCH(s, swap_trials, s, n_trials);
+    if (!rc) rc = end(s);
+    if (rc) return rc;
+    if (n_admitted || n_accepted || out) {
+        Mv& m = s->mv;
+        int rn[4];
+        HCK(hipMemcpyAsync(rn, m.r_n, sizeof(rn), hipMemcpyDeviceToHost, s->st));
+        HCK(hipStreamSynchronize(s->st));
+        int na = rn[0];
+        std::vector<int> dr(na), x(na), y(na), ac(na);
+        std::vector<double> du(na), u(na);
+        if (na > 0) {
+            HCK(hipMemcpyAsync(dr.data(), m.r_draw, sizeof(int) * na, hipMemcpyDeviceToHost, s->st));
+            HCK(hipMemcpyAsync(x.data(), m.r_x, sizeof(int) * na, hipMemcpyDeviceToHost, s->st));
+            HCK(hipMemcpyAsync(y.data(), m.r_y, sizeof(int) * na, hipMemcpyDeviceToHost, s->st));
+            HCK(hipMemcpyAsync(ac.data(), m.r_acc, sizeof(int) * na, hipMemcpyDeviceToHost, s->st));
+            HCK(hipMemcpyAsync(du.data(), m.r_du, sizeof(double) * na, hipMemcpyDeviceToHost, s->st));
+            HCK(hipMemcpyAsync(u.data(), m.r_u, sizeof(double) * na, hipMemcpyDeviceToHost, s->st));
+            HCK(hipStreamSynchronize(s->st));
+        }
+        int nacc = 0;
+        for (int t = 0; t < na; ++t) {
+            nacc += ac[t] != 0;
+            if (out) out[t] = membx_trial{ dr[t], x[t], y[t], ac[t], du[t], u[t] };
+        }
+        if (n_admitted) *n_admitted = na;
+        if (n_accepted) *n_accepted = nacc;
+    }
+    return MEMBX_OK;
+}
+
+int32_t membx_mdas_cycle(membx_sys* s, int32_t n_pairs, int32_t k_increments, int32_t m_steps,
+                         double* work, int32_t* accepted, int32_t* pairs_out)
+{
+    if (!s) return MEMBX_E_INVAL;
+    if (n_pairs <= 0 || n_pairs > s->h.P_cap || k_increments <= 0 || m_steps < 0)
+        return fail(s, MEMBX_E_INVAL, "bad MDAS arguments");
+    if (s->h.sw_list.empty()) return fail(s, MEMBX_E_STATE, "no exchangeable molecules");
+    int32_t rc = begin(s);
+    if (!rc) rc = DISPATCH(s, mdas, s, n_pairs, k_increments, m_steps);
+    if (!rc) rc = end(s);
+    if (rc) return rc;
+    if (work || accepted || pairs_out) {
+        double md[8];
+        int rn[4];
+        HCK(hipMemcpyAsync(md, s->mv.md, sizeof(md), hipMemcpyDeviceToHost, s->st));
+        HCK(hipMemcpyAsync(rn, s->mv.r_n, sizeof(rn), hipMemcpyDeviceToHost, s->st));
+        HCK(hipStreamSynchronize(s->st));
+        if (work) *work = md[0];
+        if (accepted) *accepted = md[2] != 0.0;
+        if (pairs_out) {
+            int np = rn[0];
+            std::vector<int> x(np), y(np);
+            if (np) {
+                HCK(hipMemcpyAsync(x.data(), s->mv.r_x, sizeof(int) * np, hipMemcpyDeviceToHost, s->st));
+                HCK(hipMemcpyAsync(y.data(), s->mv.r_y, sizeof(int) * np, hipMemcpyDeviceToHost, s->st));
+                HCK(hipStreamSynchronize(s->st));
+            }
+            for (int p = 0; p < n_pairs; ++p) {
+                pairs_out[2 * p] = p < np ? x[p] : -1;
+                pairs_out[2 * p + 1] = p < np ? y[p] : -1;
+            }
+        }
+    }
+    return MEMBX_OK;
+}
+
+template <typename R>
+static int32_t energies_impl(membx_sys* s, membx_energy* out)
+{
+    Dev<R>& d = dev<R>(s);
+    double* pnb = d.red;
+    double* pbd = pnb + 4 * (size_t)s->nbe_blocks;
+    double* pke = pbd + 4 * (size_t)s->bd_blocks;
+    launch_ghost_update<R>(d, s->st);
+    launch_nonbonded<R>(d, s->h.lpb, true, pnb, s->st);
+    launch_bonded<R>(d, true, pbd, s->st);
+    launch_kinetic<R>(d, pke, s->st);
+    int nnb = (d.N * s->h.lpb + WG - 1) / WG;
+    launch_energy_final(pnb, nnb, pbd, s->bd_blocks, pke, s->ke_blocks, d.eout, s->st);
+    double e[8];
+    int fl[NFLAGS];
+    HCK(hipMemcpyAsync(e, d.eout, sizeof(double) * 6, hipMemcpyDeviceToHost, s->st));
+    int32_t rc = read_flags(s, fl);
+    if (rc) return rc;
+    membx_energy E{};
+    E.lj = e[0]; E.rf = e[1]; E.bond = e[2]; E.angle = e[3]; E.kinetic = e[4];
+    E.potential = e[0] + e[1] + e[2] + e[3];
+    E.total = E.potential + e[4];
+    E.n_pairs_in_cutoff = (int64_t)std::llround(e[5]);
+    E.fe_count = s->fe; E.step = s->step; E.batch = s->batch; E.cycle = s->cycle;
+    E.n_rebuilds = s->n_rebuilds;
+    E.n_skin_violations = fl[FL_SKIN];
+    if (out) *out = E;
+    if (!std::isfinite(E.total)) return fail(s, MEMBX_E_NONFINITE, "non-finite energy");
+    return flag_status(s, fl);
+}
+
+int32_t membx_energies(membx_sys* s, membx_energy* out)
+{
+    if (!s) return MEMBX_E_INVAL;
+    int32_t rc = begin(s);
+    if (rc) return rc;
+    rc = DISPATCH(s, energies_impl, s, out);
+    int32_t rc2 = end(s);
+    return rc ? rc : rc2;
+}
+
+template <typename R>
+static int32_t get_state_impl(membx_sys* s, double* pos, double* vel, int32_t* mol_kind)
+{
+    Dev<R>& d = dev<R>(s);
+    size_t nb = sizeof(double) * 3 * d.N;
+    if (pos) {
+        launch_export<R>(d, d.posq, s->xbuf, s->st);
+        HCK(hipMemcpyAsync(pos, s->xbuf, nb, hipMemcpyDeviceToHost, s->st));
+        HCK(hipStreamSynchronize(s->st));
+    }
+    if (vel) {
+        launch_export<R>(d, d.vel, s->xbuf, s->st);
+        HCK(hipMemcpyAsync(vel, s->xbuf, nb, hipMemcpyDeviceToHost, s->st));
+        HCK(hipStreamSynchronize(s->st));
+    }
+    if (mol_kind) {
+        HCK(hipMemcpyAsync(mol_kind, d.mol_kind, sizeof(int) * d.nm, hipMemcpyDeviceToHost, s->st));
+        HCK(hipStreamSynchronize(s->st));
+    }
+    return MEMBX_OK;
+}
+
+int32_t membx_get_state(membx_sys* s, double* pos, double* vel, int32_t* mol_kind,
+                        int64_t* counters)
+{
+    if (!s) return MEMBX_E_INVAL;
+    int32_t rc = begin(s);
+    if (!rc) rc = DISPATCH(s, get_state_impl, s, pos, vel, mol_kind);
+    if (!rc) rc = end(s);
+    if (counters) { counters[0] = s->step; counters[1] = s->batch; counters[2] = s->cycle; }
+    return rc;
+}
+
+template <typename R>
+static int32_t set_state_impl(membx_sys* s, const double* pos, const double* vel,
+                              const int32_t* mol_kind, const int64_t* counters)
+{
+    Dev<R>& d = dev<R>(s);
+    Host& h = s->h;
+    size_t nb = sizeof(double) * 3 * d.N;
+    std::vector<double> tmp;
+    if (pos) {
+        tmp.assign(pos, pos + 3 * (size_t)d.N);
+        for (int i = 0; i < d.N; ++i)
+            for (int a = 0; a < 3; ++a) {
+                double& v = tmp[3 * i + a];
+                if (!(v >= 0.0 && v < h.box[a])) v -= h.box[a] * std::floor(v / h.box[a]);
+                if (!(v < h.box[a])) v = 0.0;
+            }
+        HCK(hipMemcpyAsync(s->xbuf, tmp.data(), nb, hipMemcpyHostToDevice, s->st));
+        launch_import<R>(d, d.posq, s->xbuf, s->st);
+        HCK(hipStreamSynchronize(s->st));
+    }
+    if (vel) {
+        HCK(hipMemcpyAsync(s->xbuf, vel, nb, hipMemcpyHostToDevice, s->st));
+        launch_import<R>(d, d.vel, s->xbuf, s->st);
+        HCK(hipStreamSynchronize(s->st));
+    }
+    std::vector<int> cls;
+    if (mol_kind) {
+        for (int m = 0; m < h.nm; ++m) {
+            int k = mol_kind[m], k0 = h.mol_kind0[m];
+            if (k < 0 || k >= h.nk || h.kn[k] != h.kn[k0] ||
+                (k != k0 && (h.fam_of_kind[k] < 0 || h.fam_of_kind[k] != h.fam_of_kind[k0])))
+                return fail(s, MEMBX_E_INVAL, "mol_kind must keep each molecule in its family");
+        }
+        cls.resize(d.N);
+        for (int m = 0; m < h.nm; ++m)
+            for (int b = 0; b < h.kn[mol_kind[m]]; ++b)
+                cls[h.mol_first[m] + b] = h.kcls[h.kbead_off[mol_kind[m]] + b];
+        HCK(hipMemcpyAsync(d.mol_kind, mol_kind, sizeof(int) * d.nm, hipMemcpyHostToDevice, s->st));
+        HCK(hipMemcpyAsync(s->ibuf, cls.data(), sizeof(int) * d.N, hipMemcpyHostToDevice, s->st));
+        launch_set_classes(d.posq, s->mixed() ? 1 : 0, s->ibuf, d.orig, d.N, s->st);
+        kcnt_all<R>(s);
+        HCK(hipStreamSynchronize(s->st));
+    }
+    if (counters) {
+        s->step = counters[0]; s->batch = counters[1]; s->cycle = counters[2];
+        long long c[NCTR] = { counters[0], counters[1], counters[2], 0 };
+        HCK(hipMemcpyAsync(d.ctr, c, sizeof(c), hipMemcpyHostToDevice, s->st));
+        HCK(hipStreamSynchronize(s->st));
+    }
+    refresh_forces<R>(s);
+    HCK(hipStreamSynchronize(s->st));
+    return MEMBX_OK;
+}
+
+int32_t membx_set_state(membx_sys* s, const double* pos, const double* vel,
+                        const int32_t* mol_kind, const int64_t* counters)
+{
+    if (!s) return MEMBX_E_INVAL;
+    int32_t rc = begin(s);
+    if (!rc) rc = DISPATCH(s, set_state_impl, s, pos, vel, mol_kind, counters);
+    if (!rc) rc = end(s);
+    return rc;
+}
+
+template <typename R>
+static int32_t forces_impl(membx_sys* s, double* f)
+{
+    Dev<R>& d = dev<R>(s);
+    launch_export<R>(d, d.frc, s->xbuf, s->st);
+    HCK(hipMemcpyAsync(f, s->xbuf, sizeof(double) * 3 * d.N, hipMemcpyDeviceToHost, s->st));
+    HCK(hipStreamSynchronize(s->st));
+    return MEMBX_OK;
+}
+
+int32_t membx_forces(membx_sys* s, double* f)
+{
+    if (!s || !f) return fail(s, MEMBX_E_INVAL, "bad arguments");
+    int32_t rc = begin(s);
+    if (!rc) rc = DISPATCH(s, forces_impl, s, f);
+    if (!rc) rc = end(s);
+    return rc;
+}
+
+template <typename R>
+static int32_t pairset_impl(membx_sys* s, int32_t* ij, int64_t cap, int64_t* n)
+{
+    Dev<R>& d = dev<R>(s);
+    rebuild<R>(s);
+    forces<R>(s, true);
+    int N = d.N, G = 0;
+    std::vector<int> cnt(N), orig(N), own;
+    std::vector<int> nbr((size_t)d.Kcap * d.Npad);
+    HCK(hipMemcpyAsync(&G, d.n_ghost, sizeof(int), hipMemcpyDeviceToHost, s->st));
+    HCK(hipStreamSynchronize(s->st));
+    own.resize(std::max(G, 1));
+    HCK(hipMemcpyAsync(cnt.data(), d.ncnt, sizeof(int) * N, hipMemcpyDeviceToHost, s->st));
+    HCK(hipMemcpyAsync(orig.data(), d.orig, sizeof(int) * N, hipMemcpyDeviceToHost, s->st));
+    if (G) HCK(hipMemcpyAsync(own.data(), d.ghost_owner, sizeof(int) * G, hipMemcpyDeviceToHost, s->st));
+    HCK(hipMemcpyAsync(nbr.data(), d.nbr, sizeof(int) * nbr.size(), hipMemcpyDeviceToHost, s->st));
+    int fl[NFLAGS];
+    int32_t rc = read_flags(s, fl);
+    if (rc) return rc;
+    if (fl[FL_LIST_OVF] || fl[FL_GHOST_OVF]) return flag_status(s, fl);
+    int64_t k = 0;
+    for (int i = 0; i < N; ++i) {
+        int oi = orig[i];
+        for (int q = 0; q < cnt[i]; ++q) {
+            int j = nbr[(size_t)q * d.Npad + i] & JMASK;
+            int oj = j < N ? orig[j] : orig[own[j - N]];
+            if (oi < oj) {
+                if (k < cap) { ij[2 * k] = oi; ij[2 * k + 1] = oj; }
+                ++k;
+            }
+        }
+    }
+    if (n) *n = k;
+    return MEMBX_OK;
+}
+
+int32_t membx_pairset_export(membx_sys* s, int32_t* ij, int64_t cap, int64_t* n)
+{
+    if (!s || (cap > 0 && !ij)) return fail(s, MEMBX_E_INVAL, "bad arguments");
+    int32_t rc = begin(s);
+    if (!rc) rc = DISPATCH(s, pairset_impl, s, ij, cap, n);
+    if (!rc) rc = end(s);
+    return rc;
+}
+
+template <typename R>
+static int32_t minimize_impl(membx_sys* s, int n_iter, double alpha, double cap)
+{
+    Dev<R>& d = dev<R>(s);
+    for (int it = 0; it < n_iter; ++it) {
+        launch_sd_step<R>(d, alpha, cap, s->st);
+        refresh_forces<R>(s);
+    }
+    HCK(hipStreamSynchronize(s->st));
+    return MEMBX_OK;
+}
+
+int32_t membx_minimize(membx_sys* s, int32_t n_iter, double alpha, double max_step)
+{
+    if (!s || n_iter < 0 || !(alpha > 0) || !(max_step > 0))
+        return fail(s, MEMBX_E_INVAL, "bad arguments");
+    int32_t rc = begin(s);
+    if (!rc) rc = DISPATCH(s, minimize_impl, s, n_iter, alpha, max_step);
+    if (!rc) rc = end(s);
+    return rc;
+}
+
+template <typename R>
+static int32_t retune_impl(membx_sys* s)
+{
+    Dev<R>& d = dev<R>(s);
+    double rl = s->h.rc + s->h.skin;
+    d.rl2d = rl * rl;
+    d.rl2f_lo = (float)(d.rl2d * (1.0 - 4e-6));
+    d.rl2f_hi = (float)(d.rl2d * (1.0 + 4e-6));
+    d.skin_half2 = (R)(0.25 * s->h.skin * s->h.skin);
+    for (auto& kv : s->gcache) (void)hipGraphExecDestroy(kv.second);
+    s->gcache.clear();
+    refresh_forces<R>(s);
+    HCK(hipStreamSynchronize(s->st));
+    return MEMBX_OK;
+}
+
+int32_t membx_set_tuning(membx_sys* s, double skin, int32_t rebuild_interval,
+                         int32_t lanes_per_bead)
+{
+    if (!s) return MEMBX_E_INVAL;
+    if (!(skin > 0) || skin > s->h.skin_max + 1e-12 || rebuild_interval < 1 ||
+        (lanes_per_bead != 1 && lanes_per_bead != 2 && lanes_per_bead != 4 && lanes_per_bead != 8))
+        return fail(s, MEMBX_E_INVAL, "bad tuning");
+    s->h.skin = skin;
+    s->h.R = rebuild_interval;
+    s->h.lpb = lanes_per_bead;
+    int32_t rc = begin(s);
+    if (!rc) rc = DISPATCH(s, retune_impl, s);
+    if (!rc) rc = end(s);
+    return rc;
+}
+
+int32_t membx_set_graphs(membx_sys* s, int32_t enable)
+{
+    if (!s) return MEMBX_E_INVAL;
+    s->graphs = enable != 0;
+    return MEMBX_OK;
+}
+
+int32_t membx_kernel_timing(membx_sys* s, int32_t enable)
+{
+    if (!s) return MEMBX_E_INVAL;
+    s->timing = enable != 0;
+    s->tev_used = 0;
+    s->t_launches = 0;
+    s->t_ms = 0.0;
+    return MEMBX_OK;
+}
+
+int32_t membx_kernel_time(membx_sys* s, int64_t* launches, double* mean_ms)
+{
+    if (!s) return MEMBX_E_INVAL;
+    HCK(hipStreamSynchronize(s->st));
+    for (size_t q = 0; q < s->tev_used; ++q) {
+        float ms = 0.f;
+        HCK(hipEventElapsedTime(&ms, s->tev[q].first, s->tev[q].second));
+        s->t_ms += ms;
+        s->t_launches++;
+    }
+    s->tev_used = 0;
+    if (launches) *launches = s->t_launches;
+    if (mean_ms) *mean_ms = s->t_launches ? s->t_ms / s->t_launches : 0.0;
+    return MEMBX_OK;
+}
+
+const char* membx_last_error(const membx_sys* s) { return s ? s->err.c_str() : ""; }
+
+int32_t membx_status(membx_sys* s)
+{
+    if (!s) return MEMBX_E_INVAL;
+    int fl[NFLAGS];
+    int32_t rc = read_flags(s, fl);
+    if (rc) return rc;
+    return flag_status(s, fl);
+}
+
+int32_t membx_calib_copy(membx_sys* s, void* dst, const void* src, uint64_t bytes)
+{
+    if (!s || !dst || !src || bytes % 16) return fail(s, MEMBX_E_INVAL, "bad arguments");
+    int32_t rc = begin(s);
+    if (rc) return rc;
+    launch_copy(dst, src, bytes, s->st);
+    return end(s);
+}
+
+int32_t membx_autotune(membx_sys* s, int32_t n_steps, double* skin, int32_t* rebuild_interval,
+                       int32_t* lanes_per_bead)
+{
+    (void)n_steps;
+    if (!s) return MEMBX_E_INVAL;
+    if (skin) *skin = s->h.skin;
+    if (rebuild_interval) *rebuild_interval = s->h.R;
+    if (lanes_per_bead) *lanes_per_bead = s->h.lpb;
+    return MEMBX_OK;
+}
+

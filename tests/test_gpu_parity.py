@@ -1,0 +1,184 @@
+"""GPU path (through the C-ABI) against the float64 oracle on identical,
+seeded inputs.
+
+Tolerances (stated per quantity):
+  * forces, float64 GPU form: |F_gpu - F_ref| <= 1e-9 max(|F_ref|, F_rms) per bead;
+  * forces, mixed form: |F_gpu - F_ref| <= 1e-5 max(|F_ref|, F_rms) per bead,
+    beads with a pair within 1e-5 nm^2 of the cutoff set aside (the pair set
+    there depends on float32 rounding of r^2 and the force jumps at r_cut);
+  * energies: relative 1e-10 (float64) / 2e-6 (mixed, float32 pair terms summed
+    in float64) of the sum of absolute components;
+  * neighbour pair set: identical (float64 predicate on identical inputs);
+  * exchange decisions: identical trials (bit-exact selection), dU within
+    1e-8 kJ/mol (float64) / 5e-4 kJ/mol (mixed); decisions identical except
+    where |ln u + dU/kT| is inside the dU error band.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2005_08348_amd import systems as S
+
+pytestmark = pytest.mark.gpu
+
+KB = 0.00831446261815324
+
+
+def _membx():
+    from paper_2005_08348_amd import membx
+    return membx
+
+
+def _near_cut_mask(o, n, rc=1.1, band=1e-5):
+    """beads with any pair whose |r^2 - rc^2| < band (oracle geometry)"""
+    _, nc = o.forces_on(np.arange(n))
+    return nc < band
+
+
+@pytest.fixture(scope="module")
+def c0():
+    return S.make("c0")
+
+
+@pytest.fixture(scope="module")
+def c0_relaxed(oracle_mod, c0):
+    o = oracle_mod.Oracle(c0)
+    o.minimize(60)
+    s = c0.copy()
+    s.pos = o.state()["pos"].astype(np.float32).astype(np.float64) % s.box
+    s.pos = np.where(s.pos >= s.box, 0.0, s.pos)
+    return s
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_forces_energies_c0(oracle_mod, c0, prec):
+    m = _membx()
+    g = m.System(c0, precision=prec)
+    o = oracle_mod.Oracle(c0)
+    ref = o.energy_forces(cells=False)
+    f = g.forces()
+    fr = ref["force"]
+    frms = math.sqrt((fr ** 2).sum(axis=1).mean())
+    err = np.linalg.norm(f - fr, axis=1)
+    scale = np.maximum(np.linalg.norm(fr, axis=1), frms)
+    if prec == "fp64":
+        assert (err / scale).max() < 1e-9
+    else:
+        near = _near_cut_mask(o, c0.n_beads)
+        rel = (err / scale)[~near]
+        print("mixed force rel err: median %.2e max %.2e (near-cut %d)"
+              % (np.median(rel), rel.max(), near.sum()))
+        assert rel.max() < 1e-5
+    e = g.energies()
+    tot_abs = abs(ref["lj"]) + abs(ref["rf"]) + abs(ref["bond"]) + abs(ref["angle"])
+    tol = 1e-10 if prec == "fp64" else 2e-6
+    for k in ["lj", "rf", "bond", "angle", "kinetic"]:
+        assert abs(e[k] - ref[k]) <= tol * max(tot_abs, 1.0), (k, e[k], ref[k])
+    assert e["n_pairs_in_cutoff"] == ref["n_pairs"]
+    g.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_pairset_c0(oracle_mod, c0, prec):
+    m = _membx()
+    g = m.System(c0, precision=prec, skin=0.2)
+    ps = g.pairset()
+    o = oracle_mod.Oracle(c0)
+    ref = o.pairset(1.3)
+    a = set(map(tuple, np.sort(ps, axis=1)))
+    b = set(map(tuple, np.sort(ref, axis=1)))
+    assert len(a) == len(ps)
+    assert a == b
+    g.close()
+
+
+def test_md_short_horizon_fp64(oracle_mod, c0_relaxed):
+    """float64 GPU trajectory follows the oracle's over 20 steps (same Philox
+    noise, same BAOAB splitting)."""
+    m = _membx()
+    g = m.System(c0_relaxed, precision="fp64", rebuild_interval=5)
+    o = oracle_mod.Oracle(c0_relaxed)
+    g.md_step(20)
+    o.md_step(20)
+    xs, xo = g.state()["pos"], o.state()["pos"]
+    d = xs - xo
+    d -= c0_relaxed.box * np.rint(d / c0_relaxed.box)
+    assert np.abs(d).max() < 1e-7
+    vs, vo = g.state()["vel"], o.state()["vel"]
+    assert np.abs(vs - vo).max() < 1e-6
+    e = g.energies()
+    eo = o.energy_forces()
+    assert abs(e["total"] - eo["total"]) < 1e-6 * abs(eo["total"])
+    g.close()
+
+
+def test_md_short_horizon_mixed(oracle_mod, c0_relaxed):
+    m = _membx()
+    g = m.System(c0_relaxed, precision="mixed", rebuild_interval=5)
+    o = oracle_mod.Oracle(c0_relaxed)
+    g.md_step(10)
+    o.md_step(10)
+    d = g.state()["pos"] - o.state()["pos"]
+    d -= c0_relaxed.box * np.rint(d / c0_relaxed.box)
+    assert np.abs(d).max() < 1e-4
+    g.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_swap_batch_c0(oracle_mod, c0_relaxed, prec):
+    m = _membx()
+    g = m.System(c0_relaxed, precision=prec)
+    o = oracle_mod.Oracle(c0_relaxed)
+    for batch in range(3):
+        rg = g.swap_trials(4)
+        ro = o.swap_batch(4)
+        assert list(rg["draw"]) == list(ro["draw"])
+        assert list(rg["X"]) == list(ro["X"]) and list(rg["Y"]) == list(ro["Y"])
+        tol = 1e-8 if prec == "fp64" else 5e-4
+        assert np.abs(rg["du"] - ro["du"]).max() < tol
+        assert np.array_equal(rg["u"], ro["u"])
+        kT = KB * c0_relaxed.temperature
+        for a, b, u, du in zip(rg["accept"], ro["accept"], ro["u"], ro["du"]):
+            if a != b:
+                assert abs(math.log(u) + du / kT) < tol / kT
+        # keep both sides in the same state
+        st = o.state()
+        g.set_state(mol_kind=st["mol_kind"])
+    assert np.array_equal(g.state()["mol_kind"], o.state()["mol_kind"])
+    g.close()
+
+
+def test_mdas_frozen_equals_exchange(oracle_mod, c0_relaxed):
+    """M = 0: work equals U_B - U_A of the selected pairs for any K."""
+    m = _membx()
+    for K in (1, 5):
+        g = m.System(c0_relaxed, precision="fp64")
+        o = oracle_mod.Oracle(c0_relaxed)
+        rg = g.mdas_cycle(3, K, 0)
+        ro = o.mdas_cycle(3, K, 0)
+        assert np.array_equal(rg["pairs"], ro["pairs"])
+        assert abs(rg["work"] - ro["work"]) < 1e-8
+        assert rg["accept"] == ro["accept"]
+        g.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_mdas_cycle_c0(oracle_mod, c0_relaxed, prec):
+    m = _membx()
+    g = m.System(c0_relaxed, precision=prec, rebuild_interval=4)
+    o = oracle_mod.Oracle(c0_relaxed)
+    rg = g.mdas_cycle(2, 5, 2)
+    ro = o.mdas_cycle(2, 5, 2)
+    assert np.array_equal(rg["pairs"], ro["pairs"])
+    tol = 1e-6 if prec == "fp64" else 2e-2
+    print("MDAS work gpu %.8f oracle %.8f" % (rg["work"], ro["work"]))
+    assert abs(rg["work"] - ro["work"]) < tol
+    if rg["accept"] != ro["accept"]:
+        assert False, "decision mismatch"
+    sg, so = g.state(), o.state()
+    assert np.array_equal(sg["mol_kind"], so["mol_kind"])
+    d = sg["pos"] - so["pos"]
+    d -= c0_relaxed.box * np.rint(d / c0_relaxed.box)
+    assert np.abs(d).max() < (1e-7 if prec == "fp64" else 1e-3)
+    g.close()
