@@ -113,8 +113,9 @@ __global__ __launch_bounds__(CHUNK) void k_select(Dev<R> d, Mv m, int n_want, in
     while (true) {
         if (s_stop || s_adm >= T || s_d0 >= draw_cap) break;
         const unsigned ep = base + 2u + (unsigned)chunk;
+        const int base_d = s_d0;
         // ---- phase A: draw and locate candidate d0 + t
-        const int dd = s_d0 + t;
+        const int dd = base_d + t;
         int flag = 1, X = -1, Y = -1, nb = 0;
         if (dd < draw_cap && m.n_sw > 0) {
             uint4 w = draw(d.seed, (uint32_t)dd, ctrv, stream);
@@ -273,13 +274,13 @@ __global__ __launch_bounds__(CHUNK) void k_select(Dev<R> d, Mv m, int n_want, in
             for (int q = 0; q < CHUNK && k < need; ++q)
                 if (st[q] == 1) { ord[k++] = q; last = q; }
             s_nin = k;
-            if (k == need && last >= 0) { s_d0 = s_d0 + last + 1; s_stop = 1; }
-            else s_d0 = s_d0 + CHUNK;
+            if (k == need && last >= 0) { s_d0 = base_d + last + 1; s_stop = 1; }
+            else s_d0 = base_d + CHUNK;
         }
         __syncthreads();
         if (t < s_nin) {
             int q = ord[t], a = s_adm + t;
-            m.r_draw[a] = (s_stop ? 0 : 0) + (q + (s_d0 - (s_stop ? 0 : CHUNK)));
+            m.r_draw[a] = base_d + q;
             m.r_x[a] = m.c_x[q];
             m.r_y[a] = m.c_y[q];
             m.r_nb[a] = m.c_nb[q];
