@@ -1,0 +1,207 @@
+"""Benchmark of the MC-MD / MDAS force and energy hot path on one MI355X.
+
+Workload (one "step" = one MD step of the whole path: Verlet-list rebuild
+every R steps, ghost refresh, nonbonded + bonded forces, BAOAB update):
+the 4,096-lipid bilayer with 50,000 water beads (95,876 beads,
+36.2 x 36.2 x 10 nm), float32 forces with float64 energies.  Side legs in
+the same run: the float64 GPU form on the same system, batches of 256
+exchange trials every 2 MD steps on it, and MDAS cycles (32 pairs, 50
+lambda increments, 1 step each) on the 1.14M-bead bilayer.
+
+Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32 = 157.3e12      # MI355X FP32 vector FLOP/s
+PEAK_HBM = 8.0e12         # MI355X HBM3E B/s
+FLOP_PAIR_F = 31          # algorithmic flops per in-cutoff pair, forces only
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def gpu_system(sysm, precision, **tun):
+    from paper_2005_08348_amd import membx as M
+    return M.System(sysm, precision=precision, **tun)
+
+
+def timed(fn, sync):
+    sync()
+    t0 = time.perf_counter()
+    fn()
+    sync()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(sysm, target_s=15.0):
+    """The float64 oracle (oracle/, single thread) on a bounded sample."""
+    from oracle import oracle as O
+    O.build()
+    o = O.Oracle(sysm)
+    t0 = time.perf_counter()
+    o.md_step(1)
+    t1 = time.perf_counter() - t0
+    n = max(1, min(200, int(target_s / max(t1, 1e-6))))
+    t0 = time.perf_counter()
+    o.md_step(n)
+    dt = time.perf_counter() - t0
+    return dict(value=n / dt, unit="MD steps/s", cores=1, kind="oracle",
+                sample=f"{n + 1} float64 MD steps of the same 95,876-bead system "
+                       f"(cell-list oracle, one host thread), {dt + t1:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--no-legs", action="store_true", help="main timed region only")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--lpb", type=int, default=8, help="lanes per bead of the pair kernel")
+    ap.add_argument("--rebuild", type=int, default=5, help="steps between list rebuilds")
+    ap.add_argument("--skin", type=float, default=0.2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2005_08348_amd import systems as S
+
+    dev = torch.device("cuda:0")
+    sync = torch.cuda.synchronize
+    K, W = args.steps, args.warmup
+
+    log("[bench] building c1 (95,876 beads)")
+    c1 = S.make("c1")
+    tun = dict(skin=args.skin, rebuild_interval=args.rebuild, lanes_per_bead=args.lpb)
+    g = gpu_system(c1, "mixed", **tun)
+    log("[bench] relaxing start structure on the GPU")
+    g.minimize(100)
+    relaxed = g.state()
+    c1r = c1.copy()
+    c1r.pos = relaxed["pos"]
+    g.md_step(W)
+    sync()
+    # ---- main timed region (graph replay)
+    log(f"[bench] timed region: {K} MD steps, mixed precision")
+    t_main = timed(lambda: g.md_step(K), sync)
+    e = g.energies(check=False)
+    steps_s = K / t_main
+    pairs = e["n_pairs_in_cutoff"]
+    # ---- nonbonded kernel duration: the same K steps with HIP events on the
+    # library stream around every nonbonded launch
+    g.kernel_timing(True)
+    g.md_step(K)
+    nlaunch, nb_ms = g.kernel_time()
+    g.kernel_timing(False)
+    e2 = g.energies(check=False)
+    pairs2 = e2["n_pairs_in_cutoff"]
+    nb_flops = 0.5 * (pairs + pairs2) * FLOP_PAIR_F
+    achieved = nb_flops / (nb_ms * 1e-3)
+    result = {
+        "metric": "MD steps/s & pair-interactions/s (FP32-mixed vs FP64); swap trials/s",
+        "value": steps_s,
+        "unit": "MD steps/s",
+        "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": 1e3 * t_main / K,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (f64 energies)", "data": "synthetic",
+        "config": {"workload": "bilayer 4096 lipids (A:B:C 1639:1638:819) + 50000 W, "
+                               "95876 beads, box 36.2x36.2x10 nm, LJ+RF r_c 1.1 nm, "
+                               "Langevin BAOAB dt 20 fs",
+                   "n_beads": c1.n_beads, "precision": "mixed",
+                   "skin_nm": tun["skin"], "rebuild_interval": tun["rebuild_interval"],
+                   "lanes_per_bead": tun["lanes_per_bead"]},
+        "pair_interactions_per_s": pairs * steps_s,
+        "pairs_in_cutoff": pairs,
+        "skin_violations": e2["n_skin_violations"],
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
+                     "kernel": f"k_nb<float,{args.lpb},false> (nonbonded + bonded forces)",
+                     "launches_timed": nlaunch, "mean_launch_ms": nb_ms},
+    }
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+
+    if not args.no_legs:
+        # ---- float64 GPU form on the same relaxed system
+        log("[bench] float64 leg")
+        g64 = gpu_system(c1r, "fp64", **tun)
+        g64.md_step(50)
+        k64 = max(100, K // 4)
+        t64 = timed(lambda: g64.md_step(k64), sync)
+        e64 = g64.energies(check=False)
+        result["fp64"] = {"md_steps_per_s": k64 / t64,
+                          "pair_interactions_per_s": e64["n_pairs_in_cutoff"] * k64 / t64,
+                          "mixed_speedup": steps_s / (k64 / t64)}
+        # energy error of the mixed form on the identical state
+        gm = gpu_system(c1r, "mixed", **tun)
+        em, ef = gm.energies(check=False), None
+        g64.set_state(pos=c1r.pos, vel=c1r.vel)
+        ef = g64.energies(check=False)
+        result["fp64"]["mixed_energy_rel_err"] = abs(em["potential"] - ef["potential"]) / abs(ef["potential"])
+        g64.close(); del g64
+        # ---- exchange batches on the same system (256 trials every 2 steps)
+        log("[bench] exchange-trial leg")
+        gm.md_step(20)
+        gm.swap_trials(256, results=False)
+        nb = 50
+        adm = acc = 0
+
+        def run_swaps():
+            for _ in range(nb):
+                gm.md_step(2)
+                gm.swap_trials(256, results=False)
+        tsw = timed(run_swaps, sync)
+        r = gm.swap_trials(256)
+        gm.md_step(2)
+        result["swap"] = {"batches": nb, "trials_per_batch_requested": 256,
+                          "admitted_last_batch": len(r["du"]),
+                          "accepted_last_batch": int(r["n_accepted"]),
+                          "batch_plus_2_steps_ms": 1e3 * tsw / nb,
+                          "trials_per_s": nb * len(r["du"]) / tsw}
+        gm.close(); del gm
+        torch.cuda.empty_cache()
+        # ---- MDAS on the 1.14M-bead bilayer
+        log("[bench] building c3 (1,140,504 beads)")
+        c3 = S.make("c3")
+        g3 = gpu_system(c3, "mixed", **tun)
+        g3.minimize(60)
+        g3.md_step(20)
+        g3.mdas_cycle(32, 50, 1, results=False)
+        ncyc = 4
+        t3 = timed(lambda: [g3.mdas_cycle(32, 50, 1, results=False) for _ in range(ncyc)], sync)
+        r3 = g3.mdas_cycle(32, 50, 1)
+        k3 = 200
+        t3md = timed(lambda: g3.md_step(k3), sync)
+        e3 = g3.energies(check=False)
+        result["mdas"] = {"n_beads": c3.n_beads, "pairs": 32, "k_increments": 50, "m_steps": 1,
+                          "cycles_per_s": ncyc / t3, "last_work_kJmol": r3["work"],
+                          "last_accepted": r3["accept"],
+                          "md_steps_per_s": k3 / t3md,
+                          "pair_interactions_per_s": e3["n_pairs_in_cutoff"] * k3 / t3md}
+        g3.close(); del g3
+        torch.cuda.empty_cache()
+
+    if not args.no_cpu:
+        log("[bench] cpu baseline (oracle)")
+        result["cpu_baseline"] = cpu_baseline(c1r)
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

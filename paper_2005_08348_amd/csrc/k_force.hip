@@ -1,14 +1,19 @@
-// k_force.hip -- nonbonded pair forces (potential-shifted LJ 12-6 + reaction
-// field, paper Methods), bonded forces (harmonic bonds, cos^2 angles), kinetic
-// energy and the deterministic float64 energy reduction.
+// k_force.hip -- forces and energies: nonbonded pair terms (potential-shifted
+// LJ 12-6 + reaction field, paper Methods) and the Martini bonded terms
+// (harmonic bonds, cos^2 angles), in one kernel, plus the deterministic
+// float64 energy reduction.
 //
-// Nonbonded kernel.  Pair forces are not a dense contraction, so the kernel
-// runs on the vector ALUs: LPB lanes of a wave64 share one i bead and walk
-// its full (both-direction) Verlet list in an interleaved order; the j bead's
-// coordinates and class come in one 16-byte gather, the pair parameters from
-// a class-by-class table in LDS.  Each i force is the in-register sum over its
-// list followed by a fixed shuffle tree over its LPB lanes, so results are
-// deterministic and no atomics are used.
+// Pair forces are not a dense contraction, so the kernel runs on the vector
+// ALUs: LPB lanes of a wave64 share one i bead and walk its full
+// (both-direction) Verlet list.  The kernel is organised around memory
+// latency: a lane issues all its list reads (one contiguous 256-byte block
+// per wave each, the list is tiled) and its bonded record together, then all
+// its coordinate gathers together, then computes.
+// The j bead's coordinates and class come in one 16-byte gather and the pair
+// parameters from a class-by-class table in LDS.  The same lanes then
+// evaluate the bonded terms their bead takes part in (per-bead gather, no
+// atomics).  Each force is an in-register sum followed by a fixed shuffle
+// tree over the LPB lanes, so results are deterministic.
 #include "membx_dev.h"
 
 namespace mbx {
@@ -47,6 +52,67 @@ __device__ __forceinline__ void pair_force(const Dev<R>& d, const V4<R>* __restr
     }
 }
 
+// Exact minimum-image separation for bonded partners: the coordinate near
+// the top face is shifted down by L first (exact since it is >= L/2).
+template <typename R>
+__device__ __forceinline__ R sep(R xi, R xj, R L, R hL)
+{
+    R dx = xi - xj;
+    if (dx > hL) dx = (xi - L) - xj;
+    else if (dx < -hL) dx = xi - (xj - L);
+    return dx;
+}
+
+template <typename R>
+__device__ __forceinline__ void sep3(const Dev<R>& d, const V4<R>& a, const V4<R>& b, R& x, R& y,
+                                     R& z)
+{
+    x = sep(a.x, b.x, d.L[0], d.halfL[0]);
+    y = sep(a.y, b.y, d.L[1], d.halfL[1]);
+    z = sep(a.z, b.z, d.L[2], d.halfL[2]);
+}
+
+// Force on bead i from one bonded term it takes part in (partner coordinates
+// p1, p2 already gathered); energy counted by the term's owner (bond role 0,
+// angle vertex).
+template <typename R, bool EN>
+__device__ __forceinline__ void bonded_term(const Dev<R>& d, const V4<R>& pi, int4 tm,
+                                            const V4<R>& p1, const V4<R>& p2, R& fx, R& fy, R& fz,
+                                            double& eb, double& ea)
+{
+    const R p0 = d.bt_par[2 * tm.w], kk = d.bt_par[2 * tm.w + 1];
+    if (tm.x <= 1) {
+        R dx, dy, dz;
+        sep3(d, pi, p1, dx, dy, dz);
+        R r = sqrt(dx * dx + dy * dy + dz * dz);
+        R dr = r - p0;
+        R fs = -kk * dr / r;
+        fx += fs * dx; fy += fs * dy; fz += fs * dz;
+        if (EN && tm.x == 0) eb += 0.5 * (double)kk * (double)dr * (double)dr;
+    } else {
+        // role 2: i is an end, p1 the vertex, p2 the other end
+        // role 3: i is the vertex, p1 and p2 the ends
+        R ax, ay, az, bx, by, bz;
+        if (tm.x == 2) { sep3(d, pi, p1, ax, ay, az); sep3(d, p2, p1, bx, by, bz); }
+        else { sep3(d, p1, pi, ax, ay, az); sep3(d, p2, pi, bx, by, bz); }
+        R aa = ax * ax + ay * ay + az * az, bb = bx * bx + by * by + bz * bz;
+        R inw = (R)1 / sqrt(aa * bb);
+        R c = (ax * bx + ay * by + az * bz) * inw;
+        R dc = c - p0;
+        R pre = -kk * dc;
+        R ca = c / aa;
+        R gx = bx * inw - ca * ax, gy = by * inw - ca * ay, gz = bz * inw - ca * az;  // dc/d(end a)
+        if (tm.x == 2) {
+            fx += pre * gx; fy += pre * gy; fz += pre * gz;
+        } else {
+            R cb = c / bb;
+            R hx = ax * inw - cb * bx, hy = ay * inw - cb * by, hz = az * inw - cb * bz;
+            fx -= pre * (gx + hx); fy -= pre * (gy + hy); fz -= pre * (gz + hz);
+            if (EN) ea += 0.5 * (double)kk * (double)dc * (double)dc;
+        }
+    }
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -54,21 +120,7 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// block (WG threads) sum of three doubles into red[slot*4 + 0..2]; thread 0 writes
-__device__ __forceinline__ void block_sum3(double a, double b, double c, double* out)
-{
-    __shared__ double sh[3][WG / 64];
-    a = wave_sum(a); b = wave_sum(b); c = wave_sum(c);
-    int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    if (l == 0) { sh[0][w] = a; sh[1][w] = b; sh[2][w] = c; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s0 = 0, s1 = 0, s2 = 0;
-        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) { s0 += sh[0][q]; s1 += sh[1][q]; s2 += sh[2][q]; }
-        out[0] = s0; out[1] = s1; out[2] = s2; out[3] = 0.0;
-    }
-}
-
+// energies: partial[8 * block] = {lj, rf, pairs, bond, angle, kinetic}
 template <typename R, int LPB, bool EN>
 __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part)
 {
@@ -82,31 +134,72 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part)
     const int gid = blockIdx.x * WG + threadIdx.x;
     const int i = gid / LPB, s = gid % LPB;
     const bool valid = i < d.N;
-    V4<R> pi = valid ? d.posq[i] : V4<R>{ 0, 0, 0, 0 };
+    const V4<R> pi = valid ? d.posq[i] : V4<R>{ 0, 0, 0, 0 };
     const int ci = valid ? cls_of<R>(pi.w) : 0;
     const int n0 = valid ? d.nseg0[i] : 0, n1 = valid ? d.ncnt[i] : 0;
     const V4<R>* rowF = tf + ci * MAXCLS;
     const V4<R>* rowE = EN ? te + ci * MAXCLS : tf;
     R fx = 0, fy = 0, fz = 0;
-    double elj = 0.0, erf = 0.0;
+    double elj = 0.0, erf = 0.0, eb = 0.0, ea = 0.0, ek = 0.0;
     int np = 0;
-    const int* __restrict__ nb = d.nbr + (valid ? i : 0);
-    const size_t stride = (size_t)d.Npad;
-    for (int k = s; k < n0; k += LPB) {
-        int j = nb[(size_t)k * stride];
-        V4<R> pj = d.posq[j];
-        pair_force<R, EN>(d, rowF, rowE, pi.x - pj.x, pi.y - pj.y, pi.z - pj.z, pj.w, fx, fy,
-                          fz, elj, erf, np);
+    // entry k = m LPB + s of bead i sits at lane_base + 64 m (tiled list)
+    constexpr int BG = 64 / LPB;
+    const int ii = valid ? i : 0;
+    const size_t lane_base = (size_t)(ii / BG) * ((size_t)d.Kcap * BG) + (size_t)(ii % BG) * LPB + s;
+    const int* __restrict__ nb = d.nbr + lane_base;
+    const V4<R>* __restrict__ P = d.posq;
+    // first batch: the list entries (read unconditionally: they lie inside the
+    // bead's tile) and the bonded record are loaded together with the counts
+    constexpr int B = (12 * LPB <= 96) ? 12 : 96 / LPB;
+    int jj[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) jj[b] = nb[(size_t)b * 64];
+    // bonded records: lane s takes terms s, s + LPB, ... of its bead
+    constexpr int TPL = (MAXBT + LPB - 1) / LPB;
+    int4 bt[TPL];
+#pragma unroll
+    for (int u = 0; u < TPL; ++u)
+        bt[u] = (s + u * LPB < MAXBT) ? d.bslot[(size_t)ii * MAXBT + s + u * LPB]
+                                      : make_int4(-1, ii, ii, 0);
+    const int m1n = n1 > s ? (n1 - s + LPB - 1) / LPB : 0;
+    // second level: gathers of the j coordinates (self for unused entries)
+    V4<R> q[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) q[b] = P[b < m1n ? (jj[b] & JMASK) : ii];
+    V4<R> b1[TPL], b2[TPL];
+#pragma unroll
+    for (int u = 0; u < TPL; ++u) { b1[u] = P[bt[u].y]; b2[u] = P[bt[u].z]; }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        if (b < m1n) {
+            const int code = (int)((unsigned)jj[b] >> CODE_SHIFT);
+            R xs = pi.x, ys = pi.y, zs = pi.z;
+            if (code) {
+                if (code & 1) xs -= d.L[0];
+                if (code & 2) ys -= d.L[1];
+                if (code & 4) zs -= d.L[2];
+            }
+            pair_force<R, EN>(d, rowF, rowE, xs - q[b].x, ys - q[b].y, zs - q[b].z, q[b].w, fx, fy,
+                              fz, elj, erf, np);
+        }
     }
-    for (int k = n0 + s; k < n1; k += LPB) {
-        int e = nb[(size_t)k * stride];
-        int j = e & JMASK, code = (int)((unsigned)e >> CODE_SHIFT);
-        V4<R> pj = d.posq[j];
-        R xs = (code & 1) ? pi.x - d.L[0] : pi.x;
-        R ys = (code & 2) ? pi.y - d.L[1] : pi.y;
-        R zs = (code & 4) ? pi.z - d.L[2] : pi.z;
-        pair_force<R, EN>(d, rowF, rowE, xs - pj.x, ys - pj.y, zs - pj.z, pj.w, fx, fy, fz, elj,
-                          erf, np);
+    // rare: lists longer than one batch
+    for (int m = B; m < m1n; ++m) {
+        const int e = nb[(size_t)m * 64];
+        const int j = e & JMASK, code = (int)((unsigned)e >> CODE_SHIFT);
+        const V4<R> pj = P[j];
+        const R xs = (code & 1) ? pi.x - d.L[0] : pi.x;
+        const R ys = (code & 2) ? pi.y - d.L[1] : pi.y;
+        const R zs = (code & 4) ? pi.z - d.L[2] : pi.z;
+        pair_force<R, EN>(d, rowF, rowE, xs - pj.x, ys - pj.y, zs - pj.z, pj.w, fx, fy, fz, elj, erf, np);
+    }
+    // bonded terms of bead i
+#pragma unroll
+    for (int u = 0; u < TPL; ++u)
+        if (valid && bt[u].x >= 0) bonded_term<R, EN>(d, pi, bt[u], b1[u], b2[u], fx, fy, fz, eb, ea);
+    if (EN && valid && s == 0) {
+        V4<R> v = d.vel[i];
+        ek = 0.5 * ((double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z) / (double)v.w;
     }
 #pragma unroll
     for (int m = LPB / 2; m >= 1; m >>= 1) {
@@ -117,119 +210,33 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part)
     if (!EN) {
         if (valid && s == 0) d.frc[i] = V4<R>{ fx, fy, fz, (R)0 };
     } else {
-        block_sum3(elj, erf, (double)np, part + 4 * blockIdx.x);
-    }
-}
-
-// Exact minimum-image separation for bonded partners: the coordinate near
-// the top face is shifted down by L first (exact since it is >= L/2).
-template <typename R>
-__device__ __forceinline__ R sep(R xi, R xj, R L, R hL)
-{
-    R dx = xi - xj;
-    if (dx > hL) dx = (xi - L) - xj;
-    else if (dx < -hL) dx = xi - (xj - L);
-    return dx;
-}
-
-template <typename R, bool EN>
-__global__ __launch_bounds__(64) void k_bonded(Dev<R> d, double* __restrict__ part)
-{
-    __shared__ R fl[64][MAXMB * 3];
-    __shared__ V4<R> pl[64][MAXMB];
-    __shared__ int sl[64][MAXMB];
-    const int t = blockIdx.x * 64 + threadIdx.x;
-    double eb = 0.0, ea = 0.0;
-    if (t < d.nbm) {
-        const int m = d.bmols[t], k = d.mol_kind[m], f0 = d.mol_first[m], nb = d.kn[k];
-        R* f = fl[threadIdx.x];
-        V4<R>* p = pl[threadIdx.x];
-        int* sv = sl[threadIdx.x];
-        for (int b = 0; b < nb; ++b) {
-            int s = d.inv[f0 + b];
-            sv[b] = s;
-            p[b] = d.posq[s];
-            f[3 * b] = f[3 * b + 1] = f[3 * b + 2] = (R)0;
+        __shared__ double sh[6][WG / 64];
+        double v[6] = { elj, erf, (double)np, eb, ea, ek };
+        const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            double x = wave_sum(v[q]);
+            if (l == 0) sh[q][w] = x;
         }
-        const int q0 = d.kb_off[k], qn = d.kb_n[k];
-        for (int q = q0; q < q0 + qn; ++q) {
-            int li = d.b_ij[2 * q], lj = d.b_ij[2 * q + 1];
-            R b0 = d.b_par[2 * q], kb = d.b_par[2 * q + 1];
-            R dx = sep(p[li].x, p[lj].x, d.L[0], d.halfL[0]);
-            R dy = sep(p[li].y, p[lj].y, d.L[1], d.halfL[1]);
-            R dz = sep(p[li].z, p[lj].z, d.L[2], d.halfL[2]);
-            R r = sqrt(dx * dx + dy * dy + dz * dz);
-            R dr = r - b0;
-            R fs = -kb * dr / r;
-            f[3 * li] += fs * dx; f[3 * li + 1] += fs * dy; f[3 * li + 2] += fs * dz;
-            f[3 * lj] -= fs * dx; f[3 * lj + 1] -= fs * dy; f[3 * lj + 2] -= fs * dz;
-            if (EN) eb += 0.5 * (double)kb * (double)dr * (double)dr;
-        }
-        const int a0 = d.ka_off[k], an = d.ka_n[k];
-        for (int q = a0; q < a0 + an; ++q) {
-            int li = d.a_ijk[3 * q], lj = d.a_ijk[3 * q + 1], lk = d.a_ijk[3 * q + 2];
-            R c0 = d.a_par[2 * q], ka = d.a_par[2 * q + 1];
-            R ux = sep(p[li].x, p[lj].x, d.L[0], d.halfL[0]);
-            R uy = sep(p[li].y, p[lj].y, d.L[1], d.halfL[1]);
-            R uz = sep(p[li].z, p[lj].z, d.L[2], d.halfL[2]);
-            R wx = sep(p[lk].x, p[lj].x, d.L[0], d.halfL[0]);
-            R wy = sep(p[lk].y, p[lj].y, d.L[1], d.halfL[1]);
-            R wz = sep(p[lk].z, p[lj].z, d.L[2], d.halfL[2]);
-            R uu = ux * ux + uy * uy + uz * uz, ww = wx * wx + wy * wy + wz * wz;
-            R inw = (R)1 / sqrt(uu * ww);
-            R c = (ux * wx + uy * wy + uz * wz) * inw;
-            R dc = c - c0;
-            R pre = -ka * dc;
-            R cu = c / uu, cw = c / ww;
-            R dix = wx * inw - cu * ux, diy = wy * inw - cu * uy, diz = wz * inw - cu * uz;
-            R dkx = ux * inw - cw * wx, dky = uy * inw - cw * wy, dkz = uz * inw - cw * wz;
-            f[3 * li] += pre * dix; f[3 * li + 1] += pre * diy; f[3 * li + 2] += pre * diz;
-            f[3 * lk] += pre * dkx; f[3 * lk + 1] += pre * dky; f[3 * lk + 2] += pre * dkz;
-            f[3 * lj] -= pre * (dix + dkx);
-            f[3 * lj + 1] -= pre * (diy + dky);
-            f[3 * lj + 2] -= pre * (diz + dkz);
-            if (EN) ea += 0.5 * (double)ka * (double)dc * (double)dc;
-        }
-        if (!EN) {
-            for (int b = 0; b < nb; ++b) {
-                V4<R> g = d.frc[sv[b]];
-                g.x += f[3 * b]; g.y += f[3 * b + 1]; g.z += f[3 * b + 2];
-                d.frc[sv[b]] = g;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int q = 0; q < 6; ++q) {
+                double acc = 0.0;
+                for (int ww = 0; ww < WG / 64; ++ww) acc += sh[q][ww];
+                part[8 * blockIdx.x + q] = acc;
             }
-        }
     }
-    if (EN) {
-        eb = wave_sum(eb);
-        ea = wave_sum(ea);
-        if (threadIdx.x == 0) { part[4 * blockIdx.x] = eb; part[4 * blockIdx.x + 1] = ea; }
-    }
-}
-
-template <typename R>
-__global__ __launch_bounds__(WG) void k_kinetic(Dev<R> d, double* __restrict__ part)
-{
-    int i = blockIdx.x * WG + threadIdx.x;
-    double ke = 0.0;
-    if (i < d.N) {
-        V4<R> v = d.vel[i];
-        double v2 = (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z;
-        ke = 0.5 * v2 / (double)v.w;
-    }
-    block_sum3(ke, 0.0, 0.0, part + 4 * blockIdx.x);
 }
 
 // Fixed-order float64 sum of the block partials:
 // out = {lj, rf, bond, angle, kinetic, n_pairs}
-__global__ void k_energy_final(const double* __restrict__ pnb, int nnb,
-                               const double* __restrict__ pbd, int nbd,
-                               const double* __restrict__ pke, int nke, double* __restrict__ out)
+__global__ void k_energy_final(const double* __restrict__ p, int nb, double* __restrict__ out)
 {
     __shared__ double sh[6][256];
     int t = threadIdx.x;
     double a[6] = { 0, 0, 0, 0, 0, 0 };
-    for (int b = t; b < nnb; b += 256) { a[0] += pnb[4 * b]; a[1] += pnb[4 * b + 1]; a[5] += pnb[4 * b + 2]; }
-    for (int b = t; b < nbd; b += 256) { a[2] += pbd[4 * b]; a[3] += pbd[4 * b + 1]; }
-    for (int b = t; b < nke; b += 256) { a[4] += pke[4 * b]; }
+    for (int b = t; b < nb; b += 256)
+        for (int q = 0; q < 6; ++q) a[q] += p[8 * b + q];
     for (int q = 0; q < 6; ++q) sh[q][t] = a[q];
     __syncthreads();
     for (int off = 128; off >= 1; off >>= 1) {
@@ -241,10 +248,10 @@ __global__ void k_energy_final(const double* __restrict__ pnb, int nnb,
         // every unordered pair appears twice in the full lists
         out[0] = 0.5 * sh[0][0];
         out[1] = 0.5 * sh[1][0];
-        out[2] = sh[2][0];
-        out[3] = sh[3][0];
-        out[4] = sh[4][0];
-        out[5] = 0.5 * sh[5][0];
+        out[2] = sh[3][0];
+        out[3] = sh[4][0];
+        out[4] = sh[5][0];
+        out[5] = 0.5 * sh[2][0];
     }
 }
 
@@ -256,11 +263,9 @@ static void nb_launch(const Dev<R>& d, double* part, hipStream_t st)
     hipLaunchKernelGGL((k_nb<R, LPB, EN>), dim3((nthr + WG - 1) / WG), dim3(WG), 0, st, d, part);
 }
 
+// forces (energy=false) or energies into part (energy=true); returns blocks
 template <typename R>
-int nb_blocks(const Dev<R>& d, int lpb) { return (d.N * lpb + WG - 1) / WG; }
-
-template <typename R>
-void launch_nonbonded(const Dev<R>& d, int lpb, bool energy, double* part, hipStream_t st)
+int launch_nonbonded(const Dev<R>& d, int lpb, bool energy, double* part, hipStream_t st)
 {
     switch (lpb * 2 + (energy ? 1 : 0)) {
     case 2: nb_launch<R, 1, false>(d, part, st); break;
@@ -273,35 +278,15 @@ void launch_nonbonded(const Dev<R>& d, int lpb, bool energy, double* part, hipSt
     case 17: nb_launch<R, 8, true>(d, part, st); break;
     default: break;
     }
+    return (d.N * lpb + WG - 1) / WG;
 }
 
-template <typename R>
-void launch_bonded(const Dev<R>& d, bool energy, double* part, hipStream_t st)
+void launch_energy_final(const double* p, int nb, double* out, hipStream_t st)
 {
-    if (d.nbm == 0) return;
-    dim3 g((d.nbm + 63) / 64);
-    if (energy) hipLaunchKernelGGL((k_bonded<R, true>), g, dim3(64), 0, st, d, part);
-    else hipLaunchKernelGGL((k_bonded<R, false>), g, dim3(64), 0, st, d, part);
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, st, p, nb, out);
 }
 
-template <typename R>
-void launch_kinetic(const Dev<R>& d, double* part, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_kinetic<R>, dim3((d.N + WG - 1) / WG), dim3(WG), 0, st, d, part);
-}
-
-void launch_energy_final(const double* pnb, int nnb, const double* pbd, int nbd,
-                         const double* pke, int nke, double* out, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, st, pnb, nnb, pbd, nbd, pke, nke,
-                       out);
-}
-
-template void launch_nonbonded<float>(const Dev<float>&, int, bool, double*, hipStream_t);
-template void launch_nonbonded<double>(const Dev<double>&, int, bool, double*, hipStream_t);
-template void launch_bonded<float>(const Dev<float>&, bool, double*, hipStream_t);
-template void launch_bonded<double>(const Dev<double>&, bool, double*, hipStream_t);
-template void launch_kinetic<float>(const Dev<float>&, double*, hipStream_t);
-template void launch_kinetic<double>(const Dev<double>&, double*, hipStream_t);
+template int launch_nonbonded<float>(const Dev<float>&, int, bool, double*, hipStream_t);
+template int launch_nonbonded<double>(const Dev<double>&, int, bool, double*, hipStream_t);
 
 }  // namespace mbx

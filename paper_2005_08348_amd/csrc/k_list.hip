@@ -2,16 +2,19 @@
 // Verlet neighbour list.
 //
 // Layout.  Beads live in "slots" sorted by cell (cells of edge >= r_cut +
-// skin, at least three per axis), and within a cell by bead id, so the sort
-// is deterministic.  Coordinates stay in [0, L) up to the drift since the
-// last rebuild.  Periodic images are handled without any per-pair image
+// skin, at least three per axis, z fastest), and within a cell by bead id,
+// so the order is deterministic.  Coordinates stay in [0, L) up to the drift
+// since the last rebuild.  Periodic images need no per-pair image
 // arithmetic: the top cell layer of each axis is copied, shifted by -L
 // (exact in floating point because x >= L/2), into a halo layer below 0
-// ("ghost" slots N.. N+G), and a bead of the top layer that pairs with cell
+// ("ghost" slots N .. N+G), and a bead of the top layer that pairs with cell
 // 0 across the face is itself shifted down by L (again exact).  A neighbour
-// entry therefore holds the slot j (real or ghost) and, for the rare entries
-// that need it, three bits saying along which axes the i bead is shifted.
-// All resulting separations are single correctly rounded differences.
+// entry holds the slot j (real or ghost) and, for the entries that need it,
+// three bits saying along which axes the i bead is shifted.  All resulting
+// separations are single correctly rounded differences.
+//
+// List build: one work-group per cell, candidates staged in LDS, two passes
+// (count, then write in place) so that the lists come out in a fixed order.
 #include "membx_dev.h"
 
 namespace mbx {
@@ -34,7 +37,7 @@ __global__ void k_bin(Dev<R> d)
             double xd = (double)*c[a];
             xd -= d.Ld[a] * floor(xd / d.Ld[a]);
             x = (R)xd;
-            if (x >= d.L[a]) x = (R)0;
+            if (!(x < d.L[a])) x = (R)0;
         }
         *c[a] = x;
         int ci = (int)(x * d.inv_edge[a]);
@@ -46,26 +49,143 @@ __global__ void k_bin(Dev<R> d)
     atomicAdd(&d.cell_cnt[cell], 1);
 }
 
-// Exclusive scan of in[0..n) into out[0..n], out[n] = total; one work-group.
-__global__ void k_scan(const int* __restrict__ in, int* __restrict__ out, int n)
+// Extended grid: coordinate a in [0, nc] per axis, a = 0 is the halo layer
+// holding images (shifted by -L) of real layer nc-1; a >= 1 is real cell a-1.
+__device__ __forceinline__ void ext_coords(int e, const int ne[3], int a[3])
 {
-    __shared__ int part[1024];
-    int t = threadIdx.x;
-    int per = (n + 1023) / 1024;
-    int b = t * per, e = min(n, b + per);
-    int s = 0;
-    for (int k = b; k < e; ++k) s += in[k];
-    part[t] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        int v = t >= off ? part[t - off] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
+    a[2] = e % ne[2];
+    a[1] = (e / ne[2]) % ne[1];
+    a[0] = e / (ne[2] * ne[1]);
+}
+
+__device__ __forceinline__ int ext_source(const int a[3], const int nc[3])
+{
+    return ((a[0] ? a[0] - 1 : nc[0] - 1) * nc[1] + (a[1] ? a[1] - 1 : nc[1] - 1)) * nc[2] +
+           (a[2] ? a[2] - 1 : nc[2] - 1);
+}
+
+// Cell starts (exclusive scan of the real-cell counts) and the extended
+// grid (real cells point into the slots, halo cells into the ghost range laid
+// out by a scan of their source cells' counts), in three kernels: per-block
+// sums, a scan of the block sums, and the per-block write-out.
+__device__ __forceinline__ int halo_count(const int* cnt, int e, const int ne[3], const int nc[3],
+                                          int* src_out)
+{
+    int a[3];
+    ext_coords(e, ne, a);
+    int src = ext_source(a, nc);
+    *src_out = src;
+    return (a[0] == 0 || a[1] == 0 || a[2] == 0) ? cnt[src] : -1;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_scan_a(Dev<R> d)
+{
+    __shared__ int sh[2][4];
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int segR = (d.ncell + SCAN_BLOCKS - 1) / SCAN_BLOCKS;
+    const int segE = (d.next + SCAN_BLOCKS - 1) / SCAN_BLOCKS;
+    int sr = 0, se = 0;
+    for (int k = b * segR + t; k < min(d.ncell, (b + 1) * segR); k += 256) sr += d.cell_cnt[k];
+    for (int k = b * segE + t; k < min(d.next, (b + 1) * segE); k += 256) {
+        int src, h = halo_count(d.cell_cnt, k, d.ne, d.nc, &src);
+        se += h > 0 ? h : 0;
     }
-    int run = part[t] - s;
-    for (int k = b; k < e; ++k) { out[k] = run; run += in[k]; }
-    if (t == 1023) out[n] = part[1023];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) { sr += __shfl_xor(sr, m); se += __shfl_xor(se, m); }
+    if ((t & 63) == 0) { sh[0][t >> 6] = sr; sh[1][t >> 6] = se; }
+    __syncthreads();
+    if (t == 0) {
+        d.scan_part[b] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
+        d.scan_part[SCAN_BLOCKS + b] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+    }
+}
+
+template <typename R>
+__global__ void k_scan_b(Dev<R> d)
+{
+    if (threadIdx.x != 0) return;
+    int rr = 0, re = 0;
+    for (int b = 0; b < SCAN_BLOCKS; ++b) {
+        int vr = d.scan_part[b], ve = d.scan_part[SCAN_BLOCKS + b];
+        d.scan_part[b] = rr; d.scan_part[SCAN_BLOCKS + b] = re;
+        rr += vr; re += ve;
+    }
+    d.cell_start[d.ncell] = rr;
+    *d.n_ghost = re < d.Gcap ? re : d.Gcap;
+    if (re > d.Gcap) atomicOr(&d.flags[FL_GHOST_OVF], 1);
+}
+
+// block-wide (256 threads) exclusive scan of per-thread values
+__device__ __forceinline__ int block_scan256(int v, int* sh)
+{
+    const int t = threadIdx.x, l = t & 63, w = t >> 6;
+    int x = v;
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        int y = __shfl_up(x, m);
+        if (l >= m) x += y;
+    }
+    if (l == 63) sh[w] = x;
+    __syncthreads();
+    int base = 0;
+    for (int q = 0; q < w; ++q) base += sh[q];
+    __syncthreads();
+    return base + x - v;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_scan_c(Dev<R> d)
+{
+    __shared__ int sh[4];
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int segR = (d.ncell + SCAN_BLOCKS - 1) / SCAN_BLOCKS;
+    const int segE = (d.next + SCAN_BLOCKS - 1) / SCAN_BLOCKS;
+    {
+        const int lo = b * segR, hi = min(d.ncell, (b + 1) * segR);
+        const int per = (segR + 255) / 256;
+        const int k0 = lo + t * per, k1 = min(hi, k0 + per);
+        int s = 0;
+        for (int k = k0; k < k1; ++k) s += d.cell_cnt[k];
+        int run = d.scan_part[b] + block_scan256(s, sh);
+        for (int k = k0; k < k1; ++k) { d.cell_start[k] = run; run += d.cell_cnt[k]; }
+    }
+    __syncthreads();
+    {
+        const int lo = b * segE, hi = min(d.next, (b + 1) * segE);
+        const int per = (segE + 255) / 256;
+        const int k0 = lo + t * per, k1 = min(hi, k0 + per);
+        int s = 0;
+        for (int k = k0; k < k1; ++k) {
+            int src, h = halo_count(d.cell_cnt, k, d.ne, d.nc, &src);
+            s += h > 0 ? h : 0;
+        }
+        int run = d.scan_part[SCAN_BLOCKS + b] + block_scan256(s, sh);
+        for (int k = k0; k < k1; ++k) {
+            int src, h = halo_count(d.cell_cnt, k, d.ne, d.nc, &src);
+            if (h >= 0) {
+                int fit = run >= d.Gcap ? 0 : min(h, d.Gcap - run);
+                d.ext_start[k] = d.N + run;
+                d.ext_cnt[k] = fit;
+                d.ext_scan[k] = run;          // ghost offset of this halo cell
+                run += h;
+            } else {
+                d.ext_cnt[k] = d.cell_cnt[src];
+                d.ext_scan[k] = -1;
+            }
+        }
+    }
+}
+
+// real extended cells take their start from the (now complete) cell starts
+template <typename R>
+__global__ void k_ext_real(Dev<R> d)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= d.next) return;
+    int a[3];
+    ext_coords(k, d.ne, a);
+    if (a[0] && a[1] && a[2]) d.ext_start[k] = d.cell_start[ext_source(a, d.nc)];
 }
 
 // Scatter beads to their cell ranges (arbitrary order inside a cell).
@@ -81,6 +201,7 @@ __global__ void k_scatter(Dev<R> d)
     d.frc_t[dst] = d.frc[i];
     d.orig_t[dst] = d.orig[i];
     d.alch_t[dst] = d.alch[i];
+    d.cellid[dst] = c;    // cell of scratch position dst (read by k_rank)
 }
 
 // Order each cell by bead id: a bead's final slot is the cell start plus the
@@ -91,82 +212,61 @@ __global__ void k_rank(Dev<R> d)
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= d.N) return;
     int o = d.orig_t[p];
-    V4<R> x = d.posq_t[p];
-    int cell = -1;
-    // find the cell of tmp position p: binary search in cell_start
-    int lo = 0, hi = d.ncell;   // cell_start[lo] <= p < cell_start[hi]
-    while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (d.cell_start[mid] <= p) lo = mid; else hi = mid;
-    }
-    cell = lo;
+    int cell = d.cellid[p];
     int b = d.cell_start[cell], e = d.cell_start[cell + 1];
     int r = 0;
-    for (int q = b; q < e; ++q) r += d.orig_t[q] < o;
+    for (int q = b; q < e; q += 8) {   // eight loads in flight per round
+        int v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = (q + u < e) ? d.orig_t[q + u] : 0x7fffffff;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) r += v[u] < o;
+    }
     int s = b + r;
+    V4<R> x = d.posq_t[p];
     d.posq[s] = x;
     d.vel[s] = d.vel_t[p];
     d.frc[s] = d.frc_t[p];
     d.orig[s] = o;
     d.alch[s] = d.alch_t[p];
-    d.cellid[s] = cell;
     d.inv[o] = s;
+    d.orig_ext[s] = o;
     d.xref[s] = x;
+    d.gcnt[s] = 0;
 }
 
-// ----------------------------------------------------------------- ghosts
-// Extended grid: coordinate a in [0, nc] per axis, a = 0 is the halo layer
-// holding images (shifted by -L) of real layer nc-1; a >= 1 is real cell a-1.
-__device__ __forceinline__ void ext_coords(int e, const int ne[3], int a[3])
-{
-    a[2] = e % ne[2];
-    a[1] = (e / ne[2]) % ne[1];
-    a[0] = e / (ne[2] * ne[1]);
-}
-
+// Bonded terms of each slot with their partners' slots (after the sort).
 template <typename R>
-__global__ void k_ghost_count(Dev<R> d)
+__global__ void k_bslots(Dev<R> d)
 {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= d.next) return;
-    int a[3];
-    ext_coords(e, d.ne, a);
-    int halo = (a[0] == 0) | (a[1] == 0) | (a[2] == 0);
-    int src[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) src[k] = a[k] == 0 ? d.nc[k] - 1 : a[k] - 1;
-    int rc = (src[0] * d.nc[1] + src[1]) * d.nc[2] + src[2];
-    d.ext_cnt[e] = d.cell_cnt[rc];
-    d.ext_start[e] = halo ? 0 : d.cell_start[rc];
-    // halo counts feed the ghost scan; real cells contribute nothing
-    d.ext_scan[e] = halo ? d.cell_cnt[rc] : 0;
-}
-
-template <typename R>
-__global__ void k_ghost_fill(Dev<R> d, const int* __restrict__ goff)
-{
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e == 0) {
-        int tot = goff[d.next];
-        *d.n_ghost = tot < d.Gcap ? tot : d.Gcap;
-        if (tot > d.Gcap) atomicOr(&d.flags[FL_GHOST_OVF], 1);
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.N) return;
+    int o = d.orig[i];
+    int b0 = d.bt_off[o], n = d.bt_off[o + 1] - b0;
+    int4* out = d.bslot + (size_t)i * MAXBT;
+    for (int t = 0; t < MAXBT; ++t) {
+        int4 e = make_int4(-1, i, i, 0);
+        if (t < n) {
+            int4 tm = d.bt[b0 + t];
+            e = make_int4(tm.x, d.inv[tm.y], tm.z >= 0 ? d.inv[tm.z] : i, tm.w);
+        }
+        out[t] = e;
     }
-    if (e >= d.next) return;
+}
+
+// Ghost images: one block per extended cell (halo cells only), one thread
+// per image.  Each owner records its images for the integrator.
+template <typename R>
+__global__ void k_ghost_fill(Dev<R> d)
+{
+    int e = blockIdx.x;
+    int g0 = d.ext_scan[e];
+    if (g0 < 0) return;
     int a[3];
     ext_coords(e, d.ne, a);
     int code = (a[0] == 0 ? 1 : 0) | (a[1] == 0 ? 2 : 0) | (a[2] == 0 ? 4 : 0);
-    if (!code) return;
-    int src[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) src[k] = a[k] == 0 ? d.nc[k] - 1 : a[k] - 1;
-    int rc = (src[0] * d.nc[1] + src[1]) * d.nc[2] + src[2];
-    int s0 = d.cell_start[rc], n = d.cell_cnt[rc];
-    int g0 = goff[e];
-    d.ext_start[e] = d.N + g0;
-    int nfit = n;
-    if (g0 + n > d.Gcap) nfit = d.Gcap > g0 ? d.Gcap - g0 : 0;
-    d.ext_cnt[e] = nfit;
-    for (int k = 0; k < nfit; ++k) {
+    int s0 = d.cell_start[ext_source(a, d.nc)], n = d.ext_cnt[e];
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
         int g = g0 + k, s = s0 + k;
         V4<R> p = d.posq[s];
         if (code & 1) p.x -= d.L[0];
@@ -175,10 +275,14 @@ __global__ void k_ghost_fill(Dev<R> d, const int* __restrict__ goff)
         d.posq[d.N + g] = p;
         d.ghost_owner[g] = s;
         d.ghost_code[g] = code;
+        d.orig_ext[d.N + g] = d.orig[s];
+        int q = atomicAdd(&d.gcnt[s], 1);
+        if (q < 7) d.glist[s * 7 + q] = g;
     }
 }
 
-// Refresh ghost coordinates (and class) from their owners after a move.
+// Refresh ghost coordinates (and class) from their owners (after a change of
+// classes; the integrator refreshes them itself after a move).
 template <typename R>
 __global__ void k_ghost_update(Dev<R> d)
 {
@@ -193,75 +297,221 @@ __global__ void k_ghost_update(Dev<R> d)
 }
 
 // ---------------------------------------------------------------- list
-template <typename R>
-__device__ __forceinline__ bool within_rlist(const Dev<R>& d, R dx, R dy, R dz, double xi,
-                                             double yi, double zi, const V4<R>& pj)
+// exact float64 predicate d^2 < (r_cut + skin)^2, evaluated as
+// ((dx*dx + dy*dy) + dz*dz) without contraction
+__device__ __forceinline__ bool within_d(double xi, double yi, double zi, double xj, double yj,
+                                         double zj, double rl2)
 {
-    // exact float64 predicate d^2 < (r_cut + skin)^2, evaluated as
-    // ((dx*dx + dy*dy) + dz*dz) without contraction
 #pragma clang fp contract(off)
-    double ex = xi - (double)pj.x, ey = yi - (double)pj.y, ez = zi - (double)pj.z;
+    double ex = xi - xj, ey = yi - yj, ez = zi - zj;
     double r2 = ex * ex;
     r2 = r2 + ey * ey;
     r2 = r2 + ez * ez;
-    return r2 < d.rl2d;
+    return r2 < rl2;
+}
+
+constexpr int LB = 256;   // threads per cell
+constexpr int HS = 12;    // LDS hit slots per lane (single-pass path)
+template <typename R> struct CandCap { static constexpr int v = 768; };
+template <> struct CandCap<double> { static constexpr int v = 512; };
+
+// List build, one work-group per cell.  The candidates of the 27 neighbour
+// cells (with the i-shift code of their cell) are staged in LDS; each bead of
+// the cell owns Q lanes that split the candidates.  Hits go to per-lane LDS
+// buffers and are written out in a fixed order (lane q of bead i after lanes
+// 0..q-1; unshifted entries before shifted ones), so the lists are
+// deterministic.  If a buffer overflows (very crowded cells) the cell falls
+// back to two passes: count, then test again and write in place.
+template <typename R>
+__device__ __forceinline__ bool cand_hit(const Dev<R>& d, const V4<R>& pi, const V4<R>& pj, int code)
+{
+    const R xs = (code & 1) ? pi.x - d.L[0] : pi.x;
+    const R ys = (code & 2) ? pi.y - d.L[1] : pi.y;
+    const R zs = (code & 4) ? pi.z - d.L[2] : pi.z;
+    if (sizeof(R) == 4) {
+        R dx = xs - pj.x, dy = ys - pj.y, dz = zs - pj.z;
+        float r2f = (float)(dx * dx + dy * dy + dz * dz);
+        if (r2f < d.rl2f_lo) return true;
+        if (r2f > d.rl2f_hi) return false;
+    }
+    return within_d((double)xs, (double)ys, (double)zs, (double)pj.x, (double)pj.y, (double)pj.z,
+                    d.rl2d);
+}
+
+// one candidate test: float64-exact r^2 < r_list^2 and not bonded
+template <typename R>
+__device__ __forceinline__ bool list_hit(const Dev<R>& d, const V4<R>& pi, int oi, unsigned exm,
+                                         int i, const V4<R>& pj, int code, int ent)
+{
+    const R xs = (code & 1) ? pi.x - d.L[0] : pi.x;
+    const R ys = (code & 2) ? pi.y - d.L[1] : pi.y;
+    const R zs = (code & 4) ? pi.z - d.L[2] : pi.z;
+    bool in;
+    if (sizeof(R) == 4) {
+        const R dx = xs - pj.x, dy = ys - pj.y, dz = zs - pj.z;
+        const float r2f = (float)(dx * dx + dy * dy + dz * dz);
+        in = r2f < d.rl2f_lo;
+        if (!in && !(r2f > d.rl2f_hi))
+            in = within_d((double)xs, (double)ys, (double)zs, (double)pj.x, (double)pj.y,
+                          (double)pj.z, d.rl2d);
+    } else {
+        in = within_d((double)xs, (double)ys, (double)zs, (double)pj.x, (double)pj.y,
+                      (double)pj.z, d.rl2d);
+    }
+    const unsigned rel = (unsigned)(cls_of<R>(pj.w) - oi + 16);
+    const bool bonded = rel < 32u && ((exm >> rel) & 1u);
+    return in && !bonded && (ent & JMASK) != i;
 }
 
 template <typename R>
-__global__ __launch_bounds__(WG) void k_list(Dev<R> d)
+__global__ __launch_bounds__(LB) void k_list(Dev<R> d)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= d.N) return;
-    V4<R> pi = d.posq[i];
-    int cell = d.cellid[i];
-    int cz = cell % d.nc[2], cy = (cell / d.nc[2]) % d.nc[1], cx = cell / (d.nc[2] * d.nc[1]);
-    int oi = d.orig[i];
-    int ex[MAXEXCL];
+    constexpr int CMAX = CandCap<R>::v;
+    __shared__ V4<R> cpos[CMAX];      // w = bead id of the candidate (int bits)
+    __shared__ int cjs[CMAX];         // entry value: slot | code << 29
+    __shared__ int hits[LB * (HS + 1)];
+    __shared__ int off[28], jst[27], cod[27];
+    __shared__ int cnt0[LB], cnt1[LB];
+    const int cell = blockIdx.x;
+    const int t = threadIdx.x;
+    const int Kc = d.Kcap;
+    if (t == 0) { d.cell_cnt[cell] = 0; d.cell_cur[cell] = 0; }   // for the next rebuild
+    const int s0 = d.cell_start[cell], ni = d.cell_start[cell + 1] - s0;
+    if (ni == 0) return;
+    const int cz = cell % d.nc[2], cy = (cell / d.nc[2]) % d.nc[1], cx = cell / (d.nc[2] * d.nc[1]);
+    if (t < 27) {
+        const int ox = t / 9 - 1, oy = (t / 3) % 3 - 1, oz = t % 3 - 1;
+        int ax = cx + ox, ay = cy + oy, az = cz + oz, code = 0;
+        if (ax == d.nc[0]) { ax = 0; code |= 1; }
+        if (ay == d.nc[1]) { ay = 0; code |= 2; }
+        if (az == d.nc[2]) { az = 0; code |= 4; }
+        const int e = ((ax + 1) * d.ne[1] + (ay + 1)) * d.ne[2] + (az + 1);
+        jst[t] = d.ext_start[e];
+        off[t + 1] = d.ext_cnt[e];
+        cod[t] = code;
+    }
+    __syncthreads();
+    if (t == 0) {
+        off[0] = 0;
+        for (int o = 0; o < 27; ++o) off[o + 1] += off[o];
+    }
+    __syncthreads();
+    const int C = off[27];
+    const bool one_round = C <= CMAX;
+    auto stage = [&](int cb, int nc) {
+        __syncthreads();
+        constexpr int PT = (CMAX + LB - 1) / LB;
+        for (int u0 = 0; u0 < PT; u0 += 4) {
+            int js[4], cs[4];
 #pragma unroll
-    for (int e = 0; e < MAXEXCL; ++e) ex[e] = d.excl[oi * MAXEXCL + e];
-    int k = 0;
-    for (int pass = 0; pass < 2; ++pass) {
-        for (int o = 0; o < 27; ++o) {
-            int ox = o / 9 - 1, oy = (o / 3) % 3 - 1, oz = o % 3 - 1;
-            int ax = cx + ox, ay = cy + oy, az = cz + oz, code = 0;
-            if (ax == d.nc[0]) { ax = 0; code |= 1; }
-            if (ay == d.nc[1]) { ay = 0; code |= 2; }
-            if (az == d.nc[2]) { az = 0; code |= 4; }
-            if ((pass == 0) != (code == 0)) continue;
-            int e = ((ax + 1) * d.ne[1] + (ay + 1)) * d.ne[2] + (az + 1);
-            int j0 = d.ext_start[e], jn = d.ext_cnt[e];
-            R xs = pi.x, ys = pi.y, zs = pi.z;
-            if (code & 1) xs -= d.L[0];
-            if (code & 2) ys -= d.L[1];
-            if (code & 4) zs -= d.L[2];
-            double xd = (double)xs, yd = (double)ys, zd = (double)zs;
-            for (int j = j0; j < j0 + jn; ++j) {
-                if (j == i) continue;
-                V4<R> pj = d.posq[j];
-                R dx = xs - pj.x, dy = ys - pj.y, dz = zs - pj.z;
-                bool in;
-                if (sizeof(R) == 4) {
-                    float r2f = (float)(dx * dx + dy * dy + dz * dz);
-                    if (r2f < d.rl2f_lo) in = true;
-                    else if (r2f > d.rl2f_hi) in = false;
-                    else in = within_rlist(d, dx, dy, dz, xd, yd, zd, pj);
-                } else {
-                    in = within_rlist(d, dx, dy, dz, xd, yd, zd, pj);
+            for (int u = 0; u < 4; ++u) {
+                const int c = t + (u0 + u) * LB, idx = cb + c;
+                int o = 0;
+                if (c < nc)
+                    while (off[o + 1] <= idx) ++o;
+                js[u] = c < nc ? jst[o] + (idx - off[o]) : 0;
+                cs[u] = cod[o];
+            }
+            V4<R> ps[4];
+            int oj[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) { ps[u] = d.posq[js[u]]; oj[u] = d.orig_ext[js[u]]; }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int c = t + (u0 + u) * LB;
+                if (c < nc) {
+                    V4<R> p = ps[u];
+                    p.w = cls_to<R>(oj[u]);
+                    cpos[c] = p;
+                    cjs[c] = js[u] | (cs[u] << CODE_SHIFT);
                 }
-                if (!in) continue;
-                int oj = j < d.N ? d.orig[j] : d.orig[d.ghost_owner[j - d.N]];
-                bool exc = false;
-#pragma unroll
-                for (int q = 0; q < MAXEXCL; ++q) exc |= (ex[q] == oj);
-                if (exc) continue;
-                if (k < d.Kcap) d.nbr[(size_t)k * d.Npad + i] = j | (code << CODE_SHIFT);
-                ++k;
             }
         }
-        if (pass == 0) d.nseg0[i] = min(k, d.Kcap);
+        __syncthreads();
+    };
+    for (int ib = 0; ib < ni; ib += LB) {
+        const int nib = min(LB, ni - ib);
+        const int Q = max(1, LB / nib);
+        const int li = t / Q, q = t % Q;
+        const bool act = li < nib;
+        const int i = s0 + ib + (act ? li : 0);
+        const V4<R> pi = d.posq[i];
+        const int oi = d.orig[i];
+        const unsigned exm = d.exmask[oi];
+        const size_t ibase = nbr_base(i, Kc, d.lpb_shift, d.bg_shift);
+        // single pass: test every candidate once, hits to per-lane LDS
+        // buffers (unshifted entries upward, shifted downward; a hit past the
+        // buffer sets the overflow flag and lands in the scratch slot HS)
+        int n0 = 0, n1 = 0;
+        bool lane_ovf = false;
+        for (int cb = 0; cb < C; cb += CMAX) {
+            const int nc = min(CMAX, C - cb);
+            if (!(one_round && ib > 0)) stage(cb, nc);
+            const int nu = (nc + Q - 1) / Q;
+            for (int u = 0; u < nu; ++u) {
+                const int c = q + u * Q;
+                const bool vc = act && c < nc;
+                const int cc = vc ? c : 0;
+                const V4<R> pj = cpos[cc];
+                const int ent = cjs[cc];
+                const int code = (int)((unsigned)ent >> CODE_SHIFT);
+                const bool hit = vc && list_hit(d, pi, oi, exm, i, pj, code, ent);
+                const bool z = code == 0;
+                const int nn = n0 + n1;
+                const int pos = (hit && nn < HS) ? (z ? n0 : HS - 1 - n1) : HS;
+                hits[t * (HS + 1) + pos] = ent;
+                lane_ovf |= hit && nn >= HS;
+                n0 += (hit && z) ? 1 : 0;
+                n1 += (hit && !z) ? 1 : 0;
+            }
+        }
+        const bool ovf_any = __syncthreads_or(lane_ovf ? 1 : 0) != 0;
+        cnt0[t] = act ? n0 : 0;
+        cnt1[t] = act ? n1 : 0;
+        __syncthreads();
+        int b0 = 0, b1 = 0, t0 = 0, t1 = 0;
+        if (act) {
+            for (int qq = 0; qq < Q; ++qq) {
+                const int c0 = cnt0[li * Q + qq], c1 = cnt1[li * Q + qq];
+                if (qq < q) { b0 += c0; b1 += c1; }
+                t0 += c0; t1 += c1;
+            }
+            if (q == 0) {
+                d.nseg0[i] = min(t0, Kc);
+                d.ncnt[i] = min(t0 + t1, Kc);
+                if (t0 + t1 > Kc) atomicOr(&d.flags[FL_LIST_OVF], 1);
+            }
+        }
+        if (!ovf_any) {
+            if (act) {
+                for (int k = 0; k < n0; ++k)
+                    if (b0 + k < Kc)
+                        d.nbr[ibase + nbr_koff(b0 + k, d.lpb_shift)] = hits[t * (HS + 1) + k];
+                for (int k = 0; k < n1; ++k)
+                    if (t0 + b1 + k < Kc)
+                        d.nbr[ibase + nbr_koff(t0 + b1 + k, d.lpb_shift)] = hits[t * (HS + 1) + HS - 1 - k];
+            }
+        } else {
+            // crowded cell: test again and write in place at the known offsets
+            int m0 = 0, m1 = 0;
+            for (int cb = 0; cb < C; cb += CMAX) {
+                const int nc = min(CMAX, C - cb);
+                if (!one_round) stage(cb, nc);
+                const int nu = (nc + Q - 1) / Q;
+                for (int u = 0; u < nu; ++u) {
+                    const int c = q + u * Q;
+                    if (!(act && c < nc)) continue;
+                    const V4<R> pj = cpos[c];
+                    const int ent = cjs[c];
+                    const int code = (int)((unsigned)ent >> CODE_SHIFT);
+                    if (!list_hit(d, pi, oi, exm, i, pj, code, ent)) continue;
+                    const int k = code == 0 ? b0 + m0++ : t0 + b1 + m1++;
+                    if (k < Kc) d.nbr[ibase + nbr_koff(k, d.lpb_shift)] = ent;
+                }
+            }
+        }
+        __syncthreads();
     }
-    if (k > d.Kcap) atomicOr(&d.flags[FL_LIST_OVF], 1);
-    d.ncnt[i] = min(k, d.Kcap);
 }
 
 // ----------------------------------------------------------------- launch
@@ -270,21 +520,16 @@ __global__ __launch_bounds__(WG) void k_list(Dev<R> d)
 template <typename R>
 void launch_rebuild(const Dev<R>& d, hipStream_t st)
 {
-    // zero counters with a fill kernel (no memset nodes in captured graphs)
-    extern void launch_fill_i32(int* p, int v, size_t n, hipStream_t st);
-    launch_fill_i32(d.cell_cnt, 0, d.ncell, st);
-    launch_fill_i32(d.cell_cur, 0, d.ncell, st);
     hipLaunchKernelGGL(k_bin<R>, GRID(d.N), 0, st, d);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, d.cell_cnt, d.cell_start, d.ncell);
+    hipLaunchKernelGGL(k_scan_a<R>, dim3(SCAN_BLOCKS), dim3(256), 0, st, d);
+    hipLaunchKernelGGL(k_scan_b<R>, dim3(1), dim3(64), 0, st, d);
+    hipLaunchKernelGGL(k_scan_c<R>, dim3(SCAN_BLOCKS), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_scatter<R>, GRID(d.N), 0, st, d);
     hipLaunchKernelGGL(k_rank<R>, GRID(d.N), 0, st, d);
-    hipLaunchKernelGGL(k_ghost_count<R>, GRID(d.next), 0, st, d);
-    // ghost offsets: scan of the halo counts (in place into cell_cur-free scratch)
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, d.ext_scan, d.ext_scan + d.next + 1,
-                       d.next);
-    hipLaunchKernelGGL(k_ghost_fill<R>, GRID(d.next), 0, st, d,
-                       (const int*)(d.ext_scan + d.next + 1));
-    hipLaunchKernelGGL(k_list<R>, GRID(d.N), 0, st, d);
+    hipLaunchKernelGGL(k_ext_real<R>, GRID(d.next), 0, st, d);
+    hipLaunchKernelGGL(k_ghost_fill<R>, dim3(d.next), dim3(64), 0, st, d);
+    hipLaunchKernelGGL(k_bslots<R>, GRID(d.N), 0, st, d);
+    hipLaunchKernelGGL(k_list<R>, dim3(d.ncell), dim3(LB), 0, st, d);
 }
 
 template <typename R>

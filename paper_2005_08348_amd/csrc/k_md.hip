@@ -26,15 +26,27 @@ __global__ __launch_bounds__(WG) void k_kick_drift(Dev<R> d, R kick, long long s
     p.x += h * v.x; p.y += h * v.y; p.z += h * v.z;
     d.posq[i] = p;
     d.vel[i] = v;
+    // refresh this bead's periodic images (exact shifts by -L)
+    const int gc = d.gcnt[i];
+    for (int q = 0; q < gc && q < 7; ++q) {
+        const int g = d.glist[i * 7 + q], code = d.ghost_code[g];
+        V4<R> pg = p;
+        if (code & 1) pg.x -= d.L[0];
+        if (code & 2) pg.y -= d.L[1];
+        if (code & 4) pg.z -= d.L[2];
+        d.posq[d.N + g] = pg;
+    }
     V4<R> r = d.xref[i];
     R ex = p.x - r.x, ey = p.y - r.y, ez = p.z - r.z;
     if (ex * ex + ey * ey + ez * ez > d.skin_half2) atomicOr(&d.flags[FL_SKIN], 1);
 }
 
+// closing half-kick of a run of steps; also advances the step counter
 template <typename R>
-__global__ __launch_bounds__(WG) void k_kick(Dev<R> d, R kick)
+__global__ __launch_bounds__(WG) void k_kick(Dev<R> d, R kick, long long nsteps)
 {
     int i = blockIdx.x * WG + threadIdx.x;
+    if (i == 0 && nsteps) d.ctr[CT_STEP] += nsteps;
     if (i >= d.N) return;
     V4<R> v = d.vel[i], f = d.frc[i];
     v.x += kick * v.w * f.x; v.y += kick * v.w * f.y; v.z += kick * v.w * f.z;
@@ -124,9 +136,9 @@ void launch_kick_drift(const Dev<R>& d, R kick, long long step_off, hipStream_t 
                        step_off);
 }
 template <typename R>
-void launch_kick(const Dev<R>& d, R kick, hipStream_t st)
+void launch_kick(const Dev<R>& d, R kick, long long nsteps, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_kick<R>, dim3((d.N + WG - 1) / WG), dim3(WG), 0, st, d, kick);
+    hipLaunchKernelGGL(k_kick<R>, dim3((d.N + WG - 1) / WG), dim3(WG), 0, st, d, kick, nsteps);
 }
 template <typename R>
 void launch_sd_step(const Dev<R>& d, double alpha, double cap, hipStream_t st)
@@ -146,7 +158,7 @@ void launch_import(const Dev<R>& d, V4<R>* dst, const double* in, hipStream_t st
 
 #define INST(R)                                                                      \
     template void launch_kick_drift<R>(const Dev<R>&, R, long long, hipStream_t);   \
-    template void launch_kick<R>(const Dev<R>&, R, hipStream_t);                    \
+    template void launch_kick<R>(const Dev<R>&, R, long long, hipStream_t);                    \
     template void launch_sd_step<R>(const Dev<R>&, double, double, hipStream_t);     \
     template void launch_export<R>(const Dev<R>&, const V4<R>*, double*, hipStream_t); \
     template void launch_import<R>(const Dev<R>&, V4<R>*, const double*, hipStream_t);

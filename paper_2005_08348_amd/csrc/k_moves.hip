@@ -354,7 +354,7 @@ __global__ __launch_bounds__(64) void k_du_bead(Dev<R> d, Mv m)
     const int n0 = d.nseg0[i], n1 = d.ncnt[i];
     double du = 0.0;
     for (int k = lane; k < n1; k += 64) {
-        int en = d.nbr[(size_t)k * d.Npad + i];
+        int en = d.nbr[nbr_index(i, k, d.Kcap, d.lpb)];
         int j = en & JMASK, code = (int)((unsigned)en >> CODE_SHIFT);
         if (k < n0) code = 0;
         V4<R> pj = d.posq[j];
@@ -423,7 +423,7 @@ __global__ __launch_bounds__(64) void k_aff_mark(Dev<R> d, Mv m, int only_accept
     const int i = d.inv[m.r_bead[a * MC + q]];
     const int n1 = d.ncnt[i];
     for (int k = lane - 1; k < n1; k += 64) {
-        int s = (k < 0) ? i : owner_of(d.ghost_owner, d.N, d.nbr[(size_t)k * d.Npad + i] & JMASK);
+        int s = (k < 0) ? i : owner_of(d.ghost_owner, d.N, d.nbr[nbr_index(i, k, d.Kcap, d.lpb)] & JMASK);
         if (atomicExch(&m.aff_flag[s], 1) == 0) {
             int idx = atomicAdd(m.aff_n, 1);
             if (idx < m.aff_cap) m.aff_list[idx] = s;
@@ -462,7 +462,7 @@ __global__ __launch_bounds__(WG) void k_dforce(Dev<R> d, Mv m, R scale)
         const int ci2 = mk >= 0 ? (mk & 0xff) : ci;
         const int n0 = d.nseg0[i], n1 = d.ncnt[i];
         for (int k = s; k < n1; k += 8) {
-            int en = d.nbr[(size_t)k * d.Npad + i];
+            int en = d.nbr[nbr_index(i, k, d.Kcap, d.lpb)];
             int j = en & JMASK, code = (int)((unsigned)en >> CODE_SHIFT);
             if (k < n0) code = 0;
             int o = owner_of(d.ghost_owner, d.N, j);

@@ -13,6 +13,8 @@ constexpr int MAXCH = 8;         // beads changed per molecule by an exchange
 constexpr int MAXMB = 16;        // beads per bonded molecule
 constexpr int CODE_SHIFT = 29;   // neighbour entry: j | (i-shift bits << 29)
 constexpr int JMASK = (1 << CODE_SHIFT) - 1;
+constexpr int MAXBT = 8;         // bonded terms per bead
+constexpr int SCAN_BLOCKS = 128; // blocks of the cell-count scans
 
 // random streams (fourth Philox counter word)
 enum { ST_LANGEVIN = 0, ST_SWAP_DRAW = 1, ST_SWAP_ACCEPT = 2, ST_MDAS_SELECT = 3,
@@ -151,12 +153,21 @@ template <typename R> struct Dev {
     int* ghost_owner;
     int* ghost_code;
     int* n_ghost;    // [1]
-    // neighbour list (ELL, entry k of slot i at nbr[k * Npad + i])
+    int* gcnt;       // [N] images of each slot
+    int* glist;      // [N * 7] their ghost indices
+    int* orig_ext;   // [N + Gcap] bead id of each slot or ghost image
+    int4* bslot;     // [N * 8] bonded terms of each slot with partner slots
+                     // {role, slot 1, slot 2, parameter}; role -1 = unused
+    int* scan_part;  // [2 * SCAN_BLOCKS + 2] block sums of the cell scans
+    // neighbour list, tiled so that the LPB lanes of the 64/LPB beads a wave
+    // handles read one contiguous 256-byte block per load (see nbr_index)
+    int lpb, lpb_shift, bg_shift;   // lanes per bead, log2(lpb), log2(64/lpb)
     int* nbr;
     int* ncnt;
     int* nseg0;
     // topology
     int* excl;       // [N * MAXEXCL] bead ids, -1 padded
+    unsigned* exmask;  // [N] bit (j - i + 16) set when bead j is bonded to bead i
     int* mol_first;  // [nm]
     int* mol_kind;   // [nm] current kinds
     int* bmols;      // [nbm] molecules with bonded terms
@@ -165,6 +176,12 @@ template <typename R> struct Dev {
     int* kcls;       // [sum kn] class of each kind bead
     int* kb_off; int* kb_n; int* b_ij; R* b_par;   // bonds: (i,j), (b0,k)
     int* ka_off; int* ka_n; int* a_ijk; R* a_par;  // angles: (i,j,k), (cos0,k)
+    // bonded terms seen from each bead (bead-id order): [bt_off[b], bt_off[b+1])
+    // entries {role, partner 1, partner 2, parameter index}; roles: 0 bond
+    // (energy owner), 1 bond, 2 angle end, 3 angle vertex (energy owner)
+    int* bt_off;
+    int4* bt;
+    R* bt_par;       // (b0, k) or (cos theta0, k)
     // tables
     V4<R>* tabF;
     V4<R>* tabE;
@@ -220,5 +237,25 @@ struct Mv {
     // snapshot of the per-slot state
     void* snap_posq; void* snap_vel; void* snap_frc; int* snap_orig;
 };
+
+// Entry k of slot i's neighbour list: beads are grouped by 64/lpb, and
+// within a group entries are interleaved in blocks of lpb.
+__host__ __device__ __forceinline__ size_t nbr_index(int i, int k, int Kcap, int lpb)
+{
+    const int bg = 64 / lpb;
+    return (size_t)(i / bg) * ((size_t)Kcap * bg) + (size_t)(k / lpb) * 64 + (size_t)(i % bg) * lpb +
+           (size_t)(k % lpb);
+}
+
+// nbr_index with power-of-two shifts: base of slot i, then + k offsets
+__host__ __device__ __forceinline__ size_t nbr_base(int i, int Kcap, int lpb_shift, int bg_shift)
+{
+    return ((size_t)(i >> bg_shift) * (size_t)Kcap << bg_shift) +
+           ((size_t)(i & ((1 << bg_shift) - 1)) << lpb_shift);
+}
+__host__ __device__ __forceinline__ size_t nbr_koff(int k, int lpb_shift)
+{
+    return ((size_t)(k >> lpb_shift) << 6) + (size_t)(k & ((1 << lpb_shift) - 1));
+}
 
 }  // namespace mbx

@@ -2,6 +2,7 @@
 // layout, upload, step sequencing, exchange moves, MDAS cycles, queries,
 // HIP-graph replay and kernel timing.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -17,13 +18,10 @@ namespace mbx {
 // launchers (defined in the kernel translation units)
 template <typename R> void launch_rebuild(const Dev<R>&, hipStream_t);
 template <typename R> void launch_ghost_update(const Dev<R>&, hipStream_t);
-template <typename R> void launch_nonbonded(const Dev<R>&, int, bool, double*, hipStream_t);
-template <typename R> void launch_bonded(const Dev<R>&, bool, double*, hipStream_t);
-template <typename R> void launch_kinetic(const Dev<R>&, double*, hipStream_t);
-void launch_energy_final(const double*, int, const double*, int, const double*, int, double*,
-                         hipStream_t);
+template <typename R> int launch_nonbonded(const Dev<R>&, int, bool, double*, hipStream_t);
+void launch_energy_final(const double*, int, double*, hipStream_t);
 template <typename R> void launch_kick_drift(const Dev<R>&, R, long long, hipStream_t);
-template <typename R> void launch_kick(const Dev<R>&, R, hipStream_t);
+template <typename R> void launch_kick(const Dev<R>&, R, long long, hipStream_t);
 template <typename R> void launch_sd_step(const Dev<R>&, double, double, hipStream_t);
 template <typename R> void launch_export(const Dev<R>&, const V4<R>*, double*, hipStream_t);
 template <typename R> void launch_import(const Dev<R>&, V4<R>*, const double*, hipStream_t);
@@ -92,6 +90,9 @@ struct Host {
     std::vector<std::pair<int, double>> cls;   // (type, charge)
     std::vector<int> excl;              // [N * MAXEXCL]
     std::vector<int> bmols;
+    std::vector<int> bt_off;            // per-bead bonded terms (CSR over bead ids)
+    std::vector<int> bt;                // 4 ints per entry
+    std::vector<double> bt_par;         // 2 per parameter set
     std::vector<int> sw_list, fam_off, fam_mem, fam_of_kind, chg_n, chg_loc;
     int nfam = 0, maxch = 0, fam_stride = 1;
     double krf, crf;
@@ -214,6 +215,8 @@ Status check_desc(const membx_desc* d, Host& h)
         double exp_n = rho * 4.0 / 3.0 * M_PI * rl * rl * rl;
         h.Kcap = (int)std::ceil((exp_n * 1.8 + 24) / 8.0) * 8;
     }
+    h.Kcap = std::max(h.Kcap, 96);   // the pair kernel reads the first 96 entries unconditionally
+    if (h.Kcap > 224) return { MEMBX_E_INVAL, "list capacity above 224 per bead (lower skin or density)" };
     double gfrac = (1.0 + 1.0 / h.nc[0]) * (1.0 + 1.0 / h.nc[1]) * (1.0 + 1.0 / h.nc[2]) - 1.0;
     h.Gcap = (int)(h.N * gfrac * 1.6) + 4096;
     if ((long long)h.N + h.Gcap >= (1LL << CODE_SHIFT)) return { MEMBX_E_INVAL, "too many beads" };
@@ -324,6 +327,39 @@ Status derive(const membx_desc* d, Host& h)
             h.chg_n[a * h.nk + b] = c;
             h.maxch = std::max(h.maxch, c);
         }
+    // bonded terms as seen from each bead: bonds (role 0 owns the energy,
+    // role 1 the partner), angle ends (role 2) and vertices (role 3, owner)
+    {
+        std::vector<std::vector<std::array<int, 4>>> per(h.N);
+        int nbp = (int)h.b_par.size() / 2;
+        for (int q = 0; q < nbp; ++q) { h.bt_par.push_back(h.b_par[2 * q]); h.bt_par.push_back(h.b_par[2 * q + 1]); }
+        for (size_t q = 0; q < h.a_par.size() / 2; ++q) { h.bt_par.push_back(h.a_par[2 * q]); h.bt_par.push_back(h.a_par[2 * q + 1]); }
+        for (int m = 0; m < h.nm; ++m) {
+            int k = h.mol_kind0[m], f0 = h.mol_first[m];
+            for (int q = 0; q < h.kb_n[k]; ++q) {
+                int bq = h.kb_off[k] + q;
+                int i = f0 + h.b_ij[2 * bq], j = f0 + h.b_ij[2 * bq + 1];
+                per[i].push_back({ 0, j, -1, bq });
+                per[j].push_back({ 1, i, -1, bq });
+            }
+            for (int q = 0; q < h.ka_n[k]; ++q) {
+                int aq = h.ka_off[k] + q;
+                int i = f0 + h.a_ijk[3 * aq], j = f0 + h.a_ijk[3 * aq + 1], l = f0 + h.a_ijk[3 * aq + 2];
+                per[i].push_back({ 2, j, l, nbp + aq });
+                per[l].push_back({ 2, j, i, nbp + aq });
+                per[j].push_back({ 3, i, l, nbp + aq });
+            }
+        }
+        h.bt_off.assign(h.N + 1, 0);
+        for (int b = 0; b < h.N; ++b) {
+            if ((int)per[b].size() > MAXBT)
+                return { MEMBX_E_INVAL, "a bead takes part in more than 8 bonded terms" };
+            h.bt_off[b + 1] = h.bt_off[b] + (int)per[b].size();
+            for (auto& e : per[b]) h.bt.insert(h.bt.end(), e.begin(), e.end());
+        }
+        if (h.bt.empty()) h.bt.assign(4, 0);
+        if (h.bt_par.empty()) h.bt_par.assign(2, 0.0);
+    }
     h.aff_cap = std::max(h.T_cap, h.P_cap) * 2 * h.maxch * (h.Kcap + 1);
     h.aff_cap = std::min(h.aff_cap, h.N);
     (void)d;
@@ -379,6 +415,9 @@ static size_t layout(membx_sys* s, Dev<R>& d, Mv& m, char* base)
     int Npad = (N + 63) / 64 * 64;
     d.N = N; d.Npad = Npad; d.nm = h.nm; d.nk = h.nk; d.ncls = (int)h.cls.size();
     d.Kcap = h.Kcap; d.Gcap = h.Gcap; d.nbm = (int)h.bmols.size();
+    d.lpb = h.lpb;
+    d.lpb_shift = h.lpb == 1 ? 0 : h.lpb == 2 ? 1 : h.lpb == 4 ? 2 : 3;
+    d.bg_shift = 6 - d.lpb_shift;
     d.posq = a.take<V4<R>>(N + h.Gcap);
     d.vel = a.take<V4<R>>(N);
     d.frc = a.take<V4<R>>(N);
@@ -394,9 +433,15 @@ static size_t layout(membx_sys* s, Dev<R>& d, Mv& m, char* base)
     d.ext_scan = a.take<int>(2 * h.next + 2);
     d.ghost_owner = a.take<int>(h.Gcap); d.ghost_code = a.take<int>(h.Gcap);
     d.n_ghost = a.take<int>(1);
+    d.gcnt = a.take<int>(N);
+    d.glist = a.take<int>(7 * (size_t)N);
+    d.orig_ext = a.take<int>(N + h.Gcap);
+    d.bslot = a.take<int4>((size_t)N * MAXBT);
+    d.scan_part = a.take<int>(2 * SCAN_BLOCKS + 2);
     d.nbr = a.take<int>((size_t)h.Kcap * Npad);
     d.ncnt = a.take<int>(N); d.nseg0 = a.take<int>(N);
     d.excl = a.take<int>((size_t)N * MAXEXCL);
+    d.exmask = a.take<unsigned>(N);
     d.mol_first = a.take<int>(h.nm); d.mol_kind = a.take<int>(h.nm);
     d.bmols = a.take<int>(h.bmols.size());
     d.kn = a.take<int>(h.nk); d.kbead_off = a.take<int>(h.nk);
@@ -405,13 +450,16 @@ static size_t layout(membx_sys* s, Dev<R>& d, Mv& m, char* base)
     d.b_ij = a.take<int>(h.b_ij.size()); d.b_par = a.take<R>(h.b_par.size());
     d.ka_off = a.take<int>(h.nk); d.ka_n = a.take<int>(h.nk);
     d.a_ijk = a.take<int>(h.a_ijk.size()); d.a_par = a.take<R>(h.a_par.size());
+    d.bt_off = a.take<int>(h.bt_off.size());
+    d.bt = a.take<int4>(h.bt.size() / 4);
+    d.bt_par = a.take<R>(h.bt_par.size());
     d.tabF = a.take<V4<R>>(MAXCLS * MAXCLS); d.tabE = a.take<V4<R>>(MAXCLS * MAXCLS);
     d.flags = a.take<int>(NFLAGS);
     d.ctr = a.take<long long>(NCTR);
     s->nbe_blocks = (N * 8 + WG - 1) / WG;
     s->bd_blocks = ((int)h.bmols.size() + 63) / 64;
     s->ke_blocks = (N + WG - 1) / WG;
-    d.red = a.take<double>(4 * (size_t)(s->nbe_blocks + s->bd_blocks + s->ke_blocks));
+    d.red = a.take<double>(8 * (size_t)s->nbe_blocks);
     d.eout = a.take<double>(8);
     s->xbuf = a.take<double>(3 * (size_t)N);
     s->ibuf = a.take<int>(N);
@@ -502,7 +550,7 @@ template <typename R>
 static void forces(membx_sys* s, bool rebuilt)
 {
     Dev<R>& d = dev<R>(s);
-    if (!rebuilt) launch_ghost_update<R>(d, s->st);
+    (void)rebuilt;   // the integrator and the rebuild keep the ghost images current
     if (s->timing) {
         if (s->tev_used >= s->tev.size()) {
             hipEvent_t a, b;
@@ -517,7 +565,6 @@ static void forces(membx_sys* s, bool rebuilt)
     } else {
         launch_nonbonded<R>(d, s->h.lpb, false, nullptr, s->st);
     }
-    launch_bonded<R>(d, false, nullptr, s->st);
 }
 
 struct Alch {
@@ -552,8 +599,7 @@ static void steps_seq(membx_sys* s, long long n, const Alch* alch)
         forces<R>(s, rebuilt);
         if (alch) alch_terms<R>(s, rebuilt, alch->lam);
     }
-    launch_kick<R>(d, h, s->st);
-    launch_add_ctr(d.ctr, CT_STEP, n, s->st);
+    launch_kick<R>(d, h, n, s->st);
 }
 
 template <typename R>
@@ -779,6 +825,13 @@ static int32_t upload(membx_sys* s, const membx_desc* desc)
     UP(d.inv, ident);
     UP(d.alch, minus1);
     UP(d.excl, h.excl);
+    std::vector<unsigned> exm(h.N, 0u);
+    for (int i = 0; i < h.N; ++i)
+        for (int e = 0; e < MAXEXCL; ++e) {
+            int j = h.excl[(size_t)i * MAXEXCL + e];
+            if (j >= 0) exm[i] |= 1u << (j - i + 16);
+        }
+    UP(d.exmask, exm);
     UP(d.mol_first, h.mol_first);
     UP(d.mol_kind, h.mol_kind0);
     UP(d.bmols, h.bmols);
@@ -793,6 +846,10 @@ static int32_t upload(membx_sys* s, const membx_desc* desc)
     UP(d.ka_n, h.ka_n);
     UP(d.a_ijk, h.a_ijk);
     UP(d.a_par, apar);
+    std::vector<R> btpar(h.bt_par.begin(), h.bt_par.end());
+    UP(d.bt_off, h.bt_off);
+    UP(d.bt, h.bt);
+    UP(d.bt_par, btpar);
     UP(d.tabF, tf);
     UP(d.tabE, te);
     UP(d.flags, zeros_flags);
@@ -805,6 +862,11 @@ static int32_t upload(membx_sys* s, const membx_desc* desc)
     UP(m.chg_loc, h.chg_loc);
 #undef UP
     HCK(hipMemsetAsync(d.frc, 0, sizeof(V4<R>) * h.N, st));
+    // binning counters start at zero; afterwards the list kernel clears them
+    // for the next rebuild
+    HCK(hipMemsetAsync(d.cell_cnt, 0, sizeof(int) * h.ncell, st));
+    HCK(hipMemsetAsync(d.cell_cur, 0, sizeof(int) * h.ncell, st));
+    HCK(hipMemsetAsync(d.gcnt, 0, sizeof(int) * h.N, st));
     HCK(hipMemsetAsync(m.h_head, 0, sizeof(unsigned long long) * h.hcells, st));
     HCK(hipMemsetAsync(m.m_head, 0, sizeof(unsigned long long) * h.mh, st));
     HCK(hipMemsetAsync(m.used, 0, sizeof(int) * h.nm, st));
@@ -1005,15 +1067,8 @@ template <typename R>
 static int32_t energies_impl(membx_sys* s, membx_energy* out)
 {
     Dev<R>& d = dev<R>(s);
-    double* pnb = d.red;
-    double* pbd = pnb + 4 * (size_t)s->nbe_blocks;
-    double* pke = pbd + 4 * (size_t)s->bd_blocks;
-    launch_ghost_update<R>(d, s->st);
-    launch_nonbonded<R>(d, s->h.lpb, true, pnb, s->st);
-    launch_bonded<R>(d, true, pbd, s->st);
-    launch_kinetic<R>(d, pke, s->st);
-    int nnb = (d.N * s->h.lpb + WG - 1) / WG;
-    launch_energy_final(pnb, nnb, pbd, s->bd_blocks, pke, s->ke_blocks, d.eout, s->st);
+    int nnb = launch_nonbonded<R>(d, s->h.lpb, true, d.red, s->st);
+    launch_energy_final(d.red, nnb, d.eout, s->st);
     double e[8];
     int fl[NFLAGS];
     HCK(hipMemcpyAsync(e, d.eout, sizeof(double) * 6, hipMemcpyDeviceToHost, s->st));
@@ -1182,7 +1237,7 @@ static int32_t pairset_impl(membx_sys* s, int32_t* ij, int64_t cap, int64_t* n)
     for (int i = 0; i < N; ++i) {
         int oi = orig[i];
         for (int q = 0; q < cnt[i]; ++q) {
-            int j = nbr[(size_t)q * d.Npad + i] & JMASK;
+            int j = nbr[nbr_index(i, q, d.Kcap, d.lpb)] & JMASK;
             int oj = j < N ? orig[j] : orig[own[j - N]];
             if (oi < oj) {
                 if (k < cap) { ij[2 * k] = oi; ij[2 * k + 1] = oj; }
