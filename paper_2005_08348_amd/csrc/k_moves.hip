@@ -4,12 +4,13 @@
 // filtered greedily (a candidate is admitted when it shares no molecule with,
 // and none of its changed beads is within r_cut of a changed bead of, an
 // earlier admitted candidate).  The filter is sequential by definition; here
-// one work-group examines CHUNK candidates at a time: all candidates are
-// drawn and located in parallel, conflicts between them are found through a
-// spatial hash, and the lexicographically-first admission is resolved by
-// parallel rounds (a candidate is in once every earlier conflicting
-// candidate is out, out as soon as one is in), which reproduces the
-// sequential order exactly.  Each admitted trial's dU = U(after) - U(before)
+// draws are examined in chunks: all candidates of a chunk are drawn, located
+// and checked against the trials admitted so far in parallel (one wave
+// each), conflicts between them are listed through a spatial hash, and the
+// lexicographically-first admission is resolved by parallel rounds in one
+// work-group (a candidate is in once every earlier conflicting candidate is
+// out, out as soon as one is in), which reproduces the sequential order
+// exactly.  Each admitted trial's dU = U(after) - U(before)
 // is the float64 sum of pair-energy changes over its changed beads'
 // neighbour lists.
 //
@@ -59,248 +60,498 @@ __device__ __forceinline__ int hash_cell(const Dev<R>& d, const Mv& m, const dou
     return (c[0] * m.hnc[1] + c[1]) * m.hnc[2] + c[2];
 }
 
-// push entry e into the list of `cell` for epoch ep (64-bit head: epoch|index)
-__device__ __forceinline__ void hash_push(unsigned long long* head, int* next, int cell, int e,
+// Bucket word {epoch:32, key:24, count:8}.  Words and entries that the
+// same kernel may have written are read with device-coherent atomic loads:
+// inserts land at L2 through atomics, which a plain load through the CU's L1
+// could miss.
+typedef unsigned long long u64;
+__device__ __forceinline__ u64 hw_make(unsigned ep, unsigned key, unsigned n)
+{
+    return ((u64)ep << 32) | ((u64)(key & 0xffffffu) << 8) | (u64)n;
+}
+__device__ __forceinline__ unsigned hw_ep(u64 w) { return (unsigned)(w >> 32); }
+__device__ __forceinline__ unsigned hw_key(u64 w) { return (unsigned)(w >> 8) & 0xffffffu; }
+__device__ __forceinline__ unsigned hw_n(u64 w) { return (unsigned)(w & 0xffu); }
+__device__ __forceinline__ unsigned hhash(unsigned key) { return key * 2654435761u; }
+__device__ __forceinline__ u64 hw_load(const u64* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int ld_coh(const int* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_coh(const double* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void hb_insert(u64* word, int* ent, int mask, unsigned key, int e,
                                           unsigned ep)
 {
-    unsigned long long nw = ((unsigned long long)ep << 32) | (unsigned)e;
-    unsigned long long old = head[cell];
+    key &= 0xffffffu;
+    unsigned h = hhash(key) & (unsigned)mask;
+    u64 w = hw_load(&word[h]);
     while (true) {
-        int nxt = ((unsigned)(old >> 32) == ep) ? (int)(unsigned)(old & 0xffffffffu) : -1;
-        next[e] = nxt;
-        unsigned long long got = atomicCAS(&head[cell], old, nw);
-        if (got == old) break;
-        old = got;
+        if (hw_ep(w) != ep) {
+            u64 got = atomicCAS(&word[h], w, hw_make(ep, key, 1));
+            if (got == w) { __hip_atomic_store(&ent[h * HBW], e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); return; }
+            w = got;
+            continue;
+        }
+        if (hw_key(w) == key && hw_n(w) < HBW) {
+            u64 got = atomicCAS(&word[h], w, w + 1);
+            if (got == w) {
+                __hip_atomic_store(&ent[h * HBW + hw_n(w)], e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return;
+            }
+            w = got;
+            continue;
+        }
+        h = (h + 1) & (unsigned)mask;
+        w = hw_load(&word[h]);
     }
 }
 
-__device__ __forceinline__ int hash_first(const unsigned long long* head, int cell, unsigned ep)
-{
-    unsigned long long h = head[cell];
-    return ((unsigned)(h >> 32) == ep) ? (int)(unsigned)(h & 0xffffffffu) : -1;
-}
-
-__device__ __forceinline__ void conf_add(int* lst, int& n, int t2, bool& ovf)
-{
-    for (int q = 0; q < n && q < MAXCONF; ++q)
-        if (lst[q] == t2) return;
-    if (n < MAXCONF) lst[n] = t2; else ovf = true;
-    ++n;
-}
-
-// Candidate selection.  mode 0: exchange batch (stream 1, counter = batch,
-// spatial filter); mode 1: MDAS pairs (stream 3, counter = cycle, distinct
-// molecules only).  One work-group of CHUNK threads.
+// Key of neighbour cell o27 (0..26) of the cell holding p.
 template <typename R>
-__global__ __launch_bounds__(CHUNK) void k_select(Dev<R> d, Mv m, int n_want, int draw_cap,
-                                                  int mode)
+__device__ __forceinline__ unsigned nbr_cell_key(const Dev<R>& d, const Mv& m, const double* p,
+                                                 int o27)
 {
-    __shared__ int st[CHUNK];          // 0 undecided, 1 in, 2 out
-    __shared__ int ord[CHUNK];
-    __shared__ int s_adm, s_d0, s_chg, s_nin, s_stop;
-    const int t = threadIdx.x;
-    const int T = n_want;
+    int c[3];
+    hash_cell(d, m, p, c);
+    const int cx = (c[0] + o27 / 9 - 1 + m.hnc[0]) % m.hnc[0];
+    const int cy = (c[1] + (o27 / 3) % 3 - 1 + m.hnc[1]) % m.hnc[1];
+    const int cz = (c[2] + o27 % 3 - 1 + m.hnc[2]) % m.hnc[2];
+    return (unsigned)((cx * m.hnc[1] + cy) * m.hnc[2] + cz);
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ int wave_incl_scan(int v)
+{
+    const int ln = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(v, o, 64);
+        if (ln >= o) v += u;
+    }
+    return v;
+}
+
+// ------------------------------------------------------------------------
+// Candidate selection.  mode 0: exchange batch (random stream 1, counter =
+// batch, spatial filter); mode 1: MDAS pairs (stream 3, counter = cycle,
+// distinct molecules only).  The trials admitted are the greedy filter in
+// draw order: a draw is admitted when neither molecule is used by an earlier
+// admitted trial and (mode 0) none of its changed beads lies within r_cut
+// (float64 minimum image) of an admitted trial's changed bead.  Draws are
+// examined in chunks; a chunk's admissions are the lexicographically-first
+// independent set of its conflict graph restricted to candidates free of the
+// trials admitted before the chunk, which is what the sequential filter
+// admits.  Chunk sizes only change the cost, never the result.
+
+// One wave per candidate: draw, partner, changed beads.  Returns the flag
+// (0 live, 1 no valid trial, 2 molecule already used) and fills X, Y, nb;
+// lane q < nb returns bead q's id, class and position.
+template <typename R>
+__device__ __forceinline__ int sel_candidate(const Dev<R>& d, const Mv& m, int dd, long long ctrv,
+                                             unsigned stream, int stamp, int& X, int& Y, int& nb,
+                                             int& bead, int& cls, double p[3])
+{
+    X = -1; Y = -1; nb = 0;
+    const int ln = threadIdx.x & 63;
+    if (m.n_sw <= 0) return 1;
+    const uint4 w = draw(d.seed, (uint32_t)dd, ctrv, stream);
+    X = m.sw_list[pick(w.x, (uint32_t)m.n_sw)];
+    const int kx = ld_coh(d.mol_kind + X);
+    const int f = m.fam_of_kind[kx];
+    const int nf = m.fam_off[f + 1] - m.fam_off[f];
+    const int noth = nf - m.kcnt[kx * m.fam_stride + nf];
+    if (noth <= 0) return 1;
+    Y = m.others[kx * m.fam_stride + pick(w.y, (uint32_t)noth)];
+    const int ky = ld_coh(d.mol_kind + Y);
+    const int flag = (ld_coh(m.used + X) == stamp || ld_coh(m.used + Y) == stamp) ? 2 : 0;
+    const int nch = m.chg_n[kx * d.nk + ky];
+    nb = 2 * nch;
+    if (ln < nb) {
+        const int* loc = m.chg_loc + (kx * d.nk + ky) * MAXCH;
+        const bool first = ln < nch;
+        const int l = loc[first ? ln : ln - nch];
+        bead = (first ? d.mol_first[X] : d.mol_first[Y]) + l;
+        cls = d.kcls[d.kbead_off[first ? ky : kx] + l];
+        const V4<R> q = d.posq[d.inv[bead]];
+        p[0] = (double)q.x; p[1] = (double)q.y; p[2] = (double)q.z;
+    }
+    return flag;
+}
+
+// Wave-wide: does any changed bead (positions in sp[3*q], q < nb) lie within
+// r_cut of a changed bead of the trials admitted so far (table ab, epoch
+// stamp)?
+template <typename R>
+__device__ __forceinline__ bool sel_hits_admitted(const Dev<R>& d, const Mv& m, const double* sp,
+                                                  int nb, unsigned stamp)
+{
+    const int ln = threadIdx.x & 63;
+    bool hit = false;
+    for (int it = ln; it < nb * 27; it += 64) {
+        const int q = it / 27, o27 = it - q * 27;
+        const double* p = sp + 3 * q;
+        const unsigned key = nbr_cell_key(d, m, p, o27);
+        unsigned h = hhash(key) & (unsigned)m.ab_mask;
+        u64 w = hw_load(&m.ab_word[h]);
+        while (!hit && hw_ep(w) == stamp) {
+            if (hw_key(w) == key)
+                for (unsigned s = 0; s < hw_n(w) && s < HBW; ++s) {
+                    const int e = ld_coh(m.ab_ent + h * HBW + s);
+                    double r[3];
+                    for (int k = 0; k < 3; ++k) r[k] = ld_coh(m.r_pos + 3 * e + k);
+                    if (mi_dist2(d, p, r) < d.rc2d) hit = true;
+                }
+            h = (h + 1) & (unsigned)m.ab_mask;
+            w = hw_load(&m.ab_word[h]);
+        }
+    }
+    return __ballot(hit) != 0;
+}
+
+// Draw the chunk's candidates (one wave each), set them aside when a
+// molecule is used or (mode 0) a changed bead is within r_cut of an admitted
+// trial, and hash the live ones (cells of their changed beads, molecules).
+template <typename R>
+__global__ __launch_bounds__(256) void k_sel_draw(Dev<R> d, Mv m, int draw_cap, int mode, int ck)
+{
+    __shared__ double s_pos[4][MAXMC * 3];
+    if (m.sel[SEL_DONE]) return;
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    const int t = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);
+    const int MC = m.maxcht;
+    const unsigned ep = (unsigned)m.sel[SEL_EPC];
+    const int stamp = m.sel[SEL_STAMP];
+    const int dd = m.sel[SEL_NEXT] + t;
     const long long ctrv = d.ctr[mode == 0 ? CT_BATCH : CT_CYCLE];
     const unsigned stream = mode == 0 ? ST_SWAP_DRAW : ST_MDAS_SELECT;
-    const unsigned base = (unsigned)m.r_n[2];
-    const unsigned callstamp = base + 1u;
-    unsigned long long* hhead = (unsigned long long*)m.h_head;
-    unsigned long long* mhead = (unsigned long long*)m.m_head;
-    const int MC = m.maxcht;
-    if (t == 0) { s_adm = 0; s_d0 = 0; s_stop = 0; }
+    int flag = 1, X = -1, Y = -1, nb = 0, bead = -1, cls = 0;
+    double p[3] = {0.0, 0.0, 0.0};
+    if (t < ck && dd < draw_cap)
+        flag = sel_candidate(d, m, dd, ctrv, stream, stamp, X, Y, nb, bead, cls, p);
+    if (flag != 1 && ln < nb) {
+        const int e = t * MC + ln;
+        m.c_bead[e] = bead;
+        m.c_cls[e] = cls;
+        for (int k = 0; k < 3; ++k) { m.c_pos[3 * e + k] = p[k]; s_pos[wv][3 * ln + k] = p[k]; }
+    }
     __syncthreads();
-    int chunk = 0;
-    while (true) {
-        if (s_stop || s_adm >= T || s_d0 >= draw_cap) break;
-        const unsigned ep = base + 2u + (unsigned)chunk;
-        const int base_d = s_d0;
-        // ---- phase A: draw and locate candidate d0 + t
-        const int dd = base_d + t;
-        int flag = 1, X = -1, Y = -1, nb = 0;
-        if (dd < draw_cap && m.n_sw > 0) {
-            uint4 w = draw(d.seed, (uint32_t)dd, ctrv, stream);
-            X = m.sw_list[pick(w.x, (uint32_t)m.n_sw)];
-            int kx = d.mol_kind[X];
-            int f = m.fam_of_kind[kx];
-            int f0 = m.fam_off[f], nf = m.fam_off[f + 1] - f0;
-            const int* kc = m.kcnt + kx * m.fam_stride;
-            int noth = nf - kc[nf];
-            if (noth > 0) {
-                uint32_t k = pick(w.y, (uint32_t)noth);
-                // smallest p with (p + 1) - kc[p + 1] > k
-                int lo = 0, hi = nf - 1;
-                while (lo < hi) {
-                    int mid = (lo + hi) >> 1;
-                    if ((mid + 1) - kc[mid + 1] > (int)k) hi = mid; else lo = mid + 1;
-                }
-                Y = m.fam_mem[f0 + lo];
-                int ky = d.mol_kind[Y];
-                flag = 0;
-                if (m.used[X] == (int)callstamp || m.used[Y] == (int)callstamp) flag = 2;
-                int nch = m.chg_n[kx * d.nk + ky];
-                const int* loc = m.chg_loc + (kx * d.nk + ky) * MAXCH;
-                for (int q = 0; q < nch; ++q) {
-                    int l = loc[q];
-                    int bx = d.mol_first[X] + l, by = d.mol_first[Y] + l;
-                    m.c_bead[t * MC + q] = bx;
-                    m.c_cls[t * MC + q] = d.kcls[d.kbead_off[ky] + l];
-                    m.c_bead[t * MC + nch + q] = by;
-                    m.c_cls[t * MC + nch + q] = d.kcls[d.kbead_off[kx] + l];
-                }
-                nb = 2 * nch;
-                for (int q = 0; q < nb; ++q) {
-                    V4<R> p = d.posq[d.inv[m.c_bead[t * MC + q]]];
-                    double* cp = m.c_pos + 3 * (t * MC + q);
-                    cp[0] = (double)p.x; cp[1] = (double)p.y; cp[2] = (double)p.z;
-                }
-            }
+    if (flag == 0 && mode == 0 && m.sel[SEL_ADM] > 0 &&
+        sel_hits_admitted(d, m, s_pos[wv], nb, (unsigned)stamp))
+        flag = 2;
+    if (flag == 0) {
+        if (mode == 0 && ln < nb) {
+            int c[3];
+            hb_insert(m.hb_word, m.hb_ent, m.hb_mask, (unsigned)hash_cell(d, m, p, c), t * MC + ln, ep);
         }
-        m.c_x[t] = X; m.c_y[t] = Y; m.c_nb[t] = nb; m.c_flag[t] = flag;
-        __syncthreads();
-        // ---- phase B: hash this chunk's changed beads and molecules, plus
-        // the changed beads of the trials admitted so far
-        if (mode == 0) {
-            if (flag != 1)
-                for (int q = 0; q < nb; ++q) {
-                    int c[3];
-                    int cell = hash_cell(d, m, m.c_pos + 3 * (t * MC + q), c);
-                    int e = t * MC + q;
-                    m.h_owner[e] = t;
-                    hash_push(hhead, m.h_next, cell, e, ep);
-                }
-            for (int a = t; a < s_adm; a += CHUNK) {
-                for (int q = 0; q < m.r_nb[a]; ++q) {
-                    int e = CHUNK * MC + a * MC + q;
-                    double* hp = m.h_pos + 3 * e;
-                    V4<R> p = d.posq[d.inv[m.r_bead[a * MC + q]]];
-                    hp[0] = (double)p.x; hp[1] = (double)p.y; hp[2] = (double)p.z;
-                    int c[3];
-                    int cell = hash_cell(d, m, hp, c);
-                    m.h_owner[e] = -1 - a;
-                    hash_push(hhead, m.h_next, cell, e, ep);
-                }
-            }
-        }
-        if (flag != 1) {
-            hash_push(mhead, m.m_next, X % m.mh, 2 * t, ep);
-            m.m_owner[2 * t] = t;
-            hash_push(mhead, m.m_next, Y % m.mh, 2 * t + 1, ep);
-            m.m_owner[2 * t + 1] = t;
-        }
-        __syncthreads();
-        // ---- phase C: conflicts
-        int ncf = 0;
-        bool ovf = false;
-        int* cl = m.c_conf + t * MAXCONF;
-        if (flag == 0) {
-            // shared molecules with earlier candidates of this chunk
-            for (int w2 = 0; w2 < 2; ++w2) {
-                int mol = w2 ? Y : X;
-                for (int e = hash_first(mhead, mol % m.mh, ep); e >= 0; e = m.m_next[e]) {
-                    int o = m.m_owner[e];
-                    if (o >= t) continue;
-                    int om = (e & 1) ? m.c_y[o] : m.c_x[o];
-                    if (om == mol) conf_add(cl, ncf, o, ovf);
-                }
-            }
-            if (mode == 0) {
-                for (int q = 0; q < nb && flag == 0; ++q) {
-                    const double* pq = m.c_pos + 3 * (t * MC + q);
-                    int c[3];
-                    hash_cell(d, m, pq, c);
-                    for (int o27 = 0; o27 < 27 && flag == 0; ++o27) {
-                        int cx = (c[0] + o27 / 9 - 1 + m.hnc[0]) % m.hnc[0];
-                        int cy = (c[1] + (o27 / 3) % 3 - 1 + m.hnc[1]) % m.hnc[1];
-                        int cz = (c[2] + o27 % 3 - 1 + m.hnc[2]) % m.hnc[2];
-                        int cell = (cx * m.hnc[1] + cy) * m.hnc[2] + cz;
-                        for (int e = hash_first(hhead, cell, ep); e >= 0; e = m.h_next[e]) {
-                            int o = m.h_owner[e];
-                            if (o >= t) continue;   // later candidates and self
-                            const double* pe = (o < 0) ? m.h_pos + 3 * e : m.c_pos + 3 * e;
-                            if (mi_dist2(d, pq, pe) < d.rc2d) {
-                                if (o < 0) flag = 2;
-                                else conf_add(cl, ncf, o, ovf);
-                            }
+        if (ln == 62) hb_insert(m.mb_word, m.mb_ent, m.mb_mask, (unsigned)X, 2 * t, ep);
+        if (ln == 63) hb_insert(m.mb_word, m.mb_ent, m.mb_mask, (unsigned)Y, 2 * t + 1, ep);
+    }
+    if (ln == 0 && t < ck) {
+        m.c_flag[t] = flag;
+        m.c_x[t] = X;
+        m.c_y[t] = Y;
+        m.c_nb[t] = nb;
+        m.c_conf_n[t] = 0;
+    }
+}
+
+// Conflict lists (one wave per live candidate): the earlier live candidates
+// of the chunk that share a molecule with it or (mode 0) have a changed bead
+// within r_cut of one of its own, ascending, at most SEL_CAPC listed (the
+// count is exact).
+template <typename R>
+__global__ __launch_bounds__(256) void k_sel_conf(Dev<R> d, Mv m, int mode, int ck)
+{
+    __shared__ unsigned s_bits[4][SEL_CMAX / 32];
+    if (m.sel[SEL_DONE]) return;
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    const int t = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);
+    const int MC = m.maxcht;
+    const bool act = t < ck && m.c_flag[t] == 0;
+    const unsigned ep = (unsigned)m.sel[SEL_EPC];
+    const int nw = (t + 31) >> 5;
+    unsigned* bits = s_bits[wv];
+    if (act)
+        for (int i = ln; i < nw; i += 64) bits[i] = 0u;
+    __syncthreads();
+    if (act) {
+        const int nb = m.c_nb[t];
+        const int nsp = mode == 0 ? nb * 27 : 0;
+        for (int it = ln; it < nsp + 2; it += 64) {
+            if (it < nsp) {
+                const int q = it / 27, o27 = it - q * 27;
+                const double* pq = m.c_pos + 3 * (t * MC + q);
+                const double p[3] = {pq[0], pq[1], pq[2]};
+                const unsigned key = nbr_cell_key(d, m, p, o27);
+                unsigned h = hhash(key) & (unsigned)m.hb_mask;
+                u64 w = m.hb_word[h];
+                while (hw_ep(w) == ep) {
+                    if (hw_key(w) == key)
+                        for (unsigned s = 0; s < hw_n(w) && s < HBW; ++s) {
+                            const int e = m.hb_ent[h * HBW + s];
+                            const int o = e / MC;
+                            if (o < t && mi_dist2(d, p, m.c_pos + 3 * e) < d.rc2d)
+                                atomicOr(&bits[o >> 5], 1u << (o & 31));
                         }
-                    }
+                    h = (h + 1) & (unsigned)m.hb_mask;
+                    w = m.hb_word[h];
+                }
+            } else {
+                const unsigned key = (unsigned)(it == nsp ? m.c_x[t] : m.c_y[t]) & 0xffffffu;
+                unsigned h = hhash(key) & (unsigned)m.mb_mask;
+                u64 w = m.mb_word[h];
+                while (hw_ep(w) == ep) {
+                    if (hw_key(w) == key)
+                        for (unsigned s = 0; s < hw_n(w) && s < HBW; ++s) {
+                            const int o = m.mb_ent[h * HBW + s] >> 1;
+                            if (o < t) atomicOr(&bits[o >> 5], 1u << (o & 31));
+                        }
+                    h = (h + 1) & (unsigned)m.mb_mask;
+                    w = m.mb_word[h];
                 }
             }
         }
-        m.c_conf_n[t] = ovf ? -1 : ncf;
-        st[t] = (flag != 0) ? 2 : 0;
+    }
+    __syncthreads();
+    if (act) {
+        int total = 0;
+        for (int i0 = 0; i0 < nw; i0 += 64) {
+            const int i = i0 + ln;
+            unsigned b = i < nw ? bits[i] : 0u;
+            const int c = __popc(b);
+            const int incl = wave_incl_scan(c);
+            int pos = total + incl - c;
+            while (b) {
+                const int bit = __ffs(b) - 1;
+                b &= b - 1;
+                if (pos < SEL_CAPC) m.c_conf[t * SEL_CAPC + pos] = i * 32 + bit;
+                ++pos;
+            }
+            total += __shfl(incl, 63, 64);
+        }
+        if (ln == 0) m.c_conf_n[t] = total;
+    }
+}
+
+// Admit candidate t as trial a (caller: the lanes of one wave).
+template <typename R>
+__device__ __forceinline__ void sel_admit(const Dev<R>& d, const Mv& m, int mode, int a, int draw_idx,
+                                          int X, int Y, int nb, const int* bead, const int* cls,
+                                          const double* pos, int lane0, int nlanes, int stamp)
+{
+    const int MC = m.maxcht;
+    for (int q = lane0; q < nb; q += nlanes) {
+        m.r_bead[a * MC + q] = bead[q];
+        m.r_cls[a * MC + q] = cls[q];
+        for (int k = 0; k < 3; ++k)
+            __hip_atomic_store(m.r_pos + 3 * (a * MC + q) + k, pos[3 * q + k], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        if (mode == 0) {
+            int c[3];
+            hb_insert(m.ab_word, m.ab_ent, m.ab_mask, (unsigned)hash_cell(d, m, pos + 3 * q, c),
+                      a * MC + q, (unsigned)stamp);
+        }
+    }
+    if (lane0 == 0) {
+        m.r_draw[a] = draw_idx;
+        m.r_x[a] = X;
+        m.r_y[a] = Y;
+        m.r_nb[a] = nb;
+        __hip_atomic_store(m.used + X, stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(m.used + Y, stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Resolve the chunk (one work-group): the lexicographically-first admission
+// by parallel rounds over the conflict lists held in LDS (in once every
+// earlier conflicting candidate is out, out as soon as one is in), then the
+// admitted candidates in draw order up to the number still wanted.  A
+// candidate whose list is incomplete, or does not fit, ends the chunk there:
+// the next chunk starts with its draw.
+template <typename R>
+__global__ __launch_bounds__(1024) void k_sel_resolve(Dev<R> d, Mv m, int n_want, int draw_cap,
+                                                      int mode, int ck)
+{
+    constexpr int PER = SEL_CMAX / 1024;
+    __shared__ unsigned char st[SEL_CMAX];
+    __shared__ short lst[SEL_LDS];
+    __shared__ int s_red[1024];
+    __shared__ int s_trunc, s_chg, s_stop;
+    if (m.sel[SEL_DONE]) return;
+    const int tid = threadIdx.x;
+    const int per = (ck + 1023) / 1024;
+    const int t0 = tid * per;
+    const int MC = m.maxcht;
+    const int base = m.sel[SEL_NEXT];
+    const int adm = m.sel[SEL_ADM];
+    const int stamp = m.sel[SEL_STAMP];
+    if (tid == 0) { s_trunc = ck; s_stop = -1; }
+    // per-thread candidates t0 .. t0 + per - 1 (register arrays, loops unrolled)
+    int cnt[PER], off[PER], nst[PER];
+    int mysum = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int t = t0 + k;
+        cnt[k] = 0;
+        if (k < per && t < ck && m.c_flag[t] == 0) cnt[k] = m.c_conf_n[t];
+        mysum += cnt[k] < SEL_CAPC ? cnt[k] : SEL_CAPC;
+    }
+    // exclusive prefix of the list lengths
+    s_red[tid] = mysum;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int v = tid >= o ? s_red[tid - o] : 0;
         __syncthreads();
-        // ---- phase D: resolve the lexicographically-first admission
-        while (true) {
-            if (t == 0) s_chg = 0;
-            __syncthreads();
-            int nst = st[t];
-            if (nst == 0) {
-                int cn = m.c_conf_n[t];
-                if (cn >= 0) {
-                    bool anyin = false, anyund = false;
-                    for (int q = 0; q < cn; ++q) {
-                        int s2 = st[cl[q]];
-                        anyin |= (s2 == 1);
-                        anyund |= (s2 == 0);
-                    }
-                    nst = anyin ? 2 : (anyund ? 0 : 1);
-                } else {
-                    // too many conflicts to list: compare with every earlier candidate
-                    bool anyin = false, anyund = false;
-                    for (int o = 0; o < t; ++o) {
-                        int s2 = st[o];
-                        if (s2 == 2) continue;
-                        bool cf = (m.c_x[o] == X || m.c_x[o] == Y || m.c_y[o] == X || m.c_y[o] == Y);
-                        if (mode == 0)
-                            for (int q = 0; q < nb && !cf; ++q)
-                                for (int q2 = 0; q2 < m.c_nb[o] && !cf; ++q2)
-                                    cf = mi_dist2(d, m.c_pos + 3 * (t * MC + q),
-                                                  m.c_pos + 3 * (o * MC + q2)) < d.rc2d;
-                        if (!cf) continue;
-                        anyin |= (s2 == 1);
-                        anyund |= (s2 == 0);
-                    }
-                    nst = anyin ? 2 : (anyund ? 0 : 1);
+        s_red[tid] += v;
+        __syncthreads();
+    }
+    int run = s_red[tid] - mysum;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        off[k] = run;
+        if (k < per && (cnt[k] > SEL_CAPC || run + cnt[k] > SEL_LDS)) atomicMin(&s_trunc, t0 + k);
+        run += cnt[k] < SEL_CAPC ? cnt[k] : SEL_CAPC;
+    }
+    __syncthreads();
+    const int trunc = s_trunc;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int t = t0 + k;
+        const bool live = k < per && t < trunc && m.c_flag[t] == 0;
+        if (!live) cnt[k] = 0;
+        for (int j = 0; j < cnt[k]; ++j) lst[off[k] + j] = (short)m.c_conf[t * SEL_CAPC + j];
+        nst[k] = live ? 0 : 2;
+        if (k < per) st[t] = (unsigned char)nst[k];
+    }
+    __syncthreads();
+    while (true) {
+        if (tid == 0) s_chg = 0;
+        __syncthreads();
+        bool changed = false;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            if (nst[k] == 0) {
+                bool anyin = false, anyund = false;
+                for (int j = 0; j < cnt[k]; ++j) {
+                    const int s2 = st[lst[off[k] + j]];
+                    anyin |= (s2 == 1);
+                    anyund |= (s2 == 0);
                 }
+                const int v = anyin ? 2 : (anyund ? 0 : 1);
+                if (v != 0) { nst[k] = v; changed = true; }
             }
-            __syncthreads();
-            if (nst != st[t]) { st[t] = nst; s_chg = 1; }
-            __syncthreads();
-            if (!s_chg) break;
-        }
-        // ---- phase E: take admitted candidates in draw order
-        if (t == 0) {
-            int need = T - s_adm, k = 0, last = -1;
-            for (int q = 0; q < CHUNK && k < need; ++q)
-                if (st[q] == 1) { ord[k++] = q; last = q; }
-            s_nin = k;
-            if (k == need && last >= 0) { s_d0 = base_d + last + 1; s_stop = 1; }
-            else s_d0 = base_d + CHUNK;
         }
         __syncthreads();
-        if (t < s_nin) {
-            int q = ord[t], a = s_adm + t;
-            m.r_draw[a] = base_d + q;
-            m.r_x[a] = m.c_x[q];
-            m.r_y[a] = m.c_y[q];
-            m.r_nb[a] = m.c_nb[q];
-            for (int e = 0; e < m.c_nb[q]; ++e) {
-                m.r_bead[a * MC + e] = m.c_bead[q * MC + e];
-                m.r_cls[a * MC + e] = m.c_cls[q * MC + e];
-            }
-            m.used[m.c_x[q]] = (int)callstamp;
-            m.used[m.c_y[q]] = (int)callstamp;
+        if (changed) {
+#pragma unroll
+            for (int k = 0; k < PER; ++k)
+                if (k < per) st[t0 + k] = (unsigned char)nst[k];
+            s_chg = 1;
         }
         __syncthreads();
-        if (t == 0) s_adm += s_nin;
-        ++chunk;
+        if (!s_chg) break;
+    }
+    // admitted candidates in draw order
+    int nin = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) nin += (k < per && nst[k] == 1) ? 1 : 0;
+    s_red[tid] = nin;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int v = tid >= o ? s_red[tid - o] : 0;
+        __syncthreads();
+        s_red[tid] += v;
         __syncthreads();
     }
-    if (t == 0) {
-        m.r_n[0] = s_adm;
-        m.r_n[1] = s_d0 < draw_cap ? s_d0 : draw_cap;
-        m.r_n[2] = (int)(base + 2u + (unsigned)chunk);
+    const int total = s_red[1023];
+    const int need = n_want - adm;
+    int rank = s_red[tid] - nin;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int t = t0 + k;
+        if (k < per && nst[k] == 1) {
+            if (rank < need) {
+                sel_admit(d, m, mode, adm + rank, base + t, m.c_x[t], m.c_y[t], m.c_nb[t],
+                          m.c_bead + t * MC, m.c_cls + t * MC, m.c_pos + 3 * t * MC, 0, 1, stamp);
+                if (rank == need - 1) s_stop = t;
+            }
+            ++rank;
+        }
     }
+    __syncthreads();
+    if (tid == 0) {
+        const int nadm = adm + (total < need ? total : need);
+        const int next = s_stop >= 0 ? base + s_stop + 1 : base + trunc;
+        m.sel[SEL_ADM] = nadm;
+        m.sel[SEL_NEXT] = next;
+        m.sel[SEL_DONE] = (nadm >= n_want || next >= draw_cap) ? 1 : 0;
+        m.sel[SEL_EPC] = m.sel[SEL_EPC] + 1;
+        m.r_n[0] = nadm;
+        m.r_n[1] = next < draw_cap ? next : draw_cap;
+    }
+}
+
+// Finish the selection one draw at a time (one wave) when the chunks did not
+// reach the end.
+template <typename R>
+__global__ __launch_bounds__(64) void k_sel_tail(Dev<R> d, Mv m, int n_want, int draw_cap, int mode)
+{
+    __shared__ double s_pos[MAXMC * 3];
+    __shared__ int s_bead[MAXMC], s_cls[MAXMC];
+    if (m.sel[SEL_DONE]) return;
+    const int ln = threadIdx.x;
+    const int stamp = m.sel[SEL_STAMP];
+    const long long ctrv = d.ctr[mode == 0 ? CT_BATCH : CT_CYCLE];
+    const unsigned stream = mode == 0 ? ST_SWAP_DRAW : ST_MDAS_SELECT;
+    int adm = m.sel[SEL_ADM];
+    int dd = m.sel[SEL_NEXT];
+    for (; dd < draw_cap && adm < n_want; ++dd) {
+        int X, Y, nb, bead = -1, cls = 0;
+        double p[3] = {0.0, 0.0, 0.0};
+        int flag = sel_candidate(d, m, dd, ctrv, stream, stamp, X, Y, nb, bead, cls, p);
+        if (flag != 1 && ln < nb) {
+            s_bead[ln] = bead;
+            s_cls[ln] = cls;
+            for (int k = 0; k < 3; ++k) s_pos[3 * ln + k] = p[k];
+        }
+        __syncthreads();
+        if (flag == 0 && mode == 0 && adm > 0 && sel_hits_admitted(d, m, s_pos, nb, (unsigned)stamp))
+            flag = 2;
+        if (flag == 0) {
+            sel_admit(d, m, mode, adm, dd, X, Y, nb, s_bead, s_cls, s_pos, ln, 64, stamp);
+            ++adm;
+        }
+        __threadfence();
+        __syncthreads();
+    }
+    if (ln == 0) {
+        m.sel[SEL_ADM] = adm;
+        m.sel[SEL_NEXT] = dd;
+        m.sel[SEL_DONE] = 1;
+        m.r_n[0] = adm;
+        m.r_n[1] = dd < draw_cap ? dd : draw_cap;
+    }
+}
+
+// Start a selection: fresh stamp (molecules used, admitted-bead table) and
+// chunk epoch.
+__global__ void k_sel_init(Mv m, int n_want)
+{
+    const int c = m.sel[SEL_EPC];
+    m.sel[SEL_STAMP] = c + 1;
+    m.sel[SEL_EPC] = c + 2;
+    m.sel[SEL_ADM] = 0;
+    m.sel[SEL_NEXT] = 0;
+    m.sel[SEL_DONE] = n_want <= 0 ? 1 : 0;
+    m.r_n[0] = 0;
+    m.r_n[1] = 0;
 }
 
 // Mark the changed beads of the admitted trials (tag = trial for exchange
@@ -590,16 +841,42 @@ __global__ void k_kcnt(Dev<R> d, Mv m, int kind)
         __syncthreads();
     }
     int run = part[t] - s;
-    for (int k = b; k < e; ++k) { out[k] = run; run += d.mol_kind[m.fam_mem[f0 + k]] == kind; }
+    int* oth = m.others + kind * m.fam_stride;
+    for (int k = b; k < e; ++k) {
+        const int mem = m.fam_mem[f0 + k];
+        const bool same = d.mol_kind[mem] == kind;
+        out[k] = run;
+        if (!same) oth[k - run] = mem;   // members of other kinds, ascending
+        run += same;
+    }
     if (t == 1023) out[nf] = part[1023];
 }
 
 // ----------------------------------------------------------------- launch
+// Chunk sizes: SEL_C0, SEL_C0, then doubling up to SEL_CMAX, until they
+// cover the draw cap; two more of SEL_CMAX in reserve (a chunk may end early),
+// then the one-draw-at-a-time tail.
 template <typename R>
 void launch_select(const Dev<R>& d, const Mv& m, int n_want, int draw_cap, int mode,
                    hipStream_t st)
 {
-    hipLaunchKernelGGL(k_select<R>, dim3(1), dim3(CHUNK), 0, st, d, m, n_want, draw_cap, mode);
+    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(1), 0, st, m, n_want);
+    long long covered = 0;
+    int reserve = 2, ck = SEL_C0, k = 0;
+    while (true) {
+        if (covered >= draw_cap) {
+            if (reserve == 0) break;
+            --reserve;
+            ck = SEL_CMAX;
+        }
+        hipLaunchKernelGGL(k_sel_draw<R>, dim3(ck / 4), dim3(256), 0, st, d, m, draw_cap, mode, ck);
+        hipLaunchKernelGGL(k_sel_conf<R>, dim3(ck / 4), dim3(256), 0, st, d, m, mode, ck);
+        hipLaunchKernelGGL(k_sel_resolve<R>, dim3(1), dim3(1024), 0, st, d, m, n_want, draw_cap,
+                           mode, ck);
+        covered += ck;
+        if (++k >= 2 && ck < SEL_CMAX) ck *= 2;
+    }
+    hipLaunchKernelGGL(k_sel_tail<R>, dim3(1), dim3(64), 0, st, d, m, n_want, draw_cap, mode);
 }
 
 template <typename R>

@@ -194,8 +194,14 @@ template <typename R> struct Dev {
 
 // Exchange moves (batched MC-MD trials and MDAS pair selection) and the
 // sparse alchemical force / energy difference machinery.
-constexpr int CHUNK = 1024;      // candidates examined per selection round
-constexpr int MAXCONF = 16;      // earlier conflicting candidates remembered
+constexpr int SEL_C0 = 1024;     // candidates of the first selection chunk
+constexpr int SEL_CMAX = 8192;   // largest selection chunk
+constexpr int SEL_CAPC = 64;     // earlier conflicting candidates listed per candidate
+constexpr int SEL_LDS = 16384;   // conflict-list entries one chunk may resolve
+constexpr int MAXMC = 2 * MAXCH; // changed beads per trial
+// selection state words
+enum { SEL_ADM = 0, SEL_NEXT = 1, SEL_DONE = 2, SEL_EPC = 3, SEL_STAMP = 4, SEL_NSEL = 8 };
+constexpr int HBW = 4;           // entries per hash bucket
 struct Mv {
     // static tables
     int n_sw;            // exchangeable molecules
@@ -205,27 +211,35 @@ struct Mv {
     int* fam_mem;        // family members, ascending molecule ids
     int fam_stride;      // max family size + 1
     int* kcnt;           // [nk * fam_stride] per-kind prefix counts over its family
+    int* others;         // [nk * fam_stride] family members of another kind, ascending
     int* chg_n;          // [nk * nk] changed beads between two kinds
     int* chg_loc;        // [nk * nk * MAXCH] their local indices
     int maxcht;          // max changed beads per trial (both molecules)
-    // candidate scratch (one chunk)
-    int* c_x; int* c_y; int* c_nb; int* c_bead; int* c_cls;   // [CHUNK], bead/cls [CHUNK*maxcht]
-    double* c_pos;       // [CHUNK * maxcht * 3]
-    int* c_conf_n; int* c_conf;                               // [CHUNK], [CHUNK*MAXCONF]
-    int* c_flag;         // [CHUNK]: 0 valid, 1 invalid, 2 conflicts with admitted
-    // spatial hash over the box (cells of edge >= r_cut)
+    // candidate scratch (one chunk of up to SEL_CMAX draws)
+    int* c_x; int* c_y; int* c_nb; int* c_flag;               // [SEL_CMAX]
+    int* c_bead; int* c_cls;                                  // [SEL_CMAX * maxcht]
+    double* c_pos;       // [SEL_CMAX * maxcht * 3]
+    int* c_conf_n; int* c_conf;                               // [SEL_CMAX], [SEL_CMAX * SEL_CAPC]
+    // spatial hashes over the box (cells of edge >= r_cut): open addressing,
+    // one 64-bit word per bucket {epoch:32, key:24, count:8} and up to HBW
+    // entries; a key with more entries continues in the following buckets.
+    // hb: changed beads of the chunk's live candidates (entry = t*maxcht+q);
+    // ab: changed beads of the trials admitted so far (entry = a*maxcht+q);
+    // mb: molecules of the chunk's live candidates (entry = 2t or 2t+1)
     int hnc[3], hcells;
     double hinv[3];
-    int* h_head; int* h_stamp; int* h_next; int* h_owner;     // entries [CHUNK*maxcht + T*maxcht]
-    double* h_pos;
-    int* m_head; int* m_stamp; int* m_next; int* m_owner; int mh; // molecule hash
-    int* used;           // [nm] stamp of the batch that admitted the molecule
+    unsigned long long* hb_word; int* hb_ent; int hb_mask;
+    unsigned long long* ab_word; int* ab_ent; int ab_mask;
+    unsigned long long* mb_word; int* mb_ent; int mb_mask;
+    int* used;           // [nm] stamp of the call that admitted the molecule
+    int* sel;            // [SEL_NSEL] selection state
     // results (capacity T = max(max_trials, max_pairs))
     int T;
-    int* r_n;            // [4]: admitted, draws, stamp, accepted
+    int* r_n;            // [4]: admitted, draws, -, accepted
     int* r_draw; int* r_x; int* r_y; int* r_acc;
     double* r_du; double* r_u;
     int* r_nb; int* r_bead; int* r_cls;                       // changed beads per trial
+    double* r_pos;       // [T * maxcht * 3] their positions at selection
     double* du_bead;     // [T * maxcht]
     // affected set
     int* aff_flag;       // [N]

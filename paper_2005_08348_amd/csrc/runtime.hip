@@ -197,7 +197,7 @@ Status check_desc(const membx_desc* d, Host& h)
         return { MEMBX_E_INVAL, "lanes_per_bead must be 1, 2, 4 or 8" };
     h.T_cap = d->max_trials > 0 ? d->max_trials : 256;
     h.P_cap = d->max_pairs > 0 ? d->max_pairs : 64;
-    if (h.T_cap > CHUNK || h.P_cap > CHUNK) return { MEMBX_E_INVAL, "max_trials/max_pairs > 1024" };
+    if (h.T_cap > 16384 || h.P_cap > 16384) return { MEMBX_E_INVAL, "max_trials/max_pairs > 16384" };
     double rl = h.rc + h.skin_max;
     h.ncell = 1;
     for (int a = 0; a < 3; ++a) {
@@ -472,25 +472,32 @@ static size_t layout(membx_sys* s, Dev<R>& d, Mv& m, char* base)
     m.fam_mem = a.take<int>(h.fam_mem.size());
     m.fam_stride = h.fam_stride;
     m.kcnt = a.take<int>((size_t)h.nk * h.fam_stride);
+    m.others = a.take<int>((size_t)h.nk * h.fam_stride);
     m.chg_n = a.take<int>(h.nk * h.nk);
     m.chg_loc = a.take<int>(h.nk * h.nk * MAXCH);
     m.maxcht = MC;
-    m.c_x = a.take<int>(CHUNK); m.c_y = a.take<int>(CHUNK); m.c_nb = a.take<int>(CHUNK);
-    m.c_flag = a.take<int>(CHUNK); m.c_conf_n = a.take<int>(CHUNK);
-    m.c_bead = a.take<int>(CHUNK * MC); m.c_cls = a.take<int>(CHUNK * MC);
-    m.c_pos = a.take<double>(3 * CHUNK * MC);
-    m.c_conf = a.take<int>(CHUNK * MAXCONF);
+    m.c_x = a.take<int>(SEL_CMAX); m.c_y = a.take<int>(SEL_CMAX); m.c_nb = a.take<int>(SEL_CMAX);
+    m.c_flag = a.take<int>(SEL_CMAX); m.c_conf_n = a.take<int>(SEL_CMAX);
+    m.c_bead = a.take<int>((size_t)SEL_CMAX * MC); m.c_cls = a.take<int>((size_t)SEL_CMAX * MC);
+    m.c_pos = a.take<double>(3 * (size_t)SEL_CMAX * MC);
+    m.c_conf = a.take<int>((size_t)SEL_CMAX * SEL_CAPC);
     for (int k = 0; k < 3; ++k) { m.hnc[k] = h.hnc[k]; m.hinv[k] = h.hnc[k] / h.box[k]; }
     m.hcells = h.hcells;
-    m.h_head = (int*)a.take<unsigned long long>(h.hcells);
-    m.h_stamp = nullptr;
-    m.h_next = a.take<int>((CHUNK + T) * MC);
-    m.h_owner = a.take<int>((CHUNK + T) * MC);
-    m.h_pos = a.take<double>(3 * (size_t)(CHUNK + T) * MC);
-    m.mh = h.mh;
-    m.m_head = (int*)a.take<unsigned long long>(h.mh);
-    m.m_stamp = nullptr;
-    m.m_next = a.take<int>(2 * CHUNK); m.m_owner = a.take<int>(2 * CHUNK);
+    {
+        auto pow2 = [](size_t n) { size_t p = 1; while (p < n) p <<= 1; return p; };
+        const size_t hb = pow2(2 * (size_t)SEL_CMAX * MC), ab = pow2(2 * (size_t)T * MC),
+                     mb = pow2(4 * (size_t)SEL_CMAX);
+        m.hb_mask = (int)hb - 1;
+        m.hb_word = a.take<unsigned long long>(hb);
+        m.hb_ent = a.take<int>(hb * HBW);
+        m.ab_mask = (int)ab - 1;
+        m.ab_word = a.take<unsigned long long>(ab);
+        m.ab_ent = a.take<int>(ab * HBW);
+        m.mb_mask = (int)mb - 1;
+        m.mb_word = a.take<unsigned long long>(mb);
+        m.mb_ent = a.take<int>(mb * HBW);
+    }
+    m.sel = a.take<int>(SEL_NSEL);
     m.used = a.take<int>(h.nm);
     m.T = T;
     m.r_n = a.take<int>(4);
@@ -498,6 +505,7 @@ static size_t layout(membx_sys* s, Dev<R>& d, Mv& m, char* base)
     m.r_acc = a.take<int>(T);
     m.r_du = a.take<double>(T); m.r_u = a.take<double>(T);
     m.r_nb = a.take<int>(T); m.r_bead = a.take<int>(T * MC); m.r_cls = a.take<int>(T * MC);
+    m.r_pos = a.take<double>(3 * (size_t)T * MC);
     m.du_bead = a.take<double>(T * MC);
     m.aff_flag = a.take<int>(N);
     m.aff_cap = h.aff_cap;
@@ -867,8 +875,11 @@ static int32_t upload(membx_sys* s, const membx_desc* desc)
     HCK(hipMemsetAsync(d.cell_cnt, 0, sizeof(int) * h.ncell, st));
     HCK(hipMemsetAsync(d.cell_cur, 0, sizeof(int) * h.ncell, st));
     HCK(hipMemsetAsync(d.gcnt, 0, sizeof(int) * h.N, st));
-    HCK(hipMemsetAsync(m.h_head, 0, sizeof(unsigned long long) * h.hcells, st));
-    HCK(hipMemsetAsync(m.m_head, 0, sizeof(unsigned long long) * h.mh, st));
+    HCK(hipMemsetAsync(m.hb_word, 0, sizeof(unsigned long long) * ((size_t)m.hb_mask + 1), st));
+    HCK(hipMemsetAsync(m.mb_word, 0, sizeof(unsigned long long) * ((size_t)m.mb_mask + 1), st));
+    HCK(hipMemsetAsync(m.ab_word, 0, sizeof(unsigned long long) * ((size_t)m.ab_mask + 1), st));
+    HCK(hipMemsetAsync(m.sel, 0, sizeof(int) * SEL_NSEL, st));
+    HCK(hipMemsetAsync(m.others, 0, sizeof(int) * (size_t)h.nk * h.fam_stride, st));
     HCK(hipMemsetAsync(m.used, 0, sizeof(int) * h.nm, st));
     HCK(hipMemsetAsync(m.r_n, 0, sizeof(int) * 4, st));
     HCK(hipMemsetAsync(m.aff_flag, 0, sizeof(int) * h.N, st));

@@ -182,3 +182,30 @@ def test_mdas_cycle_c0(oracle_mod, c0_relaxed, prec):
     d -= c0_relaxed.box * np.rint(d / c0_relaxed.box)
     assert np.abs(d).max() < (1e-7 if prec == "fp64" else 1e-3)
     g.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_swap_batch_256_c1(oracle_mod, prec):
+    """Batched exchange trials at the benchmark size (256 trials on the
+    95,876-bead bilayer): identical admitted trials (the greedy filter runs
+    to jamming, over several selection rounds), dU within tolerance, decisions
+    identical outside the near-tie band."""
+    m = _membx()
+    s = S.make("c1")
+    g = m.System(s, precision=prec)
+    o = oracle_mod.Oracle(s)
+    kT = KB * s.temperature
+    tol = 1e-8 if prec == "fp64" else 5e-4
+    for _ in range(2):
+        rg = g.swap_trials(256)
+        ro = o.swap_batch(256)
+        assert len(ro["draw"]) > 100
+        assert list(rg["draw"]) == list(ro["draw"])
+        assert list(rg["X"]) == list(ro["X"]) and list(rg["Y"]) == list(ro["Y"])
+        assert np.abs(rg["du"] - ro["du"]).max() < tol
+        assert np.array_equal(rg["u"], ro["u"])
+        for a, b, u, du in zip(rg["accept"], ro["accept"], ro["u"], ro["du"]):
+            if a != b:
+                assert abs(math.log(u) + du / kT) < tol / kT
+        g.set_state(mol_kind=o.state()["mol_kind"])
+    g.close()
