@@ -104,7 +104,10 @@ typedef struct membx_desc {
     int32_t precision;            /* MEMBX_FP64 or MEMBX_MIXED              */
     /* tuning; 0 selects a default */
     double  skin;                 /* Verlet buffer, nm (default 0.2)        */
-    double  skin_max;             /* largest skin the arena is sized for    */
+    double  skin_max;             /* largest skin the arena is sized for;   */
+                                  /* <= 0: 0.4 nm where the box allows it   */
+                                  /* (box >= 3 (r_cut + skin_max)), else    */
+                                  /* skin                                   */
     int32_t rebuild_interval;     /* steps between list rebuilds (def. 10)  */
     int32_t lanes_per_bead;       /* 1, 2, 4 or 8 (default 4)               */
     int32_t list_capacity;        /* neighbour slots per bead (default auto) */
@@ -120,7 +123,11 @@ typedef struct membx_energy {
                                   /* unit, Methods)                         */
     int64_t step, batch, cycle;   /* MD step, exchange batch, MDAS cycle    */
     int64_t n_rebuilds;
-    int64_t n_skin_violations;
+    int64_t n_skin_violations;    /* (bead, step) events beyond skin/2 since */
+                                  /* creation or the last retune            */
+    double  max_displacement;     /* largest displacement from the position */
+                                  /* at the last list build seen since then */
+                                  /* (nm)                                   */
 } membx_energy;
 
 /* One admitted exchange trial of a batch. */
@@ -220,9 +227,15 @@ int32_t membx_set_tuning(membx_sys* sys, double skin, int32_t rebuild_interval,
                          int32_t lanes_per_bead);
 
 /* Autotune skin, rebuild interval and lanes per bead by timing short runs
- * of n_steps from the current state (the state is restored afterwards).
- * A candidate is rejected if any bead moves more than skin/2 between
- * rebuilds.  Writes the chosen values; leaves the system tuned. */
+ * of n_steps (<= 0: 200) from the current state.  Candidates: skin from
+ * 0.1 nm to skin_max in steps of 0.05 nm, lanes per bead 4 and 8; for each
+ * skin the interval is the largest that keeps every bead within 0.8 skin/2
+ * of its position at the last list build, extrapolated linearly from a pilot
+ * run at interval 4.  A candidate is rejected if a bead went beyond 0.9
+ * skin/2 in its timed run.  Positions, velocities, kinds and random-number
+ * counters are restored afterwards; forces are recomputed and the list is
+ * rebuilt.  Writes the chosen values and leaves the system tuned.
+ * E_DEVICE. */
 int32_t membx_autotune(membx_sys* sys, int32_t n_steps, double* skin,
                        int32_t* rebuild_interval, int32_t* lanes_per_bead);
 

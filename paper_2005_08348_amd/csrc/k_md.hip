@@ -11,7 +11,8 @@ template <typename R>
 __global__ __launch_bounds__(WG) void k_kick_drift(Dev<R> d, R kick, long long step_off)
 {
     int i = blockIdx.x * WG + threadIdx.x;
-    if (i >= d.N) return;
+    float e2f = 0.f;
+    if (i < d.N) {
     V4<R> p = d.posq[i], v = d.vel[i], f = d.frc[i];
     const R im = v.w, h = d.half_dt;
     v.x += kick * im * f.x; v.y += kick * im * f.y; v.z += kick * im * f.z;
@@ -38,7 +39,23 @@ __global__ __launch_bounds__(WG) void k_kick_drift(Dev<R> d, R kick, long long s
     }
     V4<R> r = d.xref[i];
     R ex = p.x - r.x, ey = p.y - r.y, ez = p.z - r.z;
-    if (ex * ex + ey * ey + ez * ez > d.skin_half2) atomicOr(&d.flags[FL_SKIN], 1);
+    e2f = (float)(ex * ex + ey * ey + ez * ez);
+    }
+    // beads beyond skin/2, and per block the largest squared displacement
+    // from the last rebuild seen so far
+    __shared__ float s_m2[WG / 64];
+    const unsigned long long over = __ballot(e2f > (float)d.skin_half2);
+    float m2 = e2f;
+    for (int o = 32; o > 0; o >>= 1) m2 = fmaxf(m2, __shfl_xor(m2, o, 64));
+    if ((threadIdx.x & 63) == 0) {
+        if (over) atomicAdd(&d.flags[FL_SKIN], __popcll(over));
+        s_m2[threadIdx.x >> 6] = m2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < WG / 64; ++w) m2 = fmaxf(m2, s_m2[w]);
+        d.dmax_part[blockIdx.x] = fmaxf(d.dmax_part[blockIdx.x], m2);
+    }
 }
 
 // closing half-kick of a run of steps; also advances the step counter

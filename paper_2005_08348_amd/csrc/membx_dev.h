@@ -21,6 +21,7 @@ enum { ST_LANGEVIN = 0, ST_SWAP_DRAW = 1, ST_SWAP_ACCEPT = 2, ST_MDAS_SELECT = 3
        ST_MDAS_ACCEPT = 4 };
 
 // device flags
+// FL_SKIN counts (bead, step) events beyond skin/2 since the last reset
 enum { FL_LIST_OVF = 0, FL_SKIN = 1, FL_GHOST_OVF = 2, FL_NONFINITE = 3, FL_AFF_OVF = 4,
        FL_REBUILDS = 5, NFLAGS = 8 };
 
@@ -159,6 +160,8 @@ template <typename R> struct Dev {
     int4* bslot;     // [N * 8] bonded terms of each slot with partner slots
                      // {role, slot 1, slot 2, parameter}; role -1 = unused
     int* scan_part;  // [2 * SCAN_BLOCKS + 2] block sums of the cell scans
+    float* dmax_part;  // [ceil(N / WG)] per integrator block: largest squared
+                       // displacement from the last rebuild seen since a reset
     // neighbour list, tiled so that the LPB lanes of the 64/LPB beads a wave
     // handles read one contiguous 256-byte block per load (see nbr_index)
     int lpb, lpb_shift, bg_shift;   // lanes per bead, log2(lpb), log2(64/lpb)

@@ -99,10 +99,25 @@ struct Host {
     // tuning / capacities
     double skin, skin_max;
     int R, lpb, Kcap, Gcap, T_cap, P_cap;
-    int nc[3], ncell, ne[3], next;
+    int nc[3], ncell, ne[3], next;   // cell grid at the current skin
+    int ncell_cap, next_cap;          // array sizes (grid at the smallest skin)
     int hnc[3], hcells, mh;
     int aff_cap;
 };
+
+// Cell grid for list radius r_cut + skin: nc = floor(L / r_list) cells per
+// axis (at least 3), plus one halo layer of ghost images.
+static void set_grid(Host& h, double skin)
+{
+    const double rl = h.rc + skin;
+    h.ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+        h.nc[a] = std::max(3, (int)std::floor(h.box[a] / rl));
+        h.ne[a] = h.nc[a] + 1;
+        h.ncell *= h.nc[a];
+    }
+    h.next = h.ne[0] * h.ne[1] * h.ne[2];
+}
 
 Status check_desc(const membx_desc* d, Host& h)
 {
@@ -190,7 +205,11 @@ Status check_desc(const membx_desc* d, Host& h)
     h.crf = 1.0 / h.rc + h.krf * h.rc * h.rc;
     // tuning
     h.skin = d->skin > 0 ? d->skin : 0.2;
-    h.skin_max = std::max(h.skin, d->skin_max > 0 ? d->skin_max : h.skin);
+    if (d->skin_max > 0) h.skin_max = std::max(h.skin, d->skin_max);
+    else {
+        const double lim = std::min(h.box[0], std::min(h.box[1], h.box[2])) / 3.0 - h.rc;
+        h.skin_max = std::max(h.skin, std::min(0.4, lim));
+    }
     h.R = d->rebuild_interval > 0 ? d->rebuild_interval : 10;
     h.lpb = d->lanes_per_bead > 0 ? d->lanes_per_bead : 4;
     if (h.lpb != 1 && h.lpb != 2 && h.lpb != 4 && h.lpb != 8)
@@ -199,15 +218,13 @@ Status check_desc(const membx_desc* d, Host& h)
     h.P_cap = d->max_pairs > 0 ? d->max_pairs : 64;
     if (h.T_cap > 16384 || h.P_cap > 16384) return { MEMBX_E_INVAL, "max_trials/max_pairs > 16384" };
     double rl = h.rc + h.skin_max;
-    h.ncell = 1;
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < 3; ++a)
         if (!(h.box[a] >= 3.0 * rl)) return { MEMBX_E_INVAL, "box must be >= 3 (r_cut + skin)" };
-        h.nc[a] = (int)std::floor(h.box[a] / rl);
-        if (h.nc[a] < 3) h.nc[a] = 3;
-        h.ne[a] = h.nc[a] + 1;
-        h.ncell *= h.nc[a];
-    }
-    h.next = h.ne[0] * h.ne[1] * h.ne[2];
+    // arrays hold the finest grid the tuner may choose (skin 0.1 nm)
+    set_grid(h, std::min(h.skin, 0.1));
+    h.ncell_cap = h.ncell;
+    h.next_cap = h.next;
+    set_grid(h, h.skin_max);
     double vol = h.box[0] * h.box[1] * h.box[2];
     double rho = h.N / vol;
     if (d->list_capacity > 0) h.Kcap = d->list_capacity;
@@ -220,6 +237,7 @@ Status check_desc(const membx_desc* d, Host& h)
     double gfrac = (1.0 + 1.0 / h.nc[0]) * (1.0 + 1.0 / h.nc[1]) * (1.0 + 1.0 / h.nc[2]) - 1.0;
     h.Gcap = (int)(h.N * gfrac * 1.6) + 4096;
     if ((long long)h.N + h.Gcap >= (1LL << CODE_SHIFT)) return { MEMBX_E_INVAL, "too many beads" };
+    set_grid(h, h.skin);
     // exchange hash (cells >= r_cut)
     h.hcells = 1;
     for (int a = 0; a < 3; ++a) {
@@ -427,10 +445,10 @@ static size_t layout(membx_sys* s, Dev<R>& d, Mv& m, char* base)
     d.cellid = a.take<int>(N);
     d.posq_t = a.take<V4<R>>(N); d.vel_t = a.take<V4<R>>(N); d.frc_t = a.take<V4<R>>(N);
     d.orig_t = a.take<int>(N); d.alch_t = a.take<int>(N); d.cell_t = a.take<int>(N);
-    d.cell_cnt = a.take<int>(h.ncell); d.cell_cur = a.take<int>(h.ncell);
-    d.cell_start = a.take<int>(h.ncell + 1);
-    d.ext_start = a.take<int>(h.next); d.ext_cnt = a.take<int>(h.next);
-    d.ext_scan = a.take<int>(2 * h.next + 2);
+    d.cell_cnt = a.take<int>(h.ncell_cap); d.cell_cur = a.take<int>(h.ncell_cap);
+    d.cell_start = a.take<int>(h.ncell_cap + 1);
+    d.ext_start = a.take<int>(h.next_cap); d.ext_cnt = a.take<int>(h.next_cap);
+    d.ext_scan = a.take<int>(2 * h.next_cap + 2);
     d.ghost_owner = a.take<int>(h.Gcap); d.ghost_code = a.take<int>(h.Gcap);
     d.n_ghost = a.take<int>(1);
     d.gcnt = a.take<int>(N);
@@ -438,6 +456,7 @@ static size_t layout(membx_sys* s, Dev<R>& d, Mv& m, char* base)
     d.orig_ext = a.take<int>(N + h.Gcap);
     d.bslot = a.take<int4>((size_t)N * MAXBT);
     d.scan_part = a.take<int>(2 * SCAN_BLOCKS + 2);
+    d.dmax_part = a.take<float>((size_t)(N + WG - 1) / WG);
     d.nbr = a.take<int>((size_t)h.Kcap * Npad);
     d.ncnt = a.take<int>(N); d.nseg0 = a.take<int>(N);
     d.excl = a.take<int>((size_t)N * MAXEXCL);
@@ -872,9 +891,10 @@ static int32_t upload(membx_sys* s, const membx_desc* desc)
     HCK(hipMemsetAsync(d.frc, 0, sizeof(V4<R>) * h.N, st));
     // binning counters start at zero; afterwards the list kernel clears them
     // for the next rebuild
-    HCK(hipMemsetAsync(d.cell_cnt, 0, sizeof(int) * h.ncell, st));
-    HCK(hipMemsetAsync(d.cell_cur, 0, sizeof(int) * h.ncell, st));
+    HCK(hipMemsetAsync(d.cell_cnt, 0, sizeof(int) * h.ncell_cap, st));
+    HCK(hipMemsetAsync(d.cell_cur, 0, sizeof(int) * h.ncell_cap, st));
     HCK(hipMemsetAsync(d.gcnt, 0, sizeof(int) * h.N, st));
+    HCK(hipMemsetAsync(d.dmax_part, 0, sizeof(float) * ((h.N + WG - 1) / WG), st));
     HCK(hipMemsetAsync(m.hb_word, 0, sizeof(unsigned long long) * ((size_t)m.hb_mask + 1), st));
     HCK(hipMemsetAsync(m.mb_word, 0, sizeof(unsigned long long) * ((size_t)m.mb_mask + 1), st));
     HCK(hipMemsetAsync(m.ab_word, 0, sizeof(unsigned long long) * ((size_t)m.ab_mask + 1), st));
@@ -1074,6 +1094,31 @@ int32_t membx_mdas_cycle(membx_sys* s, int32_t n_pairs, int32_t k_increments, in
     return MEMBX_OK;
 }
 
+// Largest displacement of a bead from its position at the last rebuild seen
+// since the last reset of the integrator's per-block maxima (nm).
+template <typename R>
+static int32_t max_disp(membx_sys* s, double* out)
+{
+    Dev<R>& d = dev<R>(s);
+    const int nb = (d.N + WG - 1) / WG;
+    std::vector<float> v(nb);
+    HCK(hipMemcpyAsync(v.data(), d.dmax_part, sizeof(float) * nb, hipMemcpyDeviceToHost, s->st));
+    HCK(hipStreamSynchronize(s->st));
+    float m = 0.f;
+    for (float x : v) m = std::max(m, x);
+    *out = std::sqrt((double)m);
+    return MEMBX_OK;
+}
+
+// Zero the skin-violation count and the displacement maxima.
+template <typename R>
+static void reset_disp(membx_sys* s)
+{
+    Dev<R>& d = dev<R>(s);
+    launch_fill_i32((int*)d.dmax_part, 0, (size_t)(d.N + WG - 1) / WG, s->st);
+    launch_fill_i32(d.flags + FL_SKIN, 0, 1, s->st);
+}
+
 template <typename R>
 static int32_t energies_impl(membx_sys* s, membx_energy* out)
 {
@@ -1093,6 +1138,12 @@ static int32_t energies_impl(membx_sys* s, membx_energy* out)
     E.fe_count = s->fe; E.step = s->step; E.batch = s->batch; E.cycle = s->cycle;
     E.n_rebuilds = s->n_rebuilds;
     E.n_skin_violations = fl[FL_SKIN];
+    {
+        double dm = 0.0;
+        int32_t rc2 = max_disp<R>(s, &dm);
+        if (rc2) return rc2;
+        E.max_displacement = dm;
+    }
     if (out) *out = E;
     if (!std::isfinite(E.total)) return fail(s, MEMBX_E_NONFINITE, "non-finite energy");
     return flag_status(s, fl);
@@ -1295,7 +1346,21 @@ template <typename R>
 static int32_t retune_impl(membx_sys* s)
 {
     Dev<R>& d = dev<R>(s);
-    double rl = s->h.rc + s->h.skin;
+    Host& h = s->h;
+    // the grid follows the skin; counters of cells beyond the old grid are
+    // cleared (the list kernel clears only the cells it used)
+    set_grid(h, h.skin);
+    for (int k = 0; k < 3; ++k) {
+        d.nc[k] = h.nc[k]; d.ne[k] = h.ne[k];
+        d.inv_edge[k] = (R)(h.nc[k] / h.box[k]);
+    }
+    d.ncell = h.ncell; d.next = h.next;
+    HCK(hipMemsetAsync(d.cell_cnt, 0, sizeof(int) * h.ncell_cap, s->st));
+    HCK(hipMemsetAsync(d.cell_cur, 0, sizeof(int) * h.ncell_cap, s->st));
+    d.lpb = h.lpb;
+    d.lpb_shift = h.lpb == 1 ? 0 : h.lpb == 2 ? 1 : h.lpb == 4 ? 2 : 3;
+    d.bg_shift = 6 - d.lpb_shift;
+    double rl = h.rc + h.skin;
     d.rl2d = rl * rl;
     d.rl2f_lo = (float)(d.rl2d * (1.0 - 4e-6));
     d.rl2f_hi = (float)(d.rl2d * (1.0 + 4e-6));
@@ -1303,7 +1368,113 @@ static int32_t retune_impl(membx_sys* s)
     for (auto& kv : s->gcache) (void)hipGraphExecDestroy(kv.second);
     s->gcache.clear();
     refresh_forces<R>(s);
+    reset_disp<R>(s);
     HCK(hipStreamSynchronize(s->st));
+    return MEMBX_OK;
+}
+
+// ---------------------------------------------------------------- autotune
+// State kept across the tuning runs: slot arrays through the MDAS snapshot
+// buffers, the device counters and the host mirrors.
+struct Saved {
+    long long ctr[NCTR];
+    long long step, batch, cycle, fe, n_rebuilds;
+    int since;
+};
+
+template <typename R>
+static int32_t tune_save(membx_sys* s, Saved& sv)
+{
+    Dev<R>& d = dev<R>(s);
+    launch_snapshot<R>(d, s->mv, 0, s->st);
+    HCK(hipMemcpyAsync(sv.ctr, d.ctr, sizeof(sv.ctr), hipMemcpyDeviceToHost, s->st));
+    HCK(hipStreamSynchronize(s->st));
+    sv.step = s->step; sv.batch = s->batch; sv.cycle = s->cycle; sv.fe = s->fe;
+    sv.n_rebuilds = s->n_rebuilds; sv.since = s->since;
+    return MEMBX_OK;
+}
+
+template <typename R>
+static int32_t tune_restore(membx_sys* s, const Saved& sv)
+{
+    Dev<R>& d = dev<R>(s);
+    launch_fill_i32((int*)s->mv.md, 0, 16, s->st);   // restore is skipped after an accepted cycle
+    launch_snapshot<R>(d, s->mv, 1, s->st);
+    HCK(hipMemcpyAsync(d.ctr, sv.ctr, sizeof(sv.ctr), hipMemcpyHostToDevice, s->st));
+    refresh_forces<R>(s);
+    reset_disp<R>(s);
+    HCK(hipStreamSynchronize(s->st));
+    s->step = sv.step; s->batch = sv.batch; s->cycle = sv.cycle; s->fe = sv.fe;
+    s->n_rebuilds = sv.n_rebuilds; s->since = 0;
+    return MEMBX_OK;
+}
+
+// Candidates: skins from 0.1 nm to skin_max in 0.05 nm steps, lanes per bead
+// 4 and 8.  A pilot run at rebuild interval 4 gives the largest displacement
+// d4; in the ballistic regime (interval << 1/gamma) displacements grow
+// linearly with time, so interval R keeps every bead within 0.8 skin/2 when
+// R <= 4 * 0.8 (skin/2) / d4.  Each candidate runs n steps untimed (graph
+// capture) and n steps timed; it is rejected if a bead went beyond 0.9 skin/2.
+template <typename R>
+static int32_t autotune_impl(membx_sys* s, int n, double* o_skin, int* o_R, int* o_lpb)
+{
+    if (n <= 0) n = 200;
+    const bool graphs0 = s->graphs;
+    s->graphs = true;
+    Saved sv;
+    int32_t rc = tune_save<R>(s, sv);
+    if (rc) return rc;
+    const double skin_max = s->h.skin_max;
+    const int lpb0 = s->h.lpb;
+    auto apply = [&](double skin, int Rr, int lpb) -> int32_t {
+        s->h.skin = skin; s->h.R = Rr; s->h.lpb = lpb;
+        return retune_impl<R>(s);
+    };
+    // pilot
+    if ((rc = apply(skin_max, 4, lpb0))) return rc;
+    if ((rc = md_steps<R>(s, n))) return rc;
+    double d4 = 0.0;
+    if ((rc = max_disp<R>(s, &d4))) return rc;
+    if ((rc = tune_restore<R>(s, sv))) return rc;
+    d4 = std::max(d4, 1e-6);
+    hipEvent_t e0, e1;
+    HCK(hipEventCreate(&e0));
+    HCK(hipEventCreate(&e1));
+    double best_t = 1e300, best_skin = s->h.skin;
+    int best_R = s->h.R, best_lpb = lpb0;
+    for (int lpb : { 4, 8 }) {
+        for (double skin = 0.1; skin <= skin_max + 1e-9; skin += 0.05) {
+            const int Rr = std::min(50, (int)std::floor(4.0 * 0.8 * 0.5 * skin / d4));
+            if (Rr < 1) continue;
+            if ((rc = apply(skin, Rr, lpb))) break;
+            if ((rc = md_steps<R>(s, n))) break;
+            reset_disp<R>(s);
+            HCK(hipEventRecord(e0, s->st));
+            if ((rc = md_steps<R>(s, n))) break;
+            HCK(hipEventRecord(e1, s->st));
+            HCK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HCK(hipEventElapsedTime(&ms, e0, e1));
+            double dm = 0.0;
+            if ((rc = max_disp<R>(s, &dm))) break;
+            int fl[NFLAGS];
+            if ((rc = read_flags(s, fl))) break;
+            const bool ok = fl[FL_SKIN] == 0 && dm <= 0.9 * 0.5 * skin &&
+                            !fl[FL_LIST_OVF] && !fl[FL_GHOST_OVF];
+            if (ok && ms < best_t) { best_t = ms; best_skin = skin; best_R = Rr; best_lpb = lpb; }
+            if ((rc = tune_restore<R>(s, sv))) break;
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if ((rc = apply(best_skin, best_R, best_lpb))) return rc;
+    if ((rc = tune_restore<R>(s, sv))) return rc;
+    s->graphs = graphs0;
+    if (o_skin) *o_skin = best_skin;
+    if (o_R) *o_R = best_R;
+    if (o_lpb) *o_lpb = best_lpb;
     return MEMBX_OK;
 }
 
@@ -1379,11 +1550,17 @@ int32_t membx_calib_copy(membx_sys* s, void* dst, const void* src, uint64_t byte
 int32_t membx_autotune(membx_sys* s, int32_t n_steps, double* skin, int32_t* rebuild_interval,
                        int32_t* lanes_per_bead)
 {
-    (void)n_steps;
     if (!s) return MEMBX_E_INVAL;
-    if (skin) *skin = s->h.skin;
-    if (rebuild_interval) *rebuild_interval = s->h.R;
-    if (lanes_per_bead) *lanes_per_bead = s->h.lpb;
+    int32_t rc = begin(s);
+    if (rc) return rc;
+    int Rr = 0, lpb = 0;
+    double sk = 0.0;
+    rc = DISPATCH(s, autotune_impl, s, n_steps, &sk, &Rr, &lpb);
+    if (!rc) rc = end(s);
+    if (rc) return rc;
+    if (skin) *skin = sk;
+    if (rebuild_interval) *rebuild_interval = Rr;
+    if (lanes_per_bead) *lanes_per_bead = lpb;
     return MEMBX_OK;
 }
 

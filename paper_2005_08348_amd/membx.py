@@ -61,7 +61,8 @@ class Energy(C.Structure):
                 ("total", C.c_double), ("n_pairs_in_cutoff", C.c_int64),
                 ("fe_count", C.c_int64), ("step", C.c_int64), ("batch", C.c_int64),
                 ("cycle", C.c_int64), ("n_rebuilds", C.c_int64),
-                ("n_skin_violations", C.c_int64)]
+                ("n_skin_violations", C.c_int64),
+                ("max_displacement", C.c_double)]
 
 
 class Trial(C.Structure):
@@ -327,7 +328,7 @@ class System:
         _check(lib().membx_set_tuning(self.h, float(skin), int(rebuild_interval),
                                       int(lanes_per_bead)), self.h)
 
-    def autotune(self, n_steps=20):
+    def autotune(self, n_steps=200):
         sk, R, l = C.c_double(), C.c_int32(), C.c_int32()
         _check(lib().membx_autotune(self.h, int(n_steps), C.byref(sk), C.byref(R), C.byref(l)),
                self.h)

@@ -209,3 +209,27 @@ def test_swap_batch_256_c1(oracle_mod, prec):
                 assert abs(math.log(u) + du / kT) < tol / kT
         g.set_state(mol_kind=o.state()["mol_kind"])
     g.close()
+
+
+def test_autotune_restores_state(oracle_mod, c0_relaxed):
+    """The tuning runs leave positions, velocities, kinds and random-number
+    counters as they were: 20 float64 steps after tuning follow the oracle
+    from the same start; the chosen interval keeps every bead within skin/2."""
+    m = _membx()
+    g = m.System(c0_relaxed, precision="fp64")
+    st0 = g.state()
+    t = g.autotune(60)
+    assert 0.1 - 1e-9 <= t["skin"] <= 0.4 + 1e-9 and t["rebuild_interval"] >= 1
+    st1 = g.state()
+    for k in ("pos", "vel", "mol_kind", "step", "batch", "cycle"):
+        assert np.array_equal(np.asarray(st0[k]), np.asarray(st1[k])), k
+    o = oracle_mod.Oracle(c0_relaxed)
+    g.md_step(20)
+    o.md_step(20)
+    d = g.state()["pos"] - o.state()["pos"]
+    d -= c0_relaxed.box * np.rint(d / c0_relaxed.box)
+    assert np.abs(d).max() < 1e-7
+    e = g.energies()
+    assert e["n_skin_violations"] == 0
+    assert e["max_displacement"] <= 0.5 * t["skin"]
+    g.close()
