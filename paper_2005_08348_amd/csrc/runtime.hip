@@ -581,8 +581,8 @@ static void forces(membx_sys* s, bool rebuilt)
     if (s->timing) {
         if (s->tev_used >= s->tev.size()) {
             hipEvent_t a, b;
-            (void)hipEventCreate(&a);
-            (void)hipEventCreate(&b);
+            (void)hipEventCreateWithFlags(&a, hipEventDisableSystemFence);
+            (void)hipEventCreateWithFlags(&b, hipEventDisableSystemFence);
             s->tev.push_back({ a, b });
         }
         auto& pr = s->tev[s->tev_used++];
@@ -1525,6 +1525,50 @@ int32_t membx_kernel_time(membx_sys* s, int64_t* launches, double* mean_ms)
     if (launches) *launches = s->t_launches;
     if (mean_ms) *mean_ms = s->t_launches ? s->t_ms / s->t_launches : 0.0;
     return MEMBX_OK;
+}
+
+template <typename R>
+static int32_t kbench_impl(membx_sys* s, int n, double* mean_ms)
+{
+    Dev<R>& d = dev<R>(s);
+    hipGraph_t g;
+    if (hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(s, MEMBX_E_DEVICE, "stream capture failed");
+    for (int q = 0; q < n; ++q) launch_nonbonded<R>(d, s->h.lpb, false, nullptr, s->st);
+    if (hipStreamEndCapture(s->st, &g) != hipSuccess)
+        return fail(s, MEMBX_E_DEVICE, "stream capture failed");
+    hipGraphExec_t ge;
+    if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(s, MEMBX_E_DEVICE, "graph instantiation failed");
+    }
+    (void)hipGraphDestroy(g);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float ms = 0.f;
+    hipError_t e = hipEventCreateWithFlags(&e0, hipEventDisableSystemFence);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
+    if (e == hipSuccess) e = hipGraphLaunch(ge, s->st);
+    if (e == hipSuccess) e = hipEventRecord(e0, s->st);
+    if (e == hipSuccess) e = hipGraphLaunch(ge, s->st);
+    if (e == hipSuccess) e = hipEventRecord(e1, s->st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipGraphExecDestroy(ge);
+    if (e != hipSuccess) return fail(s, MEMBX_E_DEVICE, hipGetErrorString(e));
+    *mean_ms = (double)ms / n;
+    return MEMBX_OK;
+}
+
+int32_t membx_kernel_bench(membx_sys* s, int32_t n_launch, double* mean_ms)
+{
+    if (!s || !mean_ms || n_launch < 1 || n_launch > 4096) return fail(s, MEMBX_E_INVAL, "bad arguments");
+    int32_t rc = begin(s);
+    if (rc) return rc;
+    rc = DISPATCH(s, kbench_impl, s, n_launch, mean_ms);
+    if (!rc) rc = end(s);
+    return rc;
 }
 
 const char* membx_last_error(const membx_sys* s) { return s ? s->err.c_str() : ""; }

@@ -105,6 +105,7 @@ def lib():
             "membx_set_graphs": ([vp, i32], i32),
             "membx_kernel_timing": ([vp, i32], i32),
             "membx_kernel_time": ([vp, C.POINTER(i64), C.POINTER(dp)], i32),
+            "membx_kernel_bench": ([vp, i32, C.POINTER(dp)], i32),
             "membx_last_error": ([vp], C.c_char_p),
             "membx_status": ([vp], i32),
             "membx_calib_copy": ([vp, vp, vp, u64], i32),
@@ -344,6 +345,12 @@ class System:
         n, ms = C.c_int64(), C.c_double()
         _check(lib().membx_kernel_time(self.h, C.byref(n), C.byref(ms)), self.h)
         return int(n.value), float(ms.value)
+
+    def kernel_bench(self, n_launch=200):
+        """mean duration (ms) of the nonbonded kernel over n_launch graph-replayed launches"""
+        ms = C.c_double()
+        _check(lib().membx_kernel_bench(self.h, int(n_launch), C.byref(ms)), self.h)
+        return ms.value
 
     def calib_copy(self, dst, src, nbytes):
         _check(lib().membx_calib_copy(self.h, C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()),
