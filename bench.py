@@ -99,6 +99,53 @@ def cpu_baseline(sysm, target_s=15.0):
                        f"(cell-list oracle, one host thread), {dt + t1:.1f} s")
 
 
+def serving_leg(n_jobs, budget=2 << 30):
+    """Serving: n_jobs bilayers with N log-uniform in [1.4k, 250k] beads, each
+    relaxed (100 steepest-descent steps) at admission, then 4 cycles of 50 MD
+    steps and 20 MDAS cycles (8 pairs, K 50, M 1), all
+    submitted at once to a server whose arena budget forces admission to
+    wait for finished jobs."""
+    import numpy as np
+    import torch
+    from paper_2005_08348_amd import membx as M
+    from paper_2005_08348_amd import systems as S
+    log(f"[bench] serving leg: building {n_jobs} jobs")
+    jobs = S.serving_jobs(48)[:n_jobs]
+    req = dict(minimize_iters=100, md_cycles=4, md_steps=50, mdas_cycles=20, mdas_pairs=8,
+               mdas_k=50, mdas_m=1)
+    srv = M.Server(budget)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in jobs:
+        srv.submit(s, **req)
+    done, max_wait, max_res = [], 0, 0
+    last = t0
+    while len(done) < len(jobs):
+        res, nres, nwait = srv.poll()
+        done += res
+        max_wait, max_res = max(max_wait, nwait), max(max_res, nres)
+        if time.perf_counter() - last > 20:
+            last = time.perf_counter()
+            log(f"[bench] serving: {len(done)}/{len(jobs)} jobs done")
+    wall = time.perf_counter() - t0
+    cyc = srv.cycle_times()
+    srv.close()
+    bad = [r for r in done if r["status"] != 0]
+    steps = sum(r["md_steps"] for r in done)
+    pair_int = sum(r["pairs_in_cutoff"] * r["md_steps"] for r in done)
+    turn = np.array([r["finish_s"] - r["submit_s"] for r in done])
+    return {"jobs": len(done), "failed": len(bad), "budget_bytes": budget,
+            "beads_total": int(sum(s.n_beads for s in jobs)),
+            "max_resident": max_res, "max_waiting": max_wait,
+            "wall_s": wall, "jobs_per_s": len(done) / wall,
+            "md_steps_per_s": steps / wall,
+            "pair_interactions_per_s_est": pair_int / wall,
+            "cycle_ms_p50": float(np.percentile(cyc, 50)), "cycle_ms_p99": float(np.percentile(cyc, 99)),
+            "turnaround_s_p50": float(np.percentile(turn, 50)),
+            "turnaround_s_p99": float(np.percentile(turn, 99)),
+            "mdas_accepted": int(sum(r["mdas_accepted"] for r in done))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +153,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-legs", action="store_true", help="main timed region only")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serving-jobs", type=int, default=48,
+                    help="jobs of the serving leg (0: skip it)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use --skin/--rebuild/--lpb instead of the autotuner")
     ap.add_argument("--lpb", type=int, default=8, help="lanes per bead of the pair kernel")
@@ -254,6 +303,9 @@ def main():
                           "pair_interactions_per_s": e3["n_pairs_in_cutoff"] * k3 / t3md}
         g3.close(); del g3
         torch.cuda.empty_cache()
+
+    if not args.no_legs and args.serving_jobs > 0:
+        result["serving"] = serving_leg(args.serving_jobs)
 
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")

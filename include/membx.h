@@ -103,13 +103,13 @@ typedef struct membx_desc {
     uint64_t seed;                /* Philox key of every random stream      */
     int32_t precision;            /* MEMBX_FP64 or MEMBX_MIXED              */
     /* tuning; 0 selects a default */
-    double  skin;                 /* Verlet buffer, nm (default 0.2)        */
+    double  skin;                 /* Verlet buffer, nm (default 0.3)        */
     double  skin_max;             /* largest skin the arena is sized for;   */
                                   /* <= 0: 0.4 nm where the box allows it   */
                                   /* (box >= 3 (r_cut + skin_max)), else    */
                                   /* skin                                   */
-    int32_t rebuild_interval;     /* steps between list rebuilds (def. 10)  */
-    int32_t lanes_per_bead;       /* 1, 2, 4 or 8 (default 4)               */
+    int32_t rebuild_interval;     /* steps between list rebuilds (def. 5)   */
+    int32_t lanes_per_bead;       /* 1, 2, 4 or 8 (default 8)               */
     int32_t list_capacity;        /* neighbour slots per bead (default auto) */
     int32_t max_trials;           /* largest exchange batch (default 256)   */
     int32_t max_pairs;            /* largest MDAS pair count (default 64)   */
@@ -265,6 +265,77 @@ int32_t membx_status(membx_sys* sys);
 /* Bandwidth calibration: copy `bytes` (multiple of 16) from src to dst on the
  * library's stream with a plain vector-load/store kernel. */
 int32_t membx_calib_copy(membx_sys* sys, void* dst, const void* src, uint64_t bytes);
+
+/* ---------------------------------------------------------------- serving
+ * Many independent systems ("jobs") resident in one caller-owned device
+ * arena, stepped concurrently.  A job is a system descriptor plus a request:
+ * md_cycles cycles of md_steps MD steps each, then mdas_cycles MDAS cycles
+ * (mdas_pairs pairs, mdas_k increments, mdas_m steps per increment) -- the
+ * paper's MC-MD and MDAS protocols (Theory) run as a service.
+ *
+ * Admission: jobs are admitted first come, first served, when a block of
+ * membx_sys_bytes() for the job fits in the arena (first fit, freed blocks
+ * coalesced); a job that does not fit waits and blocks the queue behind it.
+ * Each resident job runs on its own HIP stream (default priority) with at
+ * most two cycles in flight; membx_server_poll advances every job without
+ * blocking (it never waits for the GPU, except for the short energy query
+ * that closes a job).  A job's results do not depend on the other jobs.
+ * The server allocates no device memory besides the caller's arena. */
+typedef struct membx_server membx_server;
+
+typedef struct membx_request {
+    int32_t minimize_iters;       /* steepest-descent steps at admission    */
+                                  /* (membx_minimize, alpha 1e-4, step cap  */
+                                  /* 0.01 nm); 0: none                      */
+    int32_t md_cycles;            /* cycles of plain MD (>= 0)              */
+    int32_t md_steps;             /* steps per MD cycle (>= 1)              */
+    int32_t mdas_cycles;          /* MDAS cycles after the MD cycles (>= 0) */
+    int32_t mdas_pairs;           /* pairs per MDAS cycle (1..max_pairs)    */
+    int32_t mdas_k;               /* lambda increments per MDAS cycle       */
+    int32_t mdas_m;               /* MD steps per increment                 */
+} membx_request;
+
+typedef struct membx_job_result {
+    int64_t job_id;
+    int32_t status;               /* MEMBX_OK or the job's first error      */
+    int32_t n_cycles;             /* cycles completed                       */
+    int32_t mdas_accepted;        /* MDAS cycles accepted                   */
+    int32_t n_beads;
+    double  submit_s, admit_s, finish_s;   /* server clock (s since create) */
+    double  cycle_ms_p50, cycle_ms_p99, cycle_ms_max;  /* per-cycle device  */
+                                  /* time, HIP events on the job's stream   */
+    int64_t md_steps;             /* MD steps run (MDAS steps included)     */
+    int64_t fe_count;             /* force evaluations                      */
+    int64_t pairs_in_cutoff;      /* at the end of the job                  */
+    double  potential;            /* final potential energy, kJ/mol         */
+} membx_job_result;
+
+/* Create a server over a device arena of arena_bytes (owned by the caller,
+ * used until membx_server_destroy).  E_INVAL. */
+int32_t membx_server_create(void* dev_arena, uint64_t arena_bytes, membx_server** out);
+
+/* Queue a job.  The descriptor is copied (read only during this call); the
+ * device state is built when the job is admitted.  E_INVAL (bad descriptor
+ * or request), E_NOMEM (the job can never fit in the arena). */
+int32_t membx_server_submit(membx_server* srv, const membx_desc* desc, const membx_request* req,
+                            int64_t* job_id);
+
+/* Advance all jobs: collect finished cycles, close finished jobs (freeing
+ * their blocks), admit waiting jobs, issue the next cycles.  Writes up to
+ * cap results of jobs finished since the last call (the rest are kept for
+ * the next call) and the numbers of resident and waiting jobs (nullable).
+ * E_INVAL, E_DEVICE. */
+int32_t membx_server_poll(membx_server* srv, membx_job_result* out, int32_t cap, int32_t* n_out,
+                          int32_t* n_resident, int32_t* n_waiting);
+
+/* Device times (ms) of every cycle completed since creation, in completion
+ * order: up to cap values, *n = total count.  E_INVAL. */
+int32_t membx_server_cycle_times(membx_server* srv, float* out, int64_t cap, int64_t* n);
+
+/* Wait for and release every resident job (their results are dropped). */
+int32_t membx_server_destroy(membx_server* srv);
+
+const char* membx_server_last_error(const membx_server* srv);
 
 #ifdef __cplusplus
 }

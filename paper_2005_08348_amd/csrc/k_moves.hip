@@ -797,7 +797,9 @@ __global__ void k_mdas_accept(Dev<R> d, Mv m)
     uint4 w = draw(d.seed, 0u, d.ctr[CT_CYCLE], ST_MDAS_ACCEPT);
     double u = u53(w.x, w.y);
     m.md[3] = u;
-    m.md[2] = (u < exp(-m.md[0] / d.kTd)) ? 1.0 : 0.0;
+    const bool acc = u < exp(-m.md[0] / d.kTd);
+    m.md[2] = acc ? 1.0 : 0.0;
+    if (acc) d.ctr[CT_MDAS_ACC] += 1;
 }
 
 // Snapshot / restore of the per-slot state around an alchemical trajectory.

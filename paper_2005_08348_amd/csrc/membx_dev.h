@@ -26,7 +26,7 @@ enum { FL_LIST_OVF = 0, FL_SKIN = 1, FL_GHOST_OVF = 2, FL_NONFINITE = 3, FL_AFF_
        FL_REBUILDS = 5, NFLAGS = 8 };
 
 // device counters (int64)
-enum { CT_STEP = 0, CT_BATCH = 1, CT_CYCLE = 2, NCTR = 4 };
+enum { CT_STEP = 0, CT_BATCH = 1, CT_CYCLE = 2, CT_MDAS_ACC = 3, NCTR = 4 };
 
 template <typename R> struct alignas(4 * sizeof(R)) V4 { R x, y, z, w; };
 

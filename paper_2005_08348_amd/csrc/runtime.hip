@@ -3,9 +3,12 @@
 // HIP-graph replay and kernel timing.
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <iterator>
 #include <map>
 #include <string>
 #include <tuple>
@@ -204,14 +207,14 @@ Status check_desc(const membx_desc* d, Host& h)
                    : (h.eps_rf - h.eps_r) / ((2.0 * h.eps_rf + h.eps_r) * h.rc * h.rc * h.rc);
     h.crf = 1.0 / h.rc + h.krf * h.rc * h.rc;
     // tuning
-    h.skin = d->skin > 0 ? d->skin : 0.2;
+    h.skin = d->skin > 0 ? d->skin : 0.3;
     if (d->skin_max > 0) h.skin_max = std::max(h.skin, d->skin_max);
     else {
         const double lim = std::min(h.box[0], std::min(h.box[1], h.box[2])) / 3.0 - h.rc;
         h.skin_max = std::max(h.skin, std::min(0.4, lim));
     }
-    h.R = d->rebuild_interval > 0 ? d->rebuild_interval : 10;
-    h.lpb = d->lanes_per_bead > 0 ? d->lanes_per_bead : 4;
+    h.R = d->rebuild_interval > 0 ? d->rebuild_interval : 5;
+    h.lpb = d->lanes_per_bead > 0 ? d->lanes_per_bead : 8;
     if (h.lpb != 1 && h.lpb != 2 && h.lpb != 4 && h.lpb != 8)
         return { MEMBX_E_INVAL, "lanes_per_bead must be 1, 2, 4 or 8" };
     h.T_cap = d->max_trials > 0 ? d->max_trials : 256;
@@ -1328,7 +1331,6 @@ static int32_t minimize_impl(membx_sys* s, int n_iter, double alpha, double cap)
         launch_sd_step<R>(d, alpha, cap, s->st);
         refresh_forces<R>(s);
     }
-    HCK(hipStreamSynchronize(s->st));
     return MEMBX_OK;
 }
 
@@ -1608,3 +1610,315 @@ int32_t membx_autotune(membx_sys* s, int32_t n_steps, double* skin, int32_t* reb
     return MEMBX_OK;
 }
 
+
+// ================================================================== serving
+// Jobs resident in one caller-owned arena, each on its own stream.  The
+// arena is managed by a first-fit free list (offset -> size, coalesced on
+// release); admission is strictly first come, first served.
+
+namespace {
+
+constexpr int SRV_DEPTH = 2;   // cycles in flight per job
+
+struct SrvJob {
+    int64_t id = 0;
+    membx_sys* s = nullptr;       // host part prepared at submit
+    membx_request rq{};
+    std::vector<double> pos, vel;
+    uint64_t bytes = 0;
+    size_t off = 0, span = 0;     // arena block
+    bool resident = false;
+    double t_submit = 0, t_admit = 0;
+    int total = 0, issued = 0, done = 0;
+    int32_t status = MEMBX_OK;
+    hipEvent_t ev[SRV_DEPTH][2] = {};
+    std::deque<int> inflight;     // event slots of cycles in flight
+    int next_slot = 0;
+    std::vector<float> cyc;
+};
+
+}  // namespace
+
+struct membx_server {
+    char* base = nullptr;
+    uint64_t bytes = 0;
+    std::map<size_t, size_t> free_;        // offset -> size
+    std::deque<SrvJob*> queue;
+    std::vector<SrvJob*> active;
+    std::deque<membx_job_result> finished;
+    std::vector<float> cycles;
+    int64_t next_id = 1;
+    std::chrono::steady_clock::time_point t0;
+    std::string err;
+    double now() const
+    {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+static bool srv_alloc(membx_server* v, size_t n, size_t* off)
+{
+    for (auto it = v->free_.begin(); it != v->free_.end(); ++it) {
+        if (it->second >= n) {
+            *off = it->first;
+            const size_t rest = it->second - n;
+            const size_t at = it->first + n;
+            v->free_.erase(it);
+            if (rest) v->free_[at] = rest;
+            return true;
+        }
+    }
+    return false;
+}
+
+static void srv_release(membx_server* v, size_t off, size_t n)
+{
+    auto it = v->free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != v->free_.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        v->free_.erase(nx);
+    }
+    if (it != v->free_.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            v->free_.erase(it);
+        }
+    }
+}
+
+static double pct(std::vector<float> v, double q)
+{
+    if (v.empty()) return 0.0;
+    std::sort(v.begin(), v.end());
+    size_t k = (size_t)std::ceil(q * (double)v.size()) - 1;
+    if (k >= v.size()) k = v.size() - 1;
+    return v[k];
+}
+
+int32_t membx_server_create(void* dev_arena, uint64_t arena_bytes, membx_server** out)
+{
+    if (!out || !dev_arena || arena_bytes < 4096) return MEMBX_E_INVAL;
+    membx_server* v = new membx_server();
+    // 256-byte aligned usable range
+    const uintptr_t b = ((uintptr_t)dev_arena + 255) / 256 * 256;
+    v->base = (char*)b;
+    v->bytes = arena_bytes - (b - (uintptr_t)dev_arena);
+    v->bytes = v->bytes / 256 * 256;
+    v->free_[0] = v->bytes;
+    v->t0 = std::chrono::steady_clock::now();
+    *out = v;
+    return MEMBX_OK;
+}
+
+int32_t membx_server_submit(membx_server* v, const membx_desc* desc, const membx_request* rq,
+                            int64_t* job_id)
+{
+    if (!v || !desc || !rq) return MEMBX_E_INVAL;
+    if (rq->minimize_iters < 0 || rq->md_cycles < 0 || rq->mdas_cycles < 0 ||
+        rq->md_cycles + rq->mdas_cycles <= 0 ||
+        (rq->md_cycles > 0 && rq->md_steps < 1) ||
+        (rq->mdas_cycles > 0 && (rq->mdas_pairs < 1 || rq->mdas_k < 1 || rq->mdas_m < 0))) {
+        v->err = "bad request";
+        return MEMBX_E_INVAL;
+    }
+    SrvJob* j = new SrvJob();
+    j->s = new membx_sys();
+    Status st = check_desc(desc, j->s->h);
+    if (!st.code) st = derive(desc, j->s->h);
+    if (!st.code && rq->mdas_cycles > 0 && (rq->mdas_pairs > j->s->h.P_cap || j->s->h.sw_list.empty()))
+        st = { MEMBX_E_INVAL, "MDAS request not possible for this system" };
+    if (st.code) {
+        v->err = st.msg;
+        delete j->s;
+        delete j;
+        return st.code;
+    }
+    membx_sys* s = j->s;
+    j->bytes = s->mixed() ? layout<float>(s, s->df, s->mv, nullptr) : layout<double>(s, s->dd, s->mv, nullptr);
+    j->span = (j->bytes + 255) / 256 * 256;
+    if (j->span > v->bytes) {
+        v->err = "job larger than the server arena";
+        delete j->s;
+        delete j;
+        return MEMBX_E_NOMEM;
+    }
+    const size_t n3 = 3 * (size_t)s->h.N;
+    j->pos.assign(desc->pos, desc->pos + n3);
+    if (desc->vel) j->vel.assign(desc->vel, desc->vel + n3);
+    j->rq = *rq;
+    j->total = rq->md_cycles + rq->mdas_cycles;
+    j->id = v->next_id++;
+    j->t_submit = v->now();
+    v->queue.push_back(j);
+    if (job_id) *job_id = j->id;
+    return MEMBX_OK;
+}
+
+// Build the job's device state in its block (on its own stream).
+static int32_t srv_admit(membx_server* v, SrvJob* j)
+{
+    membx_sys* s = j->s;
+    char* base = v->base + j->off;
+    if (s->mixed()) layout<float>(s, s->df, s->mv, base);
+    else layout<double>(s, s->dd, s->mv, base);
+    if (hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&s->ev_out, hipEventDisableTiming) != hipSuccess)
+        return MEMBX_E_DEVICE;
+    s->user = s->st;   // a job is ordered only against itself
+    for (int q = 0; q < SRV_DEPTH; ++q)
+        if (hipEventCreateWithFlags(&j->ev[q][0], hipEventDisableSystemFence) != hipSuccess ||
+            hipEventCreate(&j->ev[q][1]) != hipSuccess)
+            return MEMBX_E_DEVICE;
+    membx_desc dsc{};
+    dsc.pos = j->pos.data();
+    dsc.vel = j->vel.empty() ? nullptr : j->vel.data();
+    int32_t rc = DISPATCH(s, upload, s, &dsc);
+    if (!rc && j->rq.minimize_iters > 0) rc = membx_minimize(s, j->rq.minimize_iters, 1e-4, 0.01);
+    return rc;
+}
+
+static int32_t srv_issue(SrvJob* j)
+{
+    membx_sys* s = j->s;
+    const int slot = j->next_slot;
+    j->next_slot = (j->next_slot + 1) % SRV_DEPTH;
+    if (hipEventRecord(j->ev[slot][0], s->st) != hipSuccess) return MEMBX_E_DEVICE;
+    int32_t rc;
+    if (j->issued < j->rq.md_cycles)
+        rc = membx_md_step(s, j->rq.md_steps);
+    else
+        rc = membx_mdas_cycle(s, j->rq.mdas_pairs, j->rq.mdas_k, j->rq.mdas_m, nullptr, nullptr, nullptr);
+    if (rc) return rc;
+    if (hipEventRecord(j->ev[slot][1], s->st) != hipSuccess) return MEMBX_E_DEVICE;
+    j->inflight.push_back(slot);
+    j->issued++;
+    return MEMBX_OK;
+}
+
+static void srv_free_job(membx_server* v, SrvJob* j)
+{
+    if (j->resident) {
+        if (j->s->st) (void)hipStreamSynchronize(j->s->st);
+        for (int q = 0; q < SRV_DEPTH; ++q)
+            for (int e = 0; e < 2; ++e)
+                if (j->ev[q][e]) (void)hipEventDestroy(j->ev[q][e]);
+        srv_release(v, j->off, j->span);
+    }
+    membx_sys_destroy(j->s);
+    delete j;
+}
+
+static void srv_close(membx_server* v, SrvJob* j)
+{
+    membx_job_result r{};
+    r.job_id = j->id;
+    r.status = j->status;
+    r.n_cycles = j->done;
+    r.n_beads = j->s->h.N;
+    r.submit_s = j->t_submit;
+    r.admit_s = j->t_admit;
+    r.cycle_ms_p50 = pct(j->cyc, 0.50);
+    r.cycle_ms_p99 = pct(j->cyc, 0.99);
+    r.cycle_ms_max = pct(j->cyc, 1.0);
+    if (j->status == MEMBX_OK) {
+        membx_energy e{};
+        int32_t rc = membx_energies(j->s, &e);
+        long long ctr[NCTR] = { 0, 0, 0, 0 };
+        const long long* dctr = j->s->mixed() ? j->s->df.ctr : j->s->dd.ctr;
+        if (hipMemcpy(ctr, dctr, sizeof(ctr), hipMemcpyDeviceToHost) != hipSuccess) rc = MEMBX_E_DEVICE;
+        r.status = rc;
+        r.potential = e.potential;
+        r.pairs_in_cutoff = e.n_pairs_in_cutoff;
+        r.fe_count = e.fe_count;
+        r.md_steps = ctr[CT_STEP];
+        r.mdas_accepted = (int32_t)ctr[CT_MDAS_ACC];
+    }
+    r.finish_s = v->now();
+    v->finished.push_back(r);
+    srv_free_job(v, j);
+}
+
+int32_t membx_server_poll(membx_server* v, membx_job_result* out, int32_t cap, int32_t* n_out,
+                          int32_t* n_resident, int32_t* n_waiting)
+{
+    if (!v || cap < 0 || (cap > 0 && !out)) return MEMBX_E_INVAL;
+    // 1. collect finished cycles; close finished jobs
+    for (size_t q = 0; q < v->active.size();) {
+        SrvJob* j = v->active[q];
+        while (!j->inflight.empty()) {
+            const int slot = j->inflight.front();
+            const hipError_t e = hipEventQuery(j->ev[slot][1]);
+            if (e == hipErrorNotReady) break;
+            if (e != hipSuccess) { j->status = MEMBX_E_DEVICE; j->inflight.clear(); break; }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, j->ev[slot][0], j->ev[slot][1]);
+            j->cyc.push_back(ms);
+            v->cycles.push_back(ms);
+            j->inflight.pop_front();
+            j->done++;
+        }
+        const bool over = j->inflight.empty() && (j->done >= j->total || j->status != MEMBX_OK);
+        if (over) {
+            v->active.erase(v->active.begin() + q);
+            srv_close(v, j);
+        } else {
+            ++q;
+        }
+    }
+    // 2. admit waiting jobs in order while their blocks fit
+    while (!v->queue.empty()) {
+        SrvJob* j = v->queue.front();
+        size_t off = 0;
+        if (!srv_alloc(v, j->span, &off)) break;
+        v->queue.pop_front();
+        j->off = off;
+        j->resident = true;
+        j->t_admit = v->now();
+        const int32_t rc = srv_admit(v, j);
+        if (rc) {
+            j->status = rc;
+            v->err = "admission failed: " + j->s->err;
+            srv_close(v, j);
+            continue;
+        }
+        v->active.push_back(j);
+    }
+    // 3. keep up to SRV_DEPTH cycles in flight per job
+    for (SrvJob* j : v->active)
+        while (j->status == MEMBX_OK && j->issued < j->total && (int)j->inflight.size() < SRV_DEPTH) {
+            const int32_t rc = srv_issue(j);
+            if (rc) { j->status = rc; v->err = j->s->err; }
+        }
+    int32_t n = 0;
+    while (n < cap && !v->finished.empty()) {
+        out[n++] = v->finished.front();
+        v->finished.pop_front();
+    }
+    if (n_out) *n_out = n;
+    if (n_resident) *n_resident = (int32_t)v->active.size();
+    if (n_waiting) *n_waiting = (int32_t)v->queue.size();
+    return MEMBX_OK;
+}
+
+int32_t membx_server_cycle_times(membx_server* v, float* out, int64_t cap, int64_t* n)
+{
+    if (!v || cap < 0 || (cap > 0 && !out)) return MEMBX_E_INVAL;
+    const int64_t m = std::min<int64_t>(cap, (int64_t)v->cycles.size());
+    for (int64_t q = 0; q < m; ++q) out[q] = v->cycles[q];
+    if (n) *n = (int64_t)v->cycles.size();
+    return MEMBX_OK;
+}
+
+int32_t membx_server_destroy(membx_server* v)
+{
+    if (!v) return MEMBX_OK;
+    for (SrvJob* j : v->active) srv_free_job(v, j);
+    for (SrvJob* j : v->queue) srv_free_job(v, j);
+    delete v;
+    return MEMBX_OK;
+}
+
+const char* membx_server_last_error(const membx_server* v) { return v ? v->err.c_str() : ""; }

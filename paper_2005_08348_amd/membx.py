@@ -65,6 +65,21 @@ class Energy(C.Structure):
                 ("max_displacement", C.c_double)]
 
 
+class Request(C.Structure):
+    _fields_ = [("minimize_iters", C.c_int32),
+                ("md_cycles", C.c_int32), ("md_steps", C.c_int32), ("mdas_cycles", C.c_int32),
+                ("mdas_pairs", C.c_int32), ("mdas_k", C.c_int32), ("mdas_m", C.c_int32)]
+
+
+class JobResult(C.Structure):
+    _fields_ = [("job_id", C.c_int64), ("status", C.c_int32), ("n_cycles", C.c_int32),
+                ("mdas_accepted", C.c_int32), ("n_beads", C.c_int32),
+                ("submit_s", C.c_double), ("admit_s", C.c_double), ("finish_s", C.c_double),
+                ("cycle_ms_p50", C.c_double), ("cycle_ms_p99", C.c_double),
+                ("cycle_ms_max", C.c_double), ("md_steps", C.c_int64), ("fe_count", C.c_int64),
+                ("pairs_in_cutoff", C.c_int64), ("potential", C.c_double)]
+
+
 class Trial(C.Structure):
     _fields_ = [("draw", C.c_int32), ("mol_x", C.c_int32), ("mol_y", C.c_int32),
                 ("accepted", C.c_int32), ("delta_u", C.c_double), ("u", C.c_double)]
@@ -106,6 +121,13 @@ def lib():
             "membx_kernel_timing": ([vp, i32], i32),
             "membx_kernel_time": ([vp, C.POINTER(i64), C.POINTER(dp)], i32),
             "membx_kernel_bench": ([vp, i32, C.POINTER(dp)], i32),
+            "membx_server_create": ([vp, u64, C.POINTER(vp)], i32),
+            "membx_server_submit": ([vp, vp, C.POINTER(Request), C.POINTER(i64)], i32),
+            "membx_server_poll": ([vp, C.POINTER(JobResult), i32, C.POINTER(i32), C.POINTER(i32),
+                                   C.POINTER(i32)], i32),
+            "membx_server_cycle_times": ([vp, C.POINTER(C.c_float), i64, C.POINTER(i64)], i32),
+            "membx_server_destroy": ([vp], i32),
+            "membx_server_last_error": ([vp], C.c_char_p),
             "membx_last_error": ([vp], C.c_char_p),
             "membx_status": ([vp], i32),
             "membx_calib_copy": ([vp, vp, vp, u64], i32),
@@ -355,3 +377,62 @@ class System:
     def calib_copy(self, dst, src, nbytes):
         _check(lib().membx_calib_copy(self.h, C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()),
                                       int(nbytes)), self.h)
+
+
+class Server:
+    """Many membrane systems resident in one device arena (C-ABI serving loop).
+
+    ``submit`` queues a job (a system plus a request); ``poll`` advances every
+    job without blocking and returns the results of jobs that finished."""
+
+    def __init__(self, budget_bytes, device="cuda:0"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("membx needs a GPU (no CPU fallback)")
+        self.device = torch.device(device)
+        self.arena = torch.empty(int(budget_bytes) + 256, dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize(self.device)
+        h = C.c_void_p()
+        rc = lib().membx_server_create(C.c_void_p(self.arena.data_ptr()), int(budget_bytes) + 256,
+                                       C.byref(h))
+        if rc:
+            raise MembxError(rc, "server creation failed")
+        self.h = h
+        self._keep = {}
+
+    def _err(self, rc):
+        if rc:
+            raise MembxError(rc, lib().membx_server_last_error(self.h).decode())
+
+    def submit(self, system, minimize_iters=100, md_cycles=4, md_steps=50, mdas_cycles=20,
+               mdas_pairs=8, mdas_k=50, mdas_m=1, precision="mixed", **tuning):
+        b = _DescBuilder(system, MIXED if precision == "mixed" else FP64, *_tuning(tuning))
+        rq = Request(minimize_iters, md_cycles, md_steps, mdas_cycles, mdas_pairs, mdas_k, mdas_m)
+        jid = C.c_int64()
+        self._err(lib().membx_server_submit(self.h, C.byref(b.desc), C.byref(rq), C.byref(jid)))
+        return int(jid.value)
+
+    def poll(self, cap=64):
+        out = (JobResult * cap)()
+        n, nr, nw = C.c_int32(), C.c_int32(), C.c_int32()
+        self._err(lib().membx_server_poll(self.h, out, cap, C.byref(n), C.byref(nr), C.byref(nw)))
+        res = [{k: getattr(out[q], k) for k, _ in JobResult._fields_} for q in range(n.value)]
+        return res, nr.value, nw.value
+
+    def cycle_times(self):
+        n = C.c_int64()
+        self._err(lib().membx_server_cycle_times(self.h, None, 0, C.byref(n)))
+        buf = (C.c_float * max(1, n.value))()
+        self._err(lib().membx_server_cycle_times(self.h, buf, n.value, C.byref(n)))
+        return np.frombuffer(buf, dtype=np.float32, count=n.value).copy()
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().membx_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
