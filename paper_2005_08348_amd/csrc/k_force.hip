@@ -6,9 +6,9 @@
 // Pair forces are not a dense contraction, so the kernel runs on the vector
 // ALUs: LPB lanes of a wave64 share one i bead and walk its full
 // (both-direction) Verlet list.  The kernel is organised around memory
-// latency: a lane issues all its list reads (one contiguous 256-byte block
-// per wave each, the list is tiled) and its bonded record together, then all
-// its coordinate gathers together, then computes.
+// latency: a lane issues its bonded records, then a batch of list reads (one
+// contiguous 256-byte block per wave each, the list is tiled), then all the
+// batch's coordinate gathers, then computes the batch without branches.
 // The j bead's coordinates and class come in one 16-byte gather and the pair
 // parameters from a class-by-class table in LDS.  The same lanes then
 // evaluate the bonded terms their bead takes part in (per-bead gather, no
@@ -21,36 +21,6 @@ namespace mbx {
 template <typename R> __device__ __forceinline__ R rsq(R x);
 template <> __device__ __forceinline__ float rsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
 template <> __device__ __forceinline__ double rsq<double>(double x) { return 1.0 / sqrt(x); }
-
-template <typename R, bool EN>
-__device__ __forceinline__ void pair_force(const Dev<R>& d, const V4<R>* __restrict__ rowF,
-                                           const V4<R>* __restrict__ rowE, R dx, R dy, R dz,
-                                           R wj, R& fx, R& fy, R& fz, double& elj,
-                                           double& erf, int& np)
-{
-    R r2 = dx * dx + dy * dy + dz * dz;
-    int cj = cls_of<R>(wj);
-    V4<R> p = rowF[cj];
-    R rinv = rsq<R>(r2);
-    R rinv2 = rinv * rinv;
-    R rinv6 = rinv2 * rinv2 * rinv2;
-    R fs = (p.y * rinv6 - p.x) * (rinv6 * rinv2) + (p.z * (rinv * rinv2) - p.w);
-    bool in = r2 < d.rc2;
-    fs = in ? fs : (R)0;
-    fx += fs * dx;
-    fy += fs * dy;
-    fz += fs * dz;
-    if (EN) {
-        V4<R> q = rowE[cj];
-        R vlj = (q.y * rinv6 - q.x) * rinv6 - q.w;
-        R vrf = q.z * (rinv + d.krf * r2 - d.crf);
-        if (in) {
-            elj += (double)vlj;
-            erf += (double)vrf;
-            np += 1;
-        }
-    }
-}
 
 // Exact minimum-image separation for bonded partners: the coordinate near
 // the top face is shifted down by L first (exact since it is >= L/2).
@@ -136,7 +106,7 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part)
     const bool valid = i < d.N;
     const V4<R> pi = valid ? d.posq[i] : V4<R>{ 0, 0, 0, 0 };
     const int ci = valid ? cls_of<R>(pi.w) : 0;
-    const int n0 = valid ? d.nseg0[i] : 0, n1 = valid ? d.ncnt[i] : 0;
+    const int n1 = valid ? d.ncnt[i] : 0;
     const V4<R>* rowF = tf + ci * MAXCLS;
     const V4<R>* rowE = EN ? te + ci * MAXCLS : tf;
     R fx = 0, fy = 0, fz = 0;
@@ -148,50 +118,72 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part)
     const size_t lane_base = (size_t)(ii / BG) * ((size_t)d.Kcap * BG) + (size_t)(ii % BG) * LPB + s;
     const int* __restrict__ nb = d.nbr + lane_base;
     const V4<R>* __restrict__ P = d.posq;
-    // first batch: the list entries (read unconditionally: they lie inside the
-    // bead's tile) and the bonded record are loaded together with the counts
-    constexpr int B = (12 * LPB <= 96) ? 12 : 96 / LPB;
-    int jj[B];
-#pragma unroll
-    for (int b = 0; b < B; ++b) jj[b] = nb[(size_t)b * 64];
-    // bonded records: lane s takes terms s, s + LPB, ... of its bead
+    // bonded records (lane s takes terms s, s + LPB, ... of its bead) and the
+    // partner coordinates, issued before the list walk
     constexpr int TPL = (MAXBT + LPB - 1) / LPB;
     int4 bt[TPL];
 #pragma unroll
     for (int u = 0; u < TPL; ++u)
         bt[u] = (s + u * LPB < MAXBT) ? d.bslot[(size_t)ii * MAXBT + s + u * LPB]
                                       : make_int4(-1, ii, ii, 0);
-    const int m1n = n1 > s ? (n1 - s + LPB - 1) / LPB : 0;
-    // second level: gathers of the j coordinates (self for unused entries)
-    V4<R> q[B];
-#pragma unroll
-    for (int b = 0; b < B; ++b) q[b] = P[b < m1n ? (jj[b] & JMASK) : ii];
     V4<R> b1[TPL], b2[TPL];
 #pragma unroll
     for (int u = 0; u < TPL; ++u) { b1[u] = P[bt[u].y]; b2[u] = P[bt[u].z]; }
+    // list walk in batches of B entries per lane, branch-free inside a batch:
+    // all list reads (clamped to the bead's tile), then all coordinate
+    // gathers (the bead itself for unused slots), then the pair terms with
+    // their LDS parameter reads in flight together
+    constexpr int B = sizeof(R) == 8 ? 6 : ((12 * LPB <= 96) ? 12 : 96 / LPB);
+    const int m1n = n1 > s ? (n1 - s + LPB - 1) / LPB : 0;
+    const int mcap = d.Kcap / LPB;
+    for (int m0 = 0; m0 < m1n; m0 += B) {
+        int jj[B];
 #pragma unroll
-    for (int b = 0; b < B; ++b) {
-        if (b < m1n) {
-            const int code = (int)((unsigned)jj[b] >> CODE_SHIFT);
+        for (int b = 0; b < B; ++b) jj[b] = nb[(size_t)min(m0 + b, mcap - 1) * 64];
+        V4<R> q[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) q[b] = P[m0 + b < m1n ? (jj[b] & JMASK) : ii];
+        // i-image shifts: decoded only in waves that hold a shifted entry
+        bool shifted = false;
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+            shifted |= (m0 + b < m1n) && ((unsigned)jj[b] >> CODE_SHIFT) != 0u;
+        const bool wave_shift = __ballot(shifted) != 0ull;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const bool live = m0 + b < m1n;
             R xs = pi.x, ys = pi.y, zs = pi.z;
-            if (code) {
+            if (wave_shift) {
+                const int code = live ? (int)((unsigned)jj[b] >> CODE_SHIFT) : 0;
                 if (code & 1) xs -= d.L[0];
                 if (code & 2) ys -= d.L[1];
                 if (code & 4) zs -= d.L[2];
             }
-            pair_force<R, EN>(d, rowF, rowE, xs - q[b].x, ys - q[b].y, zs - q[b].z, q[b].w, fx, fy,
-                              fz, elj, erf, np);
+            const R dx = xs - q[b].x, dy = ys - q[b].y, dz = zs - q[b].z;
+            const R r2 = dx * dx + dy * dy + dz * dz;
+            // unused slots hold the bead itself (r2 = 0): masked, kept off rsq(0)
+            const bool in = live && r2 < d.rc2;
+            const R r2s = in ? r2 : (R)1;
+            const R rinv = rsq<R>(r2s);
+            const R rinv2 = rinv * rinv;
+            const R rinv6 = rinv2 * rinv2 * rinv2;
+            const V4<R> p = rowF[cls_of<R>(q[b].w)];
+            R fs = (p.y * rinv6 - p.x) * (rinv6 * rinv2) + (p.z * (rinv * rinv2) - p.w);
+            fs = in ? fs : (R)0;
+            fx += fs * dx;
+            fy += fs * dy;
+            fz += fs * dz;
+            if (EN) {
+                const V4<R> e = rowE[cls_of<R>(q[b].w)];
+                const R vlj = (e.y * rinv6 - e.x) * rinv6 - e.w;
+                const R vrf = e.z * (rinv + d.krf * r2s - d.crf);
+                if (in) {
+                    elj += (double)vlj;
+                    erf += (double)vrf;
+                    np += 1;
+                }
+            }
         }
-    }
-    // rare: lists longer than one batch
-    for (int m = B; m < m1n; ++m) {
-        const int e = nb[(size_t)m * 64];
-        const int j = e & JMASK, code = (int)((unsigned)e >> CODE_SHIFT);
-        const V4<R> pj = P[j];
-        const R xs = (code & 1) ? pi.x - d.L[0] : pi.x;
-        const R ys = (code & 2) ? pi.y - d.L[1] : pi.y;
-        const R zs = (code & 4) ? pi.z - d.L[2] : pi.z;
-        pair_force<R, EN>(d, rowF, rowE, xs - pj.x, ys - pj.y, zs - pj.z, pj.w, fx, fy, fz, elj, erf, np);
     }
     // bonded terms of bead i
 #pragma unroll

@@ -312,66 +312,58 @@ __device__ __forceinline__ bool within_d(double xi, double yi, double zi, double
 
 constexpr int LB = 256;   // threads per cell
 constexpr int HS = 12;    // LDS hit slots per lane (single-pass path)
+constexpr int LU = 4;     // candidates per lane per round (LDS reads in flight)
 template <typename R> struct CandCap { static constexpr int v = 768; };
 template <> struct CandCap<double> { static constexpr int v = 512; };
 
-// List build, one work-group per cell.  The candidates of the 27 neighbour
-// cells (with the i-shift code of their cell) are staged in LDS; each bead of
-// the cell owns Q lanes that split the candidates.  Hits go to per-lane LDS
-// buffers and are written out in a fixed order (lane q of bead i after lanes
-// 0..q-1; unshifted entries before shifted ones), so the lists are
-// deterministic.  If a buffer overflows (very crowded cells) the cell falls
-// back to two passes: count, then test again and write in place.
+// Exact test of one entry: float64 from the stored coordinates, the i bead
+// shifted down by L along the entry's code axes (exact), r^2 without
+// contraction.
 template <typename R>
-__device__ __forceinline__ bool cand_hit(const Dev<R>& d, const V4<R>& pi, const V4<R>& pj, int code)
+__device__ __forceinline__ bool exact_in(const Dev<R>& d, const V4<R>& pi, int ent)
 {
+    const int j = ent & JMASK, code = (int)((unsigned)ent >> CODE_SHIFT);
+    const V4<R> pj = d.posq[j];
     const R xs = (code & 1) ? pi.x - d.L[0] : pi.x;
     const R ys = (code & 2) ? pi.y - d.L[1] : pi.y;
     const R zs = (code & 4) ? pi.z - d.L[2] : pi.z;
-    if (sizeof(R) == 4) {
-        R dx = xs - pj.x, dy = ys - pj.y, dz = zs - pj.z;
-        float r2f = (float)(dx * dx + dy * dy + dz * dz);
-        if (r2f < d.rl2f_lo) return true;
-        if (r2f > d.rl2f_hi) return false;
-    }
     return within_d((double)xs, (double)ys, (double)zs, (double)pj.x, (double)pj.y, (double)pj.z,
                     d.rl2d);
 }
 
-// one candidate test: float64-exact r^2 < r_list^2 and not bonded
+// One candidate: prefilter in R on the candidate image stored in LDS (the j
+// bead shifted UP by L along the code axes, rounded): below rl2_lo a hit,
+// above rl2_hi a miss, the band in between decided exactly.  Bonded partners
+// and the bead itself are excluded through the bead's exclusion mask.
 template <typename R>
-__device__ __forceinline__ bool list_hit(const Dev<R>& d, const V4<R>& pi, int oi, unsigned exm,
-                                         int i, const V4<R>& pj, int code, int ent)
+__device__ __forceinline__ bool cand_in(const Dev<R>& d, const V4<R>& pi, int oi, unsigned exm,
+                                        const V4<R>& pj, int ent)
 {
-    const R xs = (code & 1) ? pi.x - d.L[0] : pi.x;
-    const R ys = (code & 2) ? pi.y - d.L[1] : pi.y;
-    const R zs = (code & 4) ? pi.z - d.L[2] : pi.z;
-    bool in;
-    if (sizeof(R) == 4) {
-        const R dx = xs - pj.x, dy = ys - pj.y, dz = zs - pj.z;
-        const float r2f = (float)(dx * dx + dy * dy + dz * dz);
-        in = r2f < d.rl2f_lo;
-        if (!in && !(r2f > d.rl2f_hi))
-            in = within_d((double)xs, (double)ys, (double)zs, (double)pj.x, (double)pj.y,
-                          (double)pj.z, d.rl2d);
-    } else {
-        in = within_d((double)xs, (double)ys, (double)zs, (double)pj.x, (double)pj.y,
-                      (double)pj.z, d.rl2d);
-    }
+    const R dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+    const R r2 = dx * dx + dy * dy + dz * dz;
+    bool in = r2 < d.rl2_lo;
+    if (!in && !(r2 > d.rl2_hi)) in = exact_in(d, pi, ent);
     const unsigned rel = (unsigned)(cls_of<R>(pj.w) - oi + 16);
-    const bool bonded = rel < 32u && ((exm >> rel) & 1u);
-    return in && !bonded && (ent & JMASK) != i;
+    return in && !(rel < 32u && ((exm >> rel) & 1u));
 }
 
+// List build, one work-group per cell.  The candidates of the 27 neighbour
+// cells are staged in LDS (image position, bead id, entry = slot | code << 29
+// with code the axes along which the i bead is shifted); each bead of the
+// cell owns Q lanes that split the candidates.  Hits go to per-lane LDS
+// buffers and are written out in a fixed order (lane q of bead i after lanes
+// 0..q-1), so the lists are deterministic.  If a buffer overflows (very
+// crowded cells) the cell falls back to two passes: count, then test again
+// and write in place.
 template <typename R>
 __global__ __launch_bounds__(LB) void k_list(Dev<R> d)
 {
     constexpr int CMAX = CandCap<R>::v;
-    __shared__ V4<R> cpos[CMAX];      // w = bead id of the candidate (int bits)
-    __shared__ int cjs[CMAX];         // entry value: slot | code << 29
+    __shared__ V4<R> cpos[CMAX + 1];  // + a sentinel that never hits
+    __shared__ int cjs[CMAX + 1];
     __shared__ int hits[LB * (HS + 1)];
     __shared__ int off[28], jst[27], cod[27];
-    __shared__ int cnt0[LB], cnt1[LB];
+    __shared__ int cnt[LB];
     const int cell = blockIdx.x;
     const int t = threadIdx.x;
     const int Kc = d.Kcap;
@@ -389,6 +381,11 @@ __global__ __launch_bounds__(LB) void k_list(Dev<R> d)
         jst[t] = d.ext_start[e];
         off[t + 1] = d.ext_cnt[e];
         cod[t] = code;
+    }
+    if (t == 32) {
+        const R far = (R)1e15;
+        cpos[CMAX] = V4<R>{ far, far, far, cls_to<R>(-(1 << 20)) };
+        cjs[CMAX] = 0;
     }
     __syncthreads();
     if (t == 0) {
@@ -421,6 +418,9 @@ __global__ __launch_bounds__(LB) void k_list(Dev<R> d)
                 const int c = t + (u0 + u) * LB;
                 if (c < nc) {
                     V4<R> p = ps[u];
+                    if (cs[u] & 1) p.x += d.L[0];
+                    if (cs[u] & 2) p.y += d.L[1];
+                    if (cs[u] & 4) p.z += d.L[2];
                     p.w = cls_to<R>(oj[u]);
                     cpos[c] = p;
                     cjs[c] = js[u] | (cs[u] << CODE_SHIFT);
@@ -439,61 +439,57 @@ __global__ __launch_bounds__(LB) void k_list(Dev<R> d)
         const int oi = d.orig[i];
         const unsigned exm = d.exmask[oi];
         const size_t ibase = nbr_base(i, Kc, d.lpb_shift, d.bg_shift);
-        // single pass: test every candidate once, hits to per-lane LDS
-        // buffers (unshifted entries upward, shifted downward; a hit past the
-        // buffer sets the overflow flag and lands in the scratch slot HS)
-        int n0 = 0, n1 = 0;
+        // single pass: every candidate tested once, hits to the lane's LDS
+        // buffer (a hit past the buffer sets the overflow flag and lands in
+        // the scratch slot HS)
+        int nh = 0;
         bool lane_ovf = false;
         for (int cb = 0; cb < C; cb += CMAX) {
             const int nc = min(CMAX, C - cb);
             if (!(one_round && ib > 0)) stage(cb, nc);
             const int nu = (nc + Q - 1) / Q;
-            for (int u = 0; u < nu; ++u) {
-                const int c = q + u * Q;
-                const bool vc = act && c < nc;
-                const int cc = vc ? c : 0;
-                const V4<R> pj = cpos[cc];
-                const int ent = cjs[cc];
-                const int code = (int)((unsigned)ent >> CODE_SHIFT);
-                const bool hit = vc && list_hit(d, pi, oi, exm, i, pj, code, ent);
-                const bool z = code == 0;
-                const int nn = n0 + n1;
-                const int pos = (hit && nn < HS) ? (z ? n0 : HS - 1 - n1) : HS;
-                hits[t * (HS + 1) + pos] = ent;
-                lane_ovf |= hit && nn >= HS;
-                n0 += (hit && z) ? 1 : 0;
-                n1 += (hit && !z) ? 1 : 0;
+            for (int u0 = 0; u0 < nu; u0 += LU) {
+                V4<R> pj[LU];
+                int en[LU];
+#pragma unroll
+                for (int k = 0; k < LU; ++k) {
+                    const int c = q + (u0 + k) * Q;
+                    const int cc = (act && c < nc) ? c : CMAX;
+                    pj[k] = cpos[cc];
+                    en[k] = cjs[cc];
+                }
+#pragma unroll
+                for (int k = 0; k < LU; ++k) {
+                    const bool hit = cand_in(d, pi, oi, exm, pj[k], en[k]);
+                    hits[t * (HS + 1) + ((hit && nh < HS) ? nh : HS)] = en[k];
+                    lane_ovf |= hit && nh >= HS;
+                    nh += hit ? 1 : 0;
+                }
             }
         }
         const bool ovf_any = __syncthreads_or(lane_ovf ? 1 : 0) != 0;
-        cnt0[t] = act ? n0 : 0;
-        cnt1[t] = act ? n1 : 0;
+        cnt[t] = act ? nh : 0;
         __syncthreads();
-        int b0 = 0, b1 = 0, t0 = 0, t1 = 0;
+        int b0 = 0, tot = 0;
         if (act) {
             for (int qq = 0; qq < Q; ++qq) {
-                const int c0 = cnt0[li * Q + qq], c1 = cnt1[li * Q + qq];
-                if (qq < q) { b0 += c0; b1 += c1; }
-                t0 += c0; t1 += c1;
+                const int c0 = cnt[li * Q + qq];
+                if (qq < q) b0 += c0;
+                tot += c0;
             }
             if (q == 0) {
-                d.nseg0[i] = min(t0, Kc);
-                d.ncnt[i] = min(t0 + t1, Kc);
-                if (t0 + t1 > Kc) atomicOr(&d.flags[FL_LIST_OVF], 1);
+                d.nseg0[i] = 0;
+                d.ncnt[i] = min(tot, Kc);
+                if (tot > Kc) atomicOr(&d.flags[FL_LIST_OVF], 1);
             }
         }
         if (!ovf_any) {
-            if (act) {
-                for (int k = 0; k < n0; ++k)
-                    if (b0 + k < Kc)
-                        d.nbr[ibase + nbr_koff(b0 + k, d.lpb_shift)] = hits[t * (HS + 1) + k];
-                for (int k = 0; k < n1; ++k)
-                    if (t0 + b1 + k < Kc)
-                        d.nbr[ibase + nbr_koff(t0 + b1 + k, d.lpb_shift)] = hits[t * (HS + 1) + HS - 1 - k];
-            }
+            if (act)
+                for (int k = 0; k < nh; ++k)
+                    if (b0 + k < Kc) d.nbr[ibase + nbr_koff(b0 + k, d.lpb_shift)] = hits[t * (HS + 1) + k];
         } else {
             // crowded cell: test again and write in place at the known offsets
-            int m0 = 0, m1 = 0;
+            int m0 = 0;
             for (int cb = 0; cb < C; cb += CMAX) {
                 const int nc = min(CMAX, C - cb);
                 if (!one_round) stage(cb, nc);
@@ -501,11 +497,9 @@ __global__ __launch_bounds__(LB) void k_list(Dev<R> d)
                 for (int u = 0; u < nu; ++u) {
                     const int c = q + u * Q;
                     if (!(act && c < nc)) continue;
-                    const V4<R> pj = cpos[c];
                     const int ent = cjs[c];
-                    const int code = (int)((unsigned)ent >> CODE_SHIFT);
-                    if (!list_hit(d, pi, oi, exm, i, pj, code, ent)) continue;
-                    const int k = code == 0 ? b0 + m0++ : t0 + b1 + m1++;
+                    if (!cand_in(d, pi, oi, exm, cpos[c], ent)) continue;
+                    const int k = b0 + m0++;
                     if (k < Kc) d.nbr[ibase + nbr_koff(k, d.lpb_shift)] = ent;
                 }
             }

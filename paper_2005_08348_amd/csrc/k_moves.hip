@@ -602,12 +602,11 @@ __global__ __launch_bounds__(64) void k_du_bead(Dev<R> d, Mv m)
     const int ci = cls_of<R>(pi.w);
     const int mk = d.alch[i];
     const int ci2 = mk & 0xff, tag = mk >> 8;
-    const int n0 = d.nseg0[i], n1 = d.ncnt[i];
+    const int n1 = d.ncnt[i];
     double du = 0.0;
     for (int k = lane; k < n1; k += 64) {
         int en = d.nbr[nbr_index(i, k, d.Kcap, d.lpb)];
         int j = en & JMASK, code = (int)((unsigned)en >> CODE_SHIFT);
-        if (k < n0) code = 0;
         V4<R> pj = d.posq[j];
         int o = owner_of(d.ghost_owner, d.N, j);
         int cj = cls_of<R>(d.posq[o].w);
@@ -711,12 +710,11 @@ __global__ __launch_bounds__(WG) void k_dforce(Dev<R> d, Mv m, R scale)
         const int ci = cls_of<R>(pi.w);
         const int mk = d.alch[i];
         const int ci2 = mk >= 0 ? (mk & 0xff) : ci;
-        const int n0 = d.nseg0[i], n1 = d.ncnt[i];
+        const int n1 = d.ncnt[i];
         for (int k = s; k < n1; k += 8) {
             int en = d.nbr[nbr_index(i, k, d.Kcap, d.lpb)];
             int j = en & JMASK, code = (int)((unsigned)en >> CODE_SHIFT);
-            if (k < n0) code = 0;
-            int o = owner_of(d.ghost_owner, d.N, j);
+                int o = owner_of(d.ghost_owner, d.N, j);
             int mj = d.alch[o];
             if (mk < 0 && mj < 0) continue;
             V4<R> pj = d.posq[j];

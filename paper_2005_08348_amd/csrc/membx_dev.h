@@ -119,7 +119,7 @@ template <typename R> struct Dev {
     double Ld[3];
     R rc2, krf, crf;
     double rc2d, rl2d;
-    float rl2f_lo, rl2f_hi;
+    R rl2_lo, rl2_hi;     // list prefilter band around (r_cut + skin)^2
     R skin_half2;
     // dynamics
     R dt, half_dt, c1, c2, kT;

@@ -427,6 +427,21 @@ static int32_t fail(membx_sys* s, int32_t code, const std::string& m)
             return fail(s, MEMBX_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// Prefilter band of the list build around r_list^2: the candidate images are
+// stored shifted by +L (rounded, error <= ulp(L)) and r^2 is evaluated in R;
+// candidates inside the band are decided by the exact float64 test.
+template <typename R>
+static void set_list_band(Dev<R>& d, const Host& h)
+{
+    const double rl = h.rc + h.skin, rl2 = rl * rl;
+    const double Lmax = std::max(h.box[0], std::max(h.box[1], h.box[2]));
+    const bool f32 = sizeof(R) == 4;
+    const double dr = Lmax * (f32 ? std::ldexp(1.0, -22) : std::ldexp(1.0, -51));
+    const double margin = rl2 * (f32 ? 4e-6 : 1e-12) + 2.5 * rl * dr;
+    d.rl2_lo = (R)(rl2 - margin);
+    d.rl2_hi = (R)(rl2 + margin);
+}
+
 template <typename R>
 static size_t layout(membx_sys* s, Dev<R>& d, Mv& m, char* base)
 {
@@ -549,8 +564,7 @@ static size_t layout(membx_sys* s, Dev<R>& d, Mv& m, char* base)
     d.rc2d = h.rc * h.rc;
     double rl = h.rc + h.skin;
     d.rl2d = rl * rl;
-    d.rl2f_lo = (float)(d.rl2d * (1.0 - 4e-6));
-    d.rl2f_hi = (float)(d.rl2d * (1.0 + 4e-6));
+    set_list_band(d, h);
     d.skin_half2 = (R)(0.25 * h.skin * h.skin);
     d.dt = (R)h.dt; d.half_dt = (R)(0.5 * h.dt);
     double c1 = std::exp(-h.gamma * h.dt);
@@ -855,7 +869,8 @@ static int32_t upload(membx_sys* s, const membx_desc* desc)
     UP(d.inv, ident);
     UP(d.alch, minus1);
     UP(d.excl, h.excl);
-    std::vector<unsigned> exm(h.N, 0u);
+    // bit (j - i + 16): bonded partner j; bit 16: the bead itself
+    std::vector<unsigned> exm(h.N, 1u << 16);
     for (int i = 0; i < h.N; ++i)
         for (int e = 0; e < MAXEXCL; ++e) {
             int j = h.excl[(size_t)i * MAXEXCL + e];
@@ -1364,8 +1379,7 @@ static int32_t retune_impl(membx_sys* s)
     d.bg_shift = 6 - d.lpb_shift;
     double rl = h.rc + h.skin;
     d.rl2d = rl * rl;
-    d.rl2f_lo = (float)(d.rl2d * (1.0 - 4e-6));
-    d.rl2f_hi = (float)(d.rl2d * (1.0 + 4e-6));
+    set_list_band(d, h);
     d.skin_half2 = (R)(0.25 * s->h.skin * s->h.skin);
     for (auto& kv : s->gcache) (void)hipGraphExecDestroy(kv.second);
     s->gcache.clear();
