@@ -90,9 +90,15 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// energies: partial[8 * block] = {lj, rf, pairs, bond, angle, kinetic}
-template <typename R, int LPB, bool EN>
-__global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part)
+// energies: partial[8 * block] = {lj, rf, pairs, bond, angle, kinetic}.
+// FUSE: the lane that owns bead i's force also moves the bead through the
+// next BAOAB step (its own force is all that step needs), writing the new
+// coordinates to pos_out (the other coordinate buffer: the neighbours' old
+// coordinates are still being read) and the velocity to vel_out.
+template <typename R, int LPB, bool EN, bool FUSE>
+__global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, R kick,
+                                           long long step_off, V4<R>* pos_out, V4<R>* vel_out,
+                                           int stats)
 {
     __shared__ V4<R> tf[MAXCLS * MAXCLS];
     __shared__ V4<R> te[EN ? MAXCLS * MAXCLS : 1];
@@ -200,7 +206,18 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part)
         fz += __shfl_xor(fz, m);
     }
     if (!EN) {
-        if (valid && s == 0) d.frc[i] = V4<R>{ fx, fy, fz, (R)0 };
+        const bool own = valid && s == 0;
+        if (!FUSE) {
+            if (own) d.frc[i] = V4<R>{ fx, fy, fz, (R)0 };
+        } else {
+            float e2 = 0.f;
+            if (own) {
+                const V4<R> f{ fx, fy, fz, (R)0 };
+                d.frc[i] = f;
+                e2 = baoab_bead(d, i, pi, d.vel[i], f, kick, step_off, pos_out, vel_out);
+            }
+            if (stats) disp_stats(d, e2, own);
+        }
     } else {
         __shared__ double sh[6][WG / 64];
         double v[6] = { elj, erf, (double)np, eb, ea, ek };
@@ -248,11 +265,13 @@ __global__ void k_energy_final(const double* __restrict__ p, int nb, double* __r
 }
 
 // ----------------------------------------------------------------- launch
-template <typename R, int LPB, bool EN>
-static void nb_launch(const Dev<R>& d, double* part, hipStream_t st)
+template <typename R, int LPB, bool EN, bool FUSE>
+static void nb_launch(const Dev<R>& d, double* part, R kick, long long step_off, V4<R>* pos_out,
+                      V4<R>* vel_out, int stats, hipStream_t st)
 {
     int nthr = d.N * LPB;
-    hipLaunchKernelGGL((k_nb<R, LPB, EN>), dim3((nthr + WG - 1) / WG), dim3(WG), 0, st, d, part);
+    hipLaunchKernelGGL((k_nb<R, LPB, EN, FUSE>), dim3((nthr + WG - 1) / WG), dim3(WG), 0, st, d, part,
+                       kick, step_off, pos_out, vel_out, stats);
 }
 
 // forces (energy=false) or energies into part (energy=true); returns blocks
@@ -260,17 +279,31 @@ template <typename R>
 int launch_nonbonded(const Dev<R>& d, int lpb, bool energy, double* part, hipStream_t st)
 {
     switch (lpb * 2 + (energy ? 1 : 0)) {
-    case 2: nb_launch<R, 1, false>(d, part, st); break;
-    case 3: nb_launch<R, 1, true>(d, part, st); break;
-    case 4: nb_launch<R, 2, false>(d, part, st); break;
-    case 5: nb_launch<R, 2, true>(d, part, st); break;
-    case 8: nb_launch<R, 4, false>(d, part, st); break;
-    case 9: nb_launch<R, 4, true>(d, part, st); break;
-    case 16: nb_launch<R, 8, false>(d, part, st); break;
-    case 17: nb_launch<R, 8, true>(d, part, st); break;
+    case 2: nb_launch<R, 1, false, false>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
+    case 3: nb_launch<R, 1, true, false>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
+    case 4: nb_launch<R, 2, false, false>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
+    case 5: nb_launch<R, 2, true, false>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
+    case 8: nb_launch<R, 4, false, false>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
+    case 9: nb_launch<R, 4, true, false>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
+    case 16: nb_launch<R, 8, false, false>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
+    case 17: nb_launch<R, 8, true, false>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
     default: break;
     }
     return (d.N * lpb + WG - 1) / WG;
+}
+
+// forces followed by the next step's B-A-O-A for every bead (see k_nb)
+template <typename R>
+void launch_nonbonded_fused(const Dev<R>& d, int lpb, R kick, long long step_off, V4<R>* pos_out,
+                            V4<R>* vel_out, int stats, hipStream_t st)
+{
+    switch (lpb) {
+    case 1: nb_launch<R, 1, false, true>(d, nullptr, kick, step_off, pos_out, vel_out, stats, st); break;
+    case 2: nb_launch<R, 2, false, true>(d, nullptr, kick, step_off, pos_out, vel_out, stats, st); break;
+    case 4: nb_launch<R, 4, false, true>(d, nullptr, kick, step_off, pos_out, vel_out, stats, st); break;
+    case 8: nb_launch<R, 8, false, true>(d, nullptr, kick, step_off, pos_out, vel_out, stats, st); break;
+    default: break;
+    }
 }
 
 void launch_energy_final(const double* p, int nb, double* out, hipStream_t st)
@@ -280,5 +313,9 @@ void launch_energy_final(const double* p, int nb, double* out, hipStream_t st)
 
 template int launch_nonbonded<float>(const Dev<float>&, int, bool, double*, hipStream_t);
 template int launch_nonbonded<double>(const Dev<double>&, int, bool, double*, hipStream_t);
+template void launch_nonbonded_fused<float>(const Dev<float>&, int, float, long long, V4<float>*,
+                                            V4<float>*, int, hipStream_t);
+template void launch_nonbonded_fused<double>(const Dev<double>&, int, double, long long, V4<double>*,
+                                             V4<double>*, int, hipStream_t);
 
 }  // namespace mbx

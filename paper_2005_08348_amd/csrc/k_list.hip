@@ -313,7 +313,7 @@ __device__ __forceinline__ bool within_d(double xi, double yi, double zi, double
 constexpr int LB = 256;   // threads per cell
 constexpr int HS = 12;    // LDS hit slots per lane (single-pass path)
 constexpr int LU = 4;     // candidates per lane per round (LDS reads in flight)
-template <typename R> struct CandCap { static constexpr int v = 768; };
+template <typename R> struct CandCap { static constexpr int v = 1024; };
 template <> struct CandCap<double> { static constexpr int v = 512; };
 
 // Exact test of one entry: float64 from the stored coordinates, the i bead

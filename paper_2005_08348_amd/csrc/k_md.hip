@@ -5,57 +5,16 @@
 namespace mbx {
 
 // B (kick) + A + O + A of one BAOAB step, with the closing B of the previous
-// step folded into `kick` (dt instead of dt/2 inside a run of steps).
-// x at the last rebuild is compared to flag displacements beyond skin/2.
+// step folded into `kick` (dt instead of dt/2 inside a run of steps), in
+// place; x at the last rebuild is compared to flag displacements beyond
+// skin/2.
 template <typename R>
 __global__ __launch_bounds__(WG) void k_kick_drift(Dev<R> d, R kick, long long step_off)
 {
-    int i = blockIdx.x * WG + threadIdx.x;
-    float e2f = 0.f;
-    if (i < d.N) {
-    V4<R> p = d.posq[i], v = d.vel[i], f = d.frc[i];
-    const R im = v.w, h = d.half_dt;
-    v.x += kick * im * f.x; v.y += kick * im * f.y; v.z += kick * im * f.z;
-    p.x += h * v.x; p.y += h * v.y; p.z += h * v.z;
-    uint4 w = draw(d.seed, (uint32_t)d.orig[i], d.ctr[CT_STEP] + step_off, ST_LANGEVIN);
-    R g[3];
-    gauss3<R>(w, g);
-    const R sg = d.c2 * sqrt(d.kT * im);
-    v.x = d.c1 * v.x + sg * g[0];
-    v.y = d.c1 * v.y + sg * g[1];
-    v.z = d.c1 * v.z + sg * g[2];
-    p.x += h * v.x; p.y += h * v.y; p.z += h * v.z;
-    d.posq[i] = p;
-    d.vel[i] = v;
-    // refresh this bead's periodic images (exact shifts by -L)
-    const int gc = d.gcnt[i];
-    for (int q = 0; q < gc && q < 7; ++q) {
-        const int g = d.glist[i * 7 + q], code = d.ghost_code[g];
-        V4<R> pg = p;
-        if (code & 1) pg.x -= d.L[0];
-        if (code & 2) pg.y -= d.L[1];
-        if (code & 4) pg.z -= d.L[2];
-        d.posq[d.N + g] = pg;
-    }
-    V4<R> r = d.xref[i];
-    R ex = p.x - r.x, ey = p.y - r.y, ez = p.z - r.z;
-    e2f = (float)(ex * ex + ey * ey + ez * ez);
-    }
-    // beads beyond skin/2, and per block the largest squared displacement
-    // from the last rebuild seen so far
-    __shared__ float s_m2[WG / 64];
-    const unsigned long long over = __ballot(e2f > (float)d.skin_half2);
-    float m2 = e2f;
-    for (int o = 32; o > 0; o >>= 1) m2 = fmaxf(m2, __shfl_xor(m2, o, 64));
-    if ((threadIdx.x & 63) == 0) {
-        if (over) atomicAdd(&d.flags[FL_SKIN], __popcll(over));
-        s_m2[threadIdx.x >> 6] = m2;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < WG / 64; ++w) m2 = fmaxf(m2, s_m2[w]);
-        d.dmax_part[blockIdx.x] = fmaxf(d.dmax_part[blockIdx.x], m2);
-    }
+    const int i = blockIdx.x * WG + threadIdx.x;
+    float e2 = 0.f;
+    if (i < d.N) e2 = baoab_bead(d, i, d.posq[i], d.vel[i], d.frc[i], kick, step_off, d.posq, d.vel);
+    disp_stats(d, e2, i < d.N);
 }
 
 // closing half-kick of a run of steps; also advances the step counter

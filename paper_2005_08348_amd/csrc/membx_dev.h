@@ -129,7 +129,10 @@ template <typename R> struct Dev {
     int nc[3], ncell, ne[3], next;
     R inv_edge[3];
     // per-slot state (sorted order)
-    V4<R>* posq;     // [N + Gcap], w = class bits
+    V4<R>* posq;     // [N + Gcap], w = class bits (current coordinates)
+    V4<R>* posq_alt; // [N + Gcap] the other coordinate buffer: the force kernel
+                     // that also integrates reads posq and writes the new
+                     // coordinates here, then the two are exchanged
     V4<R>* vel;      // [N], w = 1/m
     V4<R>* frc;      // [N]
     V4<R>* xref;     // [N] positions at the last rebuild
@@ -160,7 +163,7 @@ template <typename R> struct Dev {
     int4* bslot;     // [N * 8] bonded terms of each slot with partner slots
                      // {role, slot 1, slot 2, parameter}; role -1 = unused
     int* scan_part;  // [2 * SCAN_BLOCKS + 2] block sums of the cell scans
-    float* dmax_part;  // [ceil(N / WG)] per integrator block: largest squared
+    float* dmax_part;  // [ceil(8 N / WG)] per integrator block: largest squared
                        // displacement from the last rebuild seen since a reset
     // neighbour list, tiled so that the LPB lanes of the 64/LPB beads a wave
     // handles read one contiguous 256-byte block per load (see nbr_index)
@@ -254,6 +257,64 @@ struct Mv {
     // snapshot of the per-slot state
     void* snap_posq; void* snap_vel; void* snap_frc; int* snap_orig;
 };
+
+// One bead through B (kick, folding in the closing B of the previous step) +
+// A + O (Ornstein-Uhlenbeck with Philox noise) + A of a BAOAB step; the new
+// coordinates go to pos_out (the bead's slot and its periodic images, which
+// are exact shifts by -L), the velocity to vel_out.  Returns the squared
+// displacement from the coordinates of the last list build.
+template <typename R>
+__device__ __forceinline__ float baoab_bead(const Dev<R>& d, int i, V4<R> p, V4<R> v, const V4<R>& f,
+                                            R kick, long long step_off, V4<R>* __restrict__ pos_out,
+                                            V4<R>* __restrict__ vel_out)
+{
+    const R im = v.w, h = d.half_dt;
+    v.x += kick * im * f.x; v.y += kick * im * f.y; v.z += kick * im * f.z;
+    p.x += h * v.x; p.y += h * v.y; p.z += h * v.z;
+    const uint4 w = draw(d.seed, (uint32_t)d.orig[i], d.ctr[CT_STEP] + step_off, ST_LANGEVIN);
+    R g[3];
+    gauss3<R>(w, g);
+    const R sg = d.c2 * sqrt(d.kT * im);
+    v.x = d.c1 * v.x + sg * g[0];
+    v.y = d.c1 * v.y + sg * g[1];
+    v.z = d.c1 * v.z + sg * g[2];
+    p.x += h * v.x; p.y += h * v.y; p.z += h * v.z;
+    pos_out[i] = p;
+    vel_out[i] = v;
+    const int gc = d.gcnt[i];
+    for (int q = 0; q < gc && q < 7; ++q) {
+        const int gi = d.glist[i * 7 + q], code = d.ghost_code[gi];
+        V4<R> pg = p;
+        if (code & 1) pg.x -= d.L[0];
+        if (code & 2) pg.y -= d.L[1];
+        if (code & 4) pg.z -= d.L[2];
+        pos_out[d.N + gi] = pg;
+    }
+    const V4<R> r = d.xref[i];
+    const R ex = p.x - r.x, ey = p.y - r.y, ez = p.z - r.z;
+    return (float)(ex * ex + ey * ey + ez * ez);
+}
+
+// Block-wide bookkeeping of the displacements (all threads call it): beads
+// beyond skin/2 are counted, and the block's largest squared displacement
+// raises its slot of dmax_part.
+template <typename R>
+__device__ __forceinline__ void disp_stats(const Dev<R>& d, float e2, bool counted)
+{
+    __shared__ float s_m2[WG / 64];
+    const unsigned long long over = __ballot(counted && e2 > (float)d.skin_half2);
+    float m2 = counted ? e2 : 0.f;
+    for (int o = 32; o > 0; o >>= 1) m2 = fmaxf(m2, __shfl_xor(m2, o, 64));
+    if ((threadIdx.x & 63) == 0) {
+        if (over) atomicAdd(&d.flags[FL_SKIN], __popcll(over));
+        s_m2[threadIdx.x >> 6] = m2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < WG / 64; ++w) m2 = fmaxf(m2, s_m2[w]);
+        d.dmax_part[blockIdx.x] = fmaxf(d.dmax_part[blockIdx.x], m2);
+    }
+}
 
 // Entry k of slot i's neighbour list: beads are grouped by 64/lpb, and
 // within a group entries are interleaved in blocks of lpb.

@@ -22,6 +22,8 @@ namespace mbx {
 template <typename R> void launch_rebuild(const Dev<R>&, hipStream_t);
 template <typename R> void launch_ghost_update(const Dev<R>&, hipStream_t);
 template <typename R> int launch_nonbonded(const Dev<R>&, int, bool, double*, hipStream_t);
+template <typename R>
+void launch_nonbonded_fused(const Dev<R>&, int, R, long long, V4<R>*, V4<R>*, int, hipStream_t);
 void launch_energy_final(const double*, int, double*, hipStream_t);
 template <typename R> void launch_kick_drift(const Dev<R>&, R, long long, hipStream_t);
 template <typename R> void launch_kick(const Dev<R>&, R, long long, hipStream_t);
@@ -404,6 +406,8 @@ struct membx_sys {
     double* xbuf = nullptr;  // [3N] export / import buffer
     int* ibuf = nullptr;     // [N]
     bool graphs = true;
+    bool fuse = true;        // force kernel integrates the next step (plain MD)
+    int par = 0;             // which coordinate buffer is current (flips per fused step)
     std::map<std::tuple<long long, int, int>, hipGraphExec_t> gcache;
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;
@@ -455,6 +459,7 @@ static size_t layout(membx_sys* s, Dev<R>& d, Mv& m, char* base)
     d.lpb_shift = h.lpb == 1 ? 0 : h.lpb == 2 ? 1 : h.lpb == 4 ? 2 : 3;
     d.bg_shift = 6 - d.lpb_shift;
     d.posq = a.take<V4<R>>(N + h.Gcap);
+    d.posq_alt = a.take<V4<R>>(N + h.Gcap);
     d.vel = a.take<V4<R>>(N);
     d.frc = a.take<V4<R>>(N);
     d.xref = a.take<V4<R>>(N);
@@ -474,7 +479,7 @@ static size_t layout(membx_sys* s, Dev<R>& d, Mv& m, char* base)
     d.orig_ext = a.take<int>(N + h.Gcap);
     d.bslot = a.take<int4>((size_t)N * MAXBT);
     d.scan_part = a.take<int>(2 * SCAN_BLOCKS + 2);
-    d.dmax_part = a.take<float>((size_t)(N + WG - 1) / WG);
+    d.dmax_part = a.take<float>(((size_t)N * 8 + WG - 1) / WG);
     d.nbr = a.take<int>((size_t)h.Kcap * Npad);
     d.ncnt = a.take<int>(N); d.nseg0 = a.take<int>(N);
     d.excl = a.take<int>((size_t)N * MAXEXCL);
@@ -611,6 +616,15 @@ static void forces(membx_sys* s, bool rebuilt)
     }
 }
 
+// Exchange the current and the other coordinate buffer.
+template <typename R>
+static void swap_coords(membx_sys* s)
+{
+    Dev<R>& d = dev<R>(s);
+    std::swap(d.posq, d.posq_alt);
+    s->par ^= 1;
+}
+
 struct Alch {
     double lam;
 };
@@ -636,14 +650,29 @@ static void steps_seq(membx_sys* s, long long n, const Alch* alch)
 {
     Dev<R>& d = dev<R>(s);
     const R h = (R)(0.5 * s->h.dt), full = (R)s->h.dt;
+    bool moved = false;   // the previous force pass already moved the beads
     for (long long k = 0; k < n; ++k) {
-        launch_kick_drift<R>(d, k == 0 ? h : full, k, s->st);
+        if (!moved) launch_kick_drift<R>(d, k == 0 ? h : full, k, s->st);
+        moved = false;
         bool rebuilt = false;
         if (++s->since >= s->h.R) { rebuild<R>(s); rebuilt = true; }
-        forces<R>(s, rebuilt);
-        if (alch) alch_terms<R>(s, rebuilt, alch->lam);
+        if (!alch && s->fuse && !s->timing && k + 1 < n) {
+            // forces of step k and B-A-O-A of step k + 1 in one pass
+            launch_nonbonded_fused<R>(d, s->h.lpb, full, k + 1, d.posq_alt, d.vel, 1, s->st);
+            swap_coords<R>(s);
+            moved = true;
+        } else {
+            forces<R>(s, rebuilt);
+            if (alch) alch_terms<R>(s, rebuilt, alch->lam);
+        }
     }
     launch_kick<R>(d, h, n, s->st);
+}
+
+// fused steps of a k-step sequence of plain MD (each flips the buffers)
+static long long fused_flips(const membx_sys* s, long long k)
+{
+    return (s->fuse && !s->timing && k > 1) ? k - 1 : 0;
 }
 
 template <typename R>
@@ -654,10 +683,11 @@ static int32_t md_steps(membx_sys* s, long long n)
     while (n > 0) {
         long long k = std::min(n, chunk);
         if (s->graphs && !s->timing) {
-            auto key = std::make_tuple(k, s->since, 0);
+            auto key = std::make_tuple(k, s->since, 2 + s->par);
             auto it = s->gcache.find(key);
             int since0 = s->since;
             long long nrb0 = s->n_rebuilds;
+            const int par0 = s->par;
             if (it == s->gcache.end()) {
                 hipGraph_t g;
                 if (hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal) != hipSuccess)
@@ -677,12 +707,14 @@ static int32_t md_steps(membx_sys* s, long long n)
                 // capture advanced the host mirrors; restore then replay below
                 s->since = since0;
                 s->n_rebuilds = nrb0;
+                if (s->par != par0) swap_coords<R>(s);
             }
             if (hipGraphLaunch(it->second, s->st) != hipSuccess)
                 return fail(s, MEMBX_E_DEVICE, "graph launch failed");
             // advance host mirrors as the sequence does
             for (long long q = 0; q < k; ++q)
                 if (++s->since >= s->h.R) { s->since = 0; s->n_rebuilds++; }
+            if (fused_flips(s, k) & 1) swap_coords<R>(s);
         } else {
             steps_seq<R>(s, k, nullptr);
         }
@@ -732,7 +764,7 @@ template <typename R>
 static int32_t swap_trials(membx_sys* s, int n_trials)
 {
     if (s->graphs && !s->timing) {
-        auto key = std::make_tuple((long long)n_trials, -1, 1);
+        auto key = std::make_tuple((long long)n_trials, -1 - s->par, 1);
         auto it = s->gcache.find(key);
         if (it == s->gcache.end()) {
             hipGraph_t g;
@@ -912,7 +944,7 @@ static int32_t upload(membx_sys* s, const membx_desc* desc)
     HCK(hipMemsetAsync(d.cell_cnt, 0, sizeof(int) * h.ncell_cap, st));
     HCK(hipMemsetAsync(d.cell_cur, 0, sizeof(int) * h.ncell_cap, st));
     HCK(hipMemsetAsync(d.gcnt, 0, sizeof(int) * h.N, st));
-    HCK(hipMemsetAsync(d.dmax_part, 0, sizeof(float) * ((h.N + WG - 1) / WG), st));
+    HCK(hipMemsetAsync(d.dmax_part, 0, sizeof(float) * (((size_t)h.N * 8 + WG - 1) / WG), st));
     HCK(hipMemsetAsync(m.hb_word, 0, sizeof(unsigned long long) * ((size_t)m.hb_mask + 1), st));
     HCK(hipMemsetAsync(m.mb_word, 0, sizeof(unsigned long long) * ((size_t)m.mb_mask + 1), st));
     HCK(hipMemsetAsync(m.ab_word, 0, sizeof(unsigned long long) * ((size_t)m.ab_mask + 1), st));
@@ -1118,7 +1150,7 @@ template <typename R>
 static int32_t max_disp(membx_sys* s, double* out)
 {
     Dev<R>& d = dev<R>(s);
-    const int nb = (d.N + WG - 1) / WG;
+    const int nb = (int)(((size_t)d.N * 8 + WG - 1) / WG);
     std::vector<float> v(nb);
     HCK(hipMemcpyAsync(v.data(), d.dmax_part, sizeof(float) * nb, hipMemcpyDeviceToHost, s->st));
     HCK(hipStreamSynchronize(s->st));
@@ -1133,7 +1165,7 @@ template <typename R>
 static void reset_disp(membx_sys* s)
 {
     Dev<R>& d = dev<R>(s);
-    launch_fill_i32((int*)d.dmax_part, 0, (size_t)(d.N + WG - 1) / WG, s->st);
+    launch_fill_i32((int*)d.dmax_part, 0, ((size_t)d.N * 8 + WG - 1) / WG, s->st);
     launch_fill_i32(d.flags + FL_SKIN, 0, 1, s->st);
 }
 
@@ -1550,7 +1582,11 @@ static int32_t kbench_impl(membx_sys* s, int n, double* mean_ms)
     hipGraph_t g;
     if (hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(s, MEMBX_E_DEVICE, "stream capture failed");
-    for (int q = 0; q < n; ++q) launch_nonbonded<R>(d, s->h.lpb, false, nullptr, s->st);
+    // the kernel the MD steps run: forces plus the next step's update, the
+    // update written to scratch (the other coordinate buffer, the sort
+    // buffer for velocities) so that the state is unchanged
+    for (int q = 0; q < n; ++q)
+        launch_nonbonded_fused<R>(d, s->h.lpb, (R)s->h.dt, 1, d.posq_alt, d.vel_t, 0, s->st);
     if (hipStreamEndCapture(s->st, &g) != hipSuccess)
         return fail(s, MEMBX_E_DEVICE, "stream capture failed");
     hipGraphExec_t ge;

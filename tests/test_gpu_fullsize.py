@@ -1,0 +1,131 @@
+"""Parity at the benchmark sizes, in the launch configuration the benchmark
+times (skin 0.4 nm, list rebuilt every 7 steps, 4 lanes per bead, graph
+replay, force pass fused with the integrator): the oracle computes sampled
+outputs one by one (forces on sampled beads) or, where it finishes in
+seconds, the whole quantity (energies, a short trajectory).
+
+Tolerances as in test_gpu_parity: forces 1e-9 (float64) / 1e-5 (mixed) of
+max(|F_ref|, F_rms) per bead, beads with a pair within 1e-5 nm^2 of the
+cutoff set aside in the mixed form; energies relative 1e-10 / 2e-6 of the
+sum of absolute components.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2005_08348_amd import systems as S
+
+pytestmark = pytest.mark.gpu
+
+BENCH_TUNING = dict(skin=0.4, rebuild_interval=7, lanes_per_bead=4)
+
+
+def _membx():
+    from paper_2005_08348_amd import membx
+    return membx
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return S.make("c1")
+
+
+def _aged(m, sysm, prec, steps=30, **tun):
+    """GPU system relaxed and stepped so that its list is several steps old."""
+    g = m.System(sysm, precision=prec, **(tun or BENCH_TUNING))
+    g.minimize(50)
+    g.md_step(steps)
+    return g
+
+
+def _check_sampled_forces(o, g, n, prec, nsample, seed):
+    st = g.state()
+    o.set_state(pos=st["pos"], vel=st["vel"], mol_kind=st["mol_kind"])
+    rng = np.random.default_rng(seed)
+    beads = np.sort(rng.choice(n, size=nsample, replace=False))
+    fr, nc = o.forces_on(beads)
+    f = g.forces()[beads]
+    frms = math.sqrt((fr ** 2).sum(axis=1).mean())
+    err = np.linalg.norm(f - fr, axis=1) / np.maximum(np.linalg.norm(fr, axis=1), frms)
+    if prec == "fp64":
+        assert err.max() < 1e-9, err.max()
+    else:
+        keep = nc >= 1e-5
+        print("sampled mixed force rel err: median %.2e max %.2e (near-cut %d of %d)"
+              % (np.median(err[keep]), err[keep].max(), (~keep).sum(), nsample))
+        assert err[keep].max() < 1e-5
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_forces_c1_sampled_aged_list(oracle_mod, c1, prec):
+    """Forces used by the dynamics after 30 steps (list 2 steps old) on the
+    95,876-bead bilayer, 3,000 sampled beads."""
+    m = _membx()
+    g = _aged(m, c1, prec)
+    o = oracle_mod.Oracle(c1)
+    _check_sampled_forces(o, g, c1.n_beads, prec, 3000, 11)
+    e = g.energies()
+    assert e["n_skin_violations"] == 0
+    g.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_energies_c1_full(oracle_mod, c1, prec):
+    m = _membx()
+    g = _aged(m, c1, prec, steps=12)
+    st = g.state()
+    o = oracle_mod.Oracle(c1)
+    o.set_state(pos=st["pos"], vel=st["vel"], mol_kind=st["mol_kind"])
+    ref = o.energy_forces(forces=False)
+    e = g.energies()
+    tot_abs = abs(ref["lj"]) + abs(ref["rf"]) + abs(ref["bond"]) + abs(ref["angle"])
+    tol = 1e-10 if prec == "fp64" else 2e-6
+    for k in ["lj", "rf", "bond", "angle", "kinetic"]:
+        assert abs(e[k] - ref[k]) <= tol * max(tot_abs, 1.0), (k, e[k], ref[k])
+    assert e["n_pairs_in_cutoff"] == ref["n_pairs"]
+    g.close()
+
+
+def test_md_c1_short_horizon_fp64(oracle_mod, c1):
+    """Float64 trajectory over 9 steps (one list rebuild inside, force passes
+    fused with the integrator) follows the oracle from the same state."""
+    m = _membx()
+    g = m.System(c1, precision="fp64", **BENCH_TUNING)
+    g.minimize(50)
+    st = g.state()
+    o = oracle_mod.Oracle(c1)
+    assert st["step"] == 0 and st["batch"] == 0
+    o.set_state(pos=st["pos"], vel=st["vel"], mol_kind=st["mol_kind"])
+    g.md_step(9)
+    o.md_step(9)
+    d = g.state()["pos"] - o.state()["pos"]
+    d -= c1.box * np.rint(d / c1.box)
+    assert np.abs(d).max() < 1e-7
+    assert np.abs(g.state()["vel"] - o.state()["vel"]).max() < 1e-6
+    g.close()
+
+
+def test_forces_c3_sampled_mixed(oracle_mod):
+    """1,140,504-bead bilayer (the MDAS workload), 2,000 sampled beads."""
+    m = _membx()
+    c3 = S.make("c3")
+    g = _aged(m, c3, "mixed", steps=8, skin=0.35, rebuild_interval=5, lanes_per_bead=8)
+    o = oracle_mod.Oracle(c3)
+    _check_sampled_forces(o, g, c3.n_beads, "mixed", 2000, 13)
+    g.close()
+
+
+def test_mdas_frozen_c3(oracle_mod):
+    """MDAS with M = 0 on the 1.14M-bead bilayer, 32 pairs: identical pairs,
+    work = U_B - U_A of the selected pairs (float64 form)."""
+    m = _membx()
+    c3 = S.make("c3")
+    g = m.System(c3, precision="fp64", skin=0.35, rebuild_interval=5, lanes_per_bead=8)
+    o = oracle_mod.Oracle(c3)
+    rg = g.mdas_cycle(32, 4, 0)
+    ro = o.mdas_cycle(32, 4, 0)
+    assert np.array_equal(rg["pairs"], ro["pairs"])
+    assert abs(rg["work"] - ro["work"]) < 1e-6
+    assert rg["accept"] == ro["accept"]
+    g.close()
