@@ -14,6 +14,8 @@
 // evaluate the bonded terms their bead takes part in (per-bead gather, no
 // atomics).  Each force is an in-register sum followed by a fixed shuffle
 // tree over the LPB lanes, so results are deterministic.
+#include <type_traits>
+
 #include "membx_dev.h"
 
 namespace mbx {
@@ -135,28 +137,34 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
     V4<R> b1[TPL], b2[TPL];
 #pragma unroll
     for (int u = 0; u < TPL; ++u) { b1[u] = P[bt[u].y]; b2[u] = P[bt[u].z]; }
-    // list walk in batches of B entries per lane, branch-free inside a batch:
-    // all list reads (clamped to the bead's tile), then all coordinate
+    // list walk in batches of B entries per lane, then short batches of BT
+    // for the tail, the batch sizes uniform over the wave; branch-free inside a
+    // batch: all list reads (clamped to the bead's tile), then all coordinate
     // gathers (the bead itself for unused slots), then the pair terms with
     // their LDS parameter reads in flight together
-    constexpr int B = sizeof(R) == 8 ? 6 : ((12 * LPB <= 96) ? 12 : 96 / LPB);
+    constexpr int B = 4;
+    constexpr int BT = B >= 8 ? 4 : 2;
     const int m1n = n1 > s ? (n1 - s + LPB - 1) / LPB : 0;
     const int mcap = d.Kcap / LPB;
-    for (int m0 = 0; m0 < m1n; m0 += B) {
-        int jj[B];
+    int mmax = m1n;
 #pragma unroll
-        for (int b = 0; b < B; ++b) jj[b] = nb[(size_t)min(m0 + b, mcap - 1) * 64];
-        V4<R> q[B];
+    for (int o = 32; o >= 1; o >>= 1) mmax = max(mmax, __shfl_xor(mmax, o, 64));
+    auto batch = [&](int m0, auto nbt) {
+        constexpr int NB = decltype(nbt)::value;
+        int jj[NB];
 #pragma unroll
-        for (int b = 0; b < B; ++b) q[b] = P[m0 + b < m1n ? (jj[b] & JMASK) : ii];
+        for (int b = 0; b < NB; ++b) jj[b] = nb[(size_t)min(m0 + b, mcap - 1) * 64];
+        V4<R> q[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) q[b] = P[m0 + b < m1n ? (jj[b] & JMASK) : ii];
         // i-image shifts: decoded only in waves that hold a shifted entry
         bool shifted = false;
 #pragma unroll
-        for (int b = 0; b < B; ++b)
+        for (int b = 0; b < NB; ++b)
             shifted |= (m0 + b < m1n) && ((unsigned)jj[b] >> CODE_SHIFT) != 0u;
         const bool wave_shift = __ballot(shifted) != 0ull;
 #pragma unroll
-        for (int b = 0; b < B; ++b) {
+        for (int b = 0; b < NB; ++b) {
             const bool live = m0 + b < m1n;
             R xs = pi.x, ys = pi.y, zs = pi.z;
             if (wave_shift) {
@@ -190,7 +198,10 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
                 }
             }
         }
-    }
+    };
+    int m0 = 0;
+    for (; m0 + B <= mmax; m0 += B) batch(m0, std::integral_constant<int, B>{});
+    for (; m0 < mmax; m0 += BT) batch(m0, std::integral_constant<int, BT>{});
     // bonded terms of bead i
 #pragma unroll
     for (int u = 0; u < TPL; ++u)
