@@ -158,8 +158,10 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="use --skin/--rebuild/--lpb instead of the autotuner")
     ap.add_argument("--lpb", type=int, default=8, help="lanes per bead of the pair kernel")
-    ap.add_argument("--rebuild", type=int, default=5, help="steps between list rebuilds")
-    ap.add_argument("--skin", type=float, default=0.3)
+    ap.add_argument("--rebuild", type=int, default=9, help="steps between list rebuilds")
+    ap.add_argument("--skin", type=float, default=0.5)
+    ap.add_argument("--skin-inner", type=float, default=0.15)
+    ap.add_argument("--prune", type=int, default=3, help="force passes per inner-list prune")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -175,7 +177,8 @@ def main():
 
     log("[bench] building c1 (95,876 beads)")
     c1 = S.make("c1")
-    tun = dict(skin=args.skin, rebuild_interval=args.rebuild, lanes_per_bead=args.lpb)
+    tun = dict(skin=args.skin, rebuild_interval=args.rebuild, lanes_per_bead=args.lpb,
+               skin_inner=args.skin_inner, prune_interval=args.prune)
     g = gpu_system(c1, "mixed", **tun)
     log("[bench] relaxing start structure on the GPU")
     g.minimize(100)
@@ -225,7 +228,8 @@ def main():
                                "Langevin BAOAB dt 20 fs",
                    "n_beads": c1.n_beads, "precision": "mixed",
                    "skin_nm": tun["skin"], "rebuild_interval": tun["rebuild_interval"],
-                   "lanes_per_bead": tun["lanes_per_bead"]},
+                   "lanes_per_bead": tun["lanes_per_bead"],
+                   "inner_skin_nm": tun["skin_inner"], "prune_interval": tun["prune_interval"]},
         "pair_interactions_per_s": pairs * steps_s,
         "pairs_in_cutoff": pairs,
         "skin_violations": e2["n_skin_violations"],

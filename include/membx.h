@@ -113,6 +113,13 @@ typedef struct membx_desc {
     int32_t list_capacity;        /* neighbour slots per bead (default auto) */
     int32_t max_trials;           /* largest exchange batch (default 256)   */
     int32_t max_pairs;            /* largest MDAS pair count (default 64)   */
+    /* dynamic pruning: every prune_interval force passes of plain MD the
+     * pass that walks the Verlet list also writes an inner list of the pairs
+     * within r_cut + skin_inner, which the passes in between walk instead;
+     * exact while no bead moves more than skin_inner/2 between prunes
+     * (counted like the skin violations).  prune_interval <= 1: off. */
+    double  skin_inner;           /* nm, <= skin (default skin / 2)         */
+    int32_t prune_interval;
 } membx_desc;
 
 /* Energies of the current state (float64). */
@@ -124,7 +131,8 @@ typedef struct membx_energy {
     int64_t step, batch, cycle;   /* MD step, exchange batch, MDAS cycle    */
     int64_t n_rebuilds;
     int64_t n_skin_violations;    /* (bead, step) events beyond skin/2 since */
-                                  /* creation or the last retune            */
+                                  /* creation or the last retune, plus those */
+                                  /* beyond skin_inner/2 since a prune      */
     double  max_displacement;     /* largest displacement from the position */
                                   /* at the last list build seen since then */
                                   /* (nm)                                   */
@@ -222,22 +230,27 @@ int32_t membx_pairset_export(membx_sys* sys, int32_t* ij, int64_t cap, int64_t* 
 int32_t membx_minimize(membx_sys* sys, int32_t n_iter, double alpha, double max_step);
 
 /* Change the tuning of an existing system (skin <= skin_max, lanes_per_bead
- * in {1,2,4,8}, rebuild_interval >= 1).  Rebuilds the list.  E_INVAL. */
+ * in {1,2,4,8}, rebuild_interval >= 1; prune_interval <= 1 turns the inner
+ * list off, else skin_inner in (0, skin] and lanes_per_bead >= 2).  Rebuilds
+ * the list.  E_INVAL. */
 int32_t membx_set_tuning(membx_sys* sys, double skin, int32_t rebuild_interval,
-                         int32_t lanes_per_bead);
+                         int32_t lanes_per_bead, double skin_inner, int32_t prune_interval);
 
-/* Autotune skin, rebuild interval and lanes per bead by timing short runs
- * of n_steps (<= 0: 200) from the current state.  Candidates: skin from
- * 0.1 nm to skin_max in steps of 0.05 nm, lanes per bead 4 and 8; for each
- * skin the interval is the largest that keeps every bead within 0.8 skin/2
- * of its position at the last list build, extrapolated linearly from a pilot
- * run at interval 4.  A candidate is rejected if a bead went beyond 0.9
- * skin/2 in its timed run.  Positions, velocities, kinds and random-number
- * counters are restored afterwards; forces are recomputed and the list is
- * rebuilt.  Writes the chosen values and leaves the system tuned.
- * E_DEVICE. */
-int32_t membx_autotune(membx_sys* sys, int32_t n_steps, double* skin,
-                       int32_t* rebuild_interval, int32_t* lanes_per_bead);
+/* Autotune skin, rebuild interval, lanes per bead and the inner list by
+ * timing short runs of n_steps (<= 0: 200) from the current state.
+ * Candidates: skin from 0.2 nm to skin_max in steps of 0.1 nm, lanes per
+ * bead 4 and 8, prune interval 1 (no inner list), 2, 3 and 4.  A pilot run
+ * gives the largest displacement d4 over 4 steps; in the ballistic regime
+ * (interval << 1/gamma) displacements grow linearly with time, so the
+ * rebuild interval is the largest that keeps every bead within 0.8 skin/2,
+ * and the inner buffer the smallest that keeps it within 0.8 delta/2 over a
+ * prune interval.  A candidate is rejected if, in its timed run, a bead went
+ * beyond 0.9 skin/2 or beyond delta/2.  Positions, velocities, kinds and
+ * random-number counters are restored afterwards; forces are recomputed and
+ * the list is rebuilt.  Writes the chosen values and leaves the system
+ * tuned.  E_DEVICE. */
+int32_t membx_autotune(membx_sys* sys, int32_t n_steps, double* skin, int32_t* rebuild_interval,
+                       int32_t* lanes_per_bead, double* skin_inner, int32_t* prune_interval);
 
 /* Enable (1) or disable (0) HIP-graph replay of step sequences (default 1). */
 int32_t membx_set_graphs(membx_sys* sys, int32_t enable);

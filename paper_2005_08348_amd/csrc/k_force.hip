@@ -97,63 +97,94 @@ __device__ __forceinline__ double wave_sum(double v)
 // next BAOAB step (its own force is all that step needs), writing the new
 // coordinates to pos_out (the other coordinate buffer: the neighbours' old
 // coordinates are still being read) and the velocity to vel_out.
-template <typename R, int LPB, bool EN, bool FUSE>
+// LIST: 0 walk the Verlet list; 1 walk the inner list; 2 walk the Verlet
+// list and rewrite the inner list from it (dynamic pruning): lane s of bead i
+// keeps its entries within r_cut + delta, in order, as its own entries
+// s, s + LPB, ... of the inner list, with its own count, and the bead's
+// coordinates become the reference for the inner list's displacement check.
+template <typename R, int LPB, bool EN, bool FUSE, int LIST>
 __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, R kick,
                                            long long step_off, V4<R>* pos_out, V4<R>* vel_out,
                                            int stats)
 {
     __shared__ V4<R> tf[MAXCLS * MAXCLS];
     __shared__ V4<R> te[EN ? MAXCLS * MAXCLS : 1];
-    for (int t = threadIdx.x; t < MAXCLS * MAXCLS; t += WG) {
-        tf[t] = d.tabF[t];
-        if (EN) te[t] = d.tabE[t];
-    }
-    __syncthreads();
     const int gid = blockIdx.x * WG + threadIdx.x;
     const int i = gid / LPB, s = gid % LPB;
     const bool valid = i < d.N;
-    const V4<R> pi = valid ? d.posq[i] : V4<R>{ 0, 0, 0, 0 };
-    const int ci = valid ? cls_of<R>(pi.w) : 0;
-    const int n1 = valid ? d.ncnt[i] : 0;
-    const V4<R>* rowF = tf + ci * MAXCLS;
-    const V4<R>* rowE = EN ? te + ci * MAXCLS : tf;
-    R fx = 0, fy = 0, fz = 0;
-    double elj = 0.0, erf = 0.0, eb = 0.0, ea = 0.0, ek = 0.0;
-    int np = 0;
+    const int ii = valid ? i : 0;
     // entry k = m LPB + s of bead i sits at lane_base + 64 m (tiled list)
     constexpr int BG = 64 / LPB;
-    const int ii = valid ? i : 0;
     const size_t lane_base = (size_t)(ii / BG) * ((size_t)d.Kcap * BG) + (size_t)(ii % BG) * LPB + s;
-    const int* __restrict__ nb = d.nbr + lane_base;
+    const int* __restrict__ nb = (LIST == 1 ? d.nbr_in : d.nbr) + lane_base;
+    int* __restrict__ nb_out = d.nbr_in + lane_base;
     const V4<R>* __restrict__ P = d.posq;
-    // bonded records (lane s takes terms s, s + LPB, ... of its bead) and the
-    // partner coordinates, issued before the list walk
+    constexpr int B = 4;
+    constexpr int BT = B >= 8 ? 4 : 2;
+    const int mcap = d.Kcap / LPB;
+    // Every read that depends on no other read goes out first, in one round
+    // trip with the parameter table below: the bead, its counts, the first
+    // two batches of list entries (clamped to the bead's tile), its bonded
+    // records and (FUSE) what the integrator will need.
+    const V4<R> pi = d.posq[ii];
+    int jj0[B], jj1[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) jj0[b] = nb[(size_t)min(b, mcap - 1) * 64];
+#pragma unroll
+    for (int b = 0; b < B; ++b) jj1[b] = nb[(size_t)min(B + b, mcap - 1) * 64];
+    int m1n;   // entries this lane walks
+    if (LIST == 1) {
+        m1n = valid ? min(d.ncnt_in[(size_t)i * LPB + s], mcap) : 0;
+    } else {
+        const int n1 = valid ? d.ncnt[i] : 0;
+        m1n = n1 > s ? (n1 - s + LPB - 1) / LPB : 0;
+    }
+    // bonded records: lane s takes terms s, s + LPB, ... of its bead
     constexpr int TPL = (MAXBT + LPB - 1) / LPB;
     int4 bt[TPL];
 #pragma unroll
     for (int u = 0; u < TPL; ++u)
         bt[u] = (s + u * LPB < MAXBT) ? d.bslot[(size_t)ii * MAXBT + s + u * LPB]
                                       : make_int4(-1, ii, ii, 0);
+    // FUSE: after the forces, thread t < WG / LPB of the block integrates the
+    // block's bead t (forces handed over through LDS), so that the
+    // integrator runs on full waves instead of one lane per bead
+    constexpr int NBB = WG / LPB;
+    const int ib = blockIdx.x * NBB + threadIdx.x;
+    const bool integ = FUSE && threadIdx.x < NBB && ib < d.N;
+    BeadPre<R> pre{};
+    V4<R> pb{};
+    if (integ) {
+        pb = d.posq[ib];
+        pre = bead_pre(d, ib, LIST == 1);
+        if (LIST == 2) pre.xri = pb;   // this pass makes the bead's coordinates the reference
+    }
+    for (int t = threadIdx.x; t < MAXCLS * MAXCLS; t += WG) {
+        tf[t] = d.tabF[t];
+        if (EN) te[t] = d.tabE[t];
+    }
+    __syncthreads();
+    const int ci = valid ? cls_of<R>(pi.w) : 0;
+    const V4<R>* rowF = tf + ci * MAXCLS;
+    const V4<R>* rowE = EN ? te + ci * MAXCLS : tf;
+    R fx = 0, fy = 0, fz = 0;
+    double elj = 0.0, erf = 0.0, eb = 0.0, ea = 0.0, ek = 0.0;
+    int np = 0;
+    // partner coordinates of the bonded terms
     V4<R> b1[TPL], b2[TPL];
 #pragma unroll
     for (int u = 0; u < TPL; ++u) { b1[u] = P[bt[u].y]; b2[u] = P[bt[u].z]; }
     // list walk in batches of B entries per lane, then short batches of BT
     // for the tail, the batch sizes uniform over the wave; branch-free inside a
-    // batch: all list reads (clamped to the bead's tile), then all coordinate
-    // gathers (the bead itself for unused slots), then the pair terms with
-    // their LDS parameter reads in flight together
-    constexpr int B = 4;
-    constexpr int BT = B >= 8 ? 4 : 2;
-    const int m1n = n1 > s ? (n1 - s + LPB - 1) / LPB : 0;
-    const int mcap = d.Kcap / LPB;
+    // batch: all list reads, then all coordinate gathers (the bead itself for
+    // unused slots), then the pair terms with their LDS parameter reads in
+    // flight together
+    int nkeep = 0;   // LIST 2: entries kept for the inner list
     int mmax = m1n;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) mmax = max(mmax, __shfl_xor(mmax, o, 64));
-    auto batch = [&](int m0, auto nbt) {
+    auto compute = [&](int m0, const int* jj, auto nbt) {
         constexpr int NB = decltype(nbt)::value;
-        int jj[NB];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) jj[b] = nb[(size_t)min(m0 + b, mcap - 1) * 64];
         V4<R> q[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b) q[b] = P[m0 + b < m1n ? (jj[b] & JMASK) : ii];
@@ -175,6 +206,7 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
             }
             const R dx = xs - q[b].x, dy = ys - q[b].y, dz = zs - q[b].z;
             const R r2 = dx * dx + dy * dy + dz * dz;
+            if (LIST == 2 && live && r2 < d.rin2) nb_out[(size_t)(nkeep++) * 64] = jj[b];
             // unused slots hold the bead itself (r2 = 0): masked, kept off rsq(0)
             const bool in = live && r2 < d.rc2;
             const R r2s = in ? r2 : (R)1;
@@ -199,7 +231,22 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
             }
         }
     };
+    auto batch = [&](int m0, auto nbt) {
+        constexpr int NB = decltype(nbt)::value;
+        int jj[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) jj[b] = nb[(size_t)min(m0 + b, mcap - 1) * 64];
+        compute(m0, jj, nbt);
+    };
     int m0 = 0;
+    if (mmax > 0) {
+        compute(0, jj0, std::integral_constant<int, B>{});
+        m0 = B;
+    }
+    if (mmax > B) {
+        compute(B, jj1, std::integral_constant<int, B>{});
+        m0 = 2 * B;
+    }
     for (; m0 + B <= mmax; m0 += B) batch(m0, std::integral_constant<int, B>{});
     for (; m0 < mmax; m0 += BT) batch(m0, std::integral_constant<int, BT>{});
     // bonded terms of bead i
@@ -221,13 +268,22 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
         if (!FUSE) {
             if (own) d.frc[i] = V4<R>{ fx, fy, fz, (R)0 };
         } else {
-            float e2 = 0.f;
+            __shared__ V4<R> fsh[NBB];
+            if (LIST == 2 && valid) {
+                d.ncnt_in[(size_t)i * LPB + s] = nkeep;
+                if (s == 0) d.xref_in[i] = pi;
+            }
             if (own) {
                 const V4<R> f{ fx, fy, fz, (R)0 };
                 d.frc[i] = f;
-                e2 = baoab_bead(d, i, pi, d.vel[i], f, kick, step_off, pos_out, vel_out);
+                fsh[threadIdx.x / LPB] = f;
             }
-            if (stats) disp_stats(d, e2, own);
+            __syncthreads();
+            float e2 = 0.f, e2_in = 0.f;
+            if (integ)
+                e2 = baoab_bead(d, ib, pb, pre, fsh[threadIdx.x], kick, step_off, pos_out, vel_out,
+                                LIST != 0, e2_in);
+            if (stats) disp_stats(d, e2, e2_in, integ);
         }
     } else {
         __shared__ double sh[6][WG / 64];
@@ -276,45 +332,56 @@ __global__ void k_energy_final(const double* __restrict__ p, int nb, double* __r
 }
 
 // ----------------------------------------------------------------- launch
-template <typename R, int LPB, bool EN, bool FUSE>
+template <typename R, int LPB, bool EN, bool FUSE, int LIST>
 static void nb_launch(const Dev<R>& d, double* part, R kick, long long step_off, V4<R>* pos_out,
                       V4<R>* vel_out, int stats, hipStream_t st)
 {
     int nthr = d.N * LPB;
-    hipLaunchKernelGGL((k_nb<R, LPB, EN, FUSE>), dim3((nthr + WG - 1) / WG), dim3(WG), 0, st, d, part,
-                       kick, step_off, pos_out, vel_out, stats);
+    hipLaunchKernelGGL((k_nb<R, LPB, EN, FUSE, LIST>), dim3((nthr + WG - 1) / WG), dim3(WG), 0, st, d,
+                       part, kick, step_off, pos_out, vel_out, stats);
 }
 
-// forces (energy=false) or energies into part (energy=true); returns blocks
+// forces (energy=false) or energies into part (energy=true), Verlet list;
+// returns blocks
 template <typename R>
 int launch_nonbonded(const Dev<R>& d, int lpb, bool energy, double* part, hipStream_t st)
 {
     switch (lpb * 2 + (energy ? 1 : 0)) {
-    case 2: nb_launch<R, 1, false, false>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
-    case 3: nb_launch<R, 1, true, false>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
-    case 4: nb_launch<R, 2, false, false>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
-    case 5: nb_launch<R, 2, true, false>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
-    case 8: nb_launch<R, 4, false, false>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
-    case 9: nb_launch<R, 4, true, false>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
-    case 16: nb_launch<R, 8, false, false>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
-    case 17: nb_launch<R, 8, true, false>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
+    case 2: nb_launch<R, 1, false, false, 0>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
+    case 3: nb_launch<R, 1, true, false, 0>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
+    case 4: nb_launch<R, 2, false, false, 0>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
+    case 5: nb_launch<R, 2, true, false, 0>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
+    case 8: nb_launch<R, 4, false, false, 0>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
+    case 9: nb_launch<R, 4, true, false, 0>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
+    case 16: nb_launch<R, 8, false, false, 0>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
+    case 17: nb_launch<R, 8, true, false, 0>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
     default: break;
     }
     return (d.N * lpb + WG - 1) / WG;
 }
 
-// forces followed by the next step's B-A-O-A for every bead (see k_nb)
+// forces followed by the next step's B-A-O-A for every bead (see k_nb);
+// list: 0 Verlet list, 1 inner list, 2 Verlet list + prune into the inner
+// list (lanes per bead 2, 4 or 8; 1 walks the Verlet list)
 template <typename R>
-void launch_nonbonded_fused(const Dev<R>& d, int lpb, R kick, long long step_off, V4<R>* pos_out,
-                            V4<R>* vel_out, int stats, hipStream_t st)
+void launch_nonbonded_fused(const Dev<R>& d, int lpb, int list, R kick, long long step_off,
+                            V4<R>* pos_out, V4<R>* vel_out, int stats, hipStream_t st)
 {
-    switch (lpb) {
-    case 1: nb_launch<R, 1, false, true>(d, nullptr, kick, step_off, pos_out, vel_out, stats, st); break;
-    case 2: nb_launch<R, 2, false, true>(d, nullptr, kick, step_off, pos_out, vel_out, stats, st); break;
-    case 4: nb_launch<R, 4, false, true>(d, nullptr, kick, step_off, pos_out, vel_out, stats, st); break;
-    case 8: nb_launch<R, 8, false, true>(d, nullptr, kick, step_off, pos_out, vel_out, stats, st); break;
+#define NBF(L, M) nb_launch<R, L, false, true, M>(d, nullptr, kick, step_off, pos_out, vel_out, stats, st)
+    switch (lpb * 4 + list) {
+    case 4: case 5: case 6: NBF(1, 0); break;
+    case 8: NBF(2, 0); break;
+    case 9: NBF(2, 1); break;
+    case 10: NBF(2, 2); break;
+    case 16: NBF(4, 0); break;
+    case 17: NBF(4, 1); break;
+    case 18: NBF(4, 2); break;
+    case 32: NBF(8, 0); break;
+    case 33: NBF(8, 1); break;
+    case 34: NBF(8, 2); break;
     default: break;
     }
+#undef NBF
 }
 
 void launch_energy_final(const double* p, int nb, double* out, hipStream_t st)
@@ -324,9 +391,9 @@ void launch_energy_final(const double* p, int nb, double* out, hipStream_t st)
 
 template int launch_nonbonded<float>(const Dev<float>&, int, bool, double*, hipStream_t);
 template int launch_nonbonded<double>(const Dev<double>&, int, bool, double*, hipStream_t);
-template void launch_nonbonded_fused<float>(const Dev<float>&, int, float, long long, V4<float>*,
-                                            V4<float>*, int, hipStream_t);
-template void launch_nonbonded_fused<double>(const Dev<double>&, int, double, long long, V4<double>*,
-                                             V4<double>*, int, hipStream_t);
+template void launch_nonbonded_fused<float>(const Dev<float>&, int, int, float, long long,
+                                            V4<float>*, V4<float>*, int, hipStream_t);
+template void launch_nonbonded_fused<double>(const Dev<double>&, int, int, double, long long,
+                                             V4<double>*, V4<double>*, int, hipStream_t);
 
 }  // namespace mbx

@@ -233,6 +233,9 @@ __global__ void k_rank(Dev<R> d)
     d.orig_ext[s] = o;
     d.xref[s] = x;
     d.gcnt[s] = 0;
+    // no periodic images yet (ghost fill adds them)
+    reinterpret_cast<int4*>(d.glist)[2 * s] = make_int4(-1, -1, -1, -1);
+    reinterpret_cast<int4*>(d.glist)[2 * s + 1] = make_int4(-1, -1, -1, -1);
 }
 
 // Bonded terms of each slot with their partners' slots (after the sort).
@@ -277,7 +280,7 @@ __global__ void k_ghost_fill(Dev<R> d)
         d.ghost_code[g] = code;
         d.orig_ext[d.N + g] = d.orig[s];
         int q = atomicAdd(&d.gcnt[s], 1);
-        if (q < 7) d.glist[s * 7 + q] = g;
+        if (q < 8) d.glist[s * 8 + q] = g | (code << CODE_SHIFT);
     }
 }
 
@@ -311,7 +314,7 @@ __device__ __forceinline__ bool within_d(double xi, double yi, double zi, double
 }
 
 constexpr int LB = 256;   // threads per cell
-constexpr int HS = 12;    // LDS hit slots per lane (single-pass path)
+constexpr int HS = 16;    // LDS hit slots per lane (single-pass path)
 constexpr int LU = 4;     // candidates per lane per round (LDS reads in flight)
 template <typename R> struct CandCap { static constexpr int v = 1024; };
 template <> struct CandCap<double> { static constexpr int v = 512; };

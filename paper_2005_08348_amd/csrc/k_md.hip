@@ -9,12 +9,14 @@ namespace mbx {
 // place; x at the last rebuild is compared to flag displacements beyond
 // skin/2.
 template <typename R>
-__global__ __launch_bounds__(WG) void k_kick_drift(Dev<R> d, R kick, long long step_off)
+__global__ __launch_bounds__(WG) void k_kick_drift(Dev<R> d, R kick, long long step_off, int chk_in)
 {
     const int i = blockIdx.x * WG + threadIdx.x;
-    float e2 = 0.f;
-    if (i < d.N) e2 = baoab_bead(d, i, d.posq[i], d.vel[i], d.frc[i], kick, step_off, d.posq, d.vel);
-    disp_stats(d, e2, i < d.N);
+    float e2 = 0.f, e2_in = 0.f;
+    if (i < d.N)
+        e2 = baoab_bead(d, i, d.posq[i], bead_pre(d, i, chk_in != 0), d.frc[i], kick, step_off,
+                        d.posq, d.vel, chk_in != 0, e2_in);
+    disp_stats(d, e2, e2_in, i < d.N);
 }
 
 // closing half-kick of a run of steps; also advances the step counter
@@ -106,10 +108,10 @@ void launch_add_ctr(long long* ctr, int which, long long n, hipStream_t st)
 }
 
 template <typename R>
-void launch_kick_drift(const Dev<R>& d, R kick, long long step_off, hipStream_t st)
+void launch_kick_drift(const Dev<R>& d, R kick, long long step_off, int chk_in, hipStream_t st)
 {
     hipLaunchKernelGGL(k_kick_drift<R>, dim3((d.N + WG - 1) / WG), dim3(WG), 0, st, d, kick,
-                       step_off);
+                       step_off, chk_in);
 }
 template <typename R>
 void launch_kick(const Dev<R>& d, R kick, long long nsteps, hipStream_t st)
@@ -133,7 +135,7 @@ void launch_import(const Dev<R>& d, V4<R>* dst, const double* in, hipStream_t st
 }
 
 #define INST(R)                                                                      \
-    template void launch_kick_drift<R>(const Dev<R>&, R, long long, hipStream_t);   \
+    template void launch_kick_drift<R>(const Dev<R>&, R, long long, int, hipStream_t); \
     template void launch_kick<R>(const Dev<R>&, R, long long, hipStream_t);                    \
     template void launch_sd_step<R>(const Dev<R>&, double, double, hipStream_t);     \
     template void launch_export<R>(const Dev<R>&, const V4<R>*, double*, hipStream_t); \

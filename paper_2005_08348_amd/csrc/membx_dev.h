@@ -21,9 +21,10 @@ enum { ST_LANGEVIN = 0, ST_SWAP_DRAW = 1, ST_SWAP_ACCEPT = 2, ST_MDAS_SELECT = 3
        ST_MDAS_ACCEPT = 4 };
 
 // device flags
-// FL_SKIN counts (bead, step) events beyond skin/2 since the last reset
+// FL_SKIN counts (bead, step) events beyond skin/2 since the last reset;
+// FL_SKIN_IN the same for the inner list (beyond delta/2 since its prune)
 enum { FL_LIST_OVF = 0, FL_SKIN = 1, FL_GHOST_OVF = 2, FL_NONFINITE = 3, FL_AFF_OVF = 4,
-       FL_REBUILDS = 5, NFLAGS = 8 };
+       FL_REBUILDS = 5, FL_SKIN_IN = 6, NFLAGS = 8 };
 
 // device counters (int64)
 enum { CT_STEP = 0, CT_BATCH = 1, CT_CYCLE = 2, CT_MDAS_ACC = 3, NCTR = 4 };
@@ -158,7 +159,7 @@ template <typename R> struct Dev {
     int* ghost_code;
     int* n_ghost;    // [1]
     int* gcnt;       // [N] images of each slot
-    int* glist;      // [N * 7] their ghost indices
+    int* glist;      // [N * 8] their ghost indices | code << 29, -1 unused
     int* orig_ext;   // [N + Gcap] bead id of each slot or ghost image
     int4* bslot;     // [N * 8] bonded terms of each slot with partner slots
                      // {role, slot 1, slot 2, parameter}; role -1 = unused
@@ -170,6 +171,13 @@ template <typename R> struct Dev {
     int lpb, lpb_shift, bg_shift;   // lanes per bead, log2(lpb), log2(64/lpb)
     int* nbr;
     int* ncnt;
+    // inner (pruned) list, same layout and capacity: the entries of the
+    // outer list within r_cut + delta at the last prune (coordinates xref_in)
+    int* nbr_in;
+    int* ncnt_in;
+    V4<R>* xref_in;
+    R rin2;          // (r_cut + delta)^2; 0: no inner list
+    R in_half2;      // (delta / 2)^2
     int* nseg0;
     // topology
     int* excl;       // [N * MAXEXCL] bead ids, -1 padded
@@ -262,16 +270,39 @@ struct Mv {
 // A + O (Ornstein-Uhlenbeck with Philox noise) + A of a BAOAB step; the new
 // coordinates go to pos_out (the bead's slot and its periodic images, which
 // are exact shifts by -L), the velocity to vel_out.  Returns the squared
-// displacement from the coordinates of the last list build.
+// displacement from the coordinates of the last list build, and (chk_in:
+// the inner list is valid) in e2_in the one from its last prune.
+// Per-bead inputs of baoab_bead that do not depend on the force, loaded
+// early by the force kernel so that they are in flight with its first reads.
+template <typename R> struct BeadPre {
+    V4<R> v, xr, xri;
+    int orig;
+    int4 g0;
+};
+
 template <typename R>
-__device__ __forceinline__ float baoab_bead(const Dev<R>& d, int i, V4<R> p, V4<R> v, const V4<R>& f,
-                                            R kick, long long step_off, V4<R>* __restrict__ pos_out,
-                                            V4<R>* __restrict__ vel_out)
+__device__ __forceinline__ BeadPre<R> bead_pre(const Dev<R>& d, int i, bool chk_in)
 {
+    BeadPre<R> b;
+    b.v = d.vel[i];
+    b.xr = d.xref[i];
+    b.xri = chk_in ? d.xref_in[i] : b.xr;
+    b.orig = d.orig[i];
+    b.g0 = reinterpret_cast<const int4*>(d.glist)[2 * i];
+    return b;
+}
+
+template <typename R>
+__device__ __forceinline__ float baoab_bead(const Dev<R>& d, int i, V4<R> p, const BeadPre<R>& pre,
+                                            const V4<R>& f, R kick, long long step_off,
+                                            V4<R>* __restrict__ pos_out, V4<R>* __restrict__ vel_out,
+                                            bool chk_in, float& e2_in)
+{
+    V4<R> v = pre.v;
     const R im = v.w, h = d.half_dt;
     v.x += kick * im * f.x; v.y += kick * im * f.y; v.z += kick * im * f.z;
     p.x += h * v.x; p.y += h * v.y; p.z += h * v.z;
-    const uint4 w = draw(d.seed, (uint32_t)d.orig[i], d.ctr[CT_STEP] + step_off, ST_LANGEVIN);
+    const uint4 w = draw(d.seed, (uint32_t)pre.orig, d.ctr[CT_STEP] + step_off, ST_LANGEVIN);
     R g[3];
     gauss3<R>(w, g);
     const R sg = d.c2 * sqrt(d.kT * im);
@@ -281,38 +312,58 @@ __device__ __forceinline__ float baoab_bead(const Dev<R>& d, int i, V4<R> p, V4<
     p.x += h * v.x; p.y += h * v.y; p.z += h * v.z;
     pos_out[i] = p;
     vel_out[i] = v;
-    const int gc = d.gcnt[i];
-    for (int q = 0; q < gc && q < 7; ++q) {
-        const int gi = d.glist[i * 7 + q], code = d.ghost_code[gi];
+    // periodic images: one 32-byte record per bead, entries g | code << 29
+    // (all bits set: unused; a real entry never is, g < 2^29 - 1, though the
+    // z code sets the sign bit), the second half only read when the first
+    // is full
+    const int4 g0 = pre.g0;
+    int ge[8] = { g0.x, g0.y, g0.z, g0.w, -1, -1, -1, -1 };
+    if (g0.w != -1) {
+        const int4 g1 = reinterpret_cast<const int4*>(d.glist)[2 * i + 1];
+        ge[4] = g1.x; ge[5] = g1.y; ge[6] = g1.z; ge[7] = g1.w;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        if (ge[q] == -1) break;
+        const int gi = ge[q] & JMASK, code = (int)((unsigned)ge[q] >> CODE_SHIFT);
         V4<R> pg = p;
         if (code & 1) pg.x -= d.L[0];
         if (code & 2) pg.y -= d.L[1];
         if (code & 4) pg.z -= d.L[2];
         pos_out[d.N + gi] = pg;
     }
-    const V4<R> r = d.xref[i];
+    const V4<R> r = pre.xr;
     const R ex = p.x - r.x, ey = p.y - r.y, ez = p.z - r.z;
+    e2_in = 0.f;
+    if (chk_in) {
+        const V4<R> r2 = pre.xri;
+        const R fx = p.x - r2.x, fy = p.y - r2.y, fz = p.z - r2.z;
+        e2_in = (float)(fx * fx + fy * fy + fz * fz);
+    }
     return (float)(ex * ex + ey * ey + ez * ez);
 }
 
 // Block-wide bookkeeping of the displacements (all threads call it): beads
-// beyond skin/2 are counted, and the block's largest squared displacement
-// raises its slot of dmax_part.
+// beyond skin/2 (and beyond delta/2 of the inner list) are counted, and the
+// block's largest squared displacement raises its slot of dmax_part.
 template <typename R>
-__device__ __forceinline__ void disp_stats(const Dev<R>& d, float e2, bool counted)
+__device__ __forceinline__ void disp_stats(const Dev<R>& d, float e2, float e2_in, bool counted)
 {
     __shared__ float s_m2[WG / 64];
     const unsigned long long over = __ballot(counted && e2 > (float)d.skin_half2);
+    const unsigned long long over_in = __ballot(counted && e2_in > (float)d.in_half2);
     float m2 = counted ? e2 : 0.f;
     for (int o = 32; o > 0; o >>= 1) m2 = fmaxf(m2, __shfl_xor(m2, o, 64));
     if ((threadIdx.x & 63) == 0) {
         if (over) atomicAdd(&d.flags[FL_SKIN], __popcll(over));
+        if (over_in) atomicAdd(&d.flags[FL_SKIN_IN], __popcll(over_in));
         s_m2[threadIdx.x >> 6] = m2;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int w = 1; w < WG / 64; ++w) m2 = fmaxf(m2, s_m2[w]);
-        d.dmax_part[blockIdx.x] = fmaxf(d.dmax_part[blockIdx.x], m2);
+        // float bits of non-negative values order like integers
+        atomicMax(reinterpret_cast<int*>(d.dmax_part) + blockIdx.x, __float_as_int(m2));
     }
 }
 

@@ -23,9 +23,9 @@ template <typename R> void launch_rebuild(const Dev<R>&, hipStream_t);
 template <typename R> void launch_ghost_update(const Dev<R>&, hipStream_t);
 template <typename R> int launch_nonbonded(const Dev<R>&, int, bool, double*, hipStream_t);
 template <typename R>
-void launch_nonbonded_fused(const Dev<R>&, int, R, long long, V4<R>*, V4<R>*, int, hipStream_t);
+void launch_nonbonded_fused(const Dev<R>&, int, int, R, long long, V4<R>*, V4<R>*, int, hipStream_t);
 void launch_energy_final(const double*, int, double*, hipStream_t);
-template <typename R> void launch_kick_drift(const Dev<R>&, R, long long, hipStream_t);
+template <typename R> void launch_kick_drift(const Dev<R>&, R, long long, int, hipStream_t);
 template <typename R> void launch_kick(const Dev<R>&, R, long long, hipStream_t);
 template <typename R> void launch_sd_step(const Dev<R>&, double, double, hipStream_t);
 template <typename R> void launch_export(const Dev<R>&, const V4<R>*, double*, hipStream_t);
@@ -104,6 +104,8 @@ struct Host {
     // tuning / capacities
     double skin, skin_max;
     int R, lpb, Kcap, Gcap, T_cap, P_cap;
+    double skin_in;   // inner-list buffer delta (nm)
+    int prune;        // force passes per inner-list prune; 0: no inner list
     int nc[3], ncell, ne[3], next;   // cell grid at the current skin
     int ncell_cap, next_cap;          // array sizes (grid at the smallest skin)
     int hnc[3], hcells, mh;
@@ -213,10 +215,13 @@ Status check_desc(const membx_desc* d, Host& h)
     if (d->skin_max > 0) h.skin_max = std::max(h.skin, d->skin_max);
     else {
         const double lim = std::min(h.box[0], std::min(h.box[1], h.box[2])) / 3.0 - h.rc;
-        h.skin_max = std::max(h.skin, std::min(0.4, lim));
+        h.skin_max = std::max(h.skin, std::min(0.6, lim));
     }
     h.R = d->rebuild_interval > 0 ? d->rebuild_interval : 5;
     h.lpb = d->lanes_per_bead > 0 ? d->lanes_per_bead : 8;
+    h.prune = d->prune_interval > 1 ? d->prune_interval : 0;
+    h.skin_in = h.prune ? std::min(d->skin_inner > 0 ? d->skin_inner : 0.5 * h.skin, h.skin) : 0.0;
+    if (h.prune && h.lpb < 2) return { MEMBX_E_INVAL, "an inner list needs lanes_per_bead >= 2" };
     if (h.lpb != 1 && h.lpb != 2 && h.lpb != 4 && h.lpb != 8)
         return { MEMBX_E_INVAL, "lanes_per_bead must be 1, 2, 4 or 8" };
     h.T_cap = d->max_trials > 0 ? d->max_trials : 256;
@@ -238,7 +243,7 @@ Status check_desc(const membx_desc* d, Host& h)
         h.Kcap = (int)std::ceil((exp_n * 1.8 + 24) / 8.0) * 8;
     }
     h.Kcap = std::max(h.Kcap, 96);   // the pair kernel reads the first 96 entries unconditionally
-    if (h.Kcap > 224) return { MEMBX_E_INVAL, "list capacity above 224 per bead (lower skin or density)" };
+    if (h.Kcap > 512) return { MEMBX_E_INVAL, "list capacity above 512 per bead (lower skin or density)" };
     double gfrac = (1.0 + 1.0 / h.nc[0]) * (1.0 + 1.0 / h.nc[1]) * (1.0 + 1.0 / h.nc[2]) - 1.0;
     h.Gcap = (int)(h.N * gfrac * 1.6) + 4096;
     if ((long long)h.N + h.Gcap >= (1LL << CODE_SHIFT)) return { MEMBX_E_INVAL, "too many beads" };
@@ -408,6 +413,7 @@ struct membx_sys {
     bool graphs = true;
     bool fuse = true;        // force kernel integrates the next step (plain MD)
     int par = 0;             // which coordinate buffer is current (flips per fused step)
+    int sp = -1;             // force passes since the last prune; -1: no valid inner list
     std::map<std::tuple<long long, int, int>, hipGraphExec_t> gcache;
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;
@@ -444,6 +450,9 @@ static void set_list_band(Dev<R>& d, const Host& h)
     const double margin = rl2 * (f32 ? 4e-6 : 1e-12) + 2.5 * rl * dr;
     d.rl2_lo = (R)(rl2 - margin);
     d.rl2_hi = (R)(rl2 + margin);
+    const double rin = h.rc + h.skin_in;
+    d.rin2 = h.prune ? (R)(rin * rin) : (R)0;
+    d.in_half2 = (R)(0.25 * h.skin_in * h.skin_in);
 }
 
 template <typename R>
@@ -475,13 +484,16 @@ static size_t layout(membx_sys* s, Dev<R>& d, Mv& m, char* base)
     d.ghost_owner = a.take<int>(h.Gcap); d.ghost_code = a.take<int>(h.Gcap);
     d.n_ghost = a.take<int>(1);
     d.gcnt = a.take<int>(N);
-    d.glist = a.take<int>(7 * (size_t)N);
+    d.glist = a.take<int>(8 * (size_t)N);
     d.orig_ext = a.take<int>(N + h.Gcap);
     d.bslot = a.take<int4>((size_t)N * MAXBT);
     d.scan_part = a.take<int>(2 * SCAN_BLOCKS + 2);
     d.dmax_part = a.take<float>(((size_t)N * 8 + WG - 1) / WG);
     d.nbr = a.take<int>((size_t)h.Kcap * Npad);
     d.ncnt = a.take<int>(N); d.nseg0 = a.take<int>(N);
+    d.nbr_in = a.take<int>((size_t)h.Kcap * Npad);
+    d.ncnt_in = a.take<int>((size_t)N * 8);
+    d.xref_in = a.take<V4<R>>(N);
     d.excl = a.take<int>((size_t)N * MAXEXCL);
     d.exmask = a.take<unsigned>(N);
     d.mol_first = a.take<int>(h.nm); d.mol_kind = a.take<int>(h.nm);
@@ -591,6 +603,7 @@ static void rebuild(membx_sys* s)
     launch_rebuild<R>(d, s->st);
     s->since = 0;
     s->n_rebuilds++;
+    s->sp = -1;   // slots reordered: the inner list must be rebuilt
 }
 
 // nonbonded + bonded forces at the current coordinates (ghosts refreshed
@@ -644,35 +657,48 @@ static void alch_terms(membx_sys* s, bool rebuilt, double lam)
     launch_du_total<R>(d, m, m.md + 1, s->st);
 }
 
-// n steps of BAOAB; alch != nullptr: MDAS segment at fixed lambda
+// n steps of BAOAB; alch != nullptr: MDAS segment at fixed lambda.
+// launch = false only advances the host mirrors (step bookkeeping, list
+// schedule, coordinate buffer) exactly as the launches would.
 template <typename R>
-static void steps_seq(membx_sys* s, long long n, const Alch* alch)
+static void steps_seq(membx_sys* s, long long n, const Alch* alch, bool launch = true)
 {
     Dev<R>& d = dev<R>(s);
     const R h = (R)(0.5 * s->h.dt), full = (R)s->h.dt;
+    const bool inner = s->h.prune > 1 && s->h.lpb >= 2;
+    if (alch) s->sp = -1;   // MDAS segments walk the Verlet list; no inner bookkeeping
     bool moved = false;   // the previous force pass already moved the beads
     for (long long k = 0; k < n; ++k) {
-        if (!moved) launch_kick_drift<R>(d, k == 0 ? h : full, k, s->st);
+        if (!moved && launch)
+            launch_kick_drift<R>(d, k == 0 ? h : full, k, (inner && s->sp >= 0) ? 1 : 0, s->st);
         moved = false;
         bool rebuilt = false;
-        if (++s->since >= s->h.R) { rebuild<R>(s); rebuilt = true; }
+        if (++s->since >= s->h.R) {
+            if (launch) rebuild<R>(s);
+            else { s->since = 0; s->n_rebuilds++; s->sp = -1; }
+            rebuilt = true;
+        }
         if (!alch && s->fuse && !s->timing && k + 1 < n) {
-            // forces of step k and B-A-O-A of step k + 1 in one pass
-            launch_nonbonded_fused<R>(d, s->h.lpb, full, k + 1, d.posq_alt, d.vel, 1, s->st);
+            // forces of step k and B-A-O-A of step k + 1 in one pass, on the
+            // inner list between prunes
+            int list = 0;
+            if (inner) {
+                if (s->sp < 0 || s->sp >= s->h.prune - 1) { list = 2; s->sp = 0; }
+                else { list = 1; s->sp++; }
+            }
+            if (launch)
+                launch_nonbonded_fused<R>(d, s->h.lpb, list, full, k + 1, d.posq_alt, d.vel, 1, s->st);
             swap_coords<R>(s);
             moved = true;
         } else {
-            forces<R>(s, rebuilt);
-            if (alch) alch_terms<R>(s, rebuilt, alch->lam);
+            if (launch) {
+                forces<R>(s, rebuilt);
+                if (alch) alch_terms<R>(s, rebuilt, alch->lam);
+            }
+            if (s->sp >= 0) s->sp++;
         }
     }
-    launch_kick<R>(d, h, n, s->st);
-}
-
-// fused steps of a k-step sequence of plain MD (each flips the buffers)
-static long long fused_flips(const membx_sys* s, long long k)
-{
-    return (s->fuse && !s->timing && k > 1) ? k - 1 : 0;
+    if (launch) launch_kick<R>(d, h, n, s->st);
 }
 
 template <typename R>
@@ -683,11 +709,10 @@ static int32_t md_steps(membx_sys* s, long long n)
     while (n > 0) {
         long long k = std::min(n, chunk);
         if (s->graphs && !s->timing) {
-            auto key = std::make_tuple(k, s->since, 2 + s->par);
+            auto key = std::make_tuple(k, s->since, 2 + s->par + 2 * (s->sp + 1));
             auto it = s->gcache.find(key);
-            int since0 = s->since;
-            long long nrb0 = s->n_rebuilds;
-            const int par0 = s->par;
+            const int since0 = s->since, par0 = s->par, sp0 = s->sp;
+            const long long nrb0 = s->n_rebuilds;
             if (it == s->gcache.end()) {
                 hipGraph_t g;
                 if (hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal) != hipSuccess)
@@ -704,17 +729,16 @@ static int32_t md_steps(membx_sys* s, long long n)
                     s->gcache.clear();
                 }
                 it = s->gcache.emplace(key, ge).first;
-                // capture advanced the host mirrors; restore then replay below
+                // capture advanced the host mirrors; restore, then replay below
                 s->since = since0;
                 s->n_rebuilds = nrb0;
+                s->sp = sp0;
                 if (s->par != par0) swap_coords<R>(s);
             }
             if (hipGraphLaunch(it->second, s->st) != hipSuccess)
                 return fail(s, MEMBX_E_DEVICE, "graph launch failed");
-            // advance host mirrors as the sequence does
-            for (long long q = 0; q < k; ++q)
-                if (++s->since >= s->h.R) { s->since = 0; s->n_rebuilds++; }
-            if (fused_flips(s, k) & 1) swap_coords<R>(s);
+            // advance the host mirrors as the sequence does
+            steps_seq<R>(s, k, nullptr, false);
         } else {
             steps_seq<R>(s, k, nullptr);
         }
@@ -944,6 +968,7 @@ static int32_t upload(membx_sys* s, const membx_desc* desc)
     HCK(hipMemsetAsync(d.cell_cnt, 0, sizeof(int) * h.ncell_cap, st));
     HCK(hipMemsetAsync(d.cell_cur, 0, sizeof(int) * h.ncell_cap, st));
     HCK(hipMemsetAsync(d.gcnt, 0, sizeof(int) * h.N, st));
+    HCK(hipMemsetAsync(d.ncnt_in, 0, sizeof(int) * (size_t)h.N * 8, st));
     HCK(hipMemsetAsync(d.dmax_part, 0, sizeof(float) * (((size_t)h.N * 8 + WG - 1) / WG), st));
     HCK(hipMemsetAsync(m.hb_word, 0, sizeof(unsigned long long) * ((size_t)m.hb_mask + 1), st));
     HCK(hipMemsetAsync(m.mb_word, 0, sizeof(unsigned long long) * ((size_t)m.mb_mask + 1), st));
@@ -998,6 +1023,8 @@ static int32_t flag_status(membx_sys* s, const int* fl)
     if (fl[FL_LIST_OVF] || fl[FL_GHOST_OVF] || fl[FL_AFF_OVF])
         return fail(s, MEMBX_E_LIST_OVERFLOW, "neighbour list / ghost / affected-set capacity exceeded");
     if (fl[FL_SKIN]) return fail(s, MEMBX_E_SKIN, "a bead moved more than skin/2 between rebuilds");
+    if (fl[FL_SKIN_IN])
+        return fail(s, MEMBX_E_SKIN, "a bead moved more than skin_inner/2 between inner-list prunes");
     return MEMBX_OK;
 }
 
@@ -1167,6 +1194,7 @@ static void reset_disp(membx_sys* s)
     Dev<R>& d = dev<R>(s);
     launch_fill_i32((int*)d.dmax_part, 0, ((size_t)d.N * 8 + WG - 1) / WG, s->st);
     launch_fill_i32(d.flags + FL_SKIN, 0, 1, s->st);
+    launch_fill_i32(d.flags + FL_SKIN_IN, 0, 1, s->st);
 }
 
 template <typename R>
@@ -1187,7 +1215,7 @@ static int32_t energies_impl(membx_sys* s, membx_energy* out)
     E.n_pairs_in_cutoff = (int64_t)std::llround(e[5]);
     E.fe_count = s->fe; E.step = s->step; E.batch = s->batch; E.cycle = s->cycle;
     E.n_rebuilds = s->n_rebuilds;
-    E.n_skin_violations = fl[FL_SKIN];
+    E.n_skin_violations = (int64_t)fl[FL_SKIN] + fl[FL_SKIN_IN];
     {
         double dm = 0.0;
         int32_t rc2 = max_disp<R>(s, &dm);
@@ -1457,14 +1485,14 @@ static int32_t tune_restore(membx_sys* s, const Saved& sv)
     return MEMBX_OK;
 }
 
-// Candidates: skins from 0.1 nm to skin_max in 0.05 nm steps, lanes per bead
-// 4 and 8.  A pilot run at rebuild interval 4 gives the largest displacement
-// d4; in the ballistic regime (interval << 1/gamma) displacements grow
-// linearly with time, so interval R keeps every bead within 0.8 skin/2 when
-// R <= 4 * 0.8 (skin/2) / d4.  Each candidate runs n steps untimed (graph
-// capture) and n steps timed; it is rejected if a bead went beyond 0.9 skin/2.
+// Autotuner (see membx_autotune for the search).
+struct Tune {
+    double skin, skin_in;
+    int R, lpb, prune;
+};
+
 template <typename R>
-static int32_t autotune_impl(membx_sys* s, int n, double* o_skin, int* o_R, int* o_lpb)
+static int32_t autotune_impl(membx_sys* s, int n, Tune* out)
 {
     if (n <= 0) n = 200;
     const bool graphs0 = s->graphs;
@@ -1474,12 +1502,13 @@ static int32_t autotune_impl(membx_sys* s, int n, double* o_skin, int* o_R, int*
     if (rc) return rc;
     const double skin_max = s->h.skin_max;
     const int lpb0 = s->h.lpb;
-    auto apply = [&](double skin, int Rr, int lpb) -> int32_t {
-        s->h.skin = skin; s->h.R = Rr; s->h.lpb = lpb;
+    auto apply = [&](const Tune& t) -> int32_t {
+        s->h.skin = t.skin; s->h.R = t.R; s->h.lpb = t.lpb;
+        s->h.prune = t.prune; s->h.skin_in = t.prune ? t.skin_in : 0.0;
         return retune_impl<R>(s);
     };
-    // pilot
-    if ((rc = apply(skin_max, 4, lpb0))) return rc;
+    // pilot: largest displacement over rebuild intervals of 4 steps
+    if ((rc = apply(Tune{ skin_max, 0.0, 4, lpb0, 0 }))) return rc;
     if ((rc = md_steps<R>(s, n))) return rc;
     double d4 = 0.0;
     if ((rc = max_disp<R>(s, &d4))) return rc;
@@ -1488,54 +1517,68 @@ static int32_t autotune_impl(membx_sys* s, int n, double* o_skin, int* o_R, int*
     hipEvent_t e0, e1;
     HCK(hipEventCreate(&e0));
     HCK(hipEventCreate(&e1));
-    double best_t = 1e300, best_skin = s->h.skin;
-    int best_R = s->h.R, best_lpb = lpb0;
+    double best_t = 1e300;
+    Tune best{ s->h.skin, s->h.skin_in, s->h.R, lpb0, s->h.prune };
     for (int lpb : { 4, 8 }) {
-        for (double skin = 0.1; skin <= skin_max + 1e-9; skin += 0.05) {
+        for (double skin = 0.2; skin <= skin_max + 1e-9; skin += 0.1) {
             const int Rr = std::min(50, (int)std::floor(4.0 * 0.8 * 0.5 * skin / d4));
             if (Rr < 1) continue;
-            if ((rc = apply(skin, Rr, lpb))) break;
-            if ((rc = md_steps<R>(s, n))) break;
-            reset_disp<R>(s);
-            HCK(hipEventRecord(e0, s->st));
-            if ((rc = md_steps<R>(s, n))) break;
-            HCK(hipEventRecord(e1, s->st));
-            HCK(hipEventSynchronize(e1));
-            float ms = 0.f;
-            HCK(hipEventElapsedTime(&ms, e0, e1));
-            double dm = 0.0;
-            if ((rc = max_disp<R>(s, &dm))) break;
-            int fl[NFLAGS];
-            if ((rc = read_flags(s, fl))) break;
-            const bool ok = fl[FL_SKIN] == 0 && dm <= 0.9 * 0.5 * skin &&
-                            !fl[FL_LIST_OVF] && !fl[FL_GHOST_OVF];
-            if (ok && ms < best_t) { best_t = ms; best_skin = skin; best_R = Rr; best_lpb = lpb; }
-            if ((rc = tune_restore<R>(s, sv))) break;
+            for (int prune : { 0, 2, 3, 4 }) {
+                Tune t{ skin, 0.0, Rr, lpb, prune };
+                if (prune) {
+                    if (prune >= Rr) continue;
+                    // buffer keeping every bead within 0.8 delta/2 over a prune interval
+                    const double din = std::ceil(100.0 * 2.0 * d4 * prune / 4.0 / 0.8) / 100.0;
+                    if (din >= skin) continue;
+                    t.skin_in = din;
+                }
+                if ((rc = apply(t))) break;
+                if ((rc = md_steps<R>(s, n))) break;
+                reset_disp<R>(s);
+                HCK(hipEventRecord(e0, s->st));
+                if ((rc = md_steps<R>(s, n))) break;
+                HCK(hipEventRecord(e1, s->st));
+                HCK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HCK(hipEventElapsedTime(&ms, e0, e1));
+                double dm = 0.0;
+                if ((rc = max_disp<R>(s, &dm))) break;
+                int fl[NFLAGS];
+                if ((rc = read_flags(s, fl))) break;
+                const bool ok = fl[FL_SKIN] == 0 && fl[FL_SKIN_IN] == 0 && dm <= 0.9 * 0.5 * skin &&
+                                !fl[FL_LIST_OVF] && !fl[FL_GHOST_OVF];
+                if (ok && ms < best_t) { best_t = ms; best = t; }
+                if ((rc = tune_restore<R>(s, sv))) break;
+            }
+            if (rc) break;
         }
         if (rc) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
-    if ((rc = apply(best_skin, best_R, best_lpb))) return rc;
+    if ((rc = apply(best))) return rc;
     if ((rc = tune_restore<R>(s, sv))) return rc;
     s->graphs = graphs0;
-    if (o_skin) *o_skin = best_skin;
-    if (o_R) *o_R = best_R;
-    if (o_lpb) *o_lpb = best_lpb;
+    *out = best;
     return MEMBX_OK;
 }
 
 int32_t membx_set_tuning(membx_sys* s, double skin, int32_t rebuild_interval,
-                         int32_t lanes_per_bead)
+                         int32_t lanes_per_bead, double skin_inner, int32_t prune_interval)
 {
     if (!s) return MEMBX_E_INVAL;
     if (!(skin > 0) || skin > s->h.skin_max + 1e-12 || rebuild_interval < 1 ||
         (lanes_per_bead != 1 && lanes_per_bead != 2 && lanes_per_bead != 4 && lanes_per_bead != 8))
         return fail(s, MEMBX_E_INVAL, "bad tuning");
+    const int prune = prune_interval > 1 ? prune_interval : 0;
+    if (prune && (!(skin_inner > 0) || skin_inner > skin + 1e-12 || lanes_per_bead < 2))
+        return fail(s, MEMBX_E_INVAL, "bad inner-list tuning");
     s->h.skin = skin;
     s->h.R = rebuild_interval;
     s->h.lpb = lanes_per_bead;
+    s->h.prune = prune;
+    s->h.skin_in = prune ? skin_inner : 0.0;
     int32_t rc = begin(s);
     if (!rc) rc = DISPATCH(s, retune_impl, s);
     if (!rc) rc = end(s);
@@ -1585,8 +1628,9 @@ static int32_t kbench_impl(membx_sys* s, int n, double* mean_ms)
     // the kernel the MD steps run: forces plus the next step's update, the
     // update written to scratch (the other coordinate buffer, the sort
     // buffer for velocities) so that the state is unchanged
+    const int list = (s->h.prune > 1 && s->h.lpb >= 2 && s->sp >= 0) ? 1 : 0;
     for (int q = 0; q < n; ++q)
-        launch_nonbonded_fused<R>(d, s->h.lpb, (R)s->h.dt, 1, d.posq_alt, d.vel_t, 0, s->st);
+        launch_nonbonded_fused<R>(d, s->h.lpb, list, (R)s->h.dt, 1, d.posq_alt, d.vel_t, 0, s->st);
     if (hipStreamEndCapture(s->st, &g) != hipSuccess)
         return fail(s, MEMBX_E_DEVICE, "stream capture failed");
     hipGraphExec_t ge;
@@ -1644,19 +1688,20 @@ int32_t membx_calib_copy(membx_sys* s, void* dst, const void* src, uint64_t byte
 }
 
 int32_t membx_autotune(membx_sys* s, int32_t n_steps, double* skin, int32_t* rebuild_interval,
-                       int32_t* lanes_per_bead)
+                       int32_t* lanes_per_bead, double* skin_inner, int32_t* prune_interval)
 {
     if (!s) return MEMBX_E_INVAL;
     int32_t rc = begin(s);
     if (rc) return rc;
-    int Rr = 0, lpb = 0;
-    double sk = 0.0;
-    rc = DISPATCH(s, autotune_impl, s, n_steps, &sk, &Rr, &lpb);
+    Tune t{};
+    rc = DISPATCH(s, autotune_impl, s, n_steps, &t);
     if (!rc) rc = end(s);
     if (rc) return rc;
-    if (skin) *skin = sk;
-    if (rebuild_interval) *rebuild_interval = Rr;
-    if (lanes_per_bead) *lanes_per_bead = lpb;
+    if (skin) *skin = t.skin;
+    if (rebuild_interval) *rebuild_interval = t.R;
+    if (lanes_per_bead) *lanes_per_bead = t.lpb;
+    if (skin_inner) *skin_inner = t.skin_in;
+    if (prune_interval) *prune_interval = t.prune;
     return MEMBX_OK;
 }
 

@@ -52,7 +52,8 @@ class Desc(C.Structure):
                 ("skin", C.c_double), ("skin_max", C.c_double),
                 ("rebuild_interval", C.c_int32), ("lanes_per_bead", C.c_int32),
                 ("list_capacity", C.c_int32), ("max_trials", C.c_int32),
-                ("max_pairs", C.c_int32)]
+                ("max_pairs", C.c_int32), ("skin_inner", C.c_double),
+                ("prune_interval", C.c_int32)]
 
 
 class Energy(C.Structure):
@@ -115,8 +116,9 @@ def lib():
             "membx_forces": ([vp, vp], i32),
             "membx_pairset_export": ([vp, vp, i64, C.POINTER(i64)], i32),
             "membx_minimize": ([vp, i32, dp, dp], i32),
-            "membx_set_tuning": ([vp, dp, i32, i32], i32),
-            "membx_autotune": ([vp, i32, C.POINTER(dp), C.POINTER(i32), C.POINTER(i32)], i32),
+            "membx_set_tuning": ([vp, dp, i32, i32, dp, i32], i32),
+            "membx_autotune": ([vp, i32, C.POINTER(dp), C.POINTER(i32), C.POINTER(i32),
+                                C.POINTER(dp), C.POINTER(i32)], i32),
             "membx_set_graphs": ([vp, i32], i32),
             "membx_kernel_timing": ([vp, i32], i32),
             "membx_kernel_time": ([vp, C.POINTER(i64), C.POINTER(dp)], i32),
@@ -148,7 +150,7 @@ class _DescBuilder:
     """Keeps the numpy buffers a membx_desc points to alive."""
 
     def __init__(self, system, precision, skin, skin_max, rebuild_interval, lanes_per_bead,
-                 list_capacity, max_trials, max_pairs):
+                 list_capacity, max_trials, max_pairs, skin_inner=0.0, prune_interval=0):
         s = system
         self.keep = []
         kinds = (Kind * len(s.kinds))()
@@ -202,6 +204,8 @@ class _DescBuilder:
         d.list_capacity = list_capacity
         d.max_trials = max_trials
         d.max_pairs = max_pairs
+        d.skin_inner = skin_inner
+        d.prune_interval = prune_interval
         self.desc = d
 
 
@@ -222,7 +226,7 @@ def arena_bytes(system, precision="mixed", **tuning):
 def _tuning(t):
     return (t.get("skin", 0.0), t.get("skin_max", 0.0), t.get("rebuild_interval", 0),
             t.get("lanes_per_bead", 0), t.get("list_capacity", 0), t.get("max_trials", 0),
-            t.get("max_pairs", 0))
+            t.get("max_pairs", 0), t.get("skin_inner", 0.0), t.get("prune_interval", 0))
 
 
 class System:
@@ -347,15 +351,17 @@ class System:
         return lib().membx_status(self.h)
 
     # --------------------------------------------------------------- tuning
-    def set_tuning(self, skin, rebuild_interval, lanes_per_bead):
+    def set_tuning(self, skin, rebuild_interval, lanes_per_bead, skin_inner=0.0, prune_interval=0):
         _check(lib().membx_set_tuning(self.h, float(skin), int(rebuild_interval),
-                                      int(lanes_per_bead)), self.h)
+                                      int(lanes_per_bead), float(skin_inner), int(prune_interval)),
+               self.h)
 
     def autotune(self, n_steps=200):
-        sk, R, l = C.c_double(), C.c_int32(), C.c_int32()
-        _check(lib().membx_autotune(self.h, int(n_steps), C.byref(sk), C.byref(R), C.byref(l)),
-               self.h)
-        return dict(skin=sk.value, rebuild_interval=R.value, lanes_per_bead=l.value)
+        sk, R, l, si, pr = C.c_double(), C.c_int32(), C.c_int32(), C.c_double(), C.c_int32()
+        _check(lib().membx_autotune(self.h, int(n_steps), C.byref(sk), C.byref(R), C.byref(l),
+                                    C.byref(si), C.byref(pr)), self.h)
+        return dict(skin=sk.value, rebuild_interval=R.value, lanes_per_bead=l.value,
+                    skin_inner=si.value, prune_interval=pr.value)
 
     def set_graphs(self, enable):
         _check(lib().membx_set_graphs(self.h, int(bool(enable))), self.h)

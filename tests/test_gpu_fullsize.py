@@ -129,3 +129,35 @@ def test_mdas_frozen_c3(oracle_mod):
     assert abs(rg["work"] - ro["work"]) < 1e-6
     assert rg["accept"] == ro["accept"]
     g.close()
+
+
+def test_md_c1_inner_list_fp64(oracle_mod, c1):
+    """Float64 trajectory with dynamic pruning (outer skin 0.5 nm rebuilt
+    every 9 steps, inner list at r_cut + 0.15 nm pruned every 3 force passes)
+    over 12 steps follows the oracle."""
+    m = _membx()
+    g = m.System(c1, precision="fp64", skin=0.5, rebuild_interval=9, lanes_per_bead=8,
+                 skin_inner=0.15, prune_interval=3)
+    g.minimize(50)
+    st = g.state()
+    o = oracle_mod.Oracle(c1)
+    o.set_state(pos=st["pos"], vel=st["vel"], mol_kind=st["mol_kind"])
+    g.md_step(12)
+    o.md_step(12)
+    d = g.state()["pos"] - o.state()["pos"]
+    d -= c1.box * np.rint(d / c1.box)
+    assert np.abs(d).max() < 1e-7
+    e = g.energies()
+    assert e["n_skin_violations"] == 0
+    g.close()
+
+
+def test_forces_c1_inner_list_mixed(oracle_mod, c1):
+    """Forces after 40 steps with the inner list (mixed precision)."""
+    m = _membx()
+    g = _aged(m, c1, "mixed", steps=40, skin=0.5, rebuild_interval=9, lanes_per_bead=4,
+              skin_inner=0.15, prune_interval=3)
+    o = oracle_mod.Oracle(c1)
+    _check_sampled_forces(o, g, c1.n_beads, "mixed", 3000, 17)
+    assert g.energies()["n_skin_violations"] == 0
+    g.close()
