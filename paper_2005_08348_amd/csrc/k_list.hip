@@ -314,7 +314,7 @@ __device__ __forceinline__ bool within_d(double xi, double yi, double zi, double
 }
 
 constexpr int LB = 256;   // threads per cell
-constexpr int HS = 16;    // LDS hit slots per lane (single-pass path)
+constexpr int HS = 32;    // LDS candidate slots per lane (16-bit candidate indices)
 constexpr int LU = 4;     // candidates per lane per round (LDS reads in flight)
 template <typename R> struct CandCap { static constexpr int v = 1024; };
 template <> struct CandCap<double> { static constexpr int v = 512; };
@@ -334,101 +334,131 @@ __device__ __forceinline__ bool exact_in(const Dev<R>& d, const V4<R>& pi, int e
                     d.rl2d);
 }
 
+template <typename R>
+__device__ __forceinline__ R img_r2(const V4<R>& pi, const V4<R>& pj)
+{
+    const R dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+    return dx * dx + dy * dy + dz * dz;
+}
+
 // One candidate: prefilter in R on the candidate image stored in LDS (the j
 // bead shifted UP by L along the code axes, rounded): below rl2_lo a hit,
 // above rl2_hi a miss, the band in between decided exactly.  Bonded partners
-// and the bead itself are excluded through the bead's exclusion mask.
-template <typename R>
-__device__ __forceinline__ bool cand_in(const Dev<R>& d, const V4<R>& pi, int oi, unsigned exm,
-                                        const V4<R>& pj, int ent)
+// and the bead itself are excluded through the bead's exclusion mask (bit
+// 16 + class - bead id; the 64-bit shift reads zero beyond bit 31).  The band
+// is many ulps wide, so the decision does not depend on how r^2 was rounded.
+__device__ __forceinline__ bool excluded(unsigned long long exm, int rel)
 {
-    const R dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-    const R r2 = dx * dx + dy * dy + dz * dz;
+    return (exm >> min((unsigned)rel, 63u)) & 1ull;
+}
+
+template <typename R>
+__device__ __forceinline__ bool cand_in(const Dev<R>& d, const V4<R>& pi, int oi16,
+                                        unsigned long long exm, const V4<R>& pj, int ent)
+{
+    const R r2 = img_r2(pi, pj);
     bool in = r2 < d.rl2_lo;
     if (!in && !(r2 > d.rl2_hi)) in = exact_in(d, pi, ent);
-    const unsigned rel = (unsigned)(cls_of<R>(pj.w) - oi + 16);
-    return in && !(rel < 32u && ((exm >> rel) & 1u));
+    return in && !excluded(exm, cls_of<R>(pj.w) + oi16);
 }
 
 // List build, one work-group per cell.  The candidates of the 27 neighbour
 // cells are staged in LDS (image position, bead id, entry = slot | code << 29
-// with code the axes along which the i bead is shifted); each bead of the
-// cell owns Q lanes that split the candidates.  Hits go to per-lane LDS
-// buffers and are written out in a fixed order (lane q of bead i after lanes
-// 0..q-1), so the lists are deterministic.  If a buffer overflows (very
-// crowded cells) the cell falls back to two passes: count, then test again
-// and write in place.
+// with code the axes along which the i bead is shifted), followed by a
+// sentinel that never hits; each bead of the cell owns Q lanes that split
+// the candidates (lane q takes q, q + Q, ...).  Per staging round every lane
+// tests its candidates once (the rare band cases exactly, in a wave-uniform
+// branch) and notes the hits in its LDS buffer as 16-bit candidate indices;
+// lane q of bead i then writes its entries after lanes 0..q-1 and after the
+// earlier rounds, so the lists are deterministic.  A lane whose buffer
+// overflows (very crowded cells) tests its candidates again while writing.
 template <typename R>
 __global__ __launch_bounds__(LB) void k_list(Dev<R> d)
 {
     constexpr int CMAX = CandCap<R>::v;
-    __shared__ V4<R> cpos[CMAX + 1];  // + a sentinel that never hits
+    constexpr int NW = LB / 64;
+    constexpr int HP = HS + 4;   // buffer pitch (8-byte aligned rows)
+    __shared__ V4<R> cpos[CMAX + 1];
     __shared__ int cjs[CMAX + 1];
-    __shared__ int hits[LB * (HS + 1)];
+    __shared__ __align__(8) unsigned short hits[LB * HP];
     __shared__ int off[28], jst[27], cod[27];
     __shared__ int cnt[LB];
     const int cell = blockIdx.x;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
     const int Kc = d.Kcap;
     if (t == 0) { d.cell_cnt[cell] = 0; d.cell_cur[cell] = 0; }   // for the next rebuild
     const int s0 = d.cell_start[cell], ni = d.cell_start[cell + 1] - s0;
     if (ni == 0) return;
-    const int cz = cell % d.nc[2], cy = (cell / d.nc[2]) % d.nc[1], cx = cell / (d.nc[2] * d.nc[1]);
-    if (t < 27) {
-        const int ox = t / 9 - 1, oy = (t / 3) % 3 - 1, oz = t % 3 - 1;
-        int ax = cx + ox, ay = cy + oy, az = cz + oz, code = 0;
-        if (ax == d.nc[0]) { ax = 0; code |= 1; }
-        if (ay == d.nc[1]) { ay = 0; code |= 2; }
-        if (az == d.nc[2]) { az = 0; code |= 4; }
-        const int e = ((ax + 1) * d.ne[1] + (ay + 1)) * d.ne[2] + (az + 1);
-        jst[t] = d.ext_start[e];
-        off[t + 1] = d.ext_cnt[e];
-        cod[t] = code;
-    }
-    if (t == 32) {
-        const R far = (R)1e15;
-        cpos[CMAX] = V4<R>{ far, far, far, cls_to<R>(-(1 << 20)) };
-        cjs[CMAX] = 0;
-    }
-    __syncthreads();
-    if (t == 0) {
-        off[0] = 0;
-        for (int o = 0; o < 27; ++o) off[o + 1] += off[o];
+    if (w == 0) {
+        const int cz = cell % d.nc[2], cy = (cell / d.nc[2]) % d.nc[1], cx = cell / (d.nc[2] * d.nc[1]);
+        int n = 0;
+        if (l < 27) {
+            const int ox = l / 9 - 1, oy = (l / 3) % 3 - 1, oz = l % 3 - 1;
+            int ax = cx + ox, ay = cy + oy, az = cz + oz, code = 0;
+            if (ax == d.nc[0]) { ax = 0; code |= 1; }
+            if (ay == d.nc[1]) { ay = 0; code |= 2; }
+            if (az == d.nc[2]) { az = 0; code |= 4; }
+            const int e = ((ax + 1) * d.ne[1] + (ay + 1)) * d.ne[2] + (az + 1);
+            jst[l] = d.ext_start[e];
+            cod[l] = code;
+            n = d.ext_cnt[e];
+        }
+#pragma unroll
+        for (int m = 1; m < 32; m <<= 1) {
+            const int y = __shfl_up(n, m);
+            if (l >= m) n += y;
+        }
+        if (l < 27) off[l + 1] = n;
+        if (l == 0) off[0] = 0;
     }
     __syncthreads();
     const int C = off[27];
     const bool one_round = C <= CMAX;
+    // staging: wave w takes cells w, w + NW, ..., one candidate per lane
+    // (loads of all its cells in flight), cells above 64 candidates looped
     auto stage = [&](int cb, int nc) {
         __syncthreads();
-        constexpr int PT = (CMAX + LB - 1) / LB;
-        for (int u0 = 0; u0 < PT; u0 += 4) {
-            int js[4], cs[4];
+        constexpr int NU = (27 + NW - 1) / NW;
+        int js[NU], dst[NU], cs[NU];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int c = t + (u0 + u) * LB, idx = cb + c;
-                int o = 0;
-                if (c < nc)
-                    while (off[o + 1] <= idx) ++o;
-                js[u] = c < nc ? jst[o] + (idx - off[o]) : 0;
-                cs[u] = cod[o];
-            }
-            V4<R> ps[4];
-            int oj[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) { ps[u] = d.posq[js[u]]; oj[u] = d.orig_ext[js[u]]; }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int c = t + (u0 + u) * LB;
-                if (c < nc) {
-                    V4<R> p = ps[u];
-                    if (cs[u] & 1) p.x += d.L[0];
-                    if (cs[u] & 2) p.y += d.L[1];
-                    if (cs[u] & 4) p.z += d.L[2];
-                    p.w = cls_to<R>(oj[u]);
-                    cpos[c] = p;
-                    cjs[c] = js[u] | (cs[u] << CODE_SHIFT);
+        for (int u = 0; u < NU; ++u) {
+            const int o = w + u * NW;
+            dst[u] = -1; js[u] = 0; cs[u] = 0;
+            if (o < 27) {
+                const int lo = max(off[o], cb), hi = min(off[o + 1], cb + nc);
+                if (lo + l < hi) {
+                    dst[u] = lo + l - cb;
+                    js[u] = jst[o] + (lo + l - off[o]);
+                    cs[u] = cod[o];
                 }
             }
+        }
+        V4<R> ps[NU];
+        int oj[NU];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) { ps[u] = d.posq[js[u]]; oj[u] = d.orig_ext[js[u]]; }
+        auto put = [&](int c, V4<R> p, int code, int oo, int j) {
+            if (code & 1) p.x += d.L[0];
+            if (code & 2) p.y += d.L[1];
+            if (code & 4) p.z += d.L[2];
+            p.w = cls_to<R>(oo);
+            cpos[c] = p;
+            cjs[c] = j | (code << CODE_SHIFT);
+        };
+#pragma unroll
+        for (int u = 0; u < NU; ++u)
+            if (dst[u] >= 0) put(dst[u], ps[u], cs[u], oj[u], js[u]);
+        for (int o = w; o < 27; o += NW) {
+            const int lo = max(off[o], cb), hi = min(off[o + 1], cb + nc);
+            for (int idx = lo + 64 + l; idx < hi; idx += 64) {
+                const int j = jst[o] + (idx - off[o]);
+                put(idx - cb, d.posq[j], cod[o], d.orig_ext[j], j);
+            }
+        }
+        if (t == 0) {
+            const R far = (R)1e15;
+            cpos[nc] = V4<R>{ far, far, far, cls_to<R>(-(1 << 20)) };
+            cjs[nc] = 0;
         }
         __syncthreads();
     };
@@ -439,75 +469,91 @@ __global__ __launch_bounds__(LB) void k_list(Dev<R> d)
         const bool act = li < nib;
         const int i = s0 + ib + (act ? li : 0);
         const V4<R> pi = d.posq[i];
-        const int oi = d.orig[i];
-        const unsigned exm = d.exmask[oi];
+        const int oi16 = 16 - d.orig[i];
+        const unsigned long long exm = d.exmask[d.orig[i]];
         const size_t ibase = nbr_base(i, Kc, d.lpb_shift, d.bg_shift);
-        // single pass: every candidate tested once, hits to the lane's LDS
-        // buffer (a hit past the buffer sets the overflow flag and lands in
-        // the scratch slot HS)
-        int nh = 0;
-        bool lane_ovf = false;
+        unsigned short* hb = hits + t * HP;
+        int kb = 0;   // entries of bead i written by earlier rounds
         for (int cb = 0; cb < C; cb += CMAX) {
             const int nc = min(CMAX, C - cb);
             if (!(one_round && ib > 0)) stage(cb, nc);
             const int nu = (nc + Q - 1) / Q;
+            const int q0 = act ? q : nc;   // idle lanes read the sentinel only
+            // every candidate is written to the next free slot (slot HS once
+            // full); the count advances on a hit
+            int nh = 0;
+            const R lo2 = d.rl2_lo, hi2 = d.rl2_hi;
             for (int u0 = 0; u0 < nu; u0 += LU) {
+                int cc[LU];
                 V4<R> pj[LU];
-                int en[LU];
 #pragma unroll
                 for (int k = 0; k < LU; ++k) {
-                    const int c = q + (u0 + k) * Q;
-                    const int cc = (act && c < nc) ? c : CMAX;
-                    pj[k] = cpos[cc];
-                    en[k] = cjs[cc];
+                    cc[k] = min(q0 + (u0 + k) * Q, nc);
+                    pj[k] = cpos[cc[k]];
+                }
+                bool in[LU];
+                unsigned bm = 0;   // candidates in the band
+#pragma unroll
+                for (int k = 0; k < LU; ++k) {
+                    const R r2 = img_r2(pi, pj[k]);
+                    const bool ex = excluded(exm, cls_of<R>(pj[k].w) + oi16);
+                    in[k] = !(r2 > hi2) & !ex;
+                    bm |= (unsigned)(in[k] & !(r2 < lo2)) << k;
+                }
+                if (__builtin_expect(__any(bm != 0), 0)) {
+#pragma unroll
+                    for (int k = 0; k < LU; ++k)
+                        if ((bm >> k) & 1u) in[k] = exact_in(d, pi, cjs[cc[k]]);
                 }
 #pragma unroll
                 for (int k = 0; k < LU; ++k) {
-                    const bool hit = cand_in(d, pi, oi, exm, pj[k], en[k]);
-                    hits[t * (HS + 1) + ((hit && nh < HS) ? nh : HS)] = en[k];
-                    lane_ovf |= hit && nh >= HS;
-                    nh += hit ? 1 : 0;
+                    hb[min(nh, HS)] = (unsigned short)cc[k];
+                    nh += in[k] ? 1 : 0;
                 }
             }
-        }
-        const bool ovf_any = __syncthreads_or(lane_ovf ? 1 : 0) != 0;
-        cnt[t] = act ? nh : 0;
-        __syncthreads();
-        int b0 = 0, tot = 0;
-        if (act) {
-            for (int qq = 0; qq < Q; ++qq) {
-                const int c0 = cnt[li * Q + qq];
-                if (qq < q) b0 += c0;
-                tot += c0;
-            }
-            if (q == 0) {
-                d.nseg0[i] = 0;
-                d.ncnt[i] = min(tot, Kc);
-                if (tot > Kc) atomicOr(&d.flags[FL_LIST_OVF], 1);
-            }
-        }
-        if (!ovf_any) {
+            cnt[t] = act ? nh : 0;
+            __syncthreads();
+            int b0 = 0, tot = 0;
             if (act)
-                for (int k = 0; k < nh; ++k)
-                    if (b0 + k < Kc) d.nbr[ibase + nbr_koff(b0 + k, d.lpb_shift)] = hits[t * (HS + 1) + k];
-        } else {
-            // crowded cell: test again and write in place at the known offsets
-            int m0 = 0;
-            for (int cb = 0; cb < C; cb += CMAX) {
-                const int nc = min(CMAX, C - cb);
-                if (!one_round) stage(cb, nc);
-                const int nu = (nc + Q - 1) / Q;
-                for (int u = 0; u < nu; ++u) {
-                    const int c = q + u * Q;
-                    if (!(act && c < nc)) continue;
-                    const int ent = cjs[c];
-                    if (!cand_in(d, pi, oi, exm, cpos[c], ent)) continue;
-                    const int k = b0 + m0++;
-                    if (k < Kc) d.nbr[ibase + nbr_koff(k, d.lpb_shift)] = ent;
+                for (int qq = 0; qq < Q; ++qq) {
+                    const int c0 = cnt[li * Q + qq];
+                    if (qq < q) b0 += c0;
+                    tot += c0;
+                }
+            if (act) {
+                const int k0 = kb + b0;
+                if (nh <= HS) {
+                    // four entries per round: buffer word, then their entries
+                    for (int k = 0; k < nh; k += 4) {
+                        const uint2 hw = *reinterpret_cast<const uint2*>(hb + k);
+                        const int c4[4] = { (int)(hw.x & 0xffff), (int)(hw.x >> 16),
+                                            (int)(hw.y & 0xffff), (int)(hw.y >> 16) };
+                        int e4[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) e4[u] = cjs[min(c4[u], nc)];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            if (k + u < nh && k0 + k + u < Kc)
+                                d.nbr[ibase + nbr_koff(k0 + k + u, d.lpb_shift)] = e4[u];
+                    }
+                } else {
+                    int mm = 0;
+                    for (int u = 0; u < nu; ++u) {
+                        const int c = q + u * Q;
+                        if (!(c < nc && cand_in(d, pi, oi16, exm, cpos[c], cjs[c]))) continue;
+                        const int k = k0 + mm++;
+                        if (k < Kc) d.nbr[ibase + nbr_koff(k, d.lpb_shift)] = cjs[c];
+                    }
                 }
             }
+            kb += tot;
+            __syncthreads();   // cnt, the buffers and the staged candidates are reused
         }
-        __syncthreads();
+        if (act && q == 0) {
+            d.nseg0[i] = 0;
+            d.ncnt[i] = min(kb, Kc);
+            if (kb > Kc) atomicOr(&d.flags[FL_LIST_OVF], 1);
+        }
     }
 }
 
