@@ -13,41 +13,14 @@
 // three bits saying along which axes the i bead is shifted.  All resulting
 // separations are single correctly rounded differences.
 //
-// List build: one work-group per cell, candidates staged in LDS, two passes
-// (count, then write in place) so that the lists come out in a fixed order.
+// Rebuild: binning, the cell layout (one work-group), scatter,
+// per-cell sort and images, then the list build, one work-group per cell.
 #include "membx_dev.h"
 
 namespace mbx {
 
 // ---------------------------------------------------------------- binning
-template <typename R>
-__global__ void k_bin(Dev<R> d)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= d.N) return;
-    V4<R> p = d.posq[i];
-    R* c[3] = { &p.x, &p.y, &p.z };
-    int cc[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        R x = *c[a];
-        if (x >= d.L[a]) x -= d.L[a];        // exact (Sterbenz) for x in [L, 2L]
-        else if (x < (R)0) x += d.L[a];
-        if (!(x >= (R)0 && x < d.L[a])) {     // far outside (set_state, minimizer)
-            double xd = (double)*c[a];
-            xd -= d.Ld[a] * floor(xd / d.Ld[a]);
-            x = (R)xd;
-            if (!(x < d.L[a])) x = (R)0;
-        }
-        *c[a] = x;
-        int ci = (int)(x * d.inv_edge[a]);
-        cc[a] = ci < 0 ? 0 : (ci >= d.nc[a] ? d.nc[a] - 1 : ci);
-    }
-    d.posq[i] = p;
-    int cell = (cc[0] * d.nc[1] + cc[1]) * d.nc[2] + cc[2];
-    d.cell_t[i] = cell;
-    atomicAdd(&d.cell_cnt[cell], 1);
-}
+constexpr int BB = 1024;   // threads per binning block and of the cell layout
 
 // Extended grid: coordinate a in [0, nc] per axis, a = 0 is the halo layer
 // holding images (shifted by -L) of real layer nc-1; a >= 1 is real cell a-1.
@@ -64,66 +37,14 @@ __device__ __forceinline__ int ext_source(const int a[3], const int nc[3])
            (a[2] ? a[2] - 1 : nc[2] - 1);
 }
 
-// Cell starts (exclusive scan of the real-cell counts) and the extended
-// grid (real cells point into the slots, halo cells into the ghost range laid
-// out by a scan of their source cells' counts), in three kernels: per-block
-// sums, a scan of the block sums, and the per-block write-out.
-__device__ __forceinline__ int halo_count(const int* cnt, int e, const int ne[3], const int nc[3],
-                                          int* src_out)
-{
-    int a[3];
-    ext_coords(e, ne, a);
-    int src = ext_source(a, nc);
-    *src_out = src;
-    return (a[0] == 0 || a[1] == 0 || a[2] == 0) ? cnt[src] : -1;
-}
-
-template <typename R>
-__global__ __launch_bounds__(256) void k_scan_a(Dev<R> d)
-{
-    __shared__ int sh[2][4];
-    const int b = blockIdx.x, t = threadIdx.x;
-    const int segR = (d.ncell + SCAN_BLOCKS - 1) / SCAN_BLOCKS;
-    const int segE = (d.next + SCAN_BLOCKS - 1) / SCAN_BLOCKS;
-    int sr = 0, se = 0;
-    for (int k = b * segR + t; k < min(d.ncell, (b + 1) * segR); k += 256) sr += d.cell_cnt[k];
-    for (int k = b * segE + t; k < min(d.next, (b + 1) * segE); k += 256) {
-        int src, h = halo_count(d.cell_cnt, k, d.ne, d.nc, &src);
-        se += h > 0 ? h : 0;
-    }
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) { sr += __shfl_xor(sr, m); se += __shfl_xor(se, m); }
-    if ((t & 63) == 0) { sh[0][t >> 6] = sr; sh[1][t >> 6] = se; }
-    __syncthreads();
-    if (t == 0) {
-        d.scan_part[b] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
-        d.scan_part[SCAN_BLOCKS + b] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
-    }
-}
-
-template <typename R>
-__global__ void k_scan_b(Dev<R> d)
-{
-    if (threadIdx.x != 0) return;
-    int rr = 0, re = 0;
-    for (int b = 0; b < SCAN_BLOCKS; ++b) {
-        int vr = d.scan_part[b], ve = d.scan_part[SCAN_BLOCKS + b];
-        d.scan_part[b] = rr; d.scan_part[SCAN_BLOCKS + b] = re;
-        rr += vr; re += ve;
-    }
-    d.cell_start[d.ncell] = rr;
-    *d.n_ghost = re < d.Gcap ? re : d.Gcap;
-    if (re > d.Gcap) atomicOr(&d.flags[FL_GHOST_OVF], 1);
-}
-
-// block-wide (256 threads) exclusive scan of per-thread values
-__device__ __forceinline__ int block_scan256(int v, int* sh)
+// block-wide (BB threads) exclusive scan of per-thread values
+__device__ __forceinline__ int block_scan(int v, int* sh)
 {
     const int t = threadIdx.x, l = t & 63, w = t >> 6;
     int x = v;
 #pragma unroll
     for (int m = 1; m < 64; m <<= 1) {
-        int y = __shfl_up(x, m);
+        const int y = __shfl_up(x, m);
         if (l >= m) x += y;
     }
     if (l == 63) sh[w] = x;
@@ -134,153 +55,229 @@ __device__ __forceinline__ int block_scan256(int v, int* sh)
     return base + x - v;
 }
 
+// Cell starts (exclusive scan of the counts) and the extended grid: real
+// extended cells point into the slots, halo cells into the ghost range, laid
+// out by a scan of their source cells' counts.  Run by one work-group of BB
+// threads, each taking a contiguous segment, read LU_L values at a time with
+// all loads in flight.  The counts are cleared for the next rebuild.
+constexpr int LU_L = 8;
+
+__device__ __forceinline__ int load_cnt(const int* p) { return *p; }
+
 template <typename R>
-__global__ __launch_bounds__(256) void k_scan_c(Dev<R> d)
+__device__ void layout_cells(const Dev<R>& d)
 {
-    __shared__ int sh[4];
-    const int b = blockIdx.x, t = threadIdx.x;
-    const int segR = (d.ncell + SCAN_BLOCKS - 1) / SCAN_BLOCKS;
-    const int segE = (d.next + SCAN_BLOCKS - 1) / SCAN_BLOCKS;
+    __shared__ int sh[BB / 64];
+    const int t = threadIdx.x;
     {
-        const int lo = b * segR, hi = min(d.ncell, (b + 1) * segR);
-        const int per = (segR + 255) / 256;
-        const int k0 = lo + t * per, k1 = min(hi, k0 + per);
+        const int per = (d.ncell + BB - 1) / BB;
+        const int k0 = min(d.ncell, t * per), k1 = min(d.ncell, k0 + per);
+        int v[LU_L];
         int s = 0;
-        for (int k = k0; k < k1; ++k) s += d.cell_cnt[k];
-        int run = d.scan_part[b] + block_scan256(s, sh);
-        for (int k = k0; k < k1; ++k) { d.cell_start[k] = run; run += d.cell_cnt[k]; }
+        for (int kb = k0; kb < k1; kb += LU_L) {
+#pragma unroll
+            for (int u = 0; u < LU_L; ++u) v[u] = kb + u < k1 ? load_cnt(d.cell_cnt + kb + u) : 0;
+#pragma unroll
+            for (int u = 0; u < LU_L; ++u) s += v[u];
+        }
+        int run = block_scan(s, sh);
+        for (int kb = k0; kb < k1; kb += LU_L) {
+            if (per > LU_L) {   // segment longer than one batch: load again
+#pragma unroll
+                for (int u = 0; u < LU_L; ++u) v[u] = kb + u < k1 ? load_cnt(d.cell_cnt + kb + u) : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < LU_L; ++u)
+                if (kb + u < k1) { d.cell_start[kb + u] = run; run += v[u]; }
+        }
+        if (t == BB - 1) d.cell_start[d.ncell] = run;
     }
     __syncthreads();
     {
-        const int lo = b * segE, hi = min(d.next, (b + 1) * segE);
-        const int per = (segE + 255) / 256;
-        const int k0 = lo + t * per, k1 = min(hi, k0 + per);
+        const int per = (d.next + BB - 1) / BB;
+        const int k0 = min(d.next, t * per), k1 = min(d.next, k0 + per);
+        int st[LU_L], n[LU_L];
+        unsigned halo = 0;
+        auto fetch = [&](int kb) {
+            halo = 0;
+#pragma unroll
+            for (int u = 0; u < LU_L; ++u) {
+                const int k = min(kb + u, k1 - 1);
+                int a[3];
+                ext_coords(k, d.ne, a);
+                const int src = ext_source(a, d.nc);
+                st[u] = d.cell_start[src];
+                n[u] = d.cell_start[src + 1];
+                if (a[0] == 0 || a[1] == 0 || a[2] == 0) halo |= 1u << u;
+            }
+#pragma unroll
+            for (int u = 0; u < LU_L; ++u) n[u] -= st[u];
+        };
         int s = 0;
-        for (int k = k0; k < k1; ++k) {
-            int src, h = halo_count(d.cell_cnt, k, d.ne, d.nc, &src);
-            s += h > 0 ? h : 0;
+        for (int kb = k0; kb < k1; kb += LU_L) {
+            fetch(kb);
+#pragma unroll
+            for (int u = 0; u < LU_L; ++u)
+                if (kb + u < k1 && ((halo >> u) & 1u)) s += n[u];
         }
-        int run = d.scan_part[SCAN_BLOCKS + b] + block_scan256(s, sh);
-        for (int k = k0; k < k1; ++k) {
-            int src, h = halo_count(d.cell_cnt, k, d.ne, d.nc, &src);
-            if (h >= 0) {
-                int fit = run >= d.Gcap ? 0 : min(h, d.Gcap - run);
-                d.ext_start[k] = d.N + run;
-                d.ext_cnt[k] = fit;
-                d.ext_scan[k] = run;          // ghost offset of this halo cell
-                run += h;
-            } else {
-                d.ext_cnt[k] = d.cell_cnt[src];
-                d.ext_scan[k] = -1;
+        int run = block_scan(s, sh);
+        for (int kb = k0; kb < k1; kb += LU_L) {
+            if (per > LU_L) fetch(kb);
+#pragma unroll
+            for (int u = 0; u < LU_L; ++u) {
+                const int k = kb + u;
+                if (k >= k1) break;
+                if ((halo >> u) & 1u) {
+                    d.ext_start[k] = d.N + run;
+                    d.ext_cnt[k] = run >= d.Gcap ? 0 : min(n[u], d.Gcap - run);
+                    d.ext_scan[k] = run;          // ghost offset of this halo cell
+                    run += n[u];
+                } else {
+                    d.ext_start[k] = st[u];
+                    d.ext_cnt[k] = n[u];
+                    d.ext_scan[k] = -1;
+                }
             }
         }
+        if (t == BB - 1) {
+            *d.n_ghost = min(run, d.Gcap);
+            if (run > d.Gcap) atomicOr(&d.flags[FL_GHOST_OVF], 1);
+        }
+    }
+    for (int k = t; k < d.ncell; k += BB) d.cell_cnt[k] = 0;
+}
+
+// Bead -> cell, coordinates wrapped into [0, L).  Beads come in slot order,
+// which is cell order up to the beads that changed cell since the last
+// rebuild, so the lanes of a wave form few runs of equal cells: the first
+// lane of each run reserves the run's places in its cell with one atomic, and
+// a bead's place in its cell (in arbitrary order across runs; the per-cell
+// sort fixes the final order) is the reserved base plus its offset in the
+// run.
+template <typename R>
+__global__ __launch_bounds__(BB) void k_bin(Dev<R> d)
+{
+    const int i = blockIdx.x * BB + threadIdx.x;
+    const int l = threadIdx.x & 63;
+    int cell = -1;
+    if (i < d.N) {
+        V4<R> p = d.posq[i];
+        R* c[3] = { &p.x, &p.y, &p.z };
+        int cc[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            R x = *c[a];
+            if (x >= d.L[a]) x -= d.L[a];        // exact (Sterbenz) for x in [L, 2L]
+            else if (x < (R)0) x += d.L[a];
+            if (!(x >= (R)0 && x < d.L[a])) {     // far outside (set_state, minimizer)
+                double xd = (double)*c[a];
+                xd -= d.Ld[a] * floor(xd / d.Ld[a]);
+                x = (R)xd;
+                if (!(x < d.L[a])) x = (R)0;
+            }
+            *c[a] = x;
+            const int ci = (int)(x * d.inv_edge[a]);
+            cc[a] = ci < 0 ? 0 : (ci >= d.nc[a] ? d.nc[a] - 1 : ci);
+        }
+        d.posq[i] = p;
+        cell = (cc[0] * d.nc[1] + cc[1]) * d.nc[2] + cc[2];
+    }
+    const int prev = __shfl_up(cell, 1);
+    const bool head = l == 0 || prev != cell;
+    const unsigned long long hm = __ballot(head);
+    const unsigned long long upto = l == 63 ? ~0ull : ((2ull << l) - 1);   // lanes 0..l
+    const int h = 63 - __clzll((long long)(hm & upto));
+    const unsigned long long above = hm & ~upto;
+    int base = 0;
+    if (head && cell >= 0) {
+        const int len = (above ? __ffsll((long long)above) - 1 : 64) - l;
+        base = atomicAdd(&d.cell_cnt[cell], len);
+    }
+    base = __shfl(base, h);
+    if (cell >= 0) {
+        d.cell_t[i] = cell;
+        d.cell_pos[i] = base + l - h;
     }
 }
 
-// real extended cells take their start from the (now complete) cell starts
 template <typename R>
-__global__ void k_ext_real(Dev<R> d)
+__global__ __launch_bounds__(BB) void k_layout(Dev<R> d)
 {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= d.next) return;
-    int a[3];
-    ext_coords(k, d.ne, a);
-    if (a[0] && a[1] && a[2]) d.ext_start[k] = d.cell_start[ext_source(a, d.nc)];
+    layout_cells(d);
 }
 
-// Scatter beads to their cell ranges (arbitrary order inside a cell).
+// Scatter beads to their places in their cells' slot ranges.
 template <typename R>
 __global__ void k_scatter(Dev<R> d)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= d.N) return;
-    int c = d.cell_t[i];
-    int dst = d.cell_start[c] + atomicAdd(&d.cell_cur[c], 1);
+    const int dst = d.cell_start[d.cell_t[i]] + d.cell_pos[i];
     d.posq_t[dst] = d.posq[i];
     d.vel_t[dst] = d.vel[i];
     d.frc_t[dst] = d.frc[i];
     d.orig_t[dst] = d.orig[i];
     d.alch_t[dst] = d.alch[i];
-    d.cellid[dst] = c;    // cell of scratch position dst (read by k_rank)
 }
 
-// Order each cell by bead id: a bead's final slot is the cell start plus the
-// number of beads of its cell with a smaller id.
+// One wave per cell: the cell's beads in bead-id order (a bead's rank is the
+// number of the cell's beads with a smaller id) moved to their final slots,
+// and their periodic images written to the halo cells this cell sources (the
+// bead of rank r is image r of each); each bead records its images with
+// their shift codes for the integrator.
 template <typename R>
-__global__ void k_rank(Dev<R> d)
+__global__ __launch_bounds__(64) void k_place(Dev<R> d)
 {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= d.N) return;
-    int o = d.orig_t[p];
-    int cell = d.cellid[p];
-    int b = d.cell_start[cell], e = d.cell_start[cell + 1];
-    int r = 0;
-    for (int q = b; q < e; q += 8) {   // eight loads in flight per round
-        int v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = (q + u < e) ? d.orig_t[q + u] : 0x7fffffff;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) r += v[u] < o;
-    }
-    int s = b + r;
-    V4<R> x = d.posq_t[p];
-    d.posq[s] = x;
-    d.vel[s] = d.vel_t[p];
-    d.frc[s] = d.frc_t[p];
-    d.orig[s] = o;
-    d.alch[s] = d.alch_t[p];
-    d.inv[o] = s;
-    d.orig_ext[s] = o;
-    d.xref[s] = x;
-    d.gcnt[s] = 0;
-    // no periodic images yet (ghost fill adds them)
-    reinterpret_cast<int4*>(d.glist)[2 * s] = make_int4(-1, -1, -1, -1);
-    reinterpret_cast<int4*>(d.glist)[2 * s + 1] = make_int4(-1, -1, -1, -1);
-}
-
-// Bonded terms of each slot with their partners' slots (after the sort).
-template <typename R>
-__global__ void k_bslots(Dev<R> d)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= d.N) return;
-    int o = d.orig[i];
-    int b0 = d.bt_off[o], n = d.bt_off[o + 1] - b0;
-    int4* out = d.bslot + (size_t)i * MAXBT;
-    for (int t = 0; t < MAXBT; ++t) {
-        int4 e = make_int4(-1, i, i, 0);
-        if (t < n) {
-            int4 tm = d.bt[b0 + t];
-            e = make_int4(tm.x, d.inv[tm.y], tm.z >= 0 ? d.inv[tm.z] : i, tm.w);
+    __shared__ int ids[256];
+    const int cell = blockIdx.x, l = threadIdx.x;
+    const int b = d.cell_start[cell], n = d.cell_start[cell + 1] - b;
+    const int cz = cell % d.nc[2], cy = (cell / d.nc[2]) % d.nc[1], cx = cell / (d.nc[2] * d.nc[1]);
+    const int top = (cx == d.nc[0] - 1 ? 1 : 0) | (cy == d.nc[1] - 1 ? 2 : 0) |
+                    (cz == d.nc[2] - 1 ? 4 : 0);
+    for (int m0 = 0; m0 < n; m0 += 64) {
+        const int m = m0 + l;
+        const int o = m < n ? d.orig_t[b + m] : 0x7fffffff;
+        int r = 0;
+        for (int c0 = 0; c0 < n; c0 += 256) {
+            const int nn = min(256, n - c0);
+            __syncthreads();
+            for (int k = l; k < nn; k += 64) ids[k] = d.orig_t[b + c0 + k];
+            __syncthreads();
+            for (int k = 0; k < nn; ++k) r += ids[k] < o ? 1 : 0;
         }
-        out[t] = e;
-    }
-}
-
-// Ghost images: one block per extended cell (halo cells only), one thread
-// per image.  Each owner records its images for the integrator.
-template <typename R>
-__global__ void k_ghost_fill(Dev<R> d)
-{
-    int e = blockIdx.x;
-    int g0 = d.ext_scan[e];
-    if (g0 < 0) return;
-    int a[3];
-    ext_coords(e, d.ne, a);
-    int code = (a[0] == 0 ? 1 : 0) | (a[1] == 0 ? 2 : 0) | (a[2] == 0 ? 4 : 0);
-    int s0 = d.cell_start[ext_source(a, d.nc)], n = d.ext_cnt[e];
-    for (int k = threadIdx.x; k < n; k += blockDim.x) {
-        int g = g0 + k, s = s0 + k;
-        V4<R> p = d.posq[s];
-        if (code & 1) p.x -= d.L[0];
-        if (code & 2) p.y -= d.L[1];
-        if (code & 4) p.z -= d.L[2];
-        d.posq[d.N + g] = p;
-        d.ghost_owner[g] = s;
-        d.ghost_code[g] = code;
-        d.orig_ext[d.N + g] = d.orig[s];
-        int q = atomicAdd(&d.gcnt[s], 1);
-        if (q < 8) d.glist[s * 8 + q] = g | (code << CODE_SHIFT);
+        if (m >= n) continue;
+        const int p = b + m, s = b + r;
+        const V4<R> x = d.posq_t[p];
+        d.posq[s] = x;
+        d.vel[s] = d.vel_t[p];
+        d.frc[s] = d.frc_t[p];
+        d.orig[s] = o;
+        d.alch[s] = d.alch_t[p];
+        d.inv[o] = s;
+        d.orig_ext[s] = o;
+        d.xref[s] = x;
+        int4* gl = reinterpret_cast<int4*>(d.glist) + 2 * s;
+        gl[0] = make_int4(-1, -1, -1, -1);
+        gl[1] = make_int4(-1, -1, -1, -1);
+        int q = 0;
+        for (int code = 1; code < 8; ++code) {
+            if (code & ~top) continue;
+            const int e = (((code & 1) ? 0 : cx + 1) * d.ne[1] + ((code & 2) ? 0 : cy + 1)) * d.ne[2] +
+                          ((code & 4) ? 0 : cz + 1);
+            if (r < d.ext_cnt[e]) {   // else the ghost range is full (flagged)
+                const int g = d.ext_scan[e] + r;
+                V4<R> y = x;
+                if (code & 1) y.x -= d.L[0];
+                if (code & 2) y.y -= d.L[1];
+                if (code & 4) y.z -= d.L[2];
+                d.posq[d.N + g] = y;
+                d.ghost_owner[g] = s;
+                d.ghost_code[g] = code;
+                d.orig_ext[d.N + g] = o;
+                d.glist[s * 8 + q] = g | (code << CODE_SHIFT);
+            }
+            ++q;
+        }
     }
 }
 
@@ -386,9 +383,20 @@ __global__ __launch_bounds__(LB) void k_list(Dev<R> d)
     const int cell = blockIdx.x;
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
     const int Kc = d.Kcap;
-    if (t == 0) { d.cell_cnt[cell] = 0; d.cell_cur[cell] = 0; }   // for the next rebuild
     const int s0 = d.cell_start[cell], ni = d.cell_start[cell + 1] - s0;
     if (ni == 0) return;
+    // bonded terms of the cell's beads with their partners' slots
+    for (int k = t; k < ni * MAXBT; k += LB) {
+        const int i = s0 + k / MAXBT, tt = k % MAXBT;
+        const int o = d.orig[i];
+        const int b0 = d.bt_off[o], n = d.bt_off[o + 1] - b0;
+        int4 e = make_int4(-1, i, i, 0);
+        if (tt < n) {
+            const int4 tm = d.bt[b0 + tt];
+            e = make_int4(tm.x, d.inv[tm.y], tm.z >= 0 ? d.inv[tm.z] : i, tm.w);
+        }
+        d.bslot[(size_t)i * MAXBT + tt] = e;
+    }
     if (w == 0) {
         const int cz = cell % d.nc[2], cy = (cell / d.nc[2]) % d.nc[1], cx = cell / (d.nc[2] * d.nc[1]);
         int n = 0;
@@ -563,15 +571,10 @@ __global__ __launch_bounds__(LB) void k_list(Dev<R> d)
 template <typename R>
 void launch_rebuild(const Dev<R>& d, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bin<R>, GRID(d.N), 0, st, d);
-    hipLaunchKernelGGL(k_scan_a<R>, dim3(SCAN_BLOCKS), dim3(256), 0, st, d);
-    hipLaunchKernelGGL(k_scan_b<R>, dim3(1), dim3(64), 0, st, d);
-    hipLaunchKernelGGL(k_scan_c<R>, dim3(SCAN_BLOCKS), dim3(256), 0, st, d);
+    hipLaunchKernelGGL(k_bin<R>, dim3((d.N + BB - 1) / BB), dim3(BB), 0, st, d);
+    hipLaunchKernelGGL(k_layout<R>, dim3(1), dim3(BB), 0, st, d);
     hipLaunchKernelGGL(k_scatter<R>, GRID(d.N), 0, st, d);
-    hipLaunchKernelGGL(k_rank<R>, GRID(d.N), 0, st, d);
-    hipLaunchKernelGGL(k_ext_real<R>, GRID(d.next), 0, st, d);
-    hipLaunchKernelGGL(k_ghost_fill<R>, dim3(d.next), dim3(64), 0, st, d);
-    hipLaunchKernelGGL(k_bslots<R>, GRID(d.N), 0, st, d);
+    hipLaunchKernelGGL(k_place<R>, dim3(d.ncell), dim3(64), 0, st, d);
     hipLaunchKernelGGL(k_list<R>, dim3(d.ncell), dim3(LB), 0, st, d);
 }
 

@@ -14,7 +14,6 @@ constexpr int MAXMB = 16;        // beads per bonded molecule
 constexpr int CODE_SHIFT = 29;   // neighbour entry: j | (i-shift bits << 29)
 constexpr int JMASK = (1 << CODE_SHIFT) - 1;
 constexpr int MAXBT = 8;         // bonded terms per bead
-constexpr int SCAN_BLOCKS = 128; // blocks of the cell-count scans
 
 // random streams (fourth Philox counter word)
 enum { ST_LANGEVIN = 0, ST_SWAP_DRAW = 1, ST_SWAP_ACCEPT = 2, ST_MDAS_SELECT = 3,
@@ -141,16 +140,15 @@ template <typename R> struct Dev {
     int* orig;       // slot -> bead id
     int* inv;        // bead id -> slot
     int* alch;       // slot -> -1 or (new class | trial << 8)
-    int* cellid;     // slot -> real cell
     // sort scratch
     V4<R>* posq_t;
     V4<R>* vel_t;
     V4<R>* frc_t;
     int* orig_t;
     int* alch_t;
-    int* cell_t;
+    int* cell_t;     // [N] cell of each slot (binning)
+    int* cell_pos;   // [N] its place in the cell (binning, arbitrary order)
     int* cell_cnt;   // [ncell]
-    int* cell_cur;   // [ncell]
     int* cell_start; // [ncell + 1]
     int* ext_start;  // [next]
     int* ext_cnt;    // [next]
@@ -158,12 +156,10 @@ template <typename R> struct Dev {
     int* ghost_owner;
     int* ghost_code;
     int* n_ghost;    // [1]
-    int* gcnt;       // [N] images of each slot
     int* glist;      // [N * 8] their ghost indices | code << 29, -1 unused
     int* orig_ext;   // [N + Gcap] bead id of each slot or ghost image
     int4* bslot;     // [N * 8] bonded terms of each slot with partner slots
                      // {role, slot 1, slot 2, parameter}; role -1 = unused
-    int* scan_part;  // [2 * SCAN_BLOCKS + 2] block sums of the cell scans
     float* dmax_part;  // [ceil(8 N / WG)] per integrator block: largest squared
                        // displacement from the last rebuild seen since a reset
     // neighbour list, tiled so that the LPB lanes of the 64/LPB beads a wave

@@ -474,20 +474,18 @@ static size_t layout(membx_sys* s, Dev<R>& d, Mv& m, char* base)
     d.xref = a.take<V4<R>>(N);
     d.dfrc = a.take<V4<R>>(N);
     d.orig = a.take<int>(N); d.inv = a.take<int>(N); d.alch = a.take<int>(N);
-    d.cellid = a.take<int>(N);
     d.posq_t = a.take<V4<R>>(N); d.vel_t = a.take<V4<R>>(N); d.frc_t = a.take<V4<R>>(N);
     d.orig_t = a.take<int>(N); d.alch_t = a.take<int>(N); d.cell_t = a.take<int>(N);
-    d.cell_cnt = a.take<int>(h.ncell_cap); d.cell_cur = a.take<int>(h.ncell_cap);
+    d.cell_pos = a.take<int>(N);
+    d.cell_cnt = a.take<int>(h.ncell_cap);
     d.cell_start = a.take<int>(h.ncell_cap + 1);
     d.ext_start = a.take<int>(h.next_cap); d.ext_cnt = a.take<int>(h.next_cap);
     d.ext_scan = a.take<int>(2 * h.next_cap + 2);
     d.ghost_owner = a.take<int>(h.Gcap); d.ghost_code = a.take<int>(h.Gcap);
     d.n_ghost = a.take<int>(1);
-    d.gcnt = a.take<int>(N);
     d.glist = a.take<int>(8 * (size_t)N);
     d.orig_ext = a.take<int>(N + h.Gcap);
     d.bslot = a.take<int4>((size_t)N * MAXBT);
-    d.scan_part = a.take<int>(2 * SCAN_BLOCKS + 2);
     d.dmax_part = a.take<float>(((size_t)N * 8 + WG - 1) / WG);
     d.nbr = a.take<int>((size_t)h.Kcap * Npad);
     d.ncnt = a.take<int>(N); d.nseg0 = a.take<int>(N);
@@ -963,11 +961,9 @@ static int32_t upload(membx_sys* s, const membx_desc* desc)
     UP(m.chg_loc, h.chg_loc);
 #undef UP
     HCK(hipMemsetAsync(d.frc, 0, sizeof(V4<R>) * h.N, st));
-    // binning counters start at zero; afterwards the list kernel clears them
+    // binning counters start at zero; afterwards the cell layout clears them
     // for the next rebuild
     HCK(hipMemsetAsync(d.cell_cnt, 0, sizeof(int) * h.ncell_cap, st));
-    HCK(hipMemsetAsync(d.cell_cur, 0, sizeof(int) * h.ncell_cap, st));
-    HCK(hipMemsetAsync(d.gcnt, 0, sizeof(int) * h.N, st));
     HCK(hipMemsetAsync(d.ncnt_in, 0, sizeof(int) * (size_t)h.N * 8, st));
     HCK(hipMemsetAsync(d.dmax_part, 0, sizeof(float) * (((size_t)h.N * 8 + WG - 1) / WG), st));
     HCK(hipMemsetAsync(m.hb_word, 0, sizeof(unsigned long long) * ((size_t)m.hb_mask + 1), st));
@@ -1425,7 +1421,7 @@ static int32_t retune_impl(membx_sys* s)
     Dev<R>& d = dev<R>(s);
     Host& h = s->h;
     // the grid follows the skin; counters of cells beyond the old grid are
-    // cleared (the list kernel clears only the cells it used)
+    // cleared (the cell layout clears only the cells of the grid in use)
     set_grid(h, h.skin);
     for (int k = 0; k < 3; ++k) {
         d.nc[k] = h.nc[k]; d.ne[k] = h.ne[k];
@@ -1433,7 +1429,6 @@ static int32_t retune_impl(membx_sys* s)
     }
     d.ncell = h.ncell; d.next = h.next;
     HCK(hipMemsetAsync(d.cell_cnt, 0, sizeof(int) * h.ncell_cap, s->st));
-    HCK(hipMemsetAsync(d.cell_cur, 0, sizeof(int) * h.ncell_cap, s->st));
     d.lpb = h.lpb;
     d.lpb_shift = h.lpb == 1 ? 0 : h.lpb == 2 ? 1 : h.lpb == 4 ? 2 : 3;
     d.bg_shift = 6 - d.lpb_shift;
