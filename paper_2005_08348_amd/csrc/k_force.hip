@@ -6,9 +6,11 @@
 // Pair forces are not a dense contraction, so the kernel runs on the vector
 // ALUs: LPB lanes of a wave64 share one i bead and walk its full
 // (both-direction) Verlet list.  The kernel is organised around memory
-// latency: a lane issues its bonded records, then a batch of list reads (one
+// latency and occupancy: per batch a lane issues its list reads (one
 // contiguous 256-byte block per wave each, the list is tiled), then all the
-// batch's coordinate gathers, then computes the batch without branches.
+// batch's coordinate gathers, then computes the batch without branches;
+// registers are kept few (reads needed only after the walk are issued after
+// it) so that more waves hide the latency.
 // The j bead's coordinates and class come in one 16-byte gather and the pair
 // parameters from a class-by-class table in LDS.  The same lanes then
 // evaluate the bonded terms their bead takes part in (per-bead gather, no
@@ -122,16 +124,15 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
     constexpr int B = 4;
     constexpr int BT = B >= 8 ? 4 : 2;
     const int mcap = d.Kcap / LPB;
-    // Every read that depends on no other read goes out first, in one round
-    // trip with the parameter table below: the bead, its counts, the first
-    // two batches of list entries (clamped to the bead's tile), its bonded
-    // records and (FUSE) what the integrator will need.
+    // The bead, its count and its first batch of list entries (clamped to
+    // the bead's tile) go out first, in one round trip with the parameter
+    // table below.  Reads needed only after the walk (bonded records and
+    // partners, the integrator's inputs) are issued after it: held across
+    // the walk they would cost occupancy.
     const V4<R> pi = d.posq[ii];
-    int jj0[B], jj1[B];
+    int jj0[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) jj0[b] = nb[(size_t)min(b, mcap - 1) * 64];
-#pragma unroll
-    for (int b = 0; b < B; ++b) jj1[b] = nb[(size_t)min(B + b, mcap - 1) * 64];
     int m1n;   // entries this lane walks
     if (LIST == 1) {
         m1n = valid ? min(d.ncnt_in[(size_t)i * LPB + s], mcap) : 0;
@@ -139,26 +140,12 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
         const int n1 = valid ? d.ncnt[i] : 0;
         m1n = n1 > s ? (n1 - s + LPB - 1) / LPB : 0;
     }
-    // bonded records: lane s takes terms s, s + LPB, ... of its bead
-    constexpr int TPL = (MAXBT + LPB - 1) / LPB;
-    int4 bt[TPL];
-#pragma unroll
-    for (int u = 0; u < TPL; ++u)
-        bt[u] = (s + u * LPB < MAXBT) ? d.bslot[(size_t)ii * MAXBT + s + u * LPB]
-                                      : make_int4(-1, ii, ii, 0);
     // FUSE: after the forces, thread t < WG / LPB of the block integrates the
     // block's bead t (forces handed over through LDS), so that the
     // integrator runs on full waves instead of one lane per bead
     constexpr int NBB = WG / LPB;
     const int ib = blockIdx.x * NBB + threadIdx.x;
     const bool integ = FUSE && threadIdx.x < NBB && ib < d.N;
-    BeadPre<R> pre{};
-    V4<R> pb{};
-    if (integ) {
-        pb = d.posq[ib];
-        pre = bead_pre(d, ib, LIST == 1);
-        if (LIST == 2) pre.xri = pb;   // this pass makes the bead's coordinates the reference
-    }
     for (int t = threadIdx.x; t < MAXCLS * MAXCLS; t += WG) {
         tf[t] = d.tabF[t];
         if (EN) te[t] = d.tabE[t];
@@ -170,10 +157,6 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
     R fx = 0, fy = 0, fz = 0;
     double elj = 0.0, erf = 0.0, eb = 0.0, ea = 0.0, ek = 0.0;
     int np = 0;
-    // partner coordinates of the bonded terms
-    V4<R> b1[TPL], b2[TPL];
-#pragma unroll
-    for (int u = 0; u < TPL; ++u) { b1[u] = P[bt[u].y]; b2[u] = P[bt[u].z]; }
     // list walk in batches of B entries per lane, then short batches of BT
     // for the tail, the batch sizes uniform over the wave; branch-free inside a
     // batch: all list reads, then all coordinate gathers (the bead itself for
@@ -243,12 +226,30 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
         compute(0, jj0, std::integral_constant<int, B>{});
         m0 = B;
     }
-    if (mmax > B) {
-        compute(B, jj1, std::integral_constant<int, B>{});
-        m0 = 2 * B;
-    }
+
     for (; m0 + B <= mmax; m0 += B) batch(m0, std::integral_constant<int, B>{});
     for (; m0 < mmax; m0 += BT) batch(m0, std::integral_constant<int, BT>{});
+    // the integrator's inputs, in flight with the bonded terms and the
+    // force reduction (loaded here, not up front, to keep registers free
+    // during the walk)
+    BeadPre<R> pre{};
+    V4<R> pb{};
+    if (integ) {
+        pb = d.posq[ib];
+        pre = bead_pre(d, ib, LIST == 1);
+        if (LIST == 2) pre.xri = pb;   // this pass makes the bead's coordinates the reference
+    }
+    // bonded records (lane s takes terms s, s + LPB, ... of its bead) and
+    // their partners' coordinates
+    constexpr int TPL = (MAXBT + LPB - 1) / LPB;
+    int4 bt[TPL];
+#pragma unroll
+    for (int u = 0; u < TPL; ++u)
+        bt[u] = (s + u * LPB < MAXBT) ? d.bslot[(size_t)ii * MAXBT + s + u * LPB]
+                                      : make_int4(-1, ii, ii, 0);
+    V4<R> b1[TPL], b2[TPL];
+#pragma unroll
+    for (int u = 0; u < TPL; ++u) { b1[u] = P[bt[u].y]; b2[u] = P[bt[u].z]; }
     // bonded terms of bead i
 #pragma unroll
     for (int u = 0; u < TPL; ++u)

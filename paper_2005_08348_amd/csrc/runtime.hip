@@ -1515,7 +1515,8 @@ static int32_t autotune_impl(membx_sys* s, int n, Tune* out)
     double best_t = 1e300;
     Tune best{ s->h.skin, s->h.skin_in, s->h.R, lpb0, s->h.prune };
     for (int lpb : { 4, 8 }) {
-        for (double skin = 0.2; skin <= skin_max + 1e-9; skin += 0.1) {
+        for (int sk = 2; sk <= (int)std::floor(10.0 * skin_max + 1e-9); ++sk) {
+            const double skin = sk / 10.0;
             const int Rr = std::min(50, (int)std::floor(4.0 * 0.8 * 0.5 * skin / d4));
             if (Rr < 1) continue;
             for (int prune : { 0, 2, 3, 4 }) {
