@@ -39,30 +39,33 @@ def kernel_source_sha():
     return h.hexdigest()
 
 
-def measured_traffic(tag, skin):
-    """HBM bytes per launch of the nonbonded kernel from the counter summary
-    profiles/<tag>_c1_traffic.md (FETCH_SIZE and WRITE_SIZE runs scaled by a
-    plain copy of known size); None when missing or taken on other source."""
-    path = os.path.join(ROOT, "profiles", f"{tag}_c1_traffic.md")
+def measured_traffic(lpb, list_kind, skin, skin_inner):
+    """HBM bytes per launch of the force pass from the counter summary
+    profiles/k_nb_float_c1_traffic.md (FETCH_SIZE and WRITE_SIZE runs scaled
+    by a plain copy of known size), one row per tuning; None when no row
+    matches or the rows were taken on other kernel source."""
+    path = os.path.join(ROOT, "profiles", "k_nb_float_c1_traffic.md")
     if not os.path.exists(path):
         return None
-    vals = {}
+    sha, rows = None, []
     with open(path) as fh:
         for line in fh:
-            if ":" in line and line.startswith("- "):
-                k, v = line[2:].split(":", 1)
-                vals[k.strip()] = v.strip().strip("`")
-    if vals.get("kernel_source_sha256") != kernel_source_sha():
+            if line.startswith("- kernel_source_sha256:"):
+                sha = line.split(":", 1)[1].strip().strip("`")
+            elif line.startswith("| ") and not line.startswith("| lanes") and not line.startswith("|---"):
+                cells = [c.strip() for c in line.strip().strip("|").split("|")]
+                try:
+                    rows.append((int(cells[0]), int(cells[1]), float(cells[2]), float(cells[3]),
+                                 float(cells[6])))
+                except (ValueError, IndexError):
+                    pass
+    if sha != kernel_source_sha():
         return None
-    try:
-        if abs(float(vals.get("skin_nm", "nan")) - skin) > 1e-9:
-            return None
-    except ValueError:
-        return None
-    try:
-        return float(vals["traffic_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+    for r in rows:
+        if (r[0] == lpb and r[1] == list_kind and abs(r[2] - skin) < 1e-9
+                and abs(r[3] - skin_inner) < 1e-9):
+            return r[4]
+    return None
 
 
 def log(*a):
@@ -214,7 +217,9 @@ def main():
     pairs2 = e2["n_pairs_in_cutoff"]
     nb_flops = pairs2 * FLOP_PAIR_F
     achieved = nb_flops / (nb_ms * 1e-3)
-    traffic = measured_traffic(f"k_nb_float_lpb{tun['lanes_per_bead']}", tun["skin"])
+    list_kind = 1 if tun["prune_interval"] > 1 else 0
+    traffic = measured_traffic(tun["lanes_per_bead"], list_kind, tun["skin"],
+                               tun["skin_inner"] if list_kind else 0.0)
     result = {
         "metric": "MD steps/s & pair-interactions/s (FP32-mixed vs FP64); swap trials/s",
         "value": steps_s,
@@ -236,7 +241,8 @@ def main():
         "max_displacement_nm": e2["max_displacement"],
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": traffic,
-                     "kernel": f"k_nb<float,{tun['lanes_per_bead']},false> (nonbonded + bonded forces)",
+                     "kernel": f"k_nb<float,{tun['lanes_per_bead']},false,true,{list_kind}> "
+                               "(nonbonded + bonded forces + next step's B-A-O-A)",
                      "launches_timed": NB_LAUNCHES, "mean_launch_ms": nb_ms,
                      "flop_per_launch": nb_flops},
     }

@@ -262,11 +262,13 @@ int32_t membx_set_graphs(membx_sys* sys, int32_t enable);
 int32_t membx_kernel_timing(membx_sys* sys, int32_t enable);
 int32_t membx_kernel_time(membx_sys* sys, int64_t* launches, double* mean_ms);
 
-/* Mean duration (ms) of the nonbonded force kernel at the current state:
- * n_launch launches (1..4096) captured back to back in one HIP graph, one
- * replay to warm up, then HIP events on the library stream around a second
- * replay.  The kernel only rewrites the forces it computed already, so the
- * state is unchanged.  Synchronizes.  E_INVAL, E_DEVICE. */
+/* Mean duration (ms) of the force pass of the MD steps at the current
+ * state (forces plus the next step's update; the inner-list walk when
+ * pruning is on, else the Verlet-list walk): n_launch launches (1..4096)
+ * captured back to back in one HIP graph, one replay to warm up, then HIP
+ * events on the library stream around a second replay.  The update goes to
+ * scratch buffers and the forces it rewrites are the ones it computed
+ * already, so the state is unchanged.  Synchronizes.  E_INVAL, E_DEVICE. */
 int32_t membx_kernel_bench(membx_sys* sys, int32_t n_launch, double* mean_ms);
 
 /* Per-system message for the last error ("" if none). */

@@ -1621,10 +1621,12 @@ static int32_t kbench_impl(membx_sys* s, int n, double* mean_ms)
     hipGraph_t g;
     if (hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(s, MEMBX_E_DEVICE, "stream capture failed");
-    // the kernel the MD steps run: forces plus the next step's update, the
-    // update written to scratch (the other coordinate buffer, the sort
-    // buffer for velocities) so that the state is unchanged
-    const int list = (s->h.prune > 1 && s->h.lpb >= 2 && s->sp >= 0) ? 1 : 0;
+    // the kernel most MD steps run: forces plus the next step's update (the
+    // inner-list walk when pruning is on), the update written to scratch
+    // (the other coordinate buffer, the sort buffer for velocities) so that
+    // the state is unchanged; right after a rebuild the inner list is stale,
+    // which changes the values, not the work
+    const int list = (s->h.prune > 1 && s->h.lpb >= 2) ? 1 : 0;
     for (int q = 0; q < n; ++q)
         launch_nonbonded_fused<R>(d, s->h.lpb, list, (R)s->h.dt, 1, d.posq_alt, d.vel_t, 0, s->st);
     if (hipStreamEndCapture(s->st, &g) != hipSuccess)
