@@ -215,6 +215,7 @@ def main():
     nb_ms = g.kernel_bench(NB_LAUNCHES)
     e2 = g.energies(check=False)
     pairs2 = e2["n_pairs_in_cutoff"]
+    slots = e2["n_list_entries"]   # Verlet-list entries (both directions)
     nb_flops = pairs2 * FLOP_PAIR_F
     achieved = nb_flops / (nb_ms * 1e-3)
     list_kind = 1 if tun["prune_interval"] > 1 else 0
@@ -244,7 +245,14 @@ def main():
                      "kernel": f"k_nb<float,{tun['lanes_per_bead']},false,true,{list_kind}> "
                                "(nonbonded + bonded forces + next step's B-A-O-A)",
                      "launches_timed": NB_LAUNCHES, "mean_launch_ms": nb_ms,
-                     "flop_per_launch": nb_flops},
+                     "flop_per_launch": nb_flops,
+                     # computed pair slots of the Verlet list (each unordered
+                     # pair twice, masked slots included) and the share of
+                     # them within the cutoff; the same 31 flop per slot
+                     # gives the throughput of all computed slots
+                     "pair_slots_verlet": slots,
+                     "slot_efficiency": (2 * pairs2 / slots) if slots else None,
+                     "slot_tflops": slots * FLOP_PAIR_F / (nb_ms * 1e-3) / 1e12},
     }
     g.close()
     del g

@@ -136,6 +136,9 @@ typedef struct membx_energy {
     double  max_displacement;     /* largest displacement from the position */
                                   /* at the last list build seen since then */
                                   /* (nm)                                   */
+    int64_t n_list_entries;       /* entries of the Verlet list (both       */
+                                  /* directions): the pair slots one force  */
+                                  /* pass computes                          */
 } membx_energy;
 
 /* One admitted exchange trial of a batch. */
@@ -257,8 +260,7 @@ int32_t membx_set_graphs(membx_sys* sys, int32_t enable);
 
 /* Kernel timing: when enabled, HIP events on the library stream bracket
  * every launch of the nonbonded force kernel; membx_kernel_time returns the
- * number of timed launches, their mean duration (ms) and the mean number of
- * pair slots and in-cutoff pairs those launches covered.  Synchronizes. */
+ * number of timed launches and their mean duration (ms).  Synchronizes. */
 int32_t membx_kernel_timing(membx_sys* sys, int32_t enable);
 int32_t membx_kernel_time(membx_sys* sys, int64_t* launches, double* mean_ms);
 

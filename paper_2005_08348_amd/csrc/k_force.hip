@@ -287,17 +287,17 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
             if (stats) disp_stats(d, e2, e2_in, integ);
         }
     } else {
-        __shared__ double sh[6][WG / 64];
-        double v[6] = { elj, erf, (double)np, eb, ea, ek };
+        __shared__ double sh[7][WG / 64];
+        double v[7] = { elj, erf, (double)np, eb, ea, ek, valid ? (double)m1n : 0.0 };
         const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
+        for (int q = 0; q < 7; ++q) {
             double x = wave_sum(v[q]);
             if (l == 0) sh[q][w] = x;
         }
         __syncthreads();
         if (threadIdx.x == 0)
-            for (int q = 0; q < 6; ++q) {
+            for (int q = 0; q < 7; ++q) {
                 double acc = 0.0;
                 for (int ww = 0; ww < WG / 64; ++ww) acc += sh[q][ww];
                 part[8 * blockIdx.x + q] = acc;
@@ -306,19 +306,19 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
 }
 
 // Fixed-order float64 sum of the block partials:
-// out = {lj, rf, bond, angle, kinetic, n_pairs}
+// out = {lj, rf, bond, angle, kinetic, n_pairs, list entries}
 __global__ void k_energy_final(const double* __restrict__ p, int nb, double* __restrict__ out)
 {
-    __shared__ double sh[6][256];
+    __shared__ double sh[7][256];
     int t = threadIdx.x;
-    double a[6] = { 0, 0, 0, 0, 0, 0 };
+    double a[7] = { 0, 0, 0, 0, 0, 0, 0 };
     for (int b = t; b < nb; b += 256)
-        for (int q = 0; q < 6; ++q) a[q] += p[8 * b + q];
-    for (int q = 0; q < 6; ++q) sh[q][t] = a[q];
+        for (int q = 0; q < 7; ++q) a[q] += p[8 * b + q];
+    for (int q = 0; q < 7; ++q) sh[q][t] = a[q];
     __syncthreads();
     for (int off = 128; off >= 1; off >>= 1) {
         if (t < off)
-            for (int q = 0; q < 6; ++q) sh[q][t] += sh[q][t + off];
+            for (int q = 0; q < 7; ++q) sh[q][t] += sh[q][t + off];
         __syncthreads();
     }
     if (t == 0) {
@@ -329,6 +329,7 @@ __global__ void k_energy_final(const double* __restrict__ p, int nb, double* __r
         out[3] = sh[4][0];
         out[4] = sh[5][0];
         out[5] = 0.5 * sh[2][0];
+        out[6] = sh[6][0];   // entries walked: pair slots of one force pass
     }
 }
 

@@ -1201,7 +1201,7 @@ static int32_t energies_impl(membx_sys* s, membx_energy* out)
     launch_energy_final(d.red, nnb, d.eout, s->st);
     double e[8];
     int fl[NFLAGS];
-    HCK(hipMemcpyAsync(e, d.eout, sizeof(double) * 6, hipMemcpyDeviceToHost, s->st));
+    HCK(hipMemcpyAsync(e, d.eout, sizeof(double) * 7, hipMemcpyDeviceToHost, s->st));
     int32_t rc = read_flags(s, fl);
     if (rc) return rc;
     membx_energy E{};
@@ -1209,6 +1209,7 @@ static int32_t energies_impl(membx_sys* s, membx_energy* out)
     E.potential = e[0] + e[1] + e[2] + e[3];
     E.total = E.potential + e[4];
     E.n_pairs_in_cutoff = (int64_t)std::llround(e[5]);
+    E.n_list_entries = (int64_t)std::llround(e[6]);
     E.fe_count = s->fe; E.step = s->step; E.batch = s->batch; E.cycle = s->cycle;
     E.n_rebuilds = s->n_rebuilds;
     E.n_skin_violations = (int64_t)fl[FL_SKIN] + fl[FL_SKIN_IN];

@@ -63,7 +63,7 @@ class Energy(C.Structure):
                 ("fe_count", C.c_int64), ("step", C.c_int64), ("batch", C.c_int64),
                 ("cycle", C.c_int64), ("n_rebuilds", C.c_int64),
                 ("n_skin_violations", C.c_int64),
-                ("max_displacement", C.c_double)]
+                ("max_displacement", C.c_double), ("n_list_entries", C.c_int64)]
 
 
 class Request(C.Structure):

@@ -90,6 +90,8 @@ def test_pairset_c0(oracle_mod, c0, prec):
     b = set(map(tuple, np.sort(ref, axis=1)))
     assert len(a) == len(ps)
     assert a == b
+    # the pair slots one force pass computes: every listed pair, both ways
+    assert g.energies()["n_list_entries"] == 2 * len(ref)
     g.close()
 
 
