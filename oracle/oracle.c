@@ -907,3 +907,38 @@ double o_pairs_delta_u(osys* s, int n_pairs, const int* pairs)
     free(mk_b);
     return (eb[0] + eb[1] + eb[2] + eb[3]) - (ea[0] + ea[1] + ea[2] + ea[3]);
 }
+
+/* ------------------------------------------------------ mixing observable */
+/* Results: mixing is followed through the pair correlation of the PO4
+ * beads of one lipid type.  Here: over all unordered pairs of PO4 beads
+ * (bead index po4 of the kind) of the molecules of kind `kind` that sit in
+ * the same leaflet (leaflet[m] = 0 or 1, -1 skips the molecule), the
+ * lateral separation d (x and y, each by the minimum-image convention of
+ * the periodic box) falls in bin k when (k w)^2 <= d^2 < ((k+1) w)^2;
+ * counts[k] (k < n_bins) gets one per pair.  Plain double loop over pairs. */
+static double bin_edge2(int k, double w) { return ((double)k * w) * ((double)k * w); }
+
+void o_pair_histogram(const osys* s, int kind, int po4, const int* leaflet, int n_bins, double w,
+                      int64_t* counts)
+{
+    for (int k = 0; k < n_bins; ++k) counts[k] = 0;
+    for (int a = 0; a < s->nm; ++a) {
+        if (s->mkind[a] != kind || leaflet[a] < 0) continue;
+        const int ia = s->mfirst[a] + po4;
+        for (int b = a + 1; b < s->nm; ++b) {
+            if (s->mkind[b] != kind || leaflet[b] != leaflet[a]) continue;
+            const int ib = s->mfirst[b] + po4;
+            double dx = s->x[3 * ia] - s->x[3 * ib];
+            double dy = s->x[3 * ia + 1] - s->x[3 * ib + 1];
+            if (dx > 0.5 * s->box[0]) dx -= s->box[0];
+            else if (dx < -0.5 * s->box[0]) dx += s->box[0];
+            if (dy > 0.5 * s->box[1]) dy -= s->box[1];
+            else if (dy < -0.5 * s->box[1]) dy += s->box[1];
+            const double d2 = dx * dx + dy * dy;
+            int k = (int)(sqrt(d2) / w);
+            while (k > 0 && bin_edge2(k, w) > d2) --k;
+            while (bin_edge2(k + 1, w) <= d2) ++k;
+            if (k < n_bins) counts[k]++;
+        }
+    }
+}

@@ -82,6 +82,8 @@ def lib():
         L.o_mdas_cycle.restype = C.c_int
         L.o_pairs_delta_u.argtypes = [C.c_void_p, C.c_int, _i32p]
         L.o_pairs_delta_u.restype = C.c_double
+        L.o_pair_histogram.argtypes = [C.c_void_p, C.c_int, C.c_int, _i32p, C.c_int, C.c_double,
+                                       _i64p]
         L.o_philox.argtypes = [_u32p, _u32p, _u32p]
         L.o_gauss3.argtypes = [_u32p, _f64p]
         L.o_pair_term.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_double,
@@ -220,6 +222,13 @@ class Oracle:
         k = lib().o_mdas_cycle(self.h, n_pairs, K, M, C.byref(w), C.byref(acc), C.byref(u), pairs)
         return dict(work=w.value, accept=bool(acc.value), u=u.value,
                     pairs=pairs[:2 * k].reshape(-1, 2))
+
+    def pair_histogram(self, kind, po4, leaflet, n_bins, bin_width):
+        """lateral PO4-PO4 pair counts per bin (unordered pairs, same leaflet)"""
+        out = np.zeros(int(n_bins), dtype=np.int64)
+        lib().o_pair_histogram(self.h, int(kind), int(po4), _i32(leaflet), int(n_bins),
+                               float(bin_width), out)
+        return out
 
     def pairs_delta_u(self, pairs):
         p = _i32(pairs)

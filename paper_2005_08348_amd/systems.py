@@ -42,7 +42,8 @@ MASS = 72.0  # amu
 KB = 0.00831446261815324  # kJ/mol/K (used only to draw initial velocities)
 
 SEEDS = {"c0": 200508348000, "c1": 200508348001, "c2": 200508348002,
-         "c3": 200508348003}
+         "c3": 200508348003, "mix": 200508348010}
+PO4 = 1   # bead index of the phosphate in the lipid kinds A, B and D
 
 
 @dataclass
@@ -203,15 +204,18 @@ def _lipid_template(kind_id, d, s=0.235):
 
 
 def bilayer(name, n_per_leaflet, fractions, n_water, box_xy, box_z, seed,
-            kinds=None, jitter=0.05, wobble_deg=10.0):
+            kinds=None, jitter=0.05, wobble_deg=10.0, demix=False, lipid_kinds=None):
     """Two-leaflet bilayer on an nx x ny grid per leaflet, kinds assigned by a
     seeded permutation with largest-remainder counts, water on a jittered
-    lattice filling the rest of the periodic box."""
+    lattice filling the rest of the periodic box.  ``demix``: each leaflet
+    is instead filled column by column (along x) in kind order, so that each
+    kind forms one stripe (a far-from-mixed start).  ``lipid_kinds``: the
+    kind of each fraction (default 0, 1, 2, ...)."""
     rng = np.random.default_rng(seed)
     kinds = kinds if kinds is not None else standard_kinds()
     eps = epsilon_matrix(rng)
     n_lip = 2 * n_per_leaflet
-    lipid_kinds = [k for k in range(len(fractions))]
+    lipid_kinds = list(lipid_kinds) if lipid_kinds is not None else list(range(len(fractions)))
     counts = largest_remainder(n_lip, fractions)
     assign = np.concatenate([np.full(c, k, dtype=np.int32)
                              for k, c in zip(lipid_kinds, counts)])
@@ -220,6 +224,16 @@ def bilayer(name, n_per_leaflet, fractions, n_water, box_xy, box_z, seed,
     Ly = Lx
     Lz = float(np.float32(box_z))
     nx, ny = _grid_dims(n_per_leaflet)
+    if demix:
+        per_leaf = largest_remainder(n_per_leaflet, fractions)
+        stripe = np.concatenate([np.full(c, k, dtype=np.int32)
+                                 for k, c in zip(lipid_kinds, per_leaf)])
+        sites = np.arange(n_per_leaflet)
+        order = np.lexsort((sites // nx, sites % nx))   # by column x, then row
+        leaf_assign = np.empty(n_per_leaflet, dtype=np.int32)
+        leaf_assign[order] = stripe
+        assign = np.concatenate([leaf_assign, leaf_assign])
+        counts = [2 * c for c in per_leaf]
     ax, ay = Lx / nx, Ly / ny
     area = Lx * Ly
     # depth step: fit the bilayer and a water slab of density ~8.36 /nm^3
@@ -289,8 +303,13 @@ def bilayer(name, n_per_leaflet, fractions, n_water, box_xy, box_z, seed,
                   pos=pos, vel=vel, box=box, eps=eps,
                   sigma=np.full((N_TYPES, N_TYPES), SIGMA), seed=int(seed),
                   temperature=temperature)
+    # leaflet of each molecule (0 upper, 1 lower, -1 water): a structural
+    # label of the build, used by the mixing observable
+    leaflet = np.concatenate([np.zeros(n_per_leaflet, dtype=np.int32),
+                              np.ones(n_per_leaflet, dtype=np.int32),
+                              np.full(n_water, -1, dtype=np.int32)])
     sysm.meta = {"n_lipids": n_lip, "kind_counts": counts, "n_water": n_water,
-                 "grid": (nx, ny), "depth_step": d}
+                 "grid": (nx, ny), "depth_step": d, "leaflet": leaflet}
     return sysm
 
 
@@ -305,6 +324,13 @@ def make(config, seed=None, **kw):
     if config == "c3":
         return bilayer("c3", 24576, [0.3, 0.3, 0.2, 0.2], 590000, 125.4, 11.0,
                        SEEDS["c3"] if seed is None else seed, **kw)
+    if config == "mix":
+        # the paper's mixing test in shape: 400 lipids, 1:1 of a neutral lipid
+        # (A) and its anionic twin (D, head charge -1), water, far-from-mixed
+        # stripes unless demix=False
+        kw.setdefault("demix", True)
+        return bilayer("mix", 200, [0.5, 0.5], 4000, 11.31, 9.0,
+                       SEEDS["mix"] if seed is None else seed, lipid_kinds=[KIND_A, KIND_D], **kw)
     raise ValueError(f"unknown config {config!r}")
 
 

@@ -401,3 +401,80 @@ def test_mdas_continuation_rules(oracle_mod, c0_relaxed):
         assert after["step"] == before["step"] + 6     # noise is never reused
         seen.add(bool(res["accept"]))
     assert seen == {True, False}
+
+
+# ------------------------------------------------------------ mixing observable
+def _lattice_po4_system(n, a, second_leaflet_kind):
+    """n x n periodic square lattice (spacing a) of two-bead molecules
+    [head, PO4] in the upper leaflet, plus the same lattice shifted by a/2 in
+    the lower leaflet with molecules of another kind."""
+    kh = S.Kind("H", [S.TYPE_N, S.TYPE_Q], [0.0, 0.0], [(0, 1, 0.47, 1250.0)], [], 0)
+    kh2 = S.Kind("H2", [S.TYPE_N, S.TYPE_Q], [0.0, 0.0], [(0, 1, 0.47, 1250.0)], [], 0)
+    L = n * a
+    pos, mk, leaf = [], [], []
+    for lf, kind, off, z in ((0, 0, 0.0, 6.0), (1, second_leaflet_kind, 0.5 * a, 2.0)):
+        for i in range(n):
+            for j in range(n):
+                x, y = i * a + off, j * a + off
+                pos += [[x, y, z + 0.47], [x, y, z]]
+                mk.append(kind)
+                leaf.append(lf)
+    s = S.custom("lattice", [kh, kh2], mk, pos, [L, L, 9.0], np.full((S.N_TYPES, S.N_TYPES), 2.0))
+    return s, np.asarray(leaf, dtype=np.int32)
+
+
+@pytest.mark.parametrize("second_kind", [0, 1])
+def test_pair_histogram_square_lattice(oracle_mod, second_kind):
+    """Exact shell counts on a periodic square lattice: every point has 4
+    neighbours at a, 4 at a sqrt 2, 4 at 2a and 8 at a sqrt 5; pairs across
+    leaflets never count, whatever the kinds."""
+    n, a, w = 8, 1.0, 0.07
+    s, leaf = _lattice_po4_system(n, a, second_kind)
+    o = oracle_mod.Oracle(s)
+    h = o.pair_histogram(0, 1, leaf, 80, w)
+    N = n * n
+    m = 2 if second_kind == 0 else 1   # leaflets holding kind 0
+    assert h[int(a / w)] == m * N * 4 // 2                    # bin 14
+    assert h[int(a * math.sqrt(2) / w)] == m * N * 4 // 2     # bin 20
+    assert h[int(2 * a / w)] == m * N * 4 // 2                # bin 28
+    assert h[int(a * math.sqrt(5) / w)] == m * N * 8 // 2     # bin 31
+    # cross-leaflet pairs (lateral a / sqrt 2, bin 10) never count: nothing
+    # below the first shell; all same-leaflet pairs in range, nothing else
+    assert h[:14].sum() == 0
+    assert h.sum() == m * np.count_nonzero(_lattice_d2(n, a) < (80 * w) ** 2)
+
+
+def _lattice_d2(n, a):
+    ij = np.array([(i, j) for i in range(n) for j in range(n)], dtype=np.float64) * a
+    L = n * a
+    d = ij[:, None, :] - ij[None, :, :]
+    d -= L * np.rint(d / L)
+    d2 = (d ** 2).sum(-1)
+    iu = np.triu_indices(len(ij), 1)
+    return d2[iu]
+
+
+def test_pair_histogram_equals_explicit_images(oracle_mod, c0):
+    """Random bilayer (C0): the oracle's minimum-image histogram equals one
+    built from the nine explicit periodic images of every pair (smallest
+    distance) and numpy's histogram, per leaflet and kind."""
+    o = oracle_mod.Oracle(c0)
+    leaf = c0.meta["leaflet"]
+    first, _ = c0.mol_first()
+    w, nb = 0.05, 50
+    for kind in (S.KIND_A, S.KIND_B):
+        h = o.pair_histogram(kind, S.PO4, leaf, nb, w)
+        ref = np.zeros(nb, dtype=np.int64)
+        for lf in (0, 1):
+            sel = np.where((c0.mol_kind == kind) & (leaf == lf))[0]
+            p = c0.pos[first[sel] + S.PO4][:, :2]
+            best = np.full((len(p), len(p)), np.inf)
+            for sx in (-1, 0, 1):
+                for sy in (-1, 0, 1):
+                    sh = np.array([sx * c0.box[0], sy * c0.box[1]])
+                    d = p[:, None, :] - (p[None, :, :] + sh)
+                    best = np.minimum(best, np.sqrt((d ** 2).sum(-1)))
+            iu = np.triu_indices(len(p), 1)
+            ref += np.histogram(best[iu], bins=np.arange(nb + 1) * w)[0]
+        assert np.array_equal(h, ref), (kind, h, ref)
+        assert h.sum() > 0
