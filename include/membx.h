@@ -223,6 +223,20 @@ int32_t membx_set_state(membx_sys* sys, const double* pos, const double* vel,
 /* Current forces (those the next half-kick uses) in bead-id order, [3 N]. */
 int32_t membx_forces(membx_sys* sys, double* f);
 
+/* Mixing observable (Results: mixing followed through the pair
+ * correlation of the PO4 beads of one lipid type, whose highest peak decays
+ * to its mixed value): histogram of the lateral separations d (x and y, each
+ * by the minimum-image convention) over all unordered pairs of bead `po4`
+ * of the molecules of kind `kind` that sit in the same leaflet.
+ * leaflet[n_mols] (host, read during the call): 0 or 1 per molecule, -1
+ * leaves the molecule out.  Bin k < n_bins (1..4096) counts the pairs with
+ * (k w)^2 <= d^2 < ((k + 1) w)^2, w = bin_width > 0, from the float64
+ * squared distance of the current coordinates; counts[n_bins] (host)
+ * receives them.  Exact (integer counts).  Synchronizes.  E_INVAL (bad
+ * arguments, kind or bead index out of range). */
+int32_t membx_pair_histogram(membx_sys* sys, int32_t kind, int32_t po4, const int32_t* leaflet,
+                             int32_t n_bins, double bin_width, int64_t* counts);
+
 /* Rebuild the neighbour list at the current coordinates and export its pair
  * set {(i, j): i < j, not bonded, float64 |r_ij|^2 < (r_cut + skin)^2} as
  * bead-id pairs.  Writes min(n, cap) pairs to ij [2 cap]; *n = pair count. */

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmembx.so")
-SOURCES = ["k_list.hip", "k_force.hip", "k_md.hip", "k_moves.hip", "runtime.hip"]
+SOURCES = ["k_list.hip", "k_force.hip", "k_md.hip", "k_moves.hip", "k_obs.hip", "runtime.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

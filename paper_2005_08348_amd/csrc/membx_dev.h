@@ -110,6 +110,17 @@ template <> __device__ __forceinline__ void gauss3<float>(uint4 w, float g[3])
 // so that  F/r = (12 C12 r^-12 - 6 C6 r^-6) r^-2 + qq (r^-3 - 2 k_rf)
 //          V   = C12 r^-12 - C6 r^-6 - shift + qq (1/r + k_rf r^2 - c_rf).
 
+// Buffers of the mixing observable (pair histogram of PO4 beads).
+constexpr int OBS_MAXBINS = 4096;
+struct ObsBuf {
+    int* leaf;                 // [nm] leaflet of each molecule (-1: skip), from the caller
+    double2* xy;               // [nm] selected PO4 coordinates (x, y)
+    int* lf;                   // [nm] their leaflets
+    int* n;                    // [1] selected count
+    double* edge2;             // [OBS_MAXBINS + 1] squared bin edges
+    unsigned long long* hist;  // [OBS_MAXBINS] pair counts
+};
+
 // Everything a kernel needs about one system (passed by value).
 template <typename R> struct Dev {
     // sizes

@@ -31,6 +31,8 @@ template <typename R> void launch_sd_step(const Dev<R>&, double, double, hipStre
 template <typename R> void launch_export(const Dev<R>&, const V4<R>*, double*, hipStream_t);
 template <typename R> void launch_import(const Dev<R>&, V4<R>*, const double*, hipStream_t);
 void launch_fill_i32(int*, int, size_t, hipStream_t);
+template <typename R> void launch_obs_gather(const Dev<R>&, const ObsBuf&, int, int, hipStream_t);
+void launch_obs_pairs(const ObsBuf&, int, int, double, double, double, hipStream_t);
 void launch_copy(void*, const void*, size_t, hipStream_t);
 void launch_add_ctr(long long*, int, long long, hipStream_t);
 template <typename R> void launch_select(const Dev<R>&, const Mv&, int, int, int, hipStream_t);
@@ -409,6 +411,7 @@ struct membx_sys {
     int nbe_blocks = 0, bd_blocks = 0, ke_blocks = 0;
     double *p_nb = nullptr, *p_bd = nullptr, *p_ke = nullptr;
     double* xbuf = nullptr;  // [3N] export / import buffer
+    ObsBuf obs{};            // mixing observable
     int* ibuf = nullptr;     // [N]
     bool graphs = true;
     bool fuse = true;        // force kernel integrates the next step (plain MD)
@@ -514,6 +517,12 @@ static size_t layout(membx_sys* s, Dev<R>& d, Mv& m, char* base)
     d.red = a.take<double>(8 * (size_t)s->nbe_blocks);
     d.eout = a.take<double>(8);
     s->xbuf = a.take<double>(3 * (size_t)N);
+    s->obs.leaf = a.take<int>(h.nm);
+    s->obs.xy = a.take<double2>(h.nm);
+    s->obs.lf = a.take<int>(h.nm);
+    s->obs.n = a.take<int>(1);
+    s->obs.edge2 = a.take<double>(OBS_MAXBINS + 1);
+    s->obs.hist = a.take<unsigned long long>(OBS_MAXBINS);
     s->ibuf = a.take<int>(N);
     // moves
     int MC = 2 * h.maxch, T = std::max(h.T_cap, h.P_cap);
@@ -1391,6 +1400,43 @@ int32_t membx_pairset_export(membx_sys* s, int32_t* ij, int64_t cap, int64_t* n)
     if (!s || (cap > 0 && !ij)) return fail(s, MEMBX_E_INVAL, "bad arguments");
     int32_t rc = begin(s);
     if (!rc) rc = DISPATCH(s, pairset_impl, s, ij, cap, n);
+    if (!rc) rc = end(s);
+    return rc;
+}
+
+template <typename R>
+static int32_t hist_impl(membx_sys* s, int kind, int po4, const int32_t* leaflet, int nb, double w,
+                         int64_t* counts)
+{
+    Dev<R>& d = dev<R>(s);
+    Host& h = s->h;
+    std::vector<double> e2(nb + 1);
+    for (int k = 0; k <= nb; ++k) e2[k] = ((double)k * w) * ((double)k * w);
+    HCK(hipMemcpyAsync(s->obs.leaf, leaflet, sizeof(int) * h.nm, hipMemcpyHostToDevice, s->st));
+    HCK(hipMemcpyAsync(s->obs.edge2, e2.data(), sizeof(double) * (nb + 1), hipMemcpyHostToDevice, s->st));
+    launch_fill_i32(s->obs.n, 0, 1, s->st);
+    launch_fill_i32(reinterpret_cast<int*>(s->obs.hist), 0, 2 * (size_t)nb, s->st);
+    launch_obs_gather<R>(d, s->obs, kind, po4, s->st);
+    int npts = 0;
+    HCK(hipMemcpyAsync(&npts, s->obs.n, sizeof(int), hipMemcpyDeviceToHost, s->st));
+    HCK(hipStreamSynchronize(s->st));
+    launch_obs_pairs(s->obs, npts, nb, w, h.box[0], h.box[1], s->st);
+    static_assert(sizeof(unsigned long long) == sizeof(int64_t), "count width");
+    HCK(hipMemcpyAsync(counts, s->obs.hist, sizeof(int64_t) * nb, hipMemcpyDeviceToHost, s->st));
+    HCK(hipStreamSynchronize(s->st));
+    return MEMBX_OK;
+}
+
+int32_t membx_pair_histogram(membx_sys* s, int32_t kind, int32_t po4, const int32_t* leaflet,
+                             int32_t n_bins, double bin_width, int64_t* counts)
+{
+    if (!s || !leaflet || !counts || n_bins < 1 || n_bins > OBS_MAXBINS || !(bin_width > 0) ||
+        !std::isfinite(bin_width))
+        return fail(s, MEMBX_E_INVAL, "bad arguments");
+    if (kind < 0 || kind >= s->h.nk || po4 < 0 || po4 >= s->h.kn[kind])
+        return fail(s, MEMBX_E_INVAL, "kind or bead index out of range");
+    int32_t rc = begin(s);
+    if (!rc) rc = DISPATCH(s, hist_impl, s, kind, po4, leaflet, n_bins, bin_width, counts);
     if (!rc) rc = end(s);
     return rc;
 }

@@ -115,6 +115,7 @@ def lib():
             "membx_set_state": ([vp, vp, vp, vp, vp], i32),
             "membx_forces": ([vp, vp], i32),
             "membx_pairset_export": ([vp, vp, i64, C.POINTER(i64)], i32),
+            "membx_pair_histogram": ([vp, i32, i32, vp, i32, dp, vp], i32),
             "membx_minimize": ([vp, i32, dp, dp], i32),
             "membx_set_tuning": ([vp, dp, i32, i32, dp, i32], i32),
             "membx_autotune": ([vp, i32, C.POINTER(dp), C.POINTER(i32), C.POINTER(i32),
@@ -346,6 +347,18 @@ class System:
         _check(lib().membx_pairset_export(self.h, out.ctypes.data_as(C.c_void_p), n.value,
                                           C.byref(n)), self.h)
         return out[:2 * n.value].reshape(-1, 2)
+
+    def pair_histogram(self, kind, po4, leaflet, n_bins, bin_width):
+        """lateral pair counts of bead po4 of the molecules of one kind within
+        each leaflet (leaflet[n_mols]: 0/1, -1 skips), bins of bin_width"""
+        lf = np.ascontiguousarray(leaflet, dtype=np.int32)
+        if lf.shape != (self.nm,):
+            raise ValueError("leaflet must have one entry per molecule")
+        out = np.zeros(int(n_bins), dtype=np.int64)
+        _check(lib().membx_pair_histogram(self.h, int(kind), int(po4), lf.ctypes.data_as(C.c_void_p),
+                                          int(n_bins), float(bin_width),
+                                          out.ctypes.data_as(C.c_void_p)), self.h)
+        return out
 
     def status(self):
         return lib().membx_status(self.h)
