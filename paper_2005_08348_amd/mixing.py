@@ -1,0 +1,200 @@
+"""Mixing analysis and the sampler comparison of the paper's Results.
+
+The paper follows the mixing of a two-lipid bilayer through the pair
+correlation g(r) of the PO4 beads of one lipid type: its highest peak,
+max[g(r)], decays towards the value of a uniformly mixed membrane, and an
+exponential fitted to that decay against the number of force evaluations
+gives each sampler's relaxation rate; the ratio of rates is the speed-up per
+force evaluation of MC-MD or MDAS over straightforward MD.  It also
+estimates an acceptance probability from the recorded work values.
+
+Here g(r) is the lateral (in-plane) correlation within each leaflet, from
+the GPU pair histogram (``System.pair_histogram``), normalised by the ideal
+two-dimensional expectation of each leaflet.
+
+    python -m paper_2005_08348_amd.mixing [--fe 200000] [--every 4000]
+
+runs MD, MC-MD and MDAS from the same far-from-mixed start (the ``mix``
+bilayer: 400 lipids in stripes) and prints one JSON line with the traces,
+the fits and the speed-ups.  Force evaluations are counted as the paper
+does: one per MD step, per exchange trial and per MDAS step (a frozen MDAS
+cycle, M = 0, counts one).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import systems as S
+
+
+# ---------------------------------------------------------------- analysis
+def g_of_r(counts, n_per_leaflet, area, bin_width):
+    """g(r) at the bin centres from lateral pair counts within leaflets:
+    counts over the number of pairs an ideal 2-D gas of the same densities
+    would put in each annulus, sum over leaflets of n (n - 1) / 2 times the
+    annulus area over the leaflet area."""
+    counts = np.asarray(counts, dtype=np.float64)
+    k = np.arange(len(counts), dtype=np.float64)
+    annulus = math.pi * ((k + 1.0) ** 2 - k ** 2) * bin_width ** 2
+    pairs = sum(0.5 * n * (n - 1) for n in n_per_leaflet)
+    expected = pairs * annulus / area
+    g = np.divide(counts, expected, out=np.zeros_like(counts), where=expected > 0)
+    r = (k + 0.5) * bin_width
+    return r, g
+
+
+def max_g(counts, n_per_leaflet, area, bin_width, r_min=0.0):
+    """the highest peak of g(r) at r >= r_min (the sparse bins below the
+    contact distance only carry noise)"""
+    r, g = g_of_r(counts, n_per_leaflet, area, bin_width)
+    return float(g[r >= r_min].max())
+
+
+def fe_to_half(x, y, y_mixed, smooth=3):
+    """Force evaluations until the running mean (over `smooth` samples) of
+    the trace first falls halfway from its start to the mixed level; None if
+    it never does within the run."""
+    y = np.asarray(y, dtype=np.float64)
+    if len(y) < smooth:
+        return None
+    ys = np.convolve(y, np.ones(smooth) / smooth, mode="valid")
+    half = 0.5 * (y[0] + y_mixed)
+    hit = np.nonzero(ys <= half)[0]
+    return float(x[hit[0] + smooth - 1]) if len(hit) else None
+
+
+def fit_exponential(x, y):
+    """Least-squares fit y = c + a exp(-x / tau); returns (c, a, tau) or
+    None when the fit does not converge."""
+    from scipy.optimize import curve_fit
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    span = max(float(x.max() - x.min()), 1.0)
+    p0 = (float(y[-1]), float(y[0] - y[-1]), span / 3.0)
+
+    def f(t, c, a, tau):
+        return c + a * np.exp(-t / tau)
+    try:
+        p, _ = curve_fit(f, x, y, p0=p0, bounds=([-np.inf, -np.inf, 1e-9], [np.inf, np.inf, np.inf]),
+                         maxfev=20000)
+    except (RuntimeError, ValueError):
+        return None
+    return float(p[0]), float(p[1]), float(p[2])
+
+
+def acceptance_from_work(w, kT):
+    """Acceptance estimated from work values: the mean of min(1, exp(-w/kT))."""
+    w = np.asarray(w, dtype=np.float64)
+    return float(np.mean(np.minimum(1.0, np.exp(-w / kT)))) if len(w) else float("nan")
+
+
+# -------------------------------------------------------------- experiment
+R_MIN = 0.5      # nm, the peak search starts here
+BIN = 0.1        # nm
+N_BINS = 45      # up to 4.5 nm
+
+
+def _trace_point(g, sysm, kind, leaflet, n_bins, bin_width):
+    mk = g.state()["mol_kind"]
+    n_leaf = [int(np.count_nonzero((mk == kind) & (leaflet == lf))) for lf in (0, 1)]
+    h = g.pair_histogram(kind, S.PO4, leaflet, n_bins, bin_width)
+    return max_g(h, n_leaf, sysm.box[0] * sysm.box[1], bin_width, R_MIN)
+
+
+def run(method, sysm, fe_total, every, kind=S.KIND_D, n_bins=N_BINS, bin_width=BIN,
+        mc_trials=8, mc_steps=2, mdas_pairs=1, mdas_k=50, mdas_m=1, mdas_md=50, precision="mixed"):
+    """One sampler from the start structure: (force evaluations, max[g]) pairs
+    every `every` force evaluations, plus acceptance counts and works."""
+    from . import membx as M
+    leaflet = sysm.meta["leaflet"]
+    g = M.System(sysm, precision=precision)
+    g.minimize(100)
+    g.md_step(200)                       # thermalise (not counted)
+    fe, trace, works, acc, tried = 0, [], [], 0, 0
+    trace.append((0, _trace_point(g, sysm, kind, leaflet, n_bins, bin_width)))
+    next_pt = every
+    t0 = time.perf_counter()
+    while fe < fe_total:
+        if method == "md":
+            g.md_step(every)
+            fe += every
+        elif method == "mcmd":
+            r = g.swap_trials(mc_trials)
+            g.md_step(mc_steps)
+            n = len(r["accept"])
+            tried += n
+            acc += int(np.count_nonzero(r["accept"]))
+            fe += n + mc_steps
+        elif method == "mdas":
+            g.md_step(mdas_md)
+            r = g.mdas_cycle(mdas_pairs, mdas_k, mdas_m)
+            works.append(r["work"])
+            tried += 1
+            acc += int(r["accept"])
+            fe += mdas_md + (mdas_k * mdas_m if mdas_m > 0 else 1)
+        else:
+            raise ValueError(method)
+        if fe >= next_pt:
+            trace.append((fe, _trace_point(g, sysm, kind, leaflet, n_bins, bin_width)))
+            next_pt += every
+    wall = time.perf_counter() - t0
+    g.close()
+    return dict(method=method, trace=trace, accepted=acc, tried=tried, works=works, wall_s=wall)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--fe", type=int, default=200000, help="force evaluations per sampler")
+    ap.add_argument("--every", type=int, default=4000, help="force evaluations between g(r) samples")
+    ap.add_argument("--seed", type=int, default=None)
+    args = ap.parse_args(argv)
+    sysm = S.make("mix", seed=args.seed)
+    kT = S.KB * sysm.temperature
+    out = {"system": "mix: 400 lipids (A:D 1:1) in stripes + 4000 W, 11.31 x 11.31 x 9 nm",
+           "observable": f"max g(r) at r >= {R_MIN} nm, lateral PO4-PO4 of kind D within leaflets, "
+                         f"bins {BIN} nm",
+           "samplers": "MD; MC-MD: 8 exchange trials per batch + 2 MD steps; MDAS: 1 pair, "
+                       "K = 50, M = 1, after 50 MD steps",
+           "fe_counting": "1 per MD step, per exchange trial and per MDAS step", "runs": {}}
+    # the level of a uniformly mixed membrane: the same lipids randomly mixed
+    mixed = S.make("mix", seed=args.seed, demix=False)
+    ref = run("md", mixed, max(args.fe // 10, 4 * args.every), args.every)
+    y_mixed = float(np.mean([p[1] for p in ref["trace"]]))
+    out["mixed_level"] = y_mixed
+    for method in ("md", "mcmd", "mdas"):
+        print(f"[mixing] {method}", file=sys.stderr, flush=True)
+        r = run(method, sysm, args.fe, args.every)
+        x = np.array([p[0] for p in r["trace"]], dtype=np.float64)
+        y = np.array([p[1] for p in r["trace"]], dtype=np.float64)
+        fit = fit_exponential(x, y)
+        entry = {"fe": x.tolist(), "max_g": y.tolist(), "fit_c_a_tau": fit,
+                 "fe_to_half": fe_to_half(x, y, y_mixed),
+                 "accepted": r["accepted"], "tried": r["tried"], "wall_s": r["wall_s"]}
+        if method == "mdas":
+            entry["acceptance_from_work"] = acceptance_from_work(r["works"], kT)
+        out["runs"][method] = entry
+    # speed-up per force evaluation: ratio of fitted decay constants (when
+    # both fits decay within the run), and the ratio of force evaluations to
+    # reach half-way to the mixed level (a lower bound when MD never does)
+    md = out["runs"]["md"]
+    f_md = md["fit_c_a_tau"]
+    tau_md = f_md[2] if (f_md and f_md[2] < 3 * args.fe) else None
+    for method in ("mcmd", "mdas"):
+        e = out["runs"][method]
+        f = e["fit_c_a_tau"]
+        e["speedup_fit"] = tau_md / f[2] if (tau_md and f and 0 < f[2] < 3 * args.fe) else None
+        h = e["fe_to_half"]
+        if h:
+            e["speedup_half"] = (md["fe_to_half"] / h) if md["fe_to_half"] else None
+            e["speedup_half_lower_bound"] = None if md["fe_to_half"] else args.fe / h
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
