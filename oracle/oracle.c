@@ -32,7 +32,7 @@
 
 /* random stream ids (fourth counter word) */
 enum { ST_LANGEVIN = 0, ST_SWAP_DRAW = 1, ST_SWAP_ACCEPT = 2,
-       ST_MDAS_SELECT = 3, ST_MDAS_ACCEPT = 4 };
+       ST_MDAS_SELECT = 3, ST_MDAS_ACCEPT = 4, ST_VRESCALE = 5 };
 
 typedef struct {
     /* kinds */
@@ -64,6 +64,11 @@ typedef struct {
     /* scratch */
     int *mk_tmp;
     double *f_tmp;
+    /* ensemble: 0 Langevin BAOAB, 1 velocity Verlet + stochastic velocity
+     * rescaling of two coupling groups */
+    int ensemble;
+    double tau_t;
+    int kgroup[64];          /* coupling group of each kind */
 } osys;
 
 /* ------------------------------------------------------------ Philox4x32-10 */
@@ -640,9 +645,116 @@ static void baoab(osys* s, const int* mk_b, double lam)
     s->step++;
 }
 
+/* ------------------------------------------------- velocity rescaling (f2) */
+/* The paper's runs keep the temperature with stochastic velocity rescaling
+ * (Methods).  After each velocity Verlet step the kinetic energy K of each
+ * coupling group is moved to K' by one step of the stochastic dynamics of
+ * Bussi, Donadio and Parrinello (J. Chem. Phys. 126, 014101, 2007), with
+ * c = exp(-dt / tau_t), target Kt = Nf kT / 2 and Nf = 3 (beads in the
+ * group):  K' = K + (1 - c) (Kt (R1^2 + S) / Nf - K)
+ *              + 2 R1 sqrt(c (1 - c) K Kt / Nf),
+ * R1 standard normal, S chi-squared with Nf - 1 degrees of freedom; the
+ * velocities of the group are multiplied by alpha = +-sqrt(K' / K), negative
+ * when R1 + sqrt(c Nf K / ((1 - c) Kt)) < 0.  Random numbers: Philox
+ * stream 5 with counter = the step index; block (group << 16) gives R1 from
+ * its first two words, blocks (group << 16) + 1 + t the t-th attempt of the
+ * gamma sampler below. */
+
+/* one standard normal from two words (Box-Muller, cosine branch) */
+static double normal1(uint32_t a, uint32_t b)
+{
+    const double two32 = 4294967296.0, twopi = 6.283185307179586476925286766559;
+    double u1 = ((double)a + 1.0) / two32, u2 = (double)b / two32;
+    return sqrt(-2.0 * log(u1)) * cos(twopi * u2);
+}
+
+/* Gamma(a, 1), a >= 1, by Marsaglia and Tsang (ACM TOMS 26, 363, 2000):
+ * d = a - 1/3, c = 1/sqrt(9 d); draw x standard normal and u uniform until
+ * v = (1 + c x)^3 > 0 and log u < x^2 / 2 + d - d v + d log v; return d v.
+ * At most 64 attempts (then d, which has probability ~0 to matter). */
+static double gamma_mt(const osys* s, int g, double a, int64_t ctr)
+{
+    const double d = a - 1.0 / 3.0, c = 1.0 / sqrt(9.0 * d);
+    for (int t = 0; t < 64; ++t) {
+        uint32_t w[4];
+        draw(s, (uint32_t)((g << 16) + 1 + t), ctr, ST_VRESCALE, w);
+        const double x = normal1(w[0], w[1]);
+        const double u = u53(w[2], w[3]);
+        const double y = 1.0 + c * x;
+        if (y <= 0.0) continue;
+        const double v = y * y * y;
+        if (log(u) < 0.5 * x * x + d - d * v + d * log(v)) return d * v;
+    }
+    return d;
+}
+
+static double vr_alpha(const osys* s, int g, double K, double nf, int64_t ctr)
+{
+    if (!(K > 0.0) || !(nf >= 3.0)) return 1.0;
+    const double c = exp(-s->dt / s->tau_t);
+    const double kt = 0.5 * nf * s->kT;
+    uint32_t w[4];
+    draw(s, (uint32_t)(g << 16), ctr, ST_VRESCALE, w);
+    const double r1 = normal1(w[0], w[1]);
+    const double sch = 2.0 * gamma_mt(s, g, 0.5 * (nf - 1.0), ctr);
+    const double kn = K + (1.0 - c) * (kt * (r1 * r1 + sch) / nf - K) +
+                      2.0 * r1 * sqrt(c * (1.0 - c) * K * kt / nf);
+    double al = sqrt(kn / K);
+    if (r1 + sqrt(c * nf * K / ((1.0 - c) * kt)) < 0.0) al = -al;
+    return al;
+}
+
+/* one velocity Verlet step (BAOAB without the O part) and the rescaling of
+ * each group with the counter of that step */
+static void vv_vrescale(osys* s, const int* mk_b, double lam)
+{
+    const double g0 = s->gamma;
+    s->gamma = 0.0;
+    const int64_t ctr = s->step;    /* the thermostat draws with this step's counter */
+    baoab(s, mk_b, lam);            /* advances s->step */
+    s->gamma = g0;
+    double K[2] = { 0.0, 0.0 }, nf[2] = { 0.0, 0.0 };
+    for (int i = 0; i < s->n; ++i) {
+        const int g = s->kgroup[s->mkind[s->bmol[i]]];
+        const double m = bmass(s, i);
+        const double* v = s->v + 3 * i;
+        K[g] += 0.5 * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        nf[g] += 3.0;
+    }
+    const double al[2] = { vr_alpha(s, 0, K[0], nf[0], ctr), vr_alpha(s, 1, K[1], nf[1], ctr) };
+    for (int i = 0; i < s->n; ++i) {
+        const double a = al[s->kgroup[s->mkind[s->bmol[i]]]];
+        for (int q = 0; q < 3; ++q) s->v[3 * i + q] *= a;
+    }
+}
+
+void o_set_ensemble(osys* s, int ensemble, double tau_t, const int* kind_group)
+{
+    s->ensemble = ensemble;
+    s->tau_t = tau_t;
+    for (int k = 0; k < s->nk && k < 64; ++k) s->kgroup[k] = kind_group ? (kind_group[k] != 0) : 0;
+}
+
+/* the statistics pins use these directly: n draws at counters ctr0 .. ctr0 + n - 1 */
+void o_gamma_mt(osys* s, int g, double a, int64_t ctr0, int n, double* out)
+{
+    for (int t = 0; t < n; ++t) out[t] = gamma_mt(s, g, a, ctr0 + t);
+}
+void o_vr_alpha(osys* s, int g, double K, double nf, int64_t ctr0, int n, double* out)
+{
+    for (int t = 0; t < n; ++t) out[t] = vr_alpha(s, g, K, nf, ctr0 + t);
+}
+
+/* one MD step of the selected ensemble (at coupling lam for MDAS segments) */
+static void md_one(osys* s, const int* mk_b, double lam)
+{
+    if (s->ensemble == 1) vv_vrescale(s, mk_b, lam);
+    else baoab(s, mk_b, lam);
+}
+
 void o_md_step(osys* s, int nsteps)
 {
-    for (int t = 0; t < nsteps; ++t) baoab(s, NULL, 0.0);
+    for (int t = 0; t < nsteps; ++t) md_one(s, NULL, 0.0);
 }
 
 /* Capped steepest descent: each bead moves by alpha F_i, shortened to at most
@@ -862,7 +974,7 @@ int o_mdas_cycle(osys* s, int n_pairs, int K, int M, double* w_out, int* acc_out
     double work = 0.0, lam = 0.0;
     if (M == 0) s->n_fe++;   /* the single energy difference of a frozen AT */
     for (int k = 1; k <= K; ++k) {
-        for (int m = 0; m < M; ++m) baoab(s, mk_b, lam);
+        for (int m = 0; m < M; ++m) md_one(s, mk_b, lam);
         double lam_new = (double)k / (double)K;
         double ea[4], eb[4];
         energy_forces(s, s->mkind, NULL, ea, 1);

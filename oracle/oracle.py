@@ -84,6 +84,10 @@ def lib():
         L.o_pairs_delta_u.restype = C.c_double
         L.o_pair_histogram.argtypes = [C.c_void_p, C.c_int, C.c_int, _i32p, C.c_int, C.c_double,
                                        _i64p]
+        L.o_set_ensemble.argtypes = [C.c_void_p, C.c_int, C.c_double, _i32p]
+        L.o_gamma_mt.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_int64, C.c_int, _f64p]
+        L.o_vr_alpha.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_int64, C.c_int,
+                                 _f64p]
         L.o_philox.argtypes = [_u32p, _u32p, _u32p]
         L.o_gauss3.argtypes = [_u32p, _f64p]
         L.o_pair_term.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_double,
@@ -222,6 +226,28 @@ class Oracle:
         k = lib().o_mdas_cycle(self.h, n_pairs, K, M, C.byref(w), C.byref(acc), C.byref(u), pairs)
         return dict(work=w.value, accept=bool(acc.value), u=u.value,
                     pairs=pairs[:2 * k].reshape(-1, 2))
+
+    def set_ensemble(self, ensemble, tau_t=1.0, kind_group=None):
+        """0: Langevin BAOAB; 1: velocity Verlet + stochastic velocity
+        rescaling of the coupling groups kind_group[n_kinds] (0/1)"""
+        nk = len(self.system.kinds)
+        kg = np.zeros(nk, dtype=np.int32) if kind_group is None else _i32(kind_group)
+        if len(kg) != nk:
+            raise ValueError("kind_group needs one entry per molecule kind")
+        lib().o_set_ensemble(self.h, int(ensemble), float(tau_t), kg)
+
+    def gamma_mt(self, group, a, ctr0, n):
+        """the thermostat's Gamma(a, 1) draws at step counters ctr0 .. ctr0 + n - 1"""
+        out = np.zeros(n)
+        lib().o_gamma_mt(self.h, int(group), float(a), int(ctr0), int(n), out)
+        return out
+
+    def vr_alpha(self, group, K, nf, ctr0, n):
+        """the thermostat's velocity factors for kinetic energy K of a group
+        with nf degrees of freedom, at step counters ctr0 .. ctr0 + n - 1"""
+        out = np.zeros(n)
+        lib().o_vr_alpha(self.h, int(group), float(K), float(nf), int(ctr0), int(n), out)
+        return out
 
     def pair_histogram(self, kind, po4, leaflet, n_bins, bin_width):
         """lateral PO4-PO4 pair counts per bin (unordered pairs, same leaflet)"""

@@ -478,3 +478,113 @@ def test_pair_histogram_equals_explicit_images(oracle_mod, c0):
             ref += np.histogram(best[iu], bins=np.arange(nb + 1) * w)[0]
         assert np.array_equal(h, ref), (kind, h, ref)
         assert h.sum() > 0
+
+
+# ------------------------------------------- stochastic velocity rescaling
+# The paper's ensemble (Methods) uses the velocity rescaling thermostat of
+# Bussi, Donadio and Parrinello; these pins hold its oracle against
+# statistics fixed by the method's definition and by an independent
+# construction, never against its own formulas.
+
+@pytest.mark.parametrize("a", [1.0, 1.5, 7.0, 300.0, 1e5])
+def test_gamma_sampler_distribution(oracle_mod, c0, a):
+    """The thermostat's gamma draws follow Gamma(a, 1) (Kolmogorov-Smirnov
+    against scipy's distribution)."""
+    from scipy import stats
+    o = oracle_mod.Oracle(c0)
+    g = o.gamma_mt(1, a, 1000, 20000)
+    assert stats.kstest(g, stats.gamma(a).cdf).pvalue > 1e-4
+    assert abs(g.mean() / a - 1.0) < 6.0 / math.sqrt(a * len(g))
+
+
+def _o_step_alphas(K, nf, c, kT, n, seed):
+    """Velocity factors from an independent construction: nf unit-mass
+    velocity components with kinetic energy K, one Ornstein-Uhlenbeck step
+    v' = sqrt(c) v + sqrt((1 - c) kT) xi, and alpha = sign(v'.v) |v'| / |v|.
+    The kinetic energy dynamics of the rescaling thermostat is exactly this
+    step's, so both give the same distribution of alpha."""
+    rng = np.random.default_rng(seed)
+    v = np.zeros(nf); v[0] = math.sqrt(2.0 * K)
+    xi = rng.standard_normal((n, nf))
+    vp = math.sqrt(c) * v + math.sqrt((1.0 - c) * kT) * xi
+    return np.sign(vp[:, 0]) * np.linalg.norm(vp, axis=1) / np.linalg.norm(v)
+
+
+@pytest.mark.parametrize("nf,k_over_kt,c", [(3, 0.1, 0.5), (3, 2.0, 0.95), (30, 1.5, 0.9),
+                                            (300, 0.8, 0.3)])
+def test_vrescale_alpha_equals_ou_step(oracle_mod, c0, nf, k_over_kt, c):
+    from scipy import stats
+    s = c0.copy()
+    kT = KB * s.temperature
+    o = oracle_mod.Oracle(s)
+    o.set_ensemble(1, tau_t=-s.dt / math.log(c))
+    K = k_over_kt * 0.5 * nf * kT
+    a_or = o.vr_alpha(0, K, float(nf), 0, 20000)
+    a_ou = _o_step_alphas(K, nf, c, kT, 20000, seed=nf)
+    assert stats.ks_2samp(a_or, a_ou).pvalue > 1e-4
+    # the sign: reversals happen as often as the velocity turns round
+    p_neg = np.mean(a_ou < 0)
+    assert abs(np.mean(a_or < 0) - p_neg) < 6.0 * math.sqrt(max(p_neg, 1e-4) / 20000)
+
+
+def test_vrescale_limits(oracle_mod, c0):
+    """tau_t -> infinity leaves the velocities alone; tau_t -> 0 draws a
+    fresh kinetic energy from the canonical Gamma(nf / 2, kT) whatever K was."""
+    from scipy import stats
+    s = c0.copy()
+    kT = KB * s.temperature
+    o = oracle_mod.Oracle(s)
+    o.set_ensemble(1, tau_t=math.inf)
+    assert np.all(o.vr_alpha(1, 3.7, 12.0, 5, 100) == 1.0)
+    o.set_ensemble(1, tau_t=1e-9)
+    nf = 24.0
+    K = 10.0 * 0.5 * nf * kT
+    kp = o.vr_alpha(0, K, nf, 0, 20000) ** 2 * K
+    assert stats.kstest(kp, stats.gamma(0.5 * nf, scale=kT).cdf).pvalue > 1e-4
+
+
+def test_vrescale_tau_inf_is_velocity_verlet(oracle_mod, c0_relaxed):
+    """With tau_t = infinity the thermostatted integrator is plain velocity
+    Verlet whatever the Langevin friction of the system (the O step is off)."""
+    s0 = c0_relaxed.copy(); s0.gamma = 0.0
+    s1 = c0_relaxed.copy(); s1.gamma = 3.0
+    a = oracle_mod.Oracle(s0)
+    b = oracle_mod.Oracle(s1)
+    b.set_ensemble(1, tau_t=math.inf, kind_group=[0, 0, 0, 0, 1])
+    a.md_step(10)
+    b.md_step(10)
+    sa, sb = a.state(), b.state()
+    assert np.array_equal(sa["pos"], sb["pos"]) and np.array_equal(sa["vel"], sb["vel"])
+    assert sa["step"] == sb["step"] == 10
+
+
+def test_vrescale_two_groups_canonical(oracle_mod):
+    """A free gas of two kinds in two coupling groups, started one hot and
+    one cold: each group relaxes to <K> = 3/2 N kT with the canonical
+    fluctuation var K = 3/2 N (kT)^2 (a rescaling to the mean alone would
+    give none)."""
+    n = 100
+    eps = np.zeros((S.N_TYPES, S.N_TYPES))
+    ka = S.Kind("P", [4], [0.0], [], [], -1, masses=[72.0])
+    kb = S.Kind("Q", [4], [0.0], [], [], -1, masses=[36.0])
+    rng = np.random.default_rng(11)
+    pos = rng.uniform(0, 9, size=(2 * n, 3))
+    mk = [0] * n + [1] * n
+    kT = KB * 323.0
+    vel = np.concatenate([rng.standard_normal((n, 3)) * math.sqrt(4.0 * kT / 72.0),
+                          rng.standard_normal((n, 3)) * math.sqrt(0.25 * kT / 36.0)])
+    s = S.custom("gas2", [ka, kb], mk, pos, [9, 9, 9], eps, vel=vel, seed=7)
+    o = oracle_mod.Oracle(s)
+    o.set_ensemble(1, tau_t=0.1, kind_group=[0, 1])
+    o.md_step(100)
+    ks = [[], []]
+    for _ in range(400):
+        o.md_step(5)
+        v = o.state()["vel"]
+        ks[0].append(0.5 * 72.0 * (v[:n] ** 2).sum())
+        ks[1].append(0.5 * 36.0 * (v[n:] ** 2).sum())
+    for g in (0, 1):
+        k = np.asarray(ks[g])
+        assert abs(k.mean() / (1.5 * n * kT) - 1.0) < 0.05, (g, k.mean() / (1.5 * n * kT))
+        r = k.var() / (1.5 * n * kT * kT)
+        assert 0.6 < r < 1.6, (g, r)
