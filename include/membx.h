@@ -269,6 +269,22 @@ int32_t membx_set_tuning(membx_sys* sys, double skin, int32_t rebuild_interval,
 int32_t membx_autotune(membx_sys* sys, int32_t n_steps, double* skin, int32_t* rebuild_interval,
                        int32_t* lanes_per_bead, double* skin_inner, int32_t* prune_interval);
 
+/* Ensemble of the MD steps (membx_md_step and the steps of MDAS cycles).
+ * ensemble 0 (default): Langevin BAOAB with the friction of the descriptor.
+ * ensemble 1: the paper's thermostat (Methods), stochastic velocity
+ * rescaling (Bussi, Donadio, Parrinello 2007): velocity Verlet, then per
+ * coupling group the kinetic energy K takes one exact step of its stochastic
+ * dynamics with c = exp(-dt / tau_t) (tau_t > 0 in ps; infinity leaves
+ * velocity Verlet), target 3/2 N_g kT, and the group's velocities are
+ * multiplied by +-sqrt(K' / K); random numbers from Philox stream 5 with the
+ * step index as counter.  kind_group[n_kinds] (host, read during the call;
+ * null: all 0) puts each molecule kind in group 0 or 1, so a molecule's
+ * group follows exchanges of its kind.  Not fused with the force pass (three
+ * extra launches per step).  Synchronizes.  E_INVAL (ensemble, tau_t or a
+ * group out of range). */
+int32_t membx_set_ensemble(membx_sys* sys, int32_t ensemble, double tau_t,
+                           const int32_t* kind_group);
+
 /* Enable (1) or disable (0) HIP-graph replay of step sequences (default 1). */
 int32_t membx_set_graphs(membx_sys* sys, int32_t enable);
 

@@ -134,7 +134,141 @@ void launch_import(const Dev<R>& d, V4<R>* dst, const double* in, hipStream_t st
     hipLaunchKernelGGL(k_import<R>, dim3((d.N + WG - 1) / WG), dim3(WG), 0, st, d, dst, in);
 }
 
+// ------------------------------------------- stochastic velocity rescaling
+// The paper's ensemble (Methods) keeps the temperature with the velocity
+// rescaling thermostat of Bussi, Donadio and Parrinello (J. Chem. Phys. 126,
+// 014101, 2007).  After the closing half-kick of each velocity Verlet step,
+// the kinetic energy K of each coupling group (Nf = 3 x its beads) takes one
+// exact step of that method's stochastic dynamics, c = exp(-dt / tau_t),
+// Kt = Nf kT / 2:
+//   K' = c K + (1 - c) Kt (R1^2 + S) / Nf + 2 R1 sqrt(c (1 - c) K Kt / Nf),
+// R1 standard normal and S chi-squared with Nf - 1 degrees of freedom (twice a
+// Gamma((Nf - 1) / 2) variate, Marsaglia-Tsang); the group's velocities are
+// multiplied by alpha = sqrt(K' / K), with the sign of the new velocity
+// component along the old one, R1 + sqrt(c Nf K / ((1 - c) Kt)).  Random
+// words: Philox stream 5, counter = step index, block (group << 16) for R1
+// and (group << 16) + 1 + t for the t-th attempt of the gamma sampler.  Three
+// launches per step: half-kick with per-block group sums, one wave for the
+// two factors (float64 throughout), the scaling.
+
+template <typename R>
+__device__ __forceinline__ int vr_group(const Dev<R>& d, const VrBuf& vr, int i)
+{
+    return vr.kgroup[d.mol_kind[vr.bmol[d.orig[i]]]];
+}
+
+template <typename R>
+__global__ __launch_bounds__(WG) void k_kick_ke(Dev<R> d, VrBuf vr, R kick)
+{
+    const int i = blockIdx.x * WG + threadIdx.x;
+    double q[4] = { 0.0, 0.0, 0.0, 0.0 };   // K of group 0, 1; beads of group 0, 1
+    if (i < d.N) {
+        V4<R> v = d.vel[i];
+        const V4<R> f = d.frc[i];
+        v.x += kick * v.w * f.x; v.y += kick * v.w * f.y; v.z += kick * v.w * f.z;
+        d.vel[i] = v;
+        const double ek =
+            0.5 * ((double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z) / (double)v.w;
+        const bool g1 = vr_group(d, vr, i) != 0;
+        q[0] = g1 ? 0.0 : ek; q[1] = g1 ? ek : 0.0;
+        q[2] = g1 ? 0.0 : 1.0; q[3] = g1 ? 1.0 : 0.0;
+    }
+    __shared__ double sw[4][WG / 64];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        double x = q[c];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        if ((threadIdx.x & 63) == 0) sw[c][threadIdx.x >> 6] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double t = 0.0;
+        for (int w = 0; w < WG / 64; ++w) t += sw[threadIdx.x][w];
+        vr.part[4 * blockIdx.x + threadIdx.x] = t;
+    }
+}
+
+// one standard normal from two words (Box-Muller, cosine branch)
+__device__ __forceinline__ double vr_normal(uint32_t a, uint32_t b)
+{
+    const double s32 = 1.0 / 4294967296.0, tp = 6.283185307179586476925286766559;
+    return sqrt(-2.0 * log(((double)a + 1.0) * s32)) * cos(tp * ((double)b * s32));
+}
+
+// Gamma(a, 1), a >= 1 (Marsaglia and Tsang, ACM TOMS 26, 363, 2000), at most
+// 64 attempts
+__device__ double vr_gamma(uint64_t seed, int g, double a, long long ctr)
+{
+    const double dd = a - 1.0 / 3.0, cc = 1.0 / sqrt(9.0 * dd);
+    for (int t = 0; t < 64; ++t) {
+        const uint4 w = draw(seed, (uint32_t)((g << 16) + 1 + t), ctr, ST_VRESCALE);
+        const double x = vr_normal(w.x, w.y), u = u53(w.z, w.w);
+        const double y = 1.0 + cc * x;
+        if (y <= 0.0) continue;
+        const double v = y * y * y;
+        if (log(u) < 0.5 * x * x + dd - dd * v + dd * log(v)) return dd * v;
+    }
+    return dd;
+}
+
+__device__ double vr_factor(uint64_t seed, int g, double K, double nf, double kT, double c,
+                            long long ctr)
+{
+    if (!(K > 0.0) || !(nf >= 3.0)) return 1.0;
+    const double kt = 0.5 * nf * kT;
+    const uint4 w = draw(seed, (uint32_t)(g << 16), ctr, ST_VRESCALE);
+    const double r1 = vr_normal(w.x, w.y);
+    const double sch = 2.0 * vr_gamma(seed, g, 0.5 * (nf - 1.0), ctr);
+    const double kn = K + (1.0 - c) * (kt * (r1 * r1 + sch) / nf - K) +
+                      2.0 * r1 * sqrt(c * (1.0 - c) * K * kt / nf);
+    const double al = sqrt(kn / K);
+    return (r1 + sqrt(c * nf * K / ((1.0 - c) * kt)) < 0.0) ? -al : al;
+}
+
+// one wave: group sums over the blocks (fixed order), then lanes 0 and 1
+// draw the factors of groups 0 and 1
+template <typename R>
+__global__ __launch_bounds__(64) void k_vr_alpha(Dev<R> d, VrBuf vr, int nblk, long long step_off,
+                                                 double c)
+{
+    const int l = threadIdx.x;
+    double q[4] = { 0.0, 0.0, 0.0, 0.0 };
+    for (int b = l; b < nblk; b += 64)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) q[k] += vr.part[4 * b + k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        for (int o = 32; o > 0; o >>= 1) q[k] += __shfl_xor(q[k], o, 64);
+    if (l < 2) {
+        const double K = l ? q[1] : q[0], nf = 3.0 * (l ? q[3] : q[2]);
+        vr.alpha[l] = vr_factor(d.seed, l, K, nf, d.kTd, c, d.ctr[CT_STEP] + step_off);
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(WG) void k_vr_scale(Dev<R> d, VrBuf vr)
+{
+    const int i = blockIdx.x * WG + threadIdx.x;
+    if (i >= d.N) return;
+    const double a = vr.alpha[vr_group(d, vr, i)];
+    V4<R> v = d.vel[i];
+    v.x = (R)(a * (double)v.x); v.y = (R)(a * (double)v.y); v.z = (R)(a * (double)v.z);
+    d.vel[i] = v;
+}
+
+template <typename R>
+void launch_vrescale(const Dev<R>& d, const VrBuf& vr, R kick, long long step_off, double c,
+                     hipStream_t st)
+{
+    const int nb = (d.N + WG - 1) / WG;
+    hipLaunchKernelGGL(k_kick_ke<R>, dim3(nb), dim3(WG), 0, st, d, vr, kick);
+    hipLaunchKernelGGL(k_vr_alpha<R>, dim3(1), dim3(64), 0, st, d, vr, nb, step_off, c);
+    hipLaunchKernelGGL(k_vr_scale<R>, dim3(nb), dim3(WG), 0, st, d, vr);
+}
+
 #define INST(R)                                                                      \
+    template void launch_vrescale<R>(const Dev<R>&, const VrBuf&, R, long long, double, \
+                                     hipStream_t);                                   \
     template void launch_kick_drift<R>(const Dev<R>&, R, long long, int, hipStream_t); \
     template void launch_kick<R>(const Dev<R>&, R, long long, hipStream_t);                    \
     template void launch_sd_step<R>(const Dev<R>&, double, double, hipStream_t);     \

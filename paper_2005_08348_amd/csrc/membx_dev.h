@@ -17,7 +17,7 @@ constexpr int MAXBT = 8;         // bonded terms per bead
 
 // random streams (fourth Philox counter word)
 enum { ST_LANGEVIN = 0, ST_SWAP_DRAW = 1, ST_SWAP_ACCEPT = 2, ST_MDAS_SELECT = 3,
-       ST_MDAS_ACCEPT = 4 };
+       ST_MDAS_ACCEPT = 4, ST_VRESCALE = 5 };
 
 // device flags
 // FL_SKIN counts (bead, step) events beyond skin/2 since the last reset;
@@ -119,6 +119,15 @@ struct ObsBuf {
     int* n;                    // [1] selected count
     double* edge2;             // [OBS_MAXBINS + 1] squared bin edges
     unsigned long long* hist;  // [OBS_MAXBINS] pair counts
+};
+
+// Stochastic velocity rescaling with two coupling groups: the group of a
+// bead is kgroup[kind of its molecule], so it follows exchanges of kinds.
+struct VrBuf {
+    int* bmol;       // [N] molecule of each bead (bead-id order)
+    int* kgroup;     // [nk] coupling group (0/1) of each molecule kind
+    double* part;    // [4 * blocks] per block: K of group 0, 1; beads of group 0, 1
+    double* alpha;   // [2] velocity factors of the step
 };
 
 // Everything a kernel needs about one system (passed by value).

@@ -27,6 +27,8 @@ void launch_nonbonded_fused(const Dev<R>&, int, int, R, long long, V4<R>*, V4<R>
 void launch_energy_final(const double*, int, double*, hipStream_t);
 template <typename R> void launch_kick_drift(const Dev<R>&, R, long long, int, hipStream_t);
 template <typename R> void launch_kick(const Dev<R>&, R, long long, hipStream_t);
+template <typename R>
+void launch_vrescale(const Dev<R>&, const VrBuf&, R, long long, double, hipStream_t);
 template <typename R> void launch_sd_step(const Dev<R>&, double, double, hipStream_t);
 template <typename R> void launch_export(const Dev<R>&, const V4<R>*, double*, hipStream_t);
 template <typename R> void launch_import(const Dev<R>&, V4<R>*, const double*, hipStream_t);
@@ -106,6 +108,11 @@ struct Host {
     // tuning / capacities
     double skin, skin_max;
     int R, lpb, Kcap, Gcap, T_cap, P_cap;
+    // ensemble: 0 Langevin BAOAB; 1 velocity Verlet + stochastic velocity
+    // rescaling with coupling time tau_t and the group of each kind
+    int ensemble = 0;
+    double tau_t = 0.0;
+    std::vector<int> kgroup, bmol;      // [nk], [N] molecule of each bead
     double skin_in;   // inner-list buffer delta (nm)
     int prune;        // force passes per inner-list prune; 0: no inner list
     int nc[3], ncell, ne[3], next;   // cell grid at the current skin
@@ -200,6 +207,10 @@ Status check_desc(const membx_desc* d, Host& h)
     }
     if (n >= (1LL << 27)) return { MEMBX_E_INVAL, "too many beads" };
     h.N = (int)n;
+    h.bmol.resize(h.N);
+    for (int m = 0; m < h.nm; ++m)
+        for (int b = 0; b < h.kn[h.mol_kind0[m]]; ++b) h.bmol[h.mol_first[m] + b] = m;
+    h.kgroup.assign(h.nk, 0);
     h.eps.assign(d->lj_epsilon, d->lj_epsilon + h.nt * h.nt);
     h.sig.assign(d->lj_sigma, d->lj_sigma + h.nt * h.nt);
     for (int a = 0; a < 3; ++a) h.box[a] = d->box[a];
@@ -412,6 +423,7 @@ struct membx_sys {
     double *p_nb = nullptr, *p_bd = nullptr, *p_ke = nullptr;
     double* xbuf = nullptr;  // [3N] export / import buffer
     ObsBuf obs{};            // mixing observable
+    VrBuf vr{};              // velocity rescaling thermostat
     int* ibuf = nullptr;     // [N]
     bool graphs = true;
     bool fuse = true;        // force kernel integrates the next step (plain MD)
@@ -456,6 +468,16 @@ static void set_list_band(Dev<R>& d, const Host& h)
     const double rin = h.rc + h.skin_in;
     d.rin2 = h.prune ? (R)(rin * rin) : (R)0;
     d.in_half2 = (R)(0.25 * h.skin_in * h.skin_in);
+}
+
+// O part of BAOAB: v <- c1 v + c2 sqrt(kT/m) xi; off (c1 = 1, c2 = 0) under
+// the velocity rescaling thermostat, which leaves velocity Verlet
+template <typename R>
+static void set_friction(Dev<R>& d, const Host& h)
+{
+    const double c1 = h.ensemble == 1 ? 1.0 : std::exp(-h.gamma * h.dt);
+    d.c1 = (R)c1;
+    d.c2 = (R)(h.ensemble == 1 ? 0.0 : std::sqrt(1.0 - c1 * c1));
 }
 
 template <typename R>
@@ -524,6 +546,10 @@ static size_t layout(membx_sys* s, Dev<R>& d, Mv& m, char* base)
     s->obs.edge2 = a.take<double>(OBS_MAXBINS + 1);
     s->obs.hist = a.take<unsigned long long>(OBS_MAXBINS);
     s->ibuf = a.take<int>(N);
+    s->vr.bmol = a.take<int>(N);
+    s->vr.kgroup = a.take<int>(h.nk);
+    s->vr.part = a.take<double>(4 * (size_t)s->ke_blocks);
+    s->vr.alpha = a.take<double>(2);
     // moves
     int MC = 2 * h.maxch, T = std::max(h.T_cap, h.P_cap);
     m.n_sw = (int)h.sw_list.size();
@@ -591,8 +617,7 @@ static size_t layout(membx_sys* s, Dev<R>& d, Mv& m, char* base)
     set_list_band(d, h);
     d.skin_half2 = (R)(0.25 * h.skin * h.skin);
     d.dt = (R)h.dt; d.half_dt = (R)(0.5 * h.dt);
-    double c1 = std::exp(-h.gamma * h.dt);
-    d.c1 = (R)c1; d.c2 = (R)std::sqrt(1.0 - c1 * c1);
+    set_friction(d, h);
     d.kT = (R)(KB * h.T); d.kTd = KB * h.T;
     d.seed = h.seed;
     return a.off + 256;
@@ -673,11 +698,16 @@ static void steps_seq(membx_sys* s, long long n, const Alch* alch, bool launch =
     Dev<R>& d = dev<R>(s);
     const R h = (R)(0.5 * s->h.dt), full = (R)s->h.dt;
     const bool inner = s->h.prune > 1 && s->h.lpb >= 2;
+    // velocity rescaling: every step closes with its own half-kick and the
+    // thermostat, so neither kicks nor the next step's update are fused
+    const bool vr = s->h.ensemble == 1;
+    const double vr_c = vr ? std::exp(-s->h.dt / s->h.tau_t) : 1.0;
     if (alch) s->sp = -1;   // MDAS segments walk the Verlet list; no inner bookkeeping
     bool moved = false;   // the previous force pass already moved the beads
     for (long long k = 0; k < n; ++k) {
         if (!moved && launch)
-            launch_kick_drift<R>(d, k == 0 ? h : full, k, (inner && s->sp >= 0) ? 1 : 0, s->st);
+            launch_kick_drift<R>(d, (k == 0 || vr) ? h : full, k, (inner && s->sp >= 0) ? 1 : 0,
+                                 s->st);
         moved = false;
         bool rebuilt = false;
         if (++s->since >= s->h.R) {
@@ -685,7 +715,7 @@ static void steps_seq(membx_sys* s, long long n, const Alch* alch, bool launch =
             else { s->since = 0; s->n_rebuilds++; s->sp = -1; }
             rebuilt = true;
         }
-        if (!alch && s->fuse && !s->timing && k + 1 < n) {
+        if (!alch && !vr && s->fuse && !s->timing && k + 1 < n) {
             // forces of step k and B-A-O-A of step k + 1 in one pass, on the
             // inner list between prunes
             int list = 0;
@@ -701,11 +731,15 @@ static void steps_seq(membx_sys* s, long long n, const Alch* alch, bool launch =
             if (launch) {
                 forces<R>(s, rebuilt);
                 if (alch) alch_terms<R>(s, rebuilt, alch->lam);
+                if (vr) launch_vrescale<R>(d, s->vr, h, k, vr_c, s->st);
             }
             if (s->sp >= 0) s->sp++;
         }
     }
-    if (launch) launch_kick<R>(d, h, n, s->st);
+    if (launch) {
+        if (vr) launch_add_ctr(d.ctr, CT_STEP, n, s->st);
+        else launch_kick<R>(d, h, n, s->st);
+    }
 }
 
 template <typename R>
@@ -942,6 +976,8 @@ static int32_t upload(membx_sys* s, const membx_desc* desc)
     UP(d.exmask, exm);
     UP(d.mol_first, h.mol_first);
     UP(d.mol_kind, h.mol_kind0);
+    UP(s->vr.bmol, h.bmol);
+    UP(s->vr.kgroup, h.kgroup);
     UP(d.bmols, h.bmols);
     UP(d.kn, h.kn);
     UP(d.kbead_off, h.kbead_off);
@@ -1624,6 +1660,39 @@ int32_t membx_set_tuning(membx_sys* s, double skin, int32_t rebuild_interval,
     s->h.skin_in = prune ? skin_inner : 0.0;
     int32_t rc = begin(s);
     if (!rc) rc = DISPATCH(s, retune_impl, s);
+    if (!rc) rc = end(s);
+    return rc;
+}
+
+template <typename R>
+static int32_t ensemble_impl(membx_sys* s)
+{
+    set_friction(dev<R>(s), s->h);
+    HCK(hipMemcpyAsync(s->vr.kgroup, s->h.kgroup.data(), sizeof(int) * s->h.nk,
+                       hipMemcpyHostToDevice, s->st));
+    HCK(hipStreamSynchronize(s->st));   // the host vector may change on the next call
+    for (auto& kv : s->gcache) (void)hipGraphExecDestroy(kv.second);
+    s->gcache.clear();
+    return MEMBX_OK;
+}
+
+int32_t membx_set_ensemble(membx_sys* s, int32_t ensemble, double tau_t, const int32_t* kind_group)
+{
+    if (!s) return MEMBX_E_INVAL;
+    if (ensemble != 0 && ensemble != 1) return fail(s, MEMBX_E_INVAL, "ensemble must be 0 or 1");
+    if (ensemble == 1 && !(tau_t > 0.0)) return fail(s, MEMBX_E_INVAL, "tau_t must be > 0");
+    std::vector<int> kg(s->h.nk, 0);
+    if (kind_group)
+        for (int k = 0; k < s->h.nk; ++k) {
+            if (kind_group[k] != 0 && kind_group[k] != 1)
+                return fail(s, MEMBX_E_INVAL, "coupling groups must be 0 or 1");
+            kg[k] = kind_group[k];
+        }
+    s->h.ensemble = ensemble;
+    s->h.tau_t = ensemble == 1 ? tau_t : 0.0;
+    s->h.kgroup = kg;
+    int32_t rc = begin(s);
+    if (!rc) rc = DISPATCH(s, ensemble_impl, s);
     if (!rc) rc = end(s);
     return rc;
 }

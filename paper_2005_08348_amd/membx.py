@@ -121,6 +121,7 @@ def lib():
             "membx_autotune": ([vp, i32, C.POINTER(dp), C.POINTER(i32), C.POINTER(i32),
                                 C.POINTER(dp), C.POINTER(i32)], i32),
             "membx_set_graphs": ([vp, i32], i32),
+            "membx_set_ensemble": ([vp, i32, dp, vp], i32),
             "membx_kernel_timing": ([vp, i32], i32),
             "membx_kernel_time": ([vp, C.POINTER(i64), C.POINTER(dp)], i32),
             "membx_kernel_bench": ([vp, i32, C.POINTER(dp)], i32),
@@ -364,6 +365,19 @@ class System:
         return lib().membx_status(self.h)
 
     # --------------------------------------------------------------- tuning
+    def set_ensemble(self, ensemble, tau_t=1.0, kind_group=None):
+        """0: Langevin BAOAB; 1: velocity Verlet + stochastic velocity
+        rescaling with coupling time tau_t (ps) of the groups kind_group[n_kinds]
+        (0/1; None: one group)"""
+        kg = None
+        if kind_group is not None:
+            kg = np.ascontiguousarray(kind_group, dtype=np.int32)
+            if kg.shape != (len(self.system.kinds),):
+                raise ValueError("kind_group needs one entry per molecule kind")
+        _check(lib().membx_set_ensemble(self.h, int(ensemble), float(tau_t),
+                                        None if kg is None else kg.ctypes.data_as(C.c_void_p)),
+               self.h)
+
     def set_tuning(self, skin, rebuild_interval, lanes_per_bead, skin_inner=0.0, prune_interval=0):
         _check(lib().membx_set_tuning(self.h, float(skin), int(rebuild_interval),
                                       int(lanes_per_bead), float(skin_inner), int(prune_interval)),

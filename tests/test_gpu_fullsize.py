@@ -161,3 +161,27 @@ def test_forces_c1_inner_list_mixed(oracle_mod, c1):
     _check_sampled_forces(o, g, c1.n_beads, "mixed", 3000, 17)
     assert g.energies()["n_skin_violations"] == 0
     g.close()
+
+
+def test_mdas_cycle_c1_mixed(oracle_mod, c1):
+    """One MDAS cycle at the benchmark size (95,876 beads): 4 pairs, K = 10
+    increments of M = 1 step, mixed precision: identical pairs and decision,
+    work within the mixed tolerance, trajectories together."""
+    m = _membx()
+    g = m.System(c1, precision="mixed", **BENCH_TUNING)
+    g.minimize(50)
+    st = g.state()
+    o = oracle_mod.Oracle(c1)
+    o.set_state(pos=st["pos"], vel=st["vel"], mol_kind=st["mol_kind"])
+    rg = g.mdas_cycle(4, 10, 1)
+    ro = o.mdas_cycle(4, 10, 1)
+    assert np.array_equal(rg["pairs"], ro["pairs"])
+    print("C1 MDAS work gpu %.6f oracle %.6f" % (rg["work"], ro["work"]))
+    assert abs(rg["work"] - ro["work"]) < 2e-2
+    assert rg["accept"] == ro["accept"]
+    sg, so = g.state(), o.state()
+    assert np.array_equal(sg["mol_kind"], so["mol_kind"])
+    d = sg["pos"] - so["pos"]
+    d -= c1.box * np.rint(d / c1.box)
+    assert np.abs(d).max() < 1e-3
+    g.close()

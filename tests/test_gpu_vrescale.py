@@ -1,0 +1,139 @@
+"""Stochastic velocity rescaling (the paper's thermostat, Methods) on the GPU
+against the float64 oracle: same Philox draws, same velocity Verlet steps,
+same group sums.
+
+Tolerances: float64 positions 1e-7 nm and velocities 1e-6 nm/ps after 20
+steps (the group kinetic energies are summed in a different order, so the
+factors differ in the last bits); mixed positions 1e-4 nm after 10 steps.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2005_08348_amd import systems as S
+
+pytestmark = pytest.mark.gpu
+
+GROUPS = [0, 0, 0, 0, 1]     # lipids A, B, C, D in group 0, water in group 1
+
+
+def _membx():
+    from paper_2005_08348_amd import membx
+    return membx
+
+
+@pytest.fixture(scope="module")
+def c0_relaxed(oracle_mod):
+    c0 = S.make("c0")
+    o = oracle_mod.Oracle(c0)
+    o.minimize(60)
+    s = c0.copy()
+    s.pos = o.state()["pos"].astype(np.float32).astype(np.float64) % s.box
+    s.pos = np.where(s.pos >= s.box, 0.0, s.pos)
+    return s
+
+
+def _pos_err(a, b, box):
+    d = a - b
+    d -= box * np.rint(d / box)
+    return np.abs(d).max()
+
+
+@pytest.mark.parametrize("tau", [0.1, 1e-3, math.inf])
+def test_vrescale_fp64_c0(oracle_mod, c0_relaxed, tau):
+    m = _membx()
+    g = m.System(c0_relaxed, precision="fp64", rebuild_interval=5)
+    o = oracle_mod.Oracle(c0_relaxed)
+    g.set_ensemble(1, tau_t=tau, kind_group=GROUPS)
+    o.set_ensemble(1, tau_t=tau, kind_group=GROUPS)
+    for _ in range(4):           # the same captured graph replayed
+        g.md_step(5)
+    o.md_step(20)
+    sg, so = g.state(), o.state()
+    print("tau %g: pos err %.2e vel err %.2e" % (tau, _pos_err(sg["pos"], so["pos"], c0_relaxed.box),
+                                                 np.abs(sg["vel"] - so["vel"]).max()))
+    assert sg["step"] == so["step"] == 20
+    assert _pos_err(sg["pos"], so["pos"], c0_relaxed.box) < 1e-7
+    assert np.abs(sg["vel"] - so["vel"]).max() < 1e-6
+    e, eo = g.energies(), o.energy_forces()
+    assert abs(e["kinetic"] - eo["kinetic"]) < 1e-9 * abs(eo["kinetic"])
+    g.close()
+
+
+def test_vrescale_mixed_c0(oracle_mod, c0_relaxed):
+    m = _membx()
+    g = m.System(c0_relaxed, precision="mixed", rebuild_interval=5)
+    o = oracle_mod.Oracle(c0_relaxed)
+    g.set_ensemble(1, tau_t=0.1, kind_group=GROUPS)
+    o.set_ensemble(1, tau_t=0.1, kind_group=GROUPS)
+    g.md_step(10)
+    o.md_step(10)
+    assert _pos_err(g.state()["pos"], o.state()["pos"], c0_relaxed.box) < 1e-4
+    g.close()
+
+
+def test_vrescale_back_to_langevin(oracle_mod, c0_relaxed):
+    """Switching the ensemble on and off again: 5 thermostatted steps, then 5
+    Langevin steps (fused path), as in the oracle."""
+    m = _membx()
+    g = m.System(c0_relaxed, precision="fp64", rebuild_interval=5)
+    o = oracle_mod.Oracle(c0_relaxed)
+    for obj in (g, o):
+        obj.set_ensemble(1, tau_t=0.2)
+        obj.md_step(5)
+        obj.set_ensemble(0)
+        obj.md_step(5)
+    assert _pos_err(g.state()["pos"], o.state()["pos"], c0_relaxed.box) < 1e-7
+    g.close()
+
+
+def test_vrescale_mdas_cycle(oracle_mod, c0_relaxed):
+    """MDAS segments integrate in the selected ensemble on both sides."""
+    m = _membx()
+    g = m.System(c0_relaxed, precision="fp64", rebuild_interval=4)
+    o = oracle_mod.Oracle(c0_relaxed)
+    g.set_ensemble(1, tau_t=0.1, kind_group=GROUPS)
+    o.set_ensemble(1, tau_t=0.1, kind_group=GROUPS)
+    rg = g.mdas_cycle(2, 5, 2)
+    ro = o.mdas_cycle(2, 5, 2)
+    assert np.array_equal(rg["pairs"], ro["pairs"])
+    assert abs(rg["work"] - ro["work"]) < 1e-6
+    assert rg["accept"] == ro["accept"]
+    assert _pos_err(g.state()["pos"], o.state()["pos"], c0_relaxed.box) < 1e-7
+    g.close()
+
+
+def test_vrescale_c1_fp64(oracle_mod):
+    """The 95,876-bead bilayer, relaxed as the other full-size trajectory
+    tests do: 4 thermostatted float64 steps follow the oracle."""
+    m = _membx()
+    s = S.make("c1")
+    g = m.System(s, precision="fp64", skin=0.4, rebuild_interval=7, lanes_per_bead=4)
+    g.minimize(50)
+    st = g.state()
+    o = oracle_mod.Oracle(s)
+    o.set_state(pos=st["pos"], vel=st["vel"], mol_kind=st["mol_kind"])
+    g.set_ensemble(1, tau_t=0.1, kind_group=GROUPS)
+    o.set_ensemble(1, tau_t=0.1, kind_group=GROUPS)
+    g.md_step(4)
+    o.md_step(4)
+    sg, so = g.state(), o.state()
+    assert _pos_err(sg["pos"], so["pos"], s.box) < 1e-7
+    assert np.abs(sg["vel"] - so["vel"]).max() < 1e-6
+    g.close()
+
+
+def test_vrescale_refused_arguments(c0_relaxed):
+    m = _membx()
+    g = m.System(c0_relaxed, precision="mixed")
+    for bad in [dict(ensemble=2), dict(ensemble=1, tau_t=0.0), dict(ensemble=1, tau_t=math.nan),
+                dict(ensemble=1, tau_t=-1.0), dict(ensemble=1, kind_group=[0, 0, 2, 0, 1])]:
+        with pytest.raises(m.MembxError):
+            g.set_ensemble(**bad)
+    with pytest.raises(ValueError):
+        g.set_ensemble(1, kind_group=[0, 1])
+    # a refused call leaves the system as it was: Langevin steps still run
+    g.md_step(5)
+    assert np.isfinite(g.state()["pos"]).all()
+    g.close()
