@@ -297,6 +297,24 @@ def main():
                           "accepted_last_batch": int(r["n_accepted"]),
                           "batch_plus_2_steps_ms": 1e3 * tsw / nb,
                           "trials_per_s": nb * len(r["du"]) / tsw}
+        # ---- the paper's thermostat: velocity rescaling, tau_t 1 ps,
+        # membrane and solvent in two coupling groups (not fused with the
+        # force pass: three more launches per step)
+        log("[bench] velocity-rescaling leg")
+        groups = [1 if k.name == "W" else 0 for k in c1.kinds]
+        t_lang = 2.0 * gm.energies(check=False)["kinetic"] / (3 * c1.n_beads * S.KB)
+        gm.set_ensemble(1, tau_t=1.0, kind_group=groups)
+        gm.md_step(20)
+        kvr = max(100, K // 4)
+        tvr = timed(lambda: gm.md_step(kvr), sync)
+        evr = gm.energies(check=False)
+        result["vrescale"] = {"md_steps_per_s": kvr / tvr, "tau_t_ps": 1.0,
+                              "groups": "membrane, solvent",
+                              "temperature_K": 2.0 * evr["kinetic"] / (3 * c1.n_beads * S.KB),
+                              "temperature_K_langevin_before": t_lang,
+                              "skin_violations": evr["n_skin_violations"],
+                              "vs_langevin": (kvr / tvr) / steps_s}
+        gm.set_ensemble(0)
         gm.close(); del gm
         torch.cuda.empty_cache()
         # ---- MDAS on the 1.14M-bead bilayer

@@ -13,12 +13,15 @@ the GPU pair histogram (``System.pair_histogram``), normalised by the ideal
 two-dimensional expectation of each leaflet.
 
     python -m paper_2005_08348_amd.mixing [--fe 200000] [--every 4000]
+                                          [--thermostat vrescale]
 
 runs MD, MC-MD and MDAS from the same far-from-mixed start (the ``mix``
 bilayer: 400 lipids in stripes) and prints one JSON line with the traces,
 the fits and the speed-ups.  Force evaluations are counted as the paper
 does: one per MD step, per exchange trial and per MDAS step (a frozen MDAS
-cycle, M = 0, counts one).
+cycle, M = 0, counts one).  With ``--thermostat vrescale`` every sampler
+integrates with the paper's thermostat (velocity rescaling, tau_t = 1 ps,
+membrane and solvent coupled separately) instead of Langevin dynamics.
 """
 from __future__ import annotations
 
@@ -108,12 +111,15 @@ def _trace_point(g, sysm, kind, leaflet, n_bins, bin_width):
 
 
 def run(method, sysm, fe_total, every, kind=S.KIND_D, n_bins=N_BINS, bin_width=BIN,
-        mc_trials=8, mc_steps=2, mdas_pairs=1, mdas_k=50, mdas_m=1, mdas_md=50, precision="mixed"):
+        mc_trials=8, mc_steps=2, mdas_pairs=1, mdas_k=50, mdas_m=1, mdas_md=50, precision="mixed",
+        thermostat="langevin"):
     """One sampler from the start structure: (force evaluations, max[g]) pairs
     every `every` force evaluations, plus acceptance counts and works."""
     from . import membx as M
     leaflet = sysm.meta["leaflet"]
     g = M.System(sysm, precision=precision)
+    if thermostat == "vrescale":
+        g.set_ensemble(1, tau_t=1.0, kind_group=[1 if k.name == "W" else 0 for k in sysm.kinds])
     g.minimize(100)
     g.md_step(200)                       # thermalise (not counted)
     fe, trace, works, acc, tried = 0, [], [], 0, 0
@@ -153,6 +159,7 @@ def main(argv=None):
     ap.add_argument("--fe", type=int, default=200000, help="force evaluations per sampler")
     ap.add_argument("--every", type=int, default=4000, help="force evaluations between g(r) samples")
     ap.add_argument("--seed", type=int, default=None)
+    ap.add_argument("--thermostat", choices=["langevin", "vrescale"], default="langevin")
     args = ap.parse_args(argv)
     sysm = S.make("mix", seed=args.seed)
     kT = S.KB * sysm.temperature
@@ -161,15 +168,17 @@ def main(argv=None):
                          f"bins {BIN} nm",
            "samplers": "MD; MC-MD: 8 exchange trials per batch + 2 MD steps; MDAS: 1 pair, "
                        "K = 50, M = 1, after 50 MD steps",
-           "fe_counting": "1 per MD step, per exchange trial and per MDAS step", "runs": {}}
+           "fe_counting": "1 per MD step, per exchange trial and per MDAS step",
+           "thermostat": args.thermostat, "runs": {}}
     # the level of a uniformly mixed membrane: the same lipids randomly mixed
     mixed = S.make("mix", seed=args.seed, demix=False)
-    ref = run("md", mixed, max(args.fe // 10, 4 * args.every), args.every)
+    ref = run("md", mixed, max(args.fe // 10, 4 * args.every), args.every,
+              thermostat=args.thermostat)
     y_mixed = float(np.mean([p[1] for p in ref["trace"]]))
     out["mixed_level"] = y_mixed
     for method in ("md", "mcmd", "mdas"):
         print(f"[mixing] {method}", file=sys.stderr, flush=True)
-        r = run(method, sysm, args.fe, args.every)
+        r = run(method, sysm, args.fe, args.every, thermostat=args.thermostat)
         x = np.array([p[0] for p in r["trace"]], dtype=np.float64)
         y = np.array([p[1] for p in r["trace"]], dtype=np.float64)
         fit = fit_exponential(x, y)
