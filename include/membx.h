@@ -171,7 +171,9 @@ int32_t membx_sys_destroy(membx_sys* sys);
  * (v += dt/2 F/m; x += dt/2 v; v = c1 v + c2 sqrt(kT/m) xi; x += dt/2 v;
  * F = F(x); v += dt/2 F/m, with c1 = exp(-gamma dt), c2 = sqrt(1 - c1^2)),
  * one force evaluation per step.  xi are Box-Muller normals from Philox
- * stream 0 (counter = bead id, step).  Asynchronous. */
+ * stream 0 (counter = bead id, step).  Under membx_set_ensemble(.., 1, ..)
+ * the steps are velocity Verlet with stochastic velocity rescaling instead.
+ * Asynchronous. */
 int32_t membx_md_step(membx_sys* sys, int64_t n_steps);
 
 /* One batch of MC-MD exchange trials (paper, Theory, Eq. 1).  Candidates are
