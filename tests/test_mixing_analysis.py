@@ -75,3 +75,36 @@ def test_fe_to_half():
     # half-way level 1.7; running means of 3: 2.067, 1.9, 1.7 -> ends at sample 4
     assert mixing.fe_to_half(x, y, 1.2) == 4000.0
     assert mixing.fe_to_half(x, np.full(10, 2.2), 1.2) is None
+
+
+def test_summary_over_repeats():
+    """Halfway medians, ranges and speed-up statistics over repeats, with a
+    run that never reaches halfway left out of the statistics."""
+    from paper_2005_08348_amd import mixing as X
+
+    def rep(md_h, mc_h, da_h, y0=2.0):
+        runs = {"md": {"fe_to_half": md_h, "accepted": 0, "tried": 0, "max_g": [y0, 1.5]},
+                "mcmd": {"fe_to_half": mc_h, "accepted": 1, "tried": 100,
+                         "speedup_half": (md_h / mc_h) if (md_h and mc_h) else None},
+                "mdas": {"fe_to_half": da_h, "accepted": 3, "tried": 100,
+                         "speedup_half": (md_h / da_h) if (md_h and da_h) else None}}
+        return {"runs": runs, "mixed_level": 1.3}
+    reps = [rep(100000.0, 2000.0, 10000.0), rep(120000.0, 3000.0, 20000.0), rep(None, 1000.0, 5000.0),
+            rep(1000.0, 1000.0, 1000.0, y0=1.4)]   # start within MIN_GAP of the mixed level
+    s = X.summarize(reps)
+    assert s["repeats"] == 4 and s["without_signal"] == 1
+    assert s["md"]["fe_to_half_median"] == 110000.0 and s["md"]["reached_half"] == "2/3"
+    assert s["mcmd"]["fe_to_half_range"] == [1000.0, 3000.0]
+    assert s["mcmd"]["speedup_half_n"] == 2
+    assert abs(s["mcmd"]["speedup_half_mean"] - 45.0) < 1e-12
+    assert abs(s["mcmd"]["speedup_half_sd"] - np.std([50.0, 40.0], ddof=1)) < 1e-12
+    assert abs(s["mdas"]["speedup_half_mean"] - 8.0) < 1e-12
+    assert abs(s["mdas"]["acceptance"] - 0.03) < 1e-12
+
+
+def test_halfway_needs_a_gap():
+    from paper_2005_08348_amd import mixing as X
+    x = np.arange(10) * 100.0
+    y = np.array([2.0, 1.9, 1.6, 1.5, 1.5, 1.4, 1.4, 1.4, 1.4, 1.4])
+    assert X.fe_to_half(x, y, 1.3) == 400.0   # mean of samples 2..4 is the first <= 1.65
+    assert X.fe_to_half(x, y, 1.9, min_gap=0.2) is None
