@@ -69,6 +69,10 @@ typedef struct {
     int ensemble;
     double tau_t;
     int kgroup[64];          /* coupling group of each kind */
+    /* exchange regions (leaflets): 0 partners anywhere, 1 within the
+     * region of X, 2 in the other region */
+    int xmode;
+    int* region;             /* [nm] 0 or 1 */
 } osys;
 
 /* ------------------------------------------------------------ Philox4x32-10 */
@@ -203,6 +207,7 @@ osys* o_create(int nk, const int* kn, const int* ktype, const double* kq,
     }
     s->nm = nm;
     s->mkind = (int*)xcalloc(nm, sizeof(int));
+    s->region = (int*)xcalloc(nm, sizeof(int));
     s->mfirst = (int*)xcalloc(nm, sizeof(int));
     s->mk_tmp = (int*)xcalloc(nm, sizeof(int));
     int n = 0;
@@ -255,7 +260,7 @@ void o_destroy(osys* s)
     void* p[] = { s->kn, s->koff, s->ktype, s->kfam, s->kq, s->km, s->knb, s->kboff,
                   s->bi, s->bj, s->bb0, s->bk, s->kna, s->kaoff, s->ai, s->aj, s->ak,
                   s->acos0, s->akk, s->mkind, s->mfirst, s->bmol, s->bloc, s->nexcl,
-                  s->excl, s->c6, s->c12, s->x, s->v, s->f, s->mk_tmp, s->f_tmp };
+                  s->excl, s->c6, s->c12, s->x, s->v, s->f, s->mk_tmp, s->f_tmp, s->region };
     for (size_t i = 0; i < sizeof(p) / sizeof(p[0]); ++i) free(p[i]);
     free(s);
 }
@@ -735,6 +740,12 @@ void o_set_ensemble(osys* s, int ensemble, double tau_t, const int* kind_group)
     for (int k = 0; k < s->nk && k < 64; ++k) s->kgroup[k] = kind_group ? (kind_group[k] != 0) : 0;
 }
 
+void o_set_exchange_regions(osys* s, int mode, const int* region)
+{
+    s->xmode = mode;
+    for (int m = 0; m < s->nm; ++m) s->region[m] = region ? (region[m] != 0) : 0;
+}
+
 /* the statistics pins use these directly: n draws at counters ctr0 .. ctr0 + n - 1 */
 void o_gamma_mt(osys* s, int g, double a, int64_t ctr0, int n, double* out)
 {
@@ -792,10 +803,27 @@ static int changed_locals(const osys* s, int ka, int kb, int* loc)
     return n;
 }
 
+/* May molecule m partner X (kind kx, family fam) under the exchange mode?
+ * Mode 0: any molecule of the family of another kind.  Mode 1: the same,
+ * within X's region (leaflet): leaflet compositions never change.  Mode 2
+ * (the interleaflet move the paper proposes in its Discussion): any
+ * molecule of the family in the other region, whatever its kind.  Partner
+ * sets of modes 0 and 1 depend on the kinds, but the swap leaves the counts
+ * they are drawn from unchanged; the mode-2 set does not depend on the
+ * kinds at all, and a partner of X's own kind is a trial that changes
+ * nothing.  Either way the chance to propose a pair equals that of the
+ * reverse proposal, so the Metropolis test of Eq. 1 needs no correction. */
+static int may_partner(const osys* s, int m, int x, int kx, int fam)
+{
+    if (s->kfam[s->mkind[m]] != fam) return 0;
+    if (s->xmode == 2) return s->region[m] != s->region[x];
+    if (s->mkind[m] == kx) return 0;
+    return s->xmode == 1 ? s->region[m] == s->region[x] : 1;
+}
+
 /* Draw one candidate pair (X, Y) from Philox words w: X uniform over the
- * molecules of any swap family, Y uniform (ascending molecule id) over the
- * molecules of X's family whose kind differs from X's.  Returns 0 if X has
- * no partner. */
+ * molecules of any swap family, Y uniform (ascending molecule id) over X's
+ * partners (may_partner).  Returns 0 if X has none. */
 static int draw_pair(const osys* s, const uint32_t w[4], int* X, int* Y)
 {
     int nsw = 0;
@@ -808,13 +836,13 @@ static int draw_pair(const osys* s, const uint32_t w[4], int* X, int* Y)
     int fam = s->kfam[s->mkind[x]], kx = s->mkind[x];
     int nother = 0;
     for (int m = 0; m < s->nm; ++m)
-        if (s->kfam[s->mkind[m]] == fam && s->mkind[m] != kx) nother++;
+        if (may_partner(s, m, x, kx, fam)) nother++;
     if (nother == 0) return 0;
     uint32_t iy = pick(w[1], (uint32_t)nother);
     int y = -1;
     c = 0;
     for (int m = 0; m < s->nm; ++m)
-        if (s->kfam[s->mkind[m]] == fam && s->mkind[m] != kx) {
+        if (may_partner(s, m, x, kx, fam)) {
             if ((uint32_t)c == iy) { y = m; break; }
             c++;
         }

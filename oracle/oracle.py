@@ -85,6 +85,7 @@ def lib():
         L.o_pair_histogram.argtypes = [C.c_void_p, C.c_int, C.c_int, _i32p, C.c_int, C.c_double,
                                        _i64p]
         L.o_set_ensemble.argtypes = [C.c_void_p, C.c_int, C.c_double, _i32p]
+        L.o_set_exchange_regions.argtypes = [C.c_void_p, C.c_int, _i32p]
         L.o_gamma_mt.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_int64, C.c_int, _f64p]
         L.o_vr_alpha.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_int64, C.c_int,
                                  _f64p]
@@ -235,6 +236,14 @@ class Oracle:
         if len(kg) != nk:
             raise ValueError("kind_group needs one entry per molecule kind")
         lib().o_set_ensemble(self.h, int(ensemble), float(tau_t), kg)
+
+    def set_exchange_regions(self, mode, region=None):
+        """exchange partners: 0 anywhere in the family, 1 within the region
+        (leaflet) of X, 2 in the other region; region[n_mols] 0/1"""
+        rg = np.zeros(self.nm, dtype=np.int32) if region is None else _i32(region)
+        if len(rg) != self.nm:
+            raise ValueError("region needs one entry per molecule")
+        lib().o_set_exchange_regions(self.h, int(mode), rg)
 
     def gamma_mt(self, group, a, ctr0, n):
         """the thermostat's Gamma(a, 1) draws at step counters ctr0 .. ctr0 + n - 1"""

@@ -371,6 +371,24 @@ def custom(name, kinds, mol_kind, pos, box, eps, vel=None, seed=1, **kw):
     return s
 
 
+def twin_exchange_toy(m_per_region=8, n_q=8, seed=7):
+    """2 m_per_region one-bead molecules of two kinds P and Q with identical
+    parameters in one swap family, without interactions, split into two
+    regions (meta["leaflet"]: the first m_per_region molecules 0, the rest
+    1), all n_q molecules of kind Q in region 0 first.  Every exchange then
+    has dU = 0, so the kinds perform the proposal chain alone."""
+    kp = Kind("P", [TYPE_N], [0.0], [], [], 0)
+    kq = Kind("Q", [TYPE_N], [0.0], [], [], 0)
+    n = 2 * m_per_region
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0.0, 6.0, size=(n, 3))
+    mk = np.zeros(n, dtype=np.int32)
+    mk[:n_q] = 1
+    s = custom("twin", [kp, kq], mk, pos, [6.0, 6.0, 6.0], np.zeros((N_TYPES, N_TYPES)), seed=seed)
+    s.meta["leaflet"] = np.repeat(np.array([0, 1], dtype=np.int32), m_per_region)
+    return s
+
+
 def two_lipid_toy(r, type_a=TYPE_C, type_b=TYPE_U, eps=None, box=6.0):
     """Two 2-bead molecules [h, s] of kinds X (s of type a) and Y (s of type b)
     in one swap family, plus a fixed bead E at distance r from X.s.  Y sits

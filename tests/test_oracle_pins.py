@@ -588,3 +588,48 @@ def test_vrescale_two_groups_canonical(oracle_mod):
         assert abs(k.mean() / (1.5 * n * kT) - 1.0) < 0.05, (g, k.mean() / (1.5 * n * kT))
         r = k.var() / (1.5 * n * kT * kT)
         assert 0.6 < r < 1.6, (g, r)
+
+
+# ------------------------------------------------- exchange regions (leaflets)
+def _hypergeom_moments(m, t):
+    """number of the t Q molecules found in one region of m out of 2m places,
+    all arrangements equally likely"""
+    p = t / (2.0 * m)
+    return m * p, m * p * (1 - p) * (2 * m - t) / (2 * m - 1)
+
+
+def _region_chain(oracle_mod, mode, n_batches, m=8, t=8):
+    s = S.twin_exchange_toy(m, t)
+    o = oracle_mod.Oracle(s)
+    o.set_exchange_regions(mode, s.meta["leaflet"])
+    lf = s.meta["leaflet"]
+    ns, pairs = [], []
+    for _ in range(n_batches):
+        r = o.swap_batch(1)
+        pairs += list(zip(r["X"], r["Y"]))
+        mk = o.state()["mol_kind"]
+        ns.append(int(np.count_nonzero((mk == 1) & (lf == 0))))
+    return np.asarray(ns), pairs, lf
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_exchange_chain_samples_uniform_arrangements(oracle_mod, mode):
+    """Kinds with identical parameters (dU = 0, every trial accepted): the
+    number of Q molecules in region 0 must follow the hypergeometric law of
+    uniformly random arrangements, whatever partner rule the proposal uses,
+    if the proposal is symmetric.  (Drawing the interleaflet partner among
+    molecules of the other kind only would give the binomial law, twice the
+    variance.)"""
+    ns, pairs, lf = _region_chain(oracle_mod, mode, 20000)
+    mean, var = _hypergeom_moments(8, 8)
+    x = ns[1000:]
+    assert abs(x.mean() - mean) < 0.15, x.mean()
+    assert abs(x.var() / var - 1.0) < 0.12, (x.var(), var)
+    if mode == 2:
+        assert all(lf[a] != lf[b] for a, b in pairs)
+
+
+def test_exchange_within_regions_keeps_compositions(oracle_mod):
+    ns, pairs, lf = _region_chain(oracle_mod, 1, 2000, m=8, t=5)
+    assert np.all(ns == 5)
+    assert len(pairs) == 2000 and all(lf[a] == lf[b] for a, b in pairs)
