@@ -271,6 +271,22 @@ int32_t membx_set_tuning(membx_sys* sys, double skin, int32_t rebuild_interval,
 int32_t membx_autotune(membx_sys* sys, int32_t n_steps, double* skin, int32_t* rebuild_interval,
                        int32_t* lanes_per_bead, double* skin_inner, int32_t* prune_interval);
 
+/* Partner rule of exchange trials and MDAS pair selection, with a region
+ * (leaflet) per molecule.  X is drawn uniformly over the exchangeable
+ * molecules as always; Y, uniformly in ascending molecule id over:
+ *   mode 0 (default): the molecules of X's family of another kind;
+ *   mode 1: the same, within X's region: leaflet compositions never change
+ *           (an asymmetric bilayer stays asymmetric);
+ *   mode 2: every molecule of X's family in the other region, whatever its
+ *           kind: the interleaflet exchange the paper proposes in its
+ *           Discussion.  A partner of X's own kind gives a trial that changes
+ *           nothing (dU = 0, counted as accepted).
+ * Each rule proposes a pair as often as its reverse, so Eq. 1's Metropolis
+ * test applies unchanged.  region[n_mols] (host, read during the call; NULL:
+ * all 0): 0 or 1 for the molecules of swap families, ignored for the rest.
+ * Synchronizes.  E_INVAL (mode or a region out of range). */
+int32_t membx_set_exchange_regions(membx_sys* sys, int32_t mode, const int32_t* region);
+
 /* Ensemble of the MD steps (membx_md_step and the steps of MDAS cycles).
  * ensemble 0 (default): Langevin BAOAB with the friction of the descriptor.
  * ensemble 1: the paper's thermostat (Methods), stochastic velocity

@@ -165,10 +165,24 @@ __device__ __forceinline__ int sel_candidate(const Dev<R>& d, const Mv& m, int d
     X = m.sw_list[pick(w.x, (uint32_t)m.n_sw)];
     const int kx = ld_coh(d.mol_kind + X);
     const int f = m.fam_of_kind[kx];
-    const int nf = m.fam_off[f + 1] - m.fam_off[f];
-    const int noth = nf - m.kcnt[kx * m.fam_stride + nf];
-    if (noth <= 0) return 1;
-    Y = m.others[kx * m.fam_stride + pick(w.y, (uint32_t)noth)];
+    if (m.xmode == 0) {
+        const int nf = m.fam_off[f + 1] - m.fam_off[f];
+        const int noth = nf - m.kcnt[kx * m.fam_stride + nf];
+        if (noth <= 0) return 1;
+        Y = m.others[kx * m.fam_stride + pick(w.y, (uint32_t)noth)];
+    } else if (m.xmode == 1) {   // another kind, same region
+        const int r = m.region[X];
+        const int nr = m.reg_off[2 * f + r + 1] - m.reg_off[2 * f + r];
+        const int base = (kx * 2 + r) * m.fam_stride;
+        const int noth = nr - m.kcnt_r[base + nr];
+        if (noth <= 0) return 1;
+        Y = m.others_r[base + pick(w.y, (uint32_t)noth)];
+    } else {                     // any member of the other region
+        const int r = 1 - m.region[X];
+        const int o0 = m.reg_off[2 * f + r], nr = m.reg_off[2 * f + r + 1] - o0;
+        if (nr <= 0) return 1;
+        Y = m.reg_mem[o0 + pick(w.y, (uint32_t)nr)];
+    }
     const int ky = ld_coh(d.mol_kind + Y);
     const int flag = (ld_coh(m.used + X) == stamp || ld_coh(m.used + Y) == stamp) ? 2 : 0;
     const int nch = m.chg_n[kx * d.nk + ky];
@@ -819,19 +833,20 @@ __global__ void k_snapshot(Dev<R> d, Mv m, int restore)
 }
 
 // Per-kind prefix counts over the kind's family member list.
+// Prefix counts of `kind` over the member list mem[n] (out[k]: members of
+// that kind before position k, out[n] the total) and the members of other
+// kinds in ascending order (oth); all 1024 threads of the block call it.
 template <typename R>
-__global__ void k_kcnt(Dev<R> d, Mv m, int kind)
+__device__ void kcnt_list(const Dev<R>& d, const int* __restrict__ mem, int nf, int kind, int* out,
+                          int* oth)
 {
     __shared__ int part[1024];
-    int f = m.fam_of_kind[kind];
-    if (f < 0) return;
-    int f0 = m.fam_off[f], nf = m.fam_off[f + 1] - f0;
-    int* out = m.kcnt + kind * m.fam_stride;
-    int t = threadIdx.x;
-    int per = (nf + 1023) / 1024;
-    int b = t * per, e = min(nf, b + per);
+    const int t = threadIdx.x;
+    const int per = (nf + 1023) / 1024;
+    const int b = t * per, e = min(nf, b + per);
     int s = 0;
-    for (int k = b; k < e; ++k) s += d.mol_kind[m.fam_mem[f0 + k]] == kind;
+    for (int k = b; k < e; ++k) s += d.mol_kind[mem[k]] == kind;
+    __syncthreads();   // part may still be read by a previous call
     part[t] = s;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
@@ -841,15 +856,32 @@ __global__ void k_kcnt(Dev<R> d, Mv m, int kind)
         __syncthreads();
     }
     int run = part[t] - s;
-    int* oth = m.others + kind * m.fam_stride;
     for (int k = b; k < e; ++k) {
-        const int mem = m.fam_mem[f0 + k];
-        const bool same = d.mol_kind[mem] == kind;
+        const int mm = mem[k];
+        const bool same = d.mol_kind[mm] == kind;
         out[k] = run;
-        if (!same) oth[k - run] = mem;   // members of other kinds, ascending
+        if (!same) oth[k - run] = mm;   // members of other kinds, ascending
         run += same;
     }
     if (t == 1023) out[nf] = part[1023];
+}
+
+// Kind counts of one kind over its family, and (within-region exchanges)
+// over each region of the family.
+template <typename R>
+__global__ __launch_bounds__(1024) void k_kcnt(Dev<R> d, Mv m, int kind)
+{
+    const int f = m.fam_of_kind[kind];
+    if (f < 0) return;
+    const int f0 = m.fam_off[f], nf = m.fam_off[f + 1] - f0;
+    kcnt_list(d, m.fam_mem + f0, nf, kind, m.kcnt + kind * m.fam_stride,
+              m.others + kind * m.fam_stride);
+    if (m.xmode == 1)
+        for (int r = 0; r < 2; ++r) {
+            const int o0 = m.reg_off[2 * f + r], nr = m.reg_off[2 * f + r + 1] - o0;
+            const int base = (kind * 2 + r) * m.fam_stride;
+            kcnt_list(d, m.reg_mem + o0, nr, kind, m.kcnt_r + base, m.others_r + base);
+        }
 }
 
 // ----------------------------------------------------------------- launch

@@ -242,6 +242,14 @@ struct Mv {
     int fam_stride;      // max family size + 1
     int* kcnt;           // [nk * fam_stride] per-kind prefix counts over its family
     int* others;         // [nk * fam_stride] family members of another kind, ascending
+    // exchange regions (leaflets): xmode 0 partners anywhere in the family,
+    // 1 of another kind within X's region, 2 any member in the other region
+    int xmode;
+    int* region;         // [nm] 0/1
+    int* reg_off;        // [2 nfam + 1] offsets of (family, region) into reg_mem
+    int* reg_mem;        // family members by region, ascending molecule ids
+    int* kcnt_r;         // [nk * 2 * fam_stride] kcnt over the members of one region
+    int* others_r;       // [nk * 2 * fam_stride] others within one region
     int* chg_n;          // [nk * nk] changed beads between two kinds
     int* chg_loc;        // [nk * nk * MAXCH] their local indices
     int maxcht;          // max changed beads per trial (both molecules)

@@ -104,6 +104,10 @@ struct Host {
     std::vector<double> bt_par;         // 2 per parameter set
     std::vector<int> sw_list, fam_off, fam_mem, fam_of_kind, chg_n, chg_loc;
     int nfam = 0, maxch = 0, fam_stride = 1;
+    // exchange regions (leaflets) and the partner rule (0 anywhere, 1 within
+    // X's region, 2 in the other region); members of each family by region
+    int xmode = 0;
+    std::vector<int> region, reg_off, reg_mem;
     double krf, crf;
     // tuning / capacities
     double skin, skin_max;
@@ -120,6 +124,20 @@ struct Host {
     int hnc[3], hcells, mh;
     int aff_cap;
 };
+
+// Members of each swap family split by region, ascending molecule ids:
+// (family f, region r) occupies reg_mem[reg_off[2 f + r], reg_off[2 f + r + 1]).
+static void build_regions(Host& h)
+{
+    h.reg_off.assign(2 * h.nfam + 1, 0);
+    h.reg_mem.clear();
+    for (int f = 0; f < h.nfam; ++f)
+        for (int r = 0; r < 2; ++r) {
+            for (int k = h.fam_off[f]; k < h.fam_off[f + 1]; ++k)
+                if (h.region[h.fam_mem[k]] == r) h.reg_mem.push_back(h.fam_mem[k]);
+            h.reg_off[2 * f + r + 1] = (int)h.reg_mem.size();
+        }
+}
 
 // Cell grid for list radius r_cut + skin: nc = floor(L / r_list) cells per
 // axis (at least 3), plus one halo layer of ghost images.
@@ -353,6 +371,8 @@ Status derive(const membx_desc* d, Host& h)
         mx = std::max(mx, (int)mem[f].size());
     }
     h.fam_stride = mx + 1;
+    h.region.assign(h.nm, 0);
+    build_regions(h);
     h.chg_n.assign(h.nk * h.nk, 0);
     h.chg_loc.assign(h.nk * h.nk * MAXCH, 0);
     h.maxch = 1;
@@ -560,6 +580,12 @@ static size_t layout(membx_sys* s, Dev<R>& d, Mv& m, char* base)
     m.fam_stride = h.fam_stride;
     m.kcnt = a.take<int>((size_t)h.nk * h.fam_stride);
     m.others = a.take<int>((size_t)h.nk * h.fam_stride);
+    m.xmode = h.xmode;
+    m.region = a.take<int>(h.nm);
+    m.reg_off = a.take<int>(h.reg_off.size());
+    m.reg_mem = a.take<int>(h.reg_mem.size());
+    m.kcnt_r = a.take<int>((size_t)h.nk * 2 * h.fam_stride);
+    m.others_r = a.take<int>((size_t)h.nk * 2 * h.fam_stride);
     m.chg_n = a.take<int>(h.nk * h.nk);
     m.chg_loc = a.take<int>(h.nk * h.nk * MAXCH);
     m.maxcht = MC;
@@ -1004,6 +1030,9 @@ static int32_t upload(membx_sys* s, const membx_desc* desc)
     UP(m.fam_mem, h.fam_mem);
     UP(m.chg_n, h.chg_n);
     UP(m.chg_loc, h.chg_loc);
+    UP(m.region, h.region);
+    UP(m.reg_off, h.reg_off);
+    UP(m.reg_mem, h.reg_mem);
 #undef UP
     HCK(hipMemsetAsync(d.frc, 0, sizeof(V4<R>) * h.N, st));
     // binning counters start at zero; afterwards the cell layout clears them
@@ -1022,6 +1051,8 @@ static int32_t upload(membx_sys* s, const membx_desc* desc)
     HCK(hipMemsetAsync(m.aff_n, 0, sizeof(int), st));
     HCK(hipMemsetAsync(m.md, 0, sizeof(double) * 8, st));
     HCK(hipMemsetAsync(m.kcnt, 0, sizeof(int) * (size_t)h.nk * h.fam_stride, st));
+    HCK(hipMemsetAsync(m.kcnt_r, 0, sizeof(int) * (size_t)h.nk * 2 * h.fam_stride, st));
+    HCK(hipMemsetAsync(m.others_r, 0, sizeof(int) * (size_t)h.nk * 2 * h.fam_stride, st));
     kcnt_all<R>(s);
     refresh_forces<R>(s);
     HCK(hipStreamSynchronize(st));   // host staging vectors go out of scope
@@ -1674,6 +1705,46 @@ static int32_t ensemble_impl(membx_sys* s)
     for (auto& kv : s->gcache) (void)hipGraphExecDestroy(kv.second);
     s->gcache.clear();
     return MEMBX_OK;
+}
+
+template <typename R>
+static int32_t regions_impl(membx_sys* s)
+{
+    Mv& m = s->mv;
+    const Host& h = s->h;
+    HCK(hipMemcpyAsync(m.region, h.region.data(), sizeof(int) * h.nm, hipMemcpyHostToDevice, s->st));
+    HCK(hipMemcpyAsync(m.reg_off, h.reg_off.data(), sizeof(int) * h.reg_off.size(),
+                       hipMemcpyHostToDevice, s->st));
+    if (!h.reg_mem.empty())
+        HCK(hipMemcpyAsync(m.reg_mem, h.reg_mem.data(), sizeof(int) * h.reg_mem.size(),
+                           hipMemcpyHostToDevice, s->st));
+    m.xmode = h.xmode;
+    kcnt_all<R>(s);
+    HCK(hipStreamSynchronize(s->st));   // the host vectors may change on the next call
+    for (auto& kv : s->gcache) (void)hipGraphExecDestroy(kv.second);
+    s->gcache.clear();
+    return MEMBX_OK;
+}
+
+int32_t membx_set_exchange_regions(membx_sys* s, int32_t mode, const int32_t* region)
+{
+    if (!s) return MEMBX_E_INVAL;
+    if (mode < 0 || mode > 2) return fail(s, MEMBX_E_INVAL, "exchange mode must be 0, 1 or 2");
+    std::vector<int> rg(s->h.nm, 0);
+    if (region)
+        for (int m = 0; m < s->h.nm; ++m) {
+            if (s->h.fam_of_kind[s->h.mol_kind0[m]] < 0) continue;   // never exchanged
+            if (region[m] != 0 && region[m] != 1)
+                return fail(s, MEMBX_E_INVAL, "regions of exchangeable molecules must be 0 or 1");
+            rg[m] = region[m];
+        }
+    s->h.region = rg;
+    s->h.xmode = mode;
+    build_regions(s->h);
+    int32_t rc = begin(s);
+    if (!rc) rc = DISPATCH(s, regions_impl, s);
+    if (!rc) rc = end(s);
+    return rc;
 }
 
 int32_t membx_set_ensemble(membx_sys* s, int32_t ensemble, double tau_t, const int32_t* kind_group)

@@ -122,6 +122,7 @@ def lib():
                                 C.POINTER(dp), C.POINTER(i32)], i32),
             "membx_set_graphs": ([vp, i32], i32),
             "membx_set_ensemble": ([vp, i32, dp, vp], i32),
+            "membx_set_exchange_regions": ([vp, i32, vp], i32),
             "membx_kernel_timing": ([vp, i32], i32),
             "membx_kernel_time": ([vp, C.POINTER(i64), C.POINTER(dp)], i32),
             "membx_kernel_bench": ([vp, i32, C.POINTER(dp)], i32),
@@ -365,6 +366,19 @@ class System:
         return lib().membx_status(self.h)
 
     # --------------------------------------------------------------- tuning
+    def set_exchange_regions(self, mode, region=None):
+        """exchange partners: 0 anywhere in X's family (other kind), 1 other
+        kind within X's region, 2 any family member in the other region;
+        region[n_mols] 0/1 for exchangeable molecules (others ignored)"""
+        rg = None
+        if region is not None:
+            rg = np.ascontiguousarray(region, dtype=np.int32)
+            if rg.shape != (self.nm,):
+                raise ValueError("region needs one entry per molecule")
+        _check(lib().membx_set_exchange_regions(self.h, int(mode),
+                                                None if rg is None else rg.ctypes.data_as(C.c_void_p)),
+               self.h)
+
     def set_ensemble(self, ensemble, tau_t=1.0, kind_group=None):
         """0: Langevin BAOAB; 1: velocity Verlet + stochastic velocity
         rescaling with coupling time tau_t (ps) of the groups kind_group[n_kinds]
