@@ -108,3 +108,14 @@ def test_halfway_needs_a_gap():
     y = np.array([2.0, 1.9, 1.6, 1.5, 1.5, 1.4, 1.4, 1.4, 1.4, 1.4])
     assert X.fe_to_half(x, y, 1.3) == 400.0   # mean of samples 2..4 is the first <= 1.65
     assert X.fe_to_half(x, y, 1.9, min_gap=0.2) is None
+
+
+def test_flipflop_inputs_and_crossing():
+    from paper_2005_08348_amd import flipflop as F
+    s = F.asymmetric_mix()
+    lf = s.meta["leaflet"]
+    assert np.all(s.mol_kind[lf == 0] == S.KIND_A) and np.all(s.mol_kind[lf == 1] == S.KIND_D)
+    assert np.count_nonzero(lf == 0) == np.count_nonzero(lf == 1) == 200
+    x = np.arange(6) * 10.0
+    assert F.fe_to_fraction(x, [0, 0.1, 0.2, 0.3, 0.2, 0.4], 0.25) == 30.0
+    assert F.fe_to_fraction(x, [0, 0.1, 0.1, 0.1, 0.1, 0.1], 0.25) is None
