@@ -299,7 +299,7 @@ def main():
                           "trials_per_s": nb * len(r["du"]) / tsw}
         # ---- the paper's thermostat: velocity rescaling, tau_t 1 ps,
         # membrane and solvent in two coupling groups (not fused with the
-        # force pass: three more launches per step)
+        # force pass: four launches per step instead of one)
         log("[bench] velocity-rescaling leg")
         groups = [1 if k.name == "W" else 0 for k in c1.kinds]
         t_lang = 2.0 * gm.energies(check=False)["kinetic"] / (3 * c1.n_beads * S.KB)

@@ -297,8 +297,8 @@ int32_t membx_set_exchange_regions(membx_sys* sys, int32_t mode, const int32_t* 
  * multiplied by +-sqrt(K' / K); random numbers from Philox stream 5 with the
  * step index as counter.  kind_group[n_kinds] (host, read during the call;
  * null: all 0) puts each molecule kind in group 0 or 1, so a molecule's
- * group follows exchanges of its kind.  Not fused with the force pass (three
- * extra launches per step).  Synchronizes.  E_INVAL (ensemble, tau_t or a
+ * group follows exchanges of its kind.  Not fused with the force pass: four
+ * launches per step instead of one.  Synchronizes.  E_INVAL (ensemble, tau_t or a
  * group out of range). */
 int32_t membx_set_ensemble(membx_sys* sys, int32_t ensemble, double tau_t,
                            const int32_t* kind_group);

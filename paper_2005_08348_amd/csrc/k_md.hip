@@ -147,9 +147,10 @@ void launch_import(const Dev<R>& d, V4<R>* dst, const double* in, hipStream_t st
 // multiplied by alpha = sqrt(K' / K), with the sign of the new velocity
 // component along the old one, R1 + sqrt(c Nf K / ((1 - c) Kt)).  Random
 // words: Philox stream 5, counter = step index, block (group << 16) for R1
-// and (group << 16) + 1 + t for the t-th attempt of the gamma sampler.  Three
-// launches per step: half-kick with per-block group sums, one wave for the
-// two factors (float64 throughout), the scaling.
+// and (group << 16) + 1 + t for the t-th attempt of the gamma sampler.  Two
+// launches per step beyond the force pass: half-kick with per-block group
+// sums, one wave for the two factors (float64 throughout); the scaling rides
+// on the next step's update.
 
 template <typename R>
 __device__ __forceinline__ int vr_group(const Dev<R>& d, const VrBuf& vr, int i)
@@ -256,6 +257,29 @@ __global__ __launch_bounds__(WG) void k_vr_scale(Dev<R> d, VrBuf vr)
     d.vel[i] = v;
 }
 
+// the previous step's scaling folded into this step's B-A-O-A (the O part is
+// off under this thermostat): v <- alpha_g v, then the kick and drifts
+template <typename R>
+__global__ __launch_bounds__(WG) void k_vr_kick_drift(Dev<R> d, VrBuf vr, R kick, long long step_off,
+                                                      int chk_in)
+{
+    const int i = blockIdx.x * WG + threadIdx.x;
+    float e2 = 0.f, e2_in = 0.f;
+    if (i < d.N) {
+        BeadPre<R> pre = bead_pre(d, i, chk_in != 0);
+        const double a = vr.alpha[vr_group(d, vr, i)];
+        pre.v.x = (R)(a * (double)pre.v.x);
+        pre.v.y = (R)(a * (double)pre.v.y);
+        pre.v.z = (R)(a * (double)pre.v.z);
+        e2 = baoab_bead(d, i, d.posq[i], pre, d.frc[i], kick, step_off, d.posq, d.vel, chk_in != 0,
+                        e2_in);
+    }
+    disp_stats(d, e2, e2_in, i < d.N);
+}
+
+// closing half-kick with the group sums, then the factors of the step; the
+// scaling itself runs in the next step's update (k_vr_kick_drift) or, after
+// the last step of a sequence, in k_vr_scale (launch_vr_scale)
 template <typename R>
 void launch_vrescale(const Dev<R>& d, const VrBuf& vr, R kick, long long step_off, double c,
                      hipStream_t st)
@@ -263,12 +287,26 @@ void launch_vrescale(const Dev<R>& d, const VrBuf& vr, R kick, long long step_of
     const int nb = (d.N + WG - 1) / WG;
     hipLaunchKernelGGL(k_kick_ke<R>, dim3(nb), dim3(WG), 0, st, d, vr, kick);
     hipLaunchKernelGGL(k_vr_alpha<R>, dim3(1), dim3(64), 0, st, d, vr, nb, step_off, c);
-    hipLaunchKernelGGL(k_vr_scale<R>, dim3(nb), dim3(WG), 0, st, d, vr);
+}
+template <typename R>
+void launch_vr_scale(const Dev<R>& d, const VrBuf& vr, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_vr_scale<R>, dim3((d.N + WG - 1) / WG), dim3(WG), 0, st, d, vr);
+}
+template <typename R>
+void launch_vr_kick_drift(const Dev<R>& d, const VrBuf& vr, R kick, long long step_off, int chk_in,
+                          hipStream_t st)
+{
+    hipLaunchKernelGGL(k_vr_kick_drift<R>, dim3((d.N + WG - 1) / WG), dim3(WG), 0, st, d, vr, kick,
+                       step_off, chk_in);
 }
 
 #define INST(R)                                                                      \
     template void launch_vrescale<R>(const Dev<R>&, const VrBuf&, R, long long, double, \
                                      hipStream_t);                                   \
+    template void launch_vr_scale<R>(const Dev<R>&, const VrBuf&, hipStream_t);      \
+    template void launch_vr_kick_drift<R>(const Dev<R>&, const VrBuf&, R, long long, int, \
+                                          hipStream_t);                              \
     template void launch_kick_drift<R>(const Dev<R>&, R, long long, int, hipStream_t); \
     template void launch_kick<R>(const Dev<R>&, R, long long, hipStream_t);                    \
     template void launch_sd_step<R>(const Dev<R>&, double, double, hipStream_t);     \

@@ -29,6 +29,9 @@ template <typename R> void launch_kick_drift(const Dev<R>&, R, long long, int, h
 template <typename R> void launch_kick(const Dev<R>&, R, long long, hipStream_t);
 template <typename R>
 void launch_vrescale(const Dev<R>&, const VrBuf&, R, long long, double, hipStream_t);
+template <typename R> void launch_vr_scale(const Dev<R>&, const VrBuf&, hipStream_t);
+template <typename R>
+void launch_vr_kick_drift(const Dev<R>&, const VrBuf&, R, long long, int, hipStream_t);
 template <typename R> void launch_sd_step(const Dev<R>&, double, double, hipStream_t);
 template <typename R> void launch_export(const Dev<R>&, const V4<R>*, double*, hipStream_t);
 template <typename R> void launch_import(const Dev<R>&, V4<R>*, const double*, hipStream_t);
@@ -731,9 +734,11 @@ static void steps_seq(membx_sys* s, long long n, const Alch* alch, bool launch =
     if (alch) s->sp = -1;   // MDAS segments walk the Verlet list; no inner bookkeeping
     bool moved = false;   // the previous force pass already moved the beads
     for (long long k = 0; k < n; ++k) {
-        if (!moved && launch)
-            launch_kick_drift<R>(d, (k == 0 || vr) ? h : full, k, (inner && s->sp >= 0) ? 1 : 0,
-                                 s->st);
+        if (!moved && launch) {
+            const int chk = (inner && s->sp >= 0) ? 1 : 0;
+            if (vr && k > 0) launch_vr_kick_drift<R>(d, s->vr, h, k, chk, s->st);
+            else launch_kick_drift<R>(d, (k == 0 || vr) ? h : full, k, chk, s->st);
+        }
         moved = false;
         bool rebuilt = false;
         if (++s->since >= s->h.R) {
@@ -763,8 +768,12 @@ static void steps_seq(membx_sys* s, long long n, const Alch* alch, bool launch =
         }
     }
     if (launch) {
-        if (vr) launch_add_ctr(d.ctr, CT_STEP, n, s->st);
-        else launch_kick<R>(d, h, n, s->st);
+        if (vr) {
+            if (n > 0) launch_vr_scale<R>(d, s->vr, s->st);
+            launch_add_ctr(d.ctr, CT_STEP, n, s->st);
+        } else {
+            launch_kick<R>(d, h, n, s->st);
+        }
     }
 }
 
