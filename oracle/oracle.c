@@ -518,6 +518,64 @@ long o_energy_forces(osys* s, double* f, double* out_e, int use_cells)
     return np;
 }
 
+/* ------------------------------------------------------ virial, pressure */
+/* Pressure tensor diagonal (needed by the paper's barostat, Methods):
+ * P_aa V = sum_i m_i v_ia^2 + W_aa, with the virial W_aa the sum over
+ * interactions of (separation)_a (force)_a: for a pair or bond, the
+ * minimum-image separation r_i - r_j times the force on i; for an angle
+ * i-j-k, (r_i - r_j) F_i + (r_k - r_j) F_k (the three forces sum to zero).
+ * W_aa equals -dU/d eps for the affine stretch x_a -> (1 + eps) x_a of all
+ * beads and of the box. */
+typedef struct { const int* mk; double w[3]; } vir_ctx;
+
+static void vir_pair(osys* s, int i, int j, const double d[3], double r2, void* vctx)
+{
+    vir_ctx* c = (vir_ctx*)vctx;
+    double vlj, vrf, fs;
+    pair_term(s, btype_k(s, c->mk, i), btype_k(s, c->mk, j),
+              bq_k(s, c->mk, i), bq_k(s, c->mk, j), r2, &vlj, &vrf, &fs);
+    for (int a = 0; a < 3; ++a) c->w[a] += d[a] * fs * d[a];
+}
+
+/* w[0..2] = W_aa, w[3..5] = sum m v_a^2 */
+void o_virial(osys* s, double* w, int use_cells)
+{
+    vir_ctx c = { s->mkind, { 0.0, 0.0, 0.0 } };
+    for_pairs(s, s->rc, use_cells, vir_pair, &c);
+    for (int m = 0; m < s->nm; ++m) {
+        int k = s->mkind[m], f0 = s->mfirst[m];
+        for (int b = 0; b < s->knb[k]; ++b) {
+            int bb = s->kboff[k] + b;
+            int i = f0 + s->bi[bb], j = f0 + s->bj[bb];
+            double d[3];
+            min_image(s, &s->x[3 * i], &s->x[3 * j], d);
+            double r = sqrt(dist2(d));
+            double fs = -s->bk[bb] * (r - s->bb0[bb]) / r;
+            for (int a = 0; a < 3; ++a) c.w[a] += d[a] * fs * d[a];
+        }
+        for (int t = 0; t < s->kna[k]; ++t) {
+            int aa = s->kaoff[k] + t;
+            int i = f0 + s->ai[aa], j = f0 + s->aj[aa], l = f0 + s->ak[aa];
+            double u[3], v[3];
+            min_image(s, &s->x[3 * i], &s->x[3 * j], u);
+            min_image(s, &s->x[3 * l], &s->x[3 * j], v);
+            double uu = dist2(u), vv = dist2(v), nu = sqrt(uu), nv = sqrt(vv);
+            double cth = (u[0] * v[0] + u[1] * v[1] + u[2] * v[2]) / (nu * nv);
+            double pre = -s->akk[aa] * (cth - s->acos0[aa]);
+            for (int a = 0; a < 3; ++a) {
+                double fi = pre * (v[a] / (nu * nv) - cth * u[a] / uu);
+                double fk = pre * (u[a] / (nu * nv) - cth * v[a] / vv);
+                c.w[a] += u[a] * fi + v[a] * fk;
+            }
+        }
+    }
+    for (int a = 0; a < 3; ++a) { w[a] = c.w[a]; w[3 + a] = 0.0; }
+    for (int i = 0; i < s->n; ++i) {
+        double m = bmass(s, i);
+        for (int a = 0; a < 3; ++a) w[3 + a] += m * s->v[3 * i + a] * s->v[3 * i + a];
+    }
+}
+
 /* Force on selected beads by direct summation over every other bead
  * (O(N) per bead; for sampled checks on large systems).  Also returns, per
  * bead, the smallest |r^2 - rc^2| over its pairs so that callers can set

@@ -86,6 +86,7 @@ def lib():
                                        _i64p]
         L.o_set_ensemble.argtypes = [C.c_void_p, C.c_int, C.c_double, _i32p]
         L.o_set_exchange_regions.argtypes = [C.c_void_p, C.c_int, _i32p]
+        L.o_virial.argtypes = [C.c_void_p, _f64p, C.c_int]
         L.o_gamma_mt.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_int64, C.c_int, _f64p]
         L.o_vr_alpha.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_int64, C.c_int,
                                  _f64p]
@@ -115,6 +116,9 @@ def _i32(a):
 
 def _f64(a):
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(-1))
+
+
+BAR = 16.6054   # bar per kJ mol^-1 nm^-3
 
 
 class Oracle:
@@ -183,6 +187,14 @@ class Oracle:
         if forces:
             out["force"] = f.reshape(-1, 3)
         return out
+
+    def virial(self, cells=True):
+        """W_aa (kJ/mol), sum m v_a^2 (kJ/mol) and the pressure tensor
+        diagonal P_aa = (sum m v_a^2 + W_aa) / V in bar"""
+        w = np.zeros(6)
+        lib().o_virial(self.h, w, int(cells))
+        vol = float(np.prod(self.system.box))
+        return dict(w=w[:3].copy(), mv2=w[3:].copy(), pressure=(w[3:] + w[:3]) / vol * BAR)
 
     def forces_on(self, beads):
         sel = _i32(beads)

@@ -633,3 +633,68 @@ def test_exchange_within_regions_keeps_compositions(oracle_mod):
     ns, pairs, lf = _region_chain(oracle_mod, 1, 2000, m=8, t=5)
     assert np.all(ns == 5)
     assert len(pairs) == 2000 and all(lf[a] == lf[b] for a, b in pairs)
+
+
+# ------------------------------------------------------- virial, pressure
+def _stretched_potential(oracle_mod, sysm, axis, eps):
+    s = sysm.copy()
+    s.pos = sysm.pos.copy()
+    s.box = np.asarray(sysm.box, dtype=np.float64).copy()
+    s.pos[:, axis] *= 1.0 + eps
+    s.box[axis] *= 1.0 + eps
+    return oracle_mod.Oracle(s).energy_forces(forces=False)["potential"]
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_virial_is_minus_strain_derivative(oracle_mod, c0_relaxed, axis):
+    """W_aa = -dU/d eps for the affine stretch of all beads and the box
+    along axis a, on the C0 bilayer: LJ, reaction field, bonds and angles
+    together.  The shifted LJ force jumps at the cutoff, so a pair crossing
+    it inside the difference interval adds a kink; the median of central
+    differences over five small intervals sets such rare crossings aside."""
+    fds = []
+    for h in (1e-7, 2e-7, 3e-7, 5e-7, 7e-7):
+        up = _stretched_potential(oracle_mod, c0_relaxed, axis, h)
+        dn = _stretched_potential(oracle_mod, c0_relaxed, axis, -h)
+        fds.append(-(up - dn) / (2 * h))
+    w = oracle_mod.Oracle(c0_relaxed).virial()["w"][axis]
+    fd = float(np.median(fds))
+    assert abs(w - fd) < 5e-6 * max(abs(w), 1e3), (w, fds)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_virial_of_an_angle(oracle_mod, axis):
+    """An angle alone (bonds carry no force): the same identity on a bent
+    three-bead molecule across a periodic boundary."""
+    pos = [[7.8, 1.0, 1.2], [0.2, 1.3, 1.0], [0.5, 0.9, 1.4]]
+    eps = np.zeros((S.N_TYPES, S.N_TYPES))
+    k = S.Kind("T", [0] * 3, [0.0] * 3, [(0, 1, 0.47, 0.0), (1, 2, 0.47, 0.0)],
+               [(0, 1, 2, 180.0, 25.0)], -1)
+    s = S.custom("b", [k], [0], pos, [8, 8, 8], eps)
+    h = 1e-6
+    up = _stretched_potential(oracle_mod, s, axis, h)
+    dn = _stretched_potential(oracle_mod, s, axis, -h)
+    w = oracle_mod.Oracle(s).virial(cells=False)["w"][axis]
+    assert abs(w + (up - dn) / (2 * h)) < 1e-6 * max(1.0, abs(w))
+    assert abs(w) > 1e-3
+
+
+def test_pressure_of_an_ideal_gas(oracle_mod):
+    """No interactions: P_aa V = sum m v_a^2, which averages N kT under the
+    Langevin thermostat."""
+    n = 400
+    eps = np.zeros((S.N_TYPES, S.N_TYPES))
+    k = S.Kind("W", [4], [0.0], [], [], -1)
+    rng = np.random.default_rng(3)
+    s = S.custom("gas", [k], [0] * n, rng.uniform(0, 9, size=(n, 3)), [9, 9, 9], eps, seed=5)
+    s.gamma = 5.0
+    o = oracle_mod.Oracle(s)
+    ps = []
+    for _ in range(60):
+        o.md_step(10)
+        v = o.virial(cells=False)
+        assert np.all(v["w"] == 0.0)
+        ps.append(v["pressure"])
+    p = np.mean(ps[10:], axis=0)
+    ideal = n * KB * 323.0 / 729.0 * oracle_mod.BAR
+    assert np.all(np.abs(p / ideal - 1.0) < 0.06), (p, ideal)
