@@ -139,6 +139,12 @@ typedef struct membx_energy {
     int64_t n_list_entries;       /* entries of the Verlet list (both       */
                                   /* directions): the pair slots one force  */
                                   /* pass computes                          */
+    double  virial[3];            /* W_aa: sum over pairs, bonds and angles */
+                                  /* of (separation)_a (force)_a, kJ/mol    */
+    double  mv2[3];               /* sum m v_a^2, kJ/mol                    */
+    double  pressure[3];          /* P_aa = (mv2 + virial) / V, bar: the    */
+                                  /* pressure the paper's barostat couples  */
+                                  /* to (Methods)                           */
 } membx_energy;
 
 /* One admitted exchange trial of a batch. */

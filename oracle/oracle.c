@@ -526,7 +526,7 @@ long o_energy_forces(osys* s, double* f, double* out_e, int use_cells)
  * i-j-k, (r_i - r_j) F_i + (r_k - r_j) F_k (the three forces sum to zero).
  * W_aa equals -dU/d eps for the affine stretch x_a -> (1 + eps) x_a of all
  * beads and of the box. */
-typedef struct { const int* mk; double w[3]; } vir_ctx;
+typedef struct { const int* mk; double w[3], wabs[3]; } vir_ctx;
 
 static void vir_pair(osys* s, int i, int j, const double d[3], double r2, void* vctx)
 {
@@ -534,13 +534,17 @@ static void vir_pair(osys* s, int i, int j, const double d[3], double r2, void* 
     double vlj, vrf, fs;
     pair_term(s, btype_k(s, c->mk, i), btype_k(s, c->mk, j),
               bq_k(s, c->mk, i), bq_k(s, c->mk, j), r2, &vlj, &vrf, &fs);
-    for (int a = 0; a < 3; ++a) c->w[a] += d[a] * fs * d[a];
+    for (int a = 0; a < 3; ++a) {
+        c->w[a] += d[a] * fs * d[a];
+        c->wabs[a] += fabs(d[a] * fs * d[a]);
+    }
 }
 
-/* w[0..2] = W_aa, w[3..5] = sum m v_a^2 */
+/* w[0..2] = W_aa, w[3..5] = sum m v_a^2, w[6..8] = sum of |term| of W_aa
+ * (the scale of rounding errors in a reduced-precision evaluation) */
 void o_virial(osys* s, double* w, int use_cells)
 {
-    vir_ctx c = { s->mkind, { 0.0, 0.0, 0.0 } };
+    vir_ctx c = { s->mkind, { 0.0, 0.0, 0.0 }, { 0.0, 0.0, 0.0 } };
     for_pairs(s, s->rc, use_cells, vir_pair, &c);
     for (int m = 0; m < s->nm; ++m) {
         int k = s->mkind[m], f0 = s->mfirst[m];
@@ -551,7 +555,10 @@ void o_virial(osys* s, double* w, int use_cells)
             min_image(s, &s->x[3 * i], &s->x[3 * j], d);
             double r = sqrt(dist2(d));
             double fs = -s->bk[bb] * (r - s->bb0[bb]) / r;
-            for (int a = 0; a < 3; ++a) c.w[a] += d[a] * fs * d[a];
+            for (int a = 0; a < 3; ++a) {
+                c.w[a] += d[a] * fs * d[a];
+                c.wabs[a] += fabs(d[a] * fs * d[a]);
+            }
         }
         for (int t = 0; t < s->kna[k]; ++t) {
             int aa = s->kaoff[k] + t;
@@ -566,10 +573,11 @@ void o_virial(osys* s, double* w, int use_cells)
                 double fi = pre * (v[a] / (nu * nv) - cth * u[a] / uu);
                 double fk = pre * (u[a] / (nu * nv) - cth * v[a] / vv);
                 c.w[a] += u[a] * fi + v[a] * fk;
+                c.wabs[a] += fabs(u[a] * fi) + fabs(v[a] * fk);
             }
         }
     }
-    for (int a = 0; a < 3; ++a) { w[a] = c.w[a]; w[3 + a] = 0.0; }
+    for (int a = 0; a < 3; ++a) { w[a] = c.w[a]; w[3 + a] = 0.0; w[6 + a] = c.wabs[a]; }
     for (int i = 0; i < s->n; ++i) {
         double m = bmass(s, i);
         for (int a = 0; a < 3; ++a) w[3 + a] += m * s->v[3 * i + a] * s->v[3 * i + a];

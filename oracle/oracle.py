@@ -189,12 +189,14 @@ class Oracle:
         return out
 
     def virial(self, cells=True):
-        """W_aa (kJ/mol), sum m v_a^2 (kJ/mol) and the pressure tensor
-        diagonal P_aa = (sum m v_a^2 + W_aa) / V in bar"""
-        w = np.zeros(6)
+        """W_aa (kJ/mol), sum m v_a^2 (kJ/mol), the pressure tensor diagonal
+        P_aa = (sum m v_a^2 + W_aa) / V in bar, and the sum of |term| of W_aa
+        (an error scale for reduced-precision evaluations)"""
+        w = np.zeros(9)
         lib().o_virial(self.h, w, int(cells))
         vol = float(np.prod(self.system.box))
-        return dict(w=w[:3].copy(), mv2=w[3:].copy(), pressure=(w[3:] + w[:3]) / vol * BAR)
+        return dict(w=w[:3].copy(), mv2=w[3:6].copy(), pressure=(w[3:6] + w[:3]) / vol * BAR,
+                    w_abs=w[6:].copy())
 
     def forces_on(self, beads):
         sel = _i32(beads)

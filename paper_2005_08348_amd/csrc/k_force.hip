@@ -47,12 +47,13 @@ __device__ __forceinline__ void sep3(const Dev<R>& d, const V4<R>& a, const V4<R
 }
 
 // Force on bead i from one bonded term it takes part in (partner coordinates
-// p1, p2 already gathered); energy counted by the term's owner (bond role 0,
-// angle vertex).
+// p1, p2 already gathered); energy and virial counted by the term's owner
+// (bond role 0, angle vertex): for a bond (r_i - r_j)_a (F_i)_a, for an angle
+// the ends' separations from the vertex times the ends' forces.
 template <typename R, bool EN>
 __device__ __forceinline__ void bonded_term(const Dev<R>& d, const V4<R>& pi, int4 tm,
                                             const V4<R>& p1, const V4<R>& p2, R& fx, R& fy, R& fz,
-                                            double& eb, double& ea)
+                                            double& eb, double& ea, double* wb)
 {
     const R p0 = d.bt_par[2 * tm.w], kk = d.bt_par[2 * tm.w + 1];
     if (tm.x <= 1) {
@@ -62,7 +63,12 @@ __device__ __forceinline__ void bonded_term(const Dev<R>& d, const V4<R>& pi, in
         R dr = r - p0;
         R fs = -kk * dr / r;
         fx += fs * dx; fy += fs * dy; fz += fs * dz;
-        if (EN && tm.x == 0) eb += 0.5 * (double)kk * (double)dr * (double)dr;
+        if (EN && tm.x == 0) {
+            eb += 0.5 * (double)kk * (double)dr * (double)dr;
+            wb[0] += (double)(fs * dx) * (double)dx;
+            wb[1] += (double)(fs * dy) * (double)dy;
+            wb[2] += (double)(fs * dz) * (double)dz;
+        }
     } else {
         // role 2: i is an end, p1 the vertex, p2 the other end
         // role 3: i is the vertex, p1 and p2 the ends
@@ -82,7 +88,12 @@ __device__ __forceinline__ void bonded_term(const Dev<R>& d, const V4<R>& pi, in
             R cb = c / bb;
             R hx = ax * inw - cb * bx, hy = ay * inw - cb * by, hz = az * inw - cb * bz;
             fx -= pre * (gx + hx); fy -= pre * (gy + hy); fz -= pre * (gz + hz);
-            if (EN) ea += 0.5 * (double)kk * (double)dc * (double)dc;
+            if (EN) {
+                ea += 0.5 * (double)kk * (double)dc * (double)dc;
+                wb[0] += (double)ax * (double)(pre * gx) + (double)bx * (double)(pre * hx);
+                wb[1] += (double)ay * (double)(pre * gy) + (double)by * (double)(pre * hy);
+                wb[2] += (double)az * (double)(pre * gz) + (double)bz * (double)(pre * hz);
+            }
         }
     }
 }
@@ -94,7 +105,9 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// energies: partial[8 * block] = {lj, rf, pairs, bond, angle, kinetic}.
+// energies: partial[16 * block] = {lj, rf, pairs, bond, angle, kinetic,
+// list entries, pair virial (3, both directions), bonded virial (3),
+// m v_a^2 (3)}.
 // FUSE: the lane that owns bead i's force also moves the bead through the
 // next BAOAB step (its own force is all that step needs), writing the new
 // coordinates to pos_out (the other coordinate buffer: the neighbours' old
@@ -156,6 +169,7 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
     const V4<R>* rowE = EN ? te + ci * MAXCLS : tf;
     R fx = 0, fy = 0, fz = 0;
     double elj = 0.0, erf = 0.0, eb = 0.0, ea = 0.0, ek = 0.0;
+    double wp[3] = { 0.0, 0.0, 0.0 }, wb[3] = { 0.0, 0.0, 0.0 }, mv2[3] = { 0.0, 0.0, 0.0 };
     int np = 0;
     // list walk in batches of B entries per lane, then short batches of BT
     // for the tail, the batch sizes uniform over the wave; branch-free inside a
@@ -210,6 +224,9 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
                     elj += (double)vlj;
                     erf += (double)vrf;
                     np += 1;
+                    wp[0] += (double)(fs * dx) * (double)dx;
+                    wp[1] += (double)(fs * dy) * (double)dy;
+                    wp[2] += (double)(fs * dz) * (double)dz;
                 }
             }
         }
@@ -253,9 +270,13 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
     // bonded terms of bead i
 #pragma unroll
     for (int u = 0; u < TPL; ++u)
-        if (valid && bt[u].x >= 0) bonded_term<R, EN>(d, pi, bt[u], b1[u], b2[u], fx, fy, fz, eb, ea);
+        if (valid && bt[u].x >= 0)
+            bonded_term<R, EN>(d, pi, bt[u], b1[u], b2[u], fx, fy, fz, eb, ea, wb);
     if (EN && valid && s == 0) {
         V4<R> v = d.vel[i];
+        mv2[0] = (double)v.x * v.x / (double)v.w;
+        mv2[1] = (double)v.y * v.y / (double)v.w;
+        mv2[2] = (double)v.z * v.z / (double)v.w;
         ek = 0.5 * ((double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z) / (double)v.w;
     }
 #pragma unroll
@@ -287,38 +308,40 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
             if (stats) disp_stats(d, e2, e2_in, integ);
         }
     } else {
-        __shared__ double sh[7][WG / 64];
-        double v[7] = { elj, erf, (double)np, eb, ea, ek, valid ? (double)m1n : 0.0 };
+        __shared__ double sh[16][WG / 64];
+        double v[16] = { elj, erf, (double)np, eb, ea, ek, valid ? (double)m1n : 0.0,
+                         wp[0], wp[1], wp[2], wb[0], wb[1], wb[2], mv2[0], mv2[1], mv2[2] };
         const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
 #pragma unroll
-        for (int q = 0; q < 7; ++q) {
+        for (int q = 0; q < 16; ++q) {
             double x = wave_sum(v[q]);
             if (l == 0) sh[q][w] = x;
         }
         __syncthreads();
-        if (threadIdx.x == 0)
-            for (int q = 0; q < 7; ++q) {
-                double acc = 0.0;
-                for (int ww = 0; ww < WG / 64; ++ww) acc += sh[q][ww];
-                part[8 * blockIdx.x + q] = acc;
-            }
+        if (threadIdx.x < 16) {
+            double acc = 0.0;
+            for (int ww = 0; ww < WG / 64; ++ww) acc += sh[threadIdx.x][ww];
+            part[16 * blockIdx.x + threadIdx.x] = acc;
+        }
     }
 }
 
 // Fixed-order float64 sum of the block partials:
-// out = {lj, rf, bond, angle, kinetic, n_pairs, list entries}
+// out = {lj, rf, bond, angle, kinetic, n_pairs, list entries, virial W_aa (3),
+// sum m v_a^2 (3)}
 __global__ void k_energy_final(const double* __restrict__ p, int nb, double* __restrict__ out)
 {
-    __shared__ double sh[7][256];
+    __shared__ double sh[16][256];
     int t = threadIdx.x;
-    double a[7] = { 0, 0, 0, 0, 0, 0, 0 };
+    double a[16];
+    for (int q = 0; q < 16; ++q) a[q] = 0.0;
     for (int b = t; b < nb; b += 256)
-        for (int q = 0; q < 7; ++q) a[q] += p[8 * b + q];
-    for (int q = 0; q < 7; ++q) sh[q][t] = a[q];
+        for (int q = 0; q < 16; ++q) a[q] += p[16 * b + q];
+    for (int q = 0; q < 16; ++q) sh[q][t] = a[q];
     __syncthreads();
     for (int off = 128; off >= 1; off >>= 1) {
         if (t < off)
-            for (int q = 0; q < 7; ++q) sh[q][t] += sh[q][t + off];
+            for (int q = 0; q < 16; ++q) sh[q][t] += sh[q][t + off];
         __syncthreads();
     }
     if (t == 0) {
@@ -330,6 +353,10 @@ __global__ void k_energy_final(const double* __restrict__ p, int nb, double* __r
         out[4] = sh[5][0];
         out[5] = 0.5 * sh[2][0];
         out[6] = sh[6][0];   // entries walked: pair slots of one force pass
+        for (int a = 0; a < 3; ++a) {
+            out[7 + a] = 0.5 * sh[7 + a][0] + sh[10 + a][0];
+            out[10 + a] = sh[13 + a][0];
+        }
     }
 }
 

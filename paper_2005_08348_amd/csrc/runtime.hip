@@ -65,6 +65,7 @@ namespace {
 
 constexpr double KB = 0.00831446261815324;   // kJ/mol/K
 constexpr double FELEC = 138.935458;         // kJ mol^-1 nm e^-2
+constexpr double BAR = 16.6054;              // bar per kJ mol^-1 nm^-3
 
 struct Status {
     int32_t code;
@@ -559,8 +560,8 @@ static size_t layout(membx_sys* s, Dev<R>& d, Mv& m, char* base)
     s->nbe_blocks = (N * 8 + WG - 1) / WG;
     s->bd_blocks = ((int)h.bmols.size() + 63) / 64;
     s->ke_blocks = (N + WG - 1) / WG;
-    d.red = a.take<double>(8 * (size_t)s->nbe_blocks);
-    d.eout = a.take<double>(8);
+    d.red = a.take<double>(16 * (size_t)s->nbe_blocks);
+    d.eout = a.take<double>(16);
     s->xbuf = a.take<double>(3 * (size_t)N);
     s->obs.leaf = a.take<int>(h.nm);
     s->obs.xy = a.take<double2>(h.nm);
@@ -1284,9 +1285,9 @@ static int32_t energies_impl(membx_sys* s, membx_energy* out)
     Dev<R>& d = dev<R>(s);
     int nnb = launch_nonbonded<R>(d, s->h.lpb, true, d.red, s->st);
     launch_energy_final(d.red, nnb, d.eout, s->st);
-    double e[8];
+    double e[16];
     int fl[NFLAGS];
-    HCK(hipMemcpyAsync(e, d.eout, sizeof(double) * 7, hipMemcpyDeviceToHost, s->st));
+    HCK(hipMemcpyAsync(e, d.eout, sizeof(double) * 13, hipMemcpyDeviceToHost, s->st));
     int32_t rc = read_flags(s, fl);
     if (rc) return rc;
     membx_energy E{};
@@ -1295,6 +1296,12 @@ static int32_t energies_impl(membx_sys* s, membx_energy* out)
     E.total = E.potential + e[4];
     E.n_pairs_in_cutoff = (int64_t)std::llround(e[5]);
     E.n_list_entries = (int64_t)std::llround(e[6]);
+    const double vol = s->h.box[0] * s->h.box[1] * s->h.box[2];
+    for (int a = 0; a < 3; ++a) {
+        E.virial[a] = e[7 + a];
+        E.mv2[a] = e[10 + a];
+        E.pressure[a] = (e[10 + a] + e[7 + a]) / vol * BAR;
+    }
     E.fe_count = s->fe; E.step = s->step; E.batch = s->batch; E.cycle = s->cycle;
     E.n_rebuilds = s->n_rebuilds;
     E.n_skin_violations = (int64_t)fl[FL_SKIN] + fl[FL_SKIN_IN];

@@ -63,7 +63,8 @@ class Energy(C.Structure):
                 ("fe_count", C.c_int64), ("step", C.c_int64), ("batch", C.c_int64),
                 ("cycle", C.c_int64), ("n_rebuilds", C.c_int64),
                 ("n_skin_violations", C.c_int64),
-                ("max_displacement", C.c_double), ("n_list_entries", C.c_int64)]
+                ("max_displacement", C.c_double), ("n_list_entries", C.c_int64),
+                ("virial", C.c_double * 3), ("mv2", C.c_double * 3), ("pressure", C.c_double * 3)]
 
 
 class Request(C.Structure):
@@ -313,6 +314,8 @@ class System:
         if check:
             _check(rc, self.h)
         out = {k: getattr(e, k) for k, _ in Energy._fields_}
+        for k in ("virial", "mv2", "pressure"):
+            out[k] = np.array(out[k][:], dtype=np.float64)
         out["status"] = rc
         return out
 
