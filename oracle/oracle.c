@@ -32,7 +32,7 @@
 
 /* random stream ids (fourth counter word) */
 enum { ST_LANGEVIN = 0, ST_SWAP_DRAW = 1, ST_SWAP_ACCEPT = 2,
-       ST_MDAS_SELECT = 3, ST_MDAS_ACCEPT = 4, ST_VRESCALE = 5 };
+       ST_MDAS_SELECT = 3, ST_MDAS_ACCEPT = 4, ST_VRESCALE = 5, ST_BARO = 6 };
 
 typedef struct {
     /* kinds */
@@ -73,6 +73,9 @@ typedef struct {
      * region of X, 2 in the other region */
     int xmode;
     int* region;             /* [nm] 0 or 1 */
+    /* semi-isotropic pressure coupling every baro_nst steps (0: off) */
+    int baro_nst;
+    double p_ref, kappa, tau_p;   /* kJ mol^-1 nm^-3, its inverse, ps */
 } osys;
 
 /* ------------------------------------------------------------ Philox4x32-10 */
@@ -829,9 +832,61 @@ static void md_one(osys* s, const int* mk_b, double lam)
     else baoab(s, mk_b, lam);
 }
 
+/* ---------------------------------------------------- pressure coupling */
+/* The paper keeps 1 bar with a semi-isotropic barostat (Methods): the box
+ * lengths in the membrane plane (x and y together) and normal to it (z)
+ * respond separately.  Here the box follows stochastic cell rescaling
+ * (Bernetti and Bussi, J. Chem. Phys. 153, 114107, 2020) in two log-strains,
+ * e_A = ln(Lx Ly) and e_z = ln Lz, each an overdamped Langevin process
+ * whose stationary law is p(e_A, e_z) ~ V^(N+1) exp(-(U + P0 V) / kT), the
+ * isothermal-isobaric law of positions with box lengths Lx = Ly and Lz
+ * drawn uniformly in (Lx Ly, Lz).  With P_A = (N kT + (W_xx + W_yy) / 2) / V
+ * and P_z = (N kT + W_zz) / V, one Euler-Maruyama (Ito) step over t = nst dt is
+ *   d e = -(kappa / tau_p) (P0 - P) t + sqrt(2 kappa kT t / (V tau_p)) xi
+ * per strain: the drift -D (d Psi / d e + 1) that makes exp(-Psi) stationary
+ * for the diffusion D = kappa kT / (V tau_p), which falls as 1/V (Psi =
+ * (U + P0 V) / kT - (N + 1) ln V; the Jacobian term and the Ito term of the
+ * V-dependent noise cancel).  x and y scale by exp(d e_A / 2), z by
+ * exp(d e_z), about the
+ * origin, with the box; velocities are left to the thermostat.  xi: Box-
+ * Muller normals from Philox stream 6, block 0, counter = the step index
+ * after the step that triggers the coupling. */
+static void couple_pressure(osys* s)
+{
+    double w[9];
+    o_virial(s, w, 1);
+    const double V = s->box[0] * s->box[1] * s->box[2];
+    const double nkt = (double)s->n * s->kT;
+    const double pa = (nkt + 0.5 * (w[0] + w[1])) / V, pz = (nkt + w[2]) / V;
+    const double t = s->baro_nst * s->dt;
+    uint32_t r[4];
+    draw(s, 0u, s->step, ST_BARO, r);
+    const double xa = normal1(r[0], r[1]), xz = normal1(r[2], r[3]);
+    const double drift = s->kappa / s->tau_p * t, amp = sqrt(2.0 * s->kappa * s->kT * t / (V * s->tau_p));
+    const double dea = -drift * (s->p_ref - pa) + amp * xa;
+    const double dez = -drift * (s->p_ref - pz) + amp * xz;
+    const double mu[3] = { exp(0.5 * dea), exp(0.5 * dea), exp(dez) };
+    for (int i = 0; i < s->n; ++i)
+        for (int a = 0; a < 3; ++a) s->x[3 * i + a] *= mu[a];
+    for (int a = 0; a < 3; ++a) s->box[a] *= mu[a];
+    force_eval(s, NULL, 0.0, s->f);   /* forces of the rescaled configuration */
+    s->n_fe--;                        /* a refresh, not a step */
+}
+
+void o_set_barostat(osys* s, int nst, double p_ref, double kappa, double tau_p)
+{
+    s->baro_nst = nst > 0 ? nst : 0;
+    s->p_ref = p_ref; s->kappa = kappa; s->tau_p = tau_p;
+}
+
+void o_get_box(const osys* s, double* box) { for (int a = 0; a < 3; ++a) box[a] = s->box[a]; }
+
 void o_md_step(osys* s, int nsteps)
 {
-    for (int t = 0; t < nsteps; ++t) md_one(s, NULL, 0.0);
+    for (int t = 0; t < nsteps; ++t) {
+        md_one(s, NULL, 0.0);
+        if (s->baro_nst > 0 && s->step % s->baro_nst == 0) couple_pressure(s);
+    }
 }
 
 /* Capped steepest descent: each bead moves by alpha F_i, shortened to at most

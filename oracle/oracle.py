@@ -87,6 +87,8 @@ def lib():
         L.o_set_ensemble.argtypes = [C.c_void_p, C.c_int, C.c_double, _i32p]
         L.o_set_exchange_regions.argtypes = [C.c_void_p, C.c_int, _i32p]
         L.o_virial.argtypes = [C.c_void_p, _f64p, C.c_int]
+        L.o_set_barostat.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_double]
+        L.o_get_box.argtypes = [C.c_void_p, _f64p]
         L.o_gamma_mt.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_int64, C.c_int, _f64p]
         L.o_vr_alpha.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_int64, C.c_int,
                                  _f64p]
@@ -188,13 +190,23 @@ class Oracle:
             out["force"] = f.reshape(-1, 3)
         return out
 
+    def set_barostat(self, nst, p_ref_bar=1.0, compressibility=3e-4, tau_p=12.0):
+        """semi-isotropic stochastic cell rescaling every nst MD steps (0: off);
+        pressure in bar, compressibility in 1/bar, tau_p in ps"""
+        lib().o_set_barostat(self.h, int(nst), p_ref_bar / BAR, compressibility * BAR, tau_p)
+
+    def box(self):
+        b = np.zeros(3)
+        lib().o_get_box(self.h, b)
+        return b
+
     def virial(self, cells=True):
         """W_aa (kJ/mol), sum m v_a^2 (kJ/mol), the pressure tensor diagonal
         P_aa = (sum m v_a^2 + W_aa) / V in bar, and the sum of |term| of W_aa
         (an error scale for reduced-precision evaluations)"""
         w = np.zeros(9)
         lib().o_virial(self.h, w, int(cells))
-        vol = float(np.prod(self.system.box))
+        vol = float(np.prod(self.box()))
         return dict(w=w[:3].copy(), mv2=w[3:6].copy(), pressure=(w[3:6] + w[:3]) / vol * BAR,
                     w_abs=w[6:].copy())
 

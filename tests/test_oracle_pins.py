@@ -698,3 +698,39 @@ def test_pressure_of_an_ideal_gas(oracle_mod):
     p = np.mean(ps[10:], axis=0)
     ideal = n * KB * 323.0 / 729.0 * oracle_mod.BAR
     assert np.all(np.abs(p / ideal - 1.0) < 0.06), (p, ideal)
+
+
+# --------------------------------------------------- pressure coupling
+def test_barostat_ideal_gas_volume_law(oracle_mod):
+    """Ideal gas of N = 30 beads under the semi-isotropic cell rescaling at
+    P0: the volume must follow Gamma(N + 1, kT / P0), mean (N + 1) kT / P0
+    and variance (N + 1) (kT / P0)^2 (a drift that added kT / V, as for
+    velocity-scaled kinetic pressures, would give shape N + 2, 3% more
+    volume); x and y stay equal.  Coupling every
+    step with dt / tau_p = 0.05: the Euler-Maruyama step widens the law of
+    ln V by the factor 1 / (1 - dt / tau_p) at this compressibility, which
+    the variance bound allows for."""
+    n = 30
+    eps = np.zeros((S.N_TYPES, S.N_TYPES))
+    k = S.Kind("W", [4], [0.0], [], [], -1)
+    rng = np.random.default_rng(17)
+    L0 = 3.0
+    s = S.custom("gas", [k], [0] * n, rng.uniform(0, L0, size=(n, 3)), [L0, L0, L0], eps, seed=21)
+    s.gamma = 2.0
+    kT = KB * 323.0
+    p0 = (n + 1) * kT / 27.0                          # law mean 27 nm^3 (box ~3 nm)
+    p0_bar = p0 * oracle_mod.BAR
+    o = oracle_mod.Oracle(s)
+    # the ideal gas's own compressibility 1 / P0, tau_p = 0.4 ps
+    o.set_barostat(1, p_ref_bar=p0_bar, compressibility=1.0 / p0_bar, tau_p=0.4)
+    vols = []
+    for _ in range(4000):
+        o.md_step(25)
+        b = o.box()
+        assert abs(b[0] - b[1]) < 1e-12 * b[0]
+        vols.append(b[0] * b[1] * b[2])
+    v = np.asarray(vols[200:])
+    mean, var = (n + 1) * kT / p0, (n + 1) * (kT / p0) ** 2
+    print("V mean %.3f (law %.3f), var %.3f (law %.3f)" % (v.mean(), mean, v.var(), var))
+    assert abs(v.mean() / mean - 1.0) < 0.01
+    assert abs(v.var() / (var / (1 - 0.05)) - 1.0) < 0.12
