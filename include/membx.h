@@ -293,6 +293,28 @@ int32_t membx_autotune(membx_sys* sys, int32_t n_steps, double* skin, int32_t* r
  * Synchronizes.  E_INVAL (mode or a region out of range). */
 int32_t membx_set_exchange_regions(membx_sys* sys, int32_t mode, const int32_t* region);
 
+/* Pressure coupling of membx_md_step (the paper's semi-isotropic 1 bar
+ * barostat, Methods), by stochastic cell rescaling (Bernetti and Bussi,
+ * J. Chem. Phys. 153, 114107, 2020) in place of the paper's Parrinello-
+ * Rahman dynamics: after every MD step whose index is a multiple of nst,
+ * e_A = ln(Lx Ly) and e_z = ln Lz each take one Ito step over t = nst dt,
+ *   d e = -(kappa / tau_p) (P0 - P) t + sqrt(2 kappa kT t / (V tau_p)) xi,
+ * with P_A = (N kT + (W_xx + W_yy) / 2) / V, P_z = (N kT + W_zz) / V from
+ * the virial of membx_energy, kappa = compressibility (1/bar), P0 =
+ * p_ref_bar, tau_p in ps, xi from Philox stream 6 with the step index as
+ * counter; x and y scale by exp(d e_A / 2), z by exp(d e_z), positions
+ * about the origin; the list is rebuilt and the forces refreshed.  The
+ * stationary law is the isothermal-isobaric one.  MDAS cycles and exchange
+ * trials run at the current box.  nst <= 0 turns coupling off (default).
+ * Under coupling, step sequences are not replayed from HIP graphs.
+ * Errors: E_INVAL (arguments); membx_md_step returns E_STATE if an axis
+ * shrinks below three list radii. */
+int32_t membx_set_barostat(membx_sys* sys, int32_t nst, double p_ref_bar, double compressibility,
+                           double tau_p);
+
+/* Current box lengths (nm), host box[3]. */
+int32_t membx_get_box(membx_sys* sys, double* box);
+
 /* Ensemble of the MD steps (membx_md_step and the steps of MDAS cycles).
  * ensemble 0 (default): Langevin BAOAB with the friction of the descriptor.
  * ensemble 1: the paper's thermostat (Methods), stochastic velocity

@@ -257,6 +257,57 @@ __global__ __launch_bounds__(WG) void k_vr_scale(Dev<R> d, VrBuf vr)
     d.vel[i] = v;
 }
 
+// ------------------------------------------------- pressure coupling
+// Semi-isotropic stochastic cell rescaling (the paper's 1 bar barostat,
+// Methods; Bernetti and Bussi 2020): the log-strains e_A = ln(Lx Ly) and
+// e_z = ln Lz each take one Ito Euler-Maruyama step over t,
+//   d e = -(kappa / tau_p) (P0 - P) t + sqrt(2 kappa kT t / (V tau_p)) xi,
+// P_A = (N kT + (W_xx + W_yy) / 2) / V, P_z = (N kT + W_zz) / V, from the
+// virial of the energy pass (eout[7..9]); xi from Philox stream 6, block 0,
+// counter = the step index.  One thread writes the scale factors
+// {exp(d e_A / 2), exp(d e_A / 2), exp(d e_z)} to mu[0..2].
+template <typename R>
+__global__ void k_baro(Dev<R> d, const double* __restrict__ eout, double* __restrict__ mu,
+                       double p0, double kappa, double tau_p, double t, double vol)
+{
+    if (threadIdx.x != 0) return;
+    const double nkt = (double)d.N * d.kTd;
+    const double pa = (nkt + 0.5 * (eout[7] + eout[8])) / vol, pz = (nkt + eout[9]) / vol;
+    const uint4 w = draw(d.seed, 0u, d.ctr[CT_STEP], ST_BARO);
+    const double xa = vr_normal(w.x, w.y), xz = vr_normal(w.z, w.w);
+    const double drift = kappa / tau_p * t, amp = sqrt(2.0 * kappa * d.kTd * t / (vol * tau_p));
+    const double dea = -drift * (p0 - pa) + amp * xa;
+    const double dez = -drift * (p0 - pz) + amp * xz;
+    mu[0] = exp(0.5 * dea);
+    mu[1] = exp(0.5 * dea);
+    mu[2] = exp(dez);
+}
+
+// positions scaled about the origin (slots; the rebuild that follows wraps
+// them and places the images)
+template <typename R>
+__global__ __launch_bounds__(WG) void k_scale_pos(Dev<R> d, double mx, double my, double mz)
+{
+    const int i = blockIdx.x * WG + threadIdx.x;
+    if (i >= d.N) return;
+    V4<R> p = d.posq[i];
+    p.x = (R)(mx * (double)p.x); p.y = (R)(my * (double)p.y); p.z = (R)(mz * (double)p.z);
+    d.posq[i] = p;
+}
+
+template <typename R>
+void launch_baro(const Dev<R>& d, const double* eout, double* mu, double p0, double kappa,
+                 double tau_p, double t, double vol, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_baro<R>, dim3(1), dim3(64), 0, st, d, eout, mu, p0, kappa, tau_p, t, vol);
+}
+template <typename R>
+void launch_scale_pos(const Dev<R>& d, const double* mu, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_scale_pos<R>, dim3((d.N + WG - 1) / WG), dim3(WG), 0, st, d, mu[0], mu[1],
+                       mu[2]);
+}
+
 // the previous step's scaling folded into this step's B-A-O-A (the O part is
 // off under this thermostat): v <- alpha_g v, then the kick and drifts
 template <typename R>
@@ -305,6 +356,9 @@ void launch_vr_kick_drift(const Dev<R>& d, const VrBuf& vr, R kick, long long st
     template void launch_vrescale<R>(const Dev<R>&, const VrBuf&, R, long long, double, \
                                      hipStream_t);                                   \
     template void launch_vr_scale<R>(const Dev<R>&, const VrBuf&, hipStream_t);      \
+    template void launch_baro<R>(const Dev<R>&, const double*, double*, double, double, double, \
+                                 double, double, hipStream_t);                       \
+    template void launch_scale_pos<R>(const Dev<R>&, const double*, hipStream_t);    \
     template void launch_vr_kick_drift<R>(const Dev<R>&, const VrBuf&, R, long long, int, \
                                           hipStream_t);                              \
     template void launch_kick_drift<R>(const Dev<R>&, R, long long, int, hipStream_t); \

@@ -17,7 +17,7 @@ constexpr int MAXBT = 8;         // bonded terms per bead
 
 // random streams (fourth Philox counter word)
 enum { ST_LANGEVIN = 0, ST_SWAP_DRAW = 1, ST_SWAP_ACCEPT = 2, ST_MDAS_SELECT = 3,
-       ST_MDAS_ACCEPT = 4, ST_VRESCALE = 5 };
+       ST_MDAS_ACCEPT = 4, ST_VRESCALE = 5, ST_BARO = 6 };
 
 // device flags
 // FL_SKIN counts (bead, step) events beyond skin/2 since the last reset;

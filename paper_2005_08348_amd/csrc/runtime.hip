@@ -31,6 +31,10 @@ template <typename R>
 void launch_vrescale(const Dev<R>&, const VrBuf&, R, long long, double, hipStream_t);
 template <typename R> void launch_vr_scale(const Dev<R>&, const VrBuf&, hipStream_t);
 template <typename R>
+void launch_baro(const Dev<R>&, const double*, double*, double, double, double, double, double,
+                 hipStream_t);
+template <typename R> void launch_scale_pos(const Dev<R>&, const double*, hipStream_t);
+template <typename R>
 void launch_vr_kick_drift(const Dev<R>&, const VrBuf&, R, long long, int, hipStream_t);
 template <typename R> void launch_sd_step(const Dev<R>&, double, double, hipStream_t);
 template <typename R> void launch_export(const Dev<R>&, const V4<R>*, double*, hipStream_t);
@@ -125,6 +129,11 @@ struct Host {
     int prune;        // force passes per inner-list prune; 0: no inner list
     int nc[3], ncell, ne[3], next;   // cell grid at the current skin
     int ncell_cap, next_cap;          // array sizes (grid at the smallest skin)
+    int nc_cap[3] = { 0, 0, 0 };      // its cells per axis: the grid never exceeds them
+    // pressure coupling every baro_nst MD steps (0: off): P0 (kJ mol^-1 nm^-3),
+    // compressibility (its inverse), tau_p (ps)
+    int baro_nst = 0;
+    double p_ref = 0.0, kappa = 0.0, tau_p = 0.0;
     int hnc[3], hcells, mh;
     int aff_cap;
 };
@@ -151,6 +160,7 @@ static void set_grid(Host& h, double skin)
     h.ncell = 1;
     for (int a = 0; a < 3; ++a) {
         h.nc[a] = std::max(3, (int)std::floor(h.box[a] / rl));
+        if (h.nc_cap[a] > 0) h.nc[a] = std::min(h.nc[a], h.nc_cap[a]);   // box grown: coarser cells
         h.ne[a] = h.nc[a] + 1;
         h.ncell *= h.nc[a];
     }
@@ -269,6 +279,7 @@ Status check_desc(const membx_desc* d, Host& h)
     set_grid(h, std::min(h.skin, 0.1));
     h.ncell_cap = h.ncell;
     h.next_cap = h.next;
+    for (int a = 0; a < 3; ++a) h.nc_cap[a] = h.nc[a];
     set_grid(h, h.skin_max);
     double vol = h.box[0] * h.box[1] * h.box[2];
     double rho = h.N / vol;
@@ -779,13 +790,14 @@ static void steps_seq(membx_sys* s, long long n, const Alch* alch, bool launch =
 }
 
 template <typename R>
-static int32_t md_steps(membx_sys* s, long long n)
+static int32_t md_run(membx_sys* s, long long n)
 {
     if (n <= 0) return MEMBX_OK;
     const long long chunk = 32;
     while (n > 0) {
         long long k = std::min(n, chunk);
-        if (s->graphs && !s->timing) {
+        // graphs hold the box in their kernel arguments: not under pressure coupling
+        if (s->graphs && !s->timing && s->h.baro_nst == 0) {
             auto key = std::make_tuple(k, s->since, 2 + s->par + 2 * (s->sp + 1));
             auto it = s->gcache.find(key);
             const int since0 = s->since, par0 = s->par, sp0 = s->sp;
@@ -822,6 +834,87 @@ static int32_t md_steps(membx_sys* s, long long n)
         s->step += k;
         s->fe += k;
         n -= k;
+    }
+    return MEMBX_OK;
+}
+
+template <typename R> static void refresh_forces(membx_sys* s);
+template <typename R> static void reset_disp(membx_sys* s);
+
+// Box change to L' = mu L (x, y, z): positions scaled about the origin, the
+// cell grid re-planned within the array capacity (cells grow if the box
+// does), the box constants of every kernel updated, the list rebuilt and the
+// forces refreshed.  E_STATE if an axis fell below three list radii.
+template <typename R>
+static int32_t rescale_box(membx_sys* s, const double mu[3])
+{
+    Host& h = s->h;
+    Dev<R>& d = dev<R>(s);
+    Mv& m = s->mv;
+    double nb[3];
+    for (int a = 0; a < 3; ++a) nb[a] = h.box[a] * mu[a];
+    const double rl = h.rc + h.skin;
+    for (int a = 0; a < 3; ++a)
+        if (!(nb[a] >= 3.0 * rl)) return fail(s, MEMBX_E_STATE, "box below three list radii");
+    launch_scale_pos<R>(d, mu, s->st);
+    for (int a = 0; a < 3; ++a) h.box[a] = nb[a];
+    set_grid(h, h.skin);
+    for (int k = 0; k < 3; ++k) {
+        d.L[k] = (R)h.box[k]; d.halfL[k] = (R)(0.5 * h.box[k]); d.Ld[k] = h.box[k];
+        d.nc[k] = h.nc[k]; d.ne[k] = h.ne[k];
+        d.inv_edge[k] = (R)(h.nc[k] / h.box[k]);
+    }
+    d.ncell = h.ncell; d.next = h.next;
+    set_list_band(d, h);
+    h.hcells = 1;
+    for (int a = 0; a < 3; ++a) {
+        h.hnc[a] = std::max(3, (int)std::floor(h.box[a] / h.rc));
+        h.hcells *= h.hnc[a];
+        m.hnc[a] = h.hnc[a];
+        m.hinv[a] = h.hnc[a] / h.box[a];
+    }
+    m.hcells = h.hcells;
+    HCK(hipMemsetAsync(d.cell_cnt, 0, sizeof(int) * h.ncell_cap, s->st));
+    for (auto& kv : s->gcache) (void)hipGraphExecDestroy(kv.second);
+    s->gcache.clear();
+    refresh_forces<R>(s);
+    reset_disp<R>(s);
+    return MEMBX_OK;
+}
+
+// One pressure coupling at the current state: the energy pass gives the
+// virial, k_baro the scale factors (device, from the step counter), the
+// host applies them.  Synchronizes.
+template <typename R>
+static int32_t couple_pressure(membx_sys* s)
+{
+    Dev<R>& d = dev<R>(s);
+    const Host& h = s->h;
+    const int nnb = launch_nonbonded<R>(d, h.lpb, true, d.red, s->st);
+    launch_energy_final(d.red, nnb, d.eout, s->st);
+    const double vol = h.box[0] * h.box[1] * h.box[2];
+    launch_baro<R>(d, d.eout, d.eout + 13, h.p_ref, h.kappa, h.tau_p, h.baro_nst * h.dt, vol, s->st);
+    double mu[3];
+    HCK(hipMemcpyAsync(mu, d.eout + 13, sizeof(mu), hipMemcpyDeviceToHost, s->st));
+    HCK(hipStreamSynchronize(s->st));
+    if (!(std::isfinite(mu[0]) && std::isfinite(mu[2])))
+        return fail(s, MEMBX_E_NONFINITE, "non-finite pressure");
+    return rescale_box<R>(s, mu);
+}
+
+// n MD steps; under pressure coupling the run stops after every step whose
+// index is a multiple of baro_nst to couple
+template <typename R>
+static int32_t md_steps(membx_sys* s, long long n)
+{
+    const int nst = s->h.baro_nst;
+    if (nst <= 0) return md_run<R>(s, n);
+    while (n > 0) {
+        const long long k = std::min(n, (long long)(nst - s->step % nst));
+        int32_t rc = md_run<R>(s, k);
+        if (rc) return rc;
+        n -= k;
+        if (s->step % nst == 0 && (rc = couple_pressure<R>(s))) return rc;
     }
     return MEMBX_OK;
 }
@@ -1784,6 +1877,27 @@ int32_t membx_set_ensemble(membx_sys* s, int32_t ensemble, double tau_t, const i
     return rc;
 }
 
+int32_t membx_set_barostat(membx_sys* s, int32_t nst, double p_ref_bar, double compressibility,
+                           double tau_p)
+{
+    if (!s) return MEMBX_E_INVAL;
+    if (nst > 0 && !(std::isfinite(p_ref_bar) && compressibility > 0.0 && tau_p > 0.0 &&
+                     std::isfinite(compressibility) && std::isfinite(tau_p)))
+        return fail(s, MEMBX_E_INVAL, "barostat needs finite p_ref, compressibility > 0, tau_p > 0");
+    s->h.baro_nst = nst > 0 ? nst : 0;
+    s->h.p_ref = p_ref_bar / BAR;
+    s->h.kappa = compressibility * BAR;
+    s->h.tau_p = tau_p;
+    return MEMBX_OK;
+}
+
+int32_t membx_get_box(membx_sys* s, double* box)
+{
+    if (!s || !box) return MEMBX_E_INVAL;
+    for (int a = 0; a < 3; ++a) box[a] = s->h.box[a];
+    return MEMBX_OK;
+}
+
 int32_t membx_set_graphs(membx_sys* s, int32_t enable)
 {
     if (!s) return MEMBX_E_INVAL;
@@ -1895,7 +2009,10 @@ int32_t membx_autotune(membx_sys* s, int32_t n_steps, double* skin, int32_t* reb
     int32_t rc = begin(s);
     if (rc) return rc;
     Tune t{};
+    const int nst0 = s->h.baro_nst;   // the timing runs keep the box
+    s->h.baro_nst = 0;
     rc = DISPATCH(s, autotune_impl, s, n_steps, &t);
+    s->h.baro_nst = nst0;
     if (!rc) rc = end(s);
     if (rc) return rc;
     if (skin) *skin = t.skin;

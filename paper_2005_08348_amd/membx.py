@@ -124,6 +124,8 @@ def lib():
             "membx_set_graphs": ([vp, i32], i32),
             "membx_set_ensemble": ([vp, i32, dp, vp], i32),
             "membx_set_exchange_regions": ([vp, i32, vp], i32),
+            "membx_set_barostat": ([vp, i32, dp, dp, dp], i32),
+            "membx_get_box": ([vp, vp], i32),
             "membx_kernel_timing": ([vp, i32], i32),
             "membx_kernel_time": ([vp, C.POINTER(i64), C.POINTER(dp)], i32),
             "membx_kernel_bench": ([vp, i32, C.POINTER(dp)], i32),
@@ -369,6 +371,16 @@ class System:
         return lib().membx_status(self.h)
 
     # --------------------------------------------------------------- tuning
+    def set_barostat(self, nst, p_ref_bar=1.0, compressibility=3e-4, tau_p=12.0):
+        """semi-isotropic pressure coupling every nst MD steps (0: off)"""
+        _check(lib().membx_set_barostat(self.h, int(nst), float(p_ref_bar), float(compressibility),
+                                        float(tau_p)), self.h)
+
+    def box(self):
+        b = np.zeros(3)
+        _check(lib().membx_get_box(self.h, b.ctypes.data_as(C.c_void_p)), self.h)
+        return b
+
     def set_exchange_regions(self, mode, region=None):
         """exchange partners: 0 anywhere in X's family (other kind), 1 other
         kind within X's region, 2 any family member in the other region;
