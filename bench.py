@@ -314,6 +314,17 @@ def main():
                               "temperature_K_langevin_before": t_lang,
                               "skin_violations": evr["n_skin_violations"],
                               "vs_langevin": (kvr / tvr) / steps_s}
+        # the paper's full ensemble: plus the semi-isotropic barostat at 1 bar
+        # (tau_p 12 ps, compressibility 3e-4 / bar), coupling every 10 steps
+        gm.set_barostat(10, p_ref_bar=1.0, compressibility=3e-4, tau_p=12.0)
+        gm.md_step(20)
+        tnpt = timed(lambda: gm.md_step(kvr), sync)
+        enpt = gm.energies(check=False)
+        result["vrescale"]["npt"] = {"md_steps_per_s": kvr / tnpt, "coupling_interval": 10,
+                                     "box_nm": [float(x) for x in gm.box()],
+                                     "pressure_bar": [float(x) for x in enpt["pressure"]],
+                                     "skin_violations": enpt["n_skin_violations"]}
+        gm.set_barostat(0)
         gm.set_ensemble(0)
         gm.close(); del gm
         torch.cuda.empty_cache()
