@@ -76,6 +76,10 @@ typedef struct {
     /* semi-isotropic pressure coupling every baro_nst steps (0: off) */
     int baro_nst;
     double p_ref, kappa, tau_p;   /* kJ mol^-1 nm^-3, its inverse, ps */
+    /* MDAS lambda path: 0 linear in the end-state energies (Eq. 2),
+     * 1 soft-core LJ of the changed beads (Eq. 4, shift sc_delta nm^2) */
+    int mdas_path;
+    double sc_delta;
 } osys;
 
 /* ------------------------------------------------------------ Philox4x32-10 */
@@ -668,10 +672,104 @@ long o_pairset(osys* s, double rlist, int* out, long cap, int use_cells)
 }
 
 /* ------------------------------------------------------------- dynamics */
+/* ---------------------------------------------------- soft-core lambda path */
+/* Eq. 4 with sigma^2 / (r^2 + delta (1 - mu)) as the base (the printed
+ * formula's sigma over r^2 read dimensionally), written with c6 = 4 eps
+ * sigma^6, c12 = 4 eps sigma^12: V = mu (c12 / s^6 - c6 / s^3), s = r^2 +
+ * delta (1 - mu); at mu = 1 the plain 12-6 form, at mu = 0 nothing, finite
+ * at r = 0 for mu < 1.  As the paper's Martini runs shift the LJ potential to
+ * zero at the cutoff, the soft-core term is shifted by its own value at r_c
+ * (the plain shifted form at mu = 1).  fscal = -dV/dr / r. */
+static void sc_lj(double c6, double c12, double r2, double mu, double delta, double rc2,
+                  double* v, double* fscal)
+{
+    double sh = delta * (1.0 - mu);
+    double s3 = r2 + sh, i3 = 1.0 / (s3 * s3 * s3);
+    double c3 = rc2 + sh, ic3 = 1.0 / (c3 * c3 * c3);
+    *v = mu * (c12 * i3 * i3 - c6 * i3) - mu * (c12 * ic3 * ic3 - c6 * ic3);
+    *fscal = mu * (12.0 * c12 * i3 * i3 - 6.0 * c6 * i3) / s3;
+}
+
+void o_sc_lj(double c6, double c12, double r2, double mu, double delta, double rc, double* out)
+{
+    sc_lj(c6, c12, r2, mu, delta, rc * rc, &out[0], &out[1]);
+}
+
+/* The alchemical state at lambda on the soft-core path, for end-state kinds
+ * mk_b: a pair with no changed bead (same type and charge in both states)
+ * keeps its plain terms; a pair with a changed bead takes the A-state LJ at
+ * mu = 1 - lambda and the B-state LJ at mu = lambda, both soft-core, and the
+ * reaction field of the charge product (1 - lambda) q_i q_j |A + lambda
+ * q_i q_j |B.  Bonded terms are those of the family, common to both states.
+ * U_0 = U_A and U_1 = U_B exactly. */
+typedef struct { const int* mk_b; const char* chg; double lam; double* f; double u; } sc_ctx;
+
+static void sc_pair(osys* s, int i, int j, const double d[3], double r2, void* vctx)
+{
+    sc_ctx* c = (sc_ctx*)vctx;
+    double v, fs;
+    if (!c->chg[i] && !c->chg[j]) {
+        double vlj, vrf;
+        pair_term(s, btype_k(s, s->mkind, i), btype_k(s, s->mkind, j),
+                  bq_k(s, s->mkind, i), bq_k(s, s->mkind, j), r2, &vlj, &vrf, &fs);
+        v = vlj + vrf;
+    } else {
+        const int ta = btype_k(s, s->mkind, i), tb = btype_k(s, s->mkind, j);
+        const int ua = btype_k(s, c->mk_b, i), ub = btype_k(s, c->mk_b, j);
+        double va, fa, vb, fb;
+        sc_lj(s->c6[ta * s->nt + tb], s->c12[ta * s->nt + tb], r2, 1.0 - c->lam, s->sc_delta,
+              s->rc * s->rc, &va, &fa);
+        sc_lj(s->c6[ua * s->nt + ub], s->c12[ua * s->nt + ub], r2, c->lam, s->sc_delta,
+              s->rc * s->rc, &vb, &fb);
+        const double qq = (1.0 - c->lam) * bq_k(s, s->mkind, i) * bq_k(s, s->mkind, j)
+                        + c->lam * bq_k(s, c->mk_b, i) * bq_k(s, c->mk_b, j);
+        const double r = sqrt(r2), pre = s->fpre * qq;
+        v = va + vb + pre * (1.0 / r + s->krf * r2 - s->crf);
+        fs = fa + fb + pre * (1.0 / (r2 * r) - 2.0 * s->krf);
+    }
+    c->u += v;
+    if (c->f)
+        for (int a = 0; a < 3; ++a) { c->f[3 * i + a] += fs * d[a]; c->f[3 * j + a] -= fs * d[a]; }
+}
+
+static double sc_energy_forces(osys* s, const int* mk_b, double lam, double* f)
+{
+    char* chg = (char*)calloc(s->n, 1);
+    for (int i = 0; i < s->n; ++i)
+        chg[i] = btype_k(s, s->mkind, i) != btype_k(s, mk_b, i) || bq_k(s, s->mkind, i) != bq_k(s, mk_b, i);
+    if (f) memset(f, 0, sizeof(double) * 3 * s->n);
+    sc_ctx c = { mk_b, chg, lam, f, 0.0 };
+    for_pairs(s, s->rc, 1, sc_pair, &c);
+    double eb, ea;
+    bonded(s, s->mkind, f, &eb, &ea);
+    free(chg);
+    return c.u + eb + ea;
+}
+
+/* U at lambda on the soft-core path for exchanging the given pairs */
+double o_sc_energy(osys* s, int n_pairs, const int* pairs, double lam)
+{
+    int* mk_b = (int*)malloc(sizeof(int) * s->nm);
+    memcpy(mk_b, s->mkind, sizeof(int) * s->nm);
+    for (int p = 0; p < n_pairs; ++p) {
+        int X = pairs[2 * p], Y = pairs[2 * p + 1];
+        mk_b[X] = s->mkind[Y]; mk_b[Y] = s->mkind[X];
+    }
+    double u = sc_energy_forces(s, mk_b, lam, NULL);
+    free(mk_b);
+    return u;
+}
+
+void o_set_mdas_path(osys* s, int path, double delta) { s->mdas_path = path; s->sc_delta = delta; }
+
 static double force_eval(osys* s, const int* mk_b, double lam, double* f)
 {
     /* F(lam) = (1-lam) F_A + lam F_B ; returns U(lam) */
     double e[4];
+    if (mk_b && s->mdas_path == 1) {
+        s->n_fe++;
+        return sc_energy_forces(s, mk_b, lam, f);
+    }
     if (!mk_b || lam == 0.0) {
         energy_forces(s, s->mkind, f, e, 1);
         s->n_fe++;
@@ -1125,13 +1223,17 @@ int o_mdas_cycle(osys* s, int n_pairs, int K, int M, double* w_out, int* acc_out
     for (int k = 1; k <= K; ++k) {
         for (int m = 0; m < M; ++m) md_one(s, mk_b, lam);
         double lam_new = (double)k / (double)K;
-        double ea[4], eb[4];
-        energy_forces(s, s->mkind, NULL, ea, 1);
-        energy_forces(s, mk_b, NULL, eb, 1);
-        double ua = ea[0] + ea[1] + ea[2] + ea[3], ub = eb[0] + eb[1] + eb[2] + eb[3];
-        double u_new = (1.0 - lam_new) * ua + lam_new * ub;
-        double u_old = (1.0 - lam) * ua + lam * ub;
-        work += u_new - u_old;
+        if (s->mdas_path == 1) {
+            work += sc_energy_forces(s, mk_b, lam_new, NULL) - sc_energy_forces(s, mk_b, lam, NULL);
+        } else {
+            double ea[4], eb[4];
+            energy_forces(s, s->mkind, NULL, ea, 1);
+            energy_forces(s, mk_b, NULL, eb, 1);
+            double ua = ea[0] + ea[1] + ea[2] + ea[3], ub = eb[0] + eb[1] + eb[2] + eb[3];
+            double u_new = (1.0 - lam_new) * ua + lam_new * ub;
+            double u_old = (1.0 - lam) * ua + lam * ub;
+            work += u_new - u_old;
+        }
         lam = lam_new;
         if (M > 0) { force_eval(s, mk_b, lam, s->f); s->n_fe--; }
     }

@@ -89,6 +89,10 @@ def lib():
         L.o_virial.argtypes = [C.c_void_p, _f64p, C.c_int]
         L.o_set_barostat.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_double]
         L.o_get_box.argtypes = [C.c_void_p, _f64p]
+        L.o_sc_lj.argtypes = [C.c_double] * 6 + [_f64p]
+        L.o_sc_energy.argtypes = [C.c_void_p, C.c_int, _i32p, C.c_double]
+        L.o_sc_energy.restype = C.c_double
+        L.o_set_mdas_path.argtypes = [C.c_void_p, C.c_int, C.c_double]
         L.o_gamma_mt.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_int64, C.c_int, _f64p]
         L.o_vr_alpha.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_int64, C.c_int,
                                  _f64p]
@@ -110,6 +114,13 @@ def gauss3(words):
     g = np.zeros(3)
     lib().o_gauss3(np.asarray(words, dtype=np.uint32), g)
     return g
+
+
+def sc_lj(c6, c12, r2, mu, delta, rc):
+    """the soft-core LJ term of one pair: (energy, -dV/dr / r)"""
+    out = np.zeros(2)
+    lib().o_sc_lj(c6, c12, r2, mu, delta, rc, out)
+    return out[0], out[1]
 
 
 def _i32(a):
@@ -194,6 +205,15 @@ class Oracle:
         """semi-isotropic stochastic cell rescaling every nst MD steps (0: off);
         pressure in bar, compressibility in 1/bar, tau_p in ps"""
         lib().o_set_barostat(self.h, int(nst), p_ref_bar / BAR, compressibility * BAR, tau_p)
+
+    def set_mdas_path(self, path, delta=0.05):
+        """MDAS lambda path: 0 linear (Eq. 2), 1 soft-core LJ (Eq. 4, delta nm^2)"""
+        lib().o_set_mdas_path(self.h, int(path), float(delta))
+
+    def sc_energy(self, pairs, lam):
+        """U at lambda on the soft-core path for exchanging pairs [(X, Y), ...]"""
+        pr = _i32(pairs)
+        return lib().o_sc_energy(self.h, len(pr) // 2, pr, float(lam))
 
     def box(self):
         b = np.zeros(3)

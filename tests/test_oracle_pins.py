@@ -734,3 +734,76 @@ def test_barostat_ideal_gas_volume_law(oracle_mod):
     print("V mean %.3f (law %.3f), var %.3f (law %.3f)" % (v.mean(), mean, v.var(), var))
     assert abs(v.mean() / mean - 1.0) < 0.01
     assert abs(v.var() / (var / (1 - 0.05)) - 1.0) < 0.12
+
+
+# ------------------------------------------- soft-core lambda path (Eq. 4)
+def _c6c12(eps, sig):
+    return 4 * eps * sig ** 6, 4 * eps * sig ** 12
+
+
+def test_soft_core_reduces_to_lj(oracle_mod):
+    """mu = 1: the shifted 12-6 form of the pair term; mu = 0: nothing."""
+    eps, sig = 3.5, 0.47
+    c6, c12 = _c6c12(eps, sig)
+    s = S.make("c0")
+    o = oracle_mod.Oracle(s)
+    ti = tj = int(np.argmin(np.abs(s.eps.diagonal() - eps)))
+    eps = s.eps[ti, tj]; sig = s.sigma[ti, tj]
+    c6, c12 = _c6c12(eps, sig)
+    for r in (0.45, 0.6, 0.95):
+        v, f = oracle_mod.sc_lj(c6, c12, r * r, 1.0, 0.05, s.rc)
+        vlj, vrf, fs = o.pair_term(ti, tj, 0.0, 0.0, r * r)
+        assert abs(v - vlj) < 1e-12 * max(1.0, abs(vlj)) and abs(f - fs) < 1e-10 * max(1.0, abs(fs))
+        assert oracle_mod.sc_lj(c6, c12, r * r, 0.0, 0.05, s.rc) == (0.0, 0.0)
+
+
+@pytest.mark.parametrize("mu", [0.2, 0.7])
+def test_soft_core_force_and_origin(oracle_mod, mu):
+    """fscal = -dV/dr / r (central difference), V(r_c) = 0, and at r = 0 the
+    finite value mu (c12 / (delta (1 - mu))^6 - c6 / (delta (1 - mu))^3)
+    minus the shift: no end-point singularity for mu < 1."""
+    c6, c12 = _c6c12(5.6, 0.47)
+    delta, rc = 0.05, 1.1
+    for r in (0.1, 0.4, 0.8):
+        h = 1e-6
+        vp, _ = oracle_mod.sc_lj(c6, c12, (r + h) ** 2, mu, delta, rc)
+        vm, _ = oracle_mod.sc_lj(c6, c12, (r - h) ** 2, mu, delta, rc)
+        _, f = oracle_mod.sc_lj(c6, c12, r * r, mu, delta, rc)
+        assert abs(f * r + (vp - vm) / (2 * h)) < 1e-6 * max(1.0, abs(f * r))
+    assert abs(oracle_mod.sc_lj(c6, c12, rc * rc, mu, delta, rc)[0]) < 1e-15
+    s0 = delta * (1 - mu)
+    sc = rc * rc + s0
+    v0 = mu * (c12 / s0 ** 6 - c6 / s0 ** 3) - mu * (c12 / sc ** 6 - c6 / sc ** 3)
+    assert abs(oracle_mod.sc_lj(c6, c12, 0.0, mu, delta, rc)[0] - v0) < 1e-9 * abs(v0)
+
+
+@pytest.mark.parametrize("name", ["c0", "mix"])
+def test_soft_core_path_end_states(oracle_mod, name):
+    """With two exchanged pairs (C0: A <-> B changes bead types; mix: A <-> D
+    changes a head charge): U_0 = U_A and U_1 = U_B of the full system; a
+    frozen MDAS cycle on the soft-core path gives the same work U_B - U_A as
+    the linear path, for any K."""
+    c0 = S.make(name)
+    o = oracle_mod.Oracle(c0)
+    r = o.mdas_cycle(2, 1, 0)            # selects two pairs; frozen, so the state is kept or swapped
+    pairs = r["pairs"]
+    o = oracle_mod.Oracle(c0)
+    ua = o.energy_forces(forces=False)["potential"]
+    mk = c0.mol_kind.copy()
+    for x, y in pairs:
+        mk[x], mk[y] = mk[y], mk[x]
+    ob = oracle_mod.Oracle(c0)
+    ob.set_state(mol_kind=mk)
+    ub = ob.energy_forces(forces=False)["potential"]
+    assert abs(o.sc_energy(pairs, 0.0) - ua) < 1e-9 * abs(ua)
+    assert abs(o.sc_energy(pairs, 1.0) - ub) < 1e-9 * abs(ub)
+    mid = o.sc_energy(pairs, 0.5)
+    assert np.isfinite(mid)
+    for K in (1, 5):
+        lin = oracle_mod.Oracle(c0).mdas_cycle(2, K, 0)
+        osc = oracle_mod.Oracle(c0)
+        osc.set_mdas_path(1, 0.05)
+        sc = osc.mdas_cycle(2, K, 0)
+        assert np.array_equal(lin["pairs"], sc["pairs"])
+        assert abs(sc["work"] - (ub - ua)) < 1e-8 * max(1.0, abs(ua))
+        assert abs(sc["work"] - lin["work"]) < 1e-8 * max(1.0, abs(ua))
