@@ -312,6 +312,18 @@ int32_t membx_set_exchange_regions(membx_sys* sys, int32_t mode, const int32_t* 
 int32_t membx_set_barostat(membx_sys* sys, int32_t nst, double p_ref_bar, double compressibility,
                            double tau_p);
 
+/* Lambda path of MDAS cycles.  path 0 (default): linear in the end-state
+ * energies, U(lambda) = (1 - lambda) U_A + lambda U_B (Eq. 2), forces from
+ * one pass plus lambda (F_B - F_A).  path 1: the soft-core path of Eq. 4
+ * (shift delta nm^2, e.g. 0.05 = the paper's 5 A^2): each pair with a
+ * changed bead takes the A-state LJ at mu = 1 - lambda and the B-state LJ
+ * at mu = lambda, mu (c12 / s^6 - c6 / s^3) with s = r^2 + delta (1 - mu),
+ * shifted to zero at the cutoff, and the reaction field of the
+ * interpolated charge product; the work sums U(lambda_k) - U(lambda_k-1)
+ * of those pairs (float64).  The end states are the same on both paths.
+ * Errors: E_INVAL (path, delta). */
+int32_t membx_set_mdas_path(membx_sys* sys, int32_t path, double delta);
+
 /* Current box lengths (nm), host box[3]. */
 int32_t membx_get_box(membx_sys* sys, double* box);
 

@@ -762,6 +762,137 @@ __global__ __launch_bounds__(WG) void k_dforce(Dev<R> d, Mv m, R scale)
     }
 }
 
+// ------------------------------------------------ soft-core lambda path
+// Eq. 4 as the MDAS path (float64 throughout): a pair with a changed bead
+// takes the A-state LJ at mu = 1 - lambda and the B-state LJ at mu =
+// lambda, each mu (c12 / s^6 - c6 / s^3) with s = r^2 + delta (1 - mu),
+// shifted to zero at the cutoff, plus the reaction field of the
+// interpolated charge product (tabE rows: c6, c12, f q_i q_j / eps_r).  At
+// lambda = 0 this is the plain A pair, so the force pass (A classes) plus
+// F_sc(lambda) - F_sc(0) on the affected beads is the force at lambda.
+__device__ __forceinline__ void sc_lj_d(double c6, double c12, double r2, double mu, double delta,
+                                        double rc2, double& v, double& fs)
+{
+    const double sh = delta * (1.0 - mu);
+    const double s3 = r2 + sh, i3 = 1.0 / (s3 * s3 * s3);
+    const double c3 = rc2 + sh, ic3 = 1.0 / (c3 * c3 * c3);
+    v = mu * (c12 * i3 * i3 - c6 * i3) - mu * (c12 * ic3 * ic3 - c6 * ic3);
+    fs = mu * (12.0 * c12 * i3 * i3 - 6.0 * c6 * i3) / s3;
+}
+
+template <typename R>
+__device__ __forceinline__ void sc_pair_d(const Dev<R>& d, int ci, int cj, int ci2, int cj2, double r2,
+                                          double lam, double delta, double& v, double& fs)
+{
+    const V4<R> ea = d.tabE[ci * MAXCLS + cj], eb = d.tabE[ci2 * MAXCLS + cj2];
+    double va, fa, vb, fb;
+    sc_lj_d((double)ea.x, (double)ea.y, r2, 1.0 - lam, delta, d.rc2d, va, fa);
+    sc_lj_d((double)eb.x, (double)eb.y, r2, lam, delta, d.rc2d, vb, fb);
+    const double qq = (1.0 - lam) * (double)ea.z + lam * (double)eb.z;
+    const double r = sqrt(r2), krf = (double)d.krf, crf = (double)d.crf;
+    v = va + vb + qq * (1.0 / r + krf * r2 - crf);
+    fs = fa + fb + qq * (1.0 / (r2 * r) - 2.0 * krf);
+}
+
+// F += F_sc(lam_to) - F_sc(lam_from) on each affected bead (8 lanes per bead)
+template <typename R>
+__global__ __launch_bounds__(WG) void k_scforce(Dev<R> d, Mv m, double lam_from, double lam_to,
+                                                double delta)
+{
+    const int gid = blockIdx.x * WG + threadIdx.x;
+    const int k0 = gid >> 3, s = gid & 7;
+    const int na = min(*m.aff_n, m.aff_cap);
+    const bool valid = k0 < na;
+    const int i = valid ? m.aff_list[k0] : 0;
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    if (valid) {
+        const V4<R> pi = d.posq[i];
+        const int ci = cls_of<R>(pi.w);
+        const int mk = d.alch[i];
+        const int ci2 = mk >= 0 ? (mk & 0xff) : ci;
+        const int n1 = d.ncnt[i];
+        for (int k = s; k < n1; k += 8) {
+            const int en = d.nbr[nbr_index(i, k, d.Kcap, d.lpb)];
+            const int j = en & JMASK, code = (int)((unsigned)en >> CODE_SHIFT);
+            const int o = owner_of(d.ghost_owner, d.N, j);
+            const int mj = d.alch[o];
+            if (mk < 0 && mj < 0) continue;
+            const V4<R> pj = d.posq[j];
+            const int cj = cls_of<R>(d.posq[o].w);
+            const int cj2 = mj >= 0 ? (mj & 0xff) : cj;
+            const R xs = (code & 1) ? pi.x - d.L[0] : pi.x;
+            const R ys = (code & 2) ? pi.y - d.L[1] : pi.y;
+            const R zs = (code & 4) ? pi.z - d.L[2] : pi.z;
+            const double dx = (double)xs - (double)pj.x, dy = (double)ys - (double)pj.y,
+                         dz = (double)zs - (double)pj.z;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (!(r2 < d.rc2d)) continue;
+            double v1, f1, v0, f0;
+            sc_pair_d(d, ci, cj, ci2, cj2, r2, lam_to, delta, v1, f1);
+            sc_pair_d(d, ci, cj, ci2, cj2, r2, lam_from, delta, v0, f0);
+            const double fs = f1 - f0;
+            fx += fs * dx; fy += fs * dy; fz += fs * dz;
+        }
+    }
+#pragma unroll
+    for (int q = 4; q >= 1; q >>= 1) {
+        fx += __shfl_xor(fx, q);
+        fy += __shfl_xor(fy, q);
+        fz += __shfl_xor(fz, q);
+    }
+    if (valid && s == 0) {
+        V4<R> f = d.frc[i];
+        f.x = (R)((double)f.x + fx); f.y = (R)((double)f.y + fy); f.z = (R)((double)f.z + fz);
+        d.frc[i] = f;
+    }
+}
+
+// U_sc(lam1) - U_sc(lam0) over one changed bead's pairs (one wave per changed
+// bead; pairs of two changed beads visited from both ends, weight 1/2)
+template <typename R>
+__global__ __launch_bounds__(64) void k_scdu(Dev<R> d, Mv m, double lam0, double lam1, double delta)
+{
+    const int e = blockIdx.x, lane = threadIdx.x;
+    const int MC = m.maxcht;
+    const int a = e / MC, q = e % MC;
+    if (a >= m.r_n[0] || q >= m.r_nb[a]) {
+        if (lane == 0) m.du_bead[e] = 0.0;
+        return;
+    }
+    const int i = d.inv[m.r_bead[a * MC + q]];
+    const V4<R> pi = d.posq[i];
+    const int ci = cls_of<R>(pi.w);
+    const int mk = d.alch[i];
+    const int ci2 = mk & 0xff, tag = mk >> 8;
+    const int n1 = d.ncnt[i];
+    double du = 0.0;
+    for (int k = lane; k < n1; k += 64) {
+        const int en = d.nbr[nbr_index(i, k, d.Kcap, d.lpb)];
+        const int j = en & JMASK, code = (int)((unsigned)en >> CODE_SHIFT);
+        const V4<R> pj = d.posq[j];
+        const int o = owner_of(d.ghost_owner, d.N, j);
+        const int cj = cls_of<R>(d.posq[o].w);
+        const int mj = d.alch[o];
+        int cj2 = cj;
+        double wgt = 1.0;
+        if (mj >= 0 && (mj >> 8) == tag) { cj2 = mj & 0xff; wgt = 0.5; }
+        const R xs = (code & 1) ? pi.x - d.L[0] : pi.x;
+        const R ys = (code & 2) ? pi.y - d.L[1] : pi.y;
+        const R zs = (code & 4) ? pi.z - d.L[2] : pi.z;
+        const double dx = (double)xs - (double)pj.x, dy = (double)ys - (double)pj.y,
+                     dz = (double)zs - (double)pj.z;
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 < d.rc2d) {
+            double v1, f1, v0, f0;
+            sc_pair_d(d, ci, cj, ci2, cj2, r2, lam1, delta, v1, f1);
+            sc_pair_d(d, ci, cj, ci2, cj2, r2, lam0, delta, v0, f0);
+            du += wgt * (v1 - v0);
+        }
+    }
+    du = dwave_sum(du);
+    if (lane == 0) m.du_bead[e] = du;
+}
+
 // F += dl (F_B - F_A) on the affected beads (a lambda increment, Eq. 2).
 template <typename R>
 __global__ void k_dlam(Dev<R> d, Mv m, R dl)
@@ -964,6 +1095,22 @@ void launch_dforce(const Dev<R>& d, const Mv& m, R scale, hipStream_t st)
 }
 
 template <typename R>
+void launch_scforce(const Dev<R>& d, const Mv& m, double lam_from, double lam_to, double delta,
+                    hipStream_t st)
+{
+    int n = m.aff_cap * 8;
+    hipLaunchKernelGGL(k_scforce<R>, dim3((n + WG - 1) / WG), dim3(WG), 0, st, d, m, lam_from, lam_to,
+                       delta);
+}
+
+template <typename R>
+void launch_scdu(const Dev<R>& d, const Mv& m, int T, double lam0, double lam1, double delta,
+                 hipStream_t st)
+{
+    hipLaunchKernelGGL(k_scdu<R>, dim3(T * m.maxcht), dim3(64), 0, st, d, m, lam0, lam1, delta);
+}
+
+template <typename R>
 void launch_dlam(const Dev<R>& d, const Mv& m, R dl, hipStream_t st)
 {
     hipLaunchKernelGGL(k_dlam<R>, dim3((m.aff_cap + 255) / 256), dim3(256), 0, st, d, m, dl);
@@ -1010,6 +1157,10 @@ void launch_kcnt(const Dev<R>& d, const Mv& m, int kind, hipStream_t st)
     template void launch_aff_clear<R>(const Dev<R>&, const Mv&, hipStream_t);             \
     template void launch_dforce<R>(const Dev<R>&, const Mv&, R, hipStream_t);             \
     template void launch_dlam<R>(const Dev<R>&, const Mv&, R, hipStream_t);               \
+    template void launch_scforce<R>(const Dev<R>&, const Mv&, double, double, double,      \
+                                    hipStream_t);                                         \
+    template void launch_scdu<R>(const Dev<R>&, const Mv&, int, double, double, double,    \
+                                 hipStream_t);                                            \
     template void launch_commit<R>(const Dev<R>&, const Mv&, int, int, hipStream_t);      \
     template void launch_mdas_accept<R>(const Dev<R>&, const Mv&, hipStream_t);           \
     template void launch_snapshot<R>(const Dev<R>&, const Mv&, int, hipStream_t);         \

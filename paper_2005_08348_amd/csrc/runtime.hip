@@ -53,6 +53,10 @@ template <typename R> void launch_du_total(const Dev<R>&, const Mv&, double*, hi
 template <typename R> void launch_aff_build(const Dev<R>&, const Mv&, int, int, hipStream_t);
 template <typename R> void launch_aff_clear(const Dev<R>&, const Mv&, hipStream_t);
 template <typename R> void launch_dforce(const Dev<R>&, const Mv&, R, hipStream_t);
+template <typename R>
+void launch_scforce(const Dev<R>&, const Mv&, double, double, double, hipStream_t);
+template <typename R>
+void launch_scdu(const Dev<R>&, const Mv&, int, double, double, double, hipStream_t);
 template <typename R> void launch_dlam(const Dev<R>&, const Mv&, R, hipStream_t);
 template <typename R> void launch_commit(const Dev<R>&, const Mv&, int, int, hipStream_t);
 void launch_work(double*, double, hipStream_t);
@@ -134,6 +138,9 @@ struct Host {
     // compressibility (its inverse), tau_p (ps)
     int baro_nst = 0;
     double p_ref = 0.0, kappa = 0.0, tau_p = 0.0;
+    // MDAS lambda path: 0 linear (Eq. 2), 1 soft-core LJ (Eq. 4), shift (nm^2)
+    int mdas_path = 0;
+    double sc_delta = 0.05;
     int hnc[3], hcells, mh;
     int aff_cap;
 };
@@ -725,6 +732,10 @@ static void alch_terms(membx_sys* s, bool rebuilt, double lam)
         launch_aff_clear<R>(d, m, s->st);
         launch_aff_build<R>(d, m, 0, T, s->st);
     }
+    if (s->h.mdas_path == 1) {   // force pass (A) + F_sc(lam) - F_sc(0)
+        launch_scforce<R>(d, m, 0.0, lam, s->h.sc_delta, s->st);
+        return;
+    }
     launch_dforce<R>(d, m, (R)lam, s->st);
     launch_du<R>(d, m, T, s->st);
     launch_du_total<R>(d, m, m.md + 1, s->st);
@@ -996,9 +1007,12 @@ static int32_t mdas(membx_sys* s, int P, int K, int M)
     launch_aff_build<R>(d, m, 0, T, st);
     launch_fill_i32((int*)m.md, 0, 16, st);
     launch_ghost_update<R>(d, st);
-    launch_dforce<R>(d, m, (R)0, st);
-    launch_du<R>(d, m, T, st);
-    launch_du_total<R>(d, m, m.md + 1, st);
+    const bool sc = s->h.mdas_path == 1;
+    if (!sc) {
+        launch_dforce<R>(d, m, (R)0, st);
+        launch_du<R>(d, m, T, st);
+        launch_du_total<R>(d, m, m.md + 1, st);
+    }
     double lam = 0.0;
     for (int k = 1; k <= K; ++k) {
         if (M > 0) {
@@ -1009,8 +1023,15 @@ static int32_t mdas(membx_sys* s, int P, int K, int M)
         }
         double lam_new = (double)k / (double)K;
         double dl = lam_new - lam;
-        launch_work(m.md, dl, st);
-        launch_dlam<R>(d, m, (R)dl, st);
+        if (sc) {   // w += U_sc(lam_new) - U_sc(lam) at x; forces follow lambda
+            launch_scdu<R>(d, m, T, lam, lam_new, s->h.sc_delta, st);
+            launch_du_total<R>(d, m, m.md + 1, st);
+            launch_work(m.md, 1.0, st);
+            launch_scforce<R>(d, m, lam, lam_new, s->h.sc_delta, st);
+        } else {
+            launch_work(m.md, dl, st);
+            launch_dlam<R>(d, m, (R)dl, st);
+        }
         lam = lam_new;
     }
     if (M == 0) s->fe += 1;
@@ -1888,6 +1909,17 @@ int32_t membx_set_barostat(membx_sys* s, int32_t nst, double p_ref_bar, double c
     s->h.p_ref = p_ref_bar / BAR;
     s->h.kappa = compressibility * BAR;
     s->h.tau_p = tau_p;
+    return MEMBX_OK;
+}
+
+int32_t membx_set_mdas_path(membx_sys* s, int32_t path, double delta)
+{
+    if (!s) return MEMBX_E_INVAL;
+    if (path != 0 && path != 1) return fail(s, MEMBX_E_INVAL, "MDAS path must be 0 or 1");
+    if (path == 1 && !(delta > 0.0 && std::isfinite(delta)))
+        return fail(s, MEMBX_E_INVAL, "soft-core shift must be > 0");
+    s->h.mdas_path = path;
+    if (path == 1) s->h.sc_delta = delta;
     return MEMBX_OK;
 }
 

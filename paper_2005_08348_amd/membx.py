@@ -126,6 +126,7 @@ def lib():
             "membx_set_exchange_regions": ([vp, i32, vp], i32),
             "membx_set_barostat": ([vp, i32, dp, dp, dp], i32),
             "membx_get_box": ([vp, vp], i32),
+            "membx_set_mdas_path": ([vp, i32, dp], i32),
             "membx_kernel_timing": ([vp, i32], i32),
             "membx_kernel_time": ([vp, C.POINTER(i64), C.POINTER(dp)], i32),
             "membx_kernel_bench": ([vp, i32, C.POINTER(dp)], i32),
@@ -375,6 +376,10 @@ class System:
         """semi-isotropic pressure coupling every nst MD steps (0: off)"""
         _check(lib().membx_set_barostat(self.h, int(nst), float(p_ref_bar), float(compressibility),
                                         float(tau_p)), self.h)
+
+    def set_mdas_path(self, path, delta=0.05):
+        """MDAS lambda path: 0 linear (Eq. 2), 1 soft-core LJ (Eq. 4, delta nm^2)"""
+        _check(lib().membx_set_mdas_path(self.h, int(path), float(delta)), self.h)
 
     def box(self):
         b = np.zeros(3)
