@@ -348,6 +348,16 @@ def main():
                           "last_accepted": r3["accept"],
                           "md_steps_per_s": k3 / t3md,
                           "pair_interactions_per_s": e3["n_pairs_in_cutoff"] * k3 / t3md}
+        # the soft-core lambda path (Eq. 4): the same cycles with the changed
+        # beads' LJ switched through soft-core terms (two extra small kernels
+        # per step and per increment)
+        g3.set_mdas_path(1, 0.05)
+        g3.mdas_cycle(32, 50, 1, results=False)
+        tsc = timed(lambda: [g3.mdas_cycle(32, 50, 1, results=False) for _ in range(ncyc)], sync)
+        rsc = g3.mdas_cycle(32, 50, 1)
+        result["mdas"]["soft_core"] = {"cycles_per_s": ncyc / tsc, "delta_nm2": 0.05,
+                                       "last_work_kJmol": rsc["work"], "last_accepted": rsc["accept"]}
+        g3.set_mdas_path(0)
         g3.close(); del g3
         torch.cuda.empty_cache()
 
