@@ -254,7 +254,8 @@ int32_t membx_pairset_export(membx_sys* sys, int32_t* ij, int64_t cap, int64_t* 
  * by alpha F_i, shortened to at most max_step nm, n_iter times. */
 int32_t membx_minimize(membx_sys* sys, int32_t n_iter, double alpha, double max_step);
 
-/* Change the tuning of an existing system (skin <= skin_max, lanes_per_bead
+/* Change the tuning of an existing system (skin <= skin_max and, as the box
+ * may have changed under pressure coupling, box >= 3 (r_cut + skin); lanes_per_bead
  * in {1,2,4,8}, rebuild_interval >= 1; prune_interval <= 1 turns the inner
  * list off, else skin_inner in (0, skin] and lanes_per_bead >= 2).  Rebuilds
  * the list.  E_INVAL. */
@@ -263,7 +264,8 @@ int32_t membx_set_tuning(membx_sys* sys, double skin, int32_t rebuild_interval,
 
 /* Autotune skin, rebuild interval, lanes per bead and the inner list by
  * timing short runs of n_steps (<= 0: 200) from the current state.
- * Candidates: skin from 0.2 nm to skin_max in steps of 0.1 nm, lanes per
+ * Candidates: skin from 0.2 nm to skin_max (at most what the current box
+ * allows, box >= 3 (r_cut + skin)) in steps of 0.1 nm, lanes per
  * bead 4 and 8, prune interval 1 (no inner list), 2, 3 and 4.  A pilot run
  * gives the largest displacement d4 over 4 steps; in the ballistic regime
  * (interval << 1/gamma) displacements grow linearly with time, so the

@@ -159,6 +159,15 @@ static void build_regions(Host& h)
         }
 }
 
+// Largest skin the current box allows: cells of edge >= r_cut + skin need at
+// least three per axis (the box may have shrunk under pressure coupling).
+static double box_skin_limit(const Host& h)
+{
+    double lim = h.skin_max;
+    for (int a = 0; a < 3; ++a) lim = std::min(lim, h.box[a] / 3.0 - h.rc);
+    return lim;
+}
+
 // Cell grid for list radius r_cut + skin: nc = floor(L / r_list) cells per
 // axis (at least 3), plus one halo layer of ghost images.
 static void set_grid(Host& h, double skin)
@@ -1739,7 +1748,8 @@ static int32_t autotune_impl(membx_sys* s, int n, Tune* out)
     Saved sv;
     int32_t rc = tune_save<R>(s, sv);
     if (rc) return rc;
-    const double skin_max = s->h.skin_max;
+    const double skin_max = std::min(s->h.skin_max, std::floor(10.0 * box_skin_limit(s->h) + 1e-9) / 10.0);
+    if (!(skin_max >= 0.1)) return fail(s, MEMBX_E_STATE, "box too small to tune the skin");
     const int lpb0 = s->h.lpb;
     auto apply = [&](const Tune& t) -> int32_t {
         s->h.skin = t.skin; s->h.R = t.R; s->h.lpb = t.lpb;
@@ -1808,7 +1818,7 @@ int32_t membx_set_tuning(membx_sys* s, double skin, int32_t rebuild_interval,
                          int32_t lanes_per_bead, double skin_inner, int32_t prune_interval)
 {
     if (!s) return MEMBX_E_INVAL;
-    if (!(skin > 0) || skin > s->h.skin_max + 1e-12 || rebuild_interval < 1 ||
+    if (!(skin > 0) || skin > box_skin_limit(s->h) + 1e-12 || rebuild_interval < 1 ||
         (lanes_per_bead != 1 && lanes_per_bead != 2 && lanes_per_bead != 4 && lanes_per_bead != 8))
         return fail(s, MEMBX_E_INVAL, "bad tuning");
     const int prune = prune_interval > 1 ? prune_interval : 0;

@@ -152,3 +152,24 @@ def test_barostat_c1_pressure_converges():
     vol = b[:, 0] * b[:, 1] * b[:, 2]
     assert abs(vol[375:].mean() / vol[-125:].mean() - 1.0) < 2e-3
     g.close()
+
+
+def test_barostat_shrunk_box_limits_the_skin(c0_relaxed):
+    """A box compressed by a high reference pressure: skins that would leave
+    fewer than three cells of edge r_cut + skin are refused by set_tuning,
+    and the autotuner only tries the ones that fit."""
+    m = _membx()
+    g = m.System(c0_relaxed, precision="mixed", skin=0.2, rebuild_interval=4)
+    g.set_barostat(2, p_ref_bar=3000.0, compressibility=3e-4, tau_p=2.0)
+    while g.box()[0] / 3.0 - 1.1 > 0.35:
+        g.md_step(2)
+    lim = g.box().min() / 3.0 - 1.1
+    assert lim < 0.4
+    with pytest.raises(m.MembxError):
+        g.set_tuning(0.4, 4, 4)
+    g.set_barostat(0)
+    t = g.autotune(40)
+    assert t["skin"] <= lim + 1e-9
+    g.md_step(20)
+    assert g.energies()["n_skin_violations"] == 0
+    g.close()
