@@ -21,7 +21,9 @@ the fits and the speed-ups.  Force evaluations are counted as the paper
 does: one per MD step, per exchange trial and per MDAS step (a frozen MDAS
 cycle, M = 0, counts one).  With ``--thermostat vrescale`` every sampler
 integrates with the paper's thermostat (velocity rescaling, tau_t = 1 ps,
-membrane and solvent coupled separately) instead of Langevin dynamics;
+membrane and solvent coupled separately) instead of Langevin dynamics, and
+``--thermostat npt`` adds the semi-isotropic barostat at 1 bar (tau_p 12 ps):
+the paper's ensemble;
 ``--repeats`` runs independent seeds and summarises the halfway speed-ups
 (mean and standard deviation over the runs); ``--combine`` summarises the
 repeats of several earlier outputs together.
@@ -118,7 +120,8 @@ def _trace_point(g, sysm, kind, leaflet, n_bins, bin_width):
     mk = g.state()["mol_kind"]
     n_leaf = [int(np.count_nonzero((mk == kind) & (leaflet == lf))) for lf in (0, 1)]
     h = g.pair_histogram(kind, S.PO4, leaflet, n_bins, bin_width)
-    return max_g(h, n_leaf, sysm.box[0] * sysm.box[1], bin_width, R_MIN)
+    box = g.box()                       # changes under pressure coupling
+    return max_g(h, n_leaf, box[0] * box[1], bin_width, R_MIN)
 
 
 def run(method, sysm, fe_total, every, kind=S.KIND_D, n_bins=N_BINS, bin_width=BIN,
@@ -130,40 +133,51 @@ def run(method, sysm, fe_total, every, kind=S.KIND_D, n_bins=N_BINS, bin_width=B
     from . import membx as M
     leaflet = sysm.meta["leaflet"]
     g = M.System(sysm, precision=precision)
-    if thermostat == "vrescale":
+    if thermostat in ("vrescale", "npt"):
         g.set_ensemble(1, tau_t=1.0, kind_group=[1 if k.name == "W" else 0 for k in sysm.kinds])
+    if thermostat == "npt":   # and the semi-isotropic barostat at 1 bar
+        g.set_barostat(10, p_ref_bar=1.0, compressibility=3e-4, tau_p=12.0)
     g.minimize(100)
     g.md_step(max(equil, 200))           # thermalise (not counted)
     fe, trace, works, acc, tried = 0, [], [], 0, 0
     trace.append((0, _trace_point(g, sysm, kind, leaflet, n_bins, bin_width)))
     next_pt = every
     t0 = time.perf_counter()
-    while fe < fe_total:
+    stopped = None
+
+    def advance():
+        """one unit of the sampler; returns (force evaluations, trials, accepted)"""
         if method == "md":
             g.md_step(every)
-            fe += every
-        elif method == "mcmd":
+            return every, 0, 0
+        if method == "mcmd":
             r = g.swap_trials(mc_trials)
             g.md_step(mc_steps)
             n = len(r["accept"])
-            tried += n
-            acc += int(np.count_nonzero(r["accept"]))
-            fe += n + mc_steps
-        elif method == "mdas":
+            return n + mc_steps, n, int(np.count_nonzero(r["accept"]))
+        if method == "mdas":
             g.md_step(mdas_md)
             r = g.mdas_cycle(mdas_pairs, mdas_k, mdas_m)
             works.append(r["work"])
-            tried += 1
-            acc += int(r["accept"])
-            fe += mdas_md + (mdas_k * mdas_m if mdas_m > 0 else 1)
-        else:
-            raise ValueError(method)
-        if fe >= next_pt:
-            trace.append((fe, _trace_point(g, sysm, kind, leaflet, n_bins, bin_width)))
-            next_pt += every
+            return mdas_md + (mdas_k * mdas_m if mdas_m > 0 else 1), 1, int(r["accept"])
+        raise ValueError(method)
+
+    while fe < fe_total:
+        try:
+            dfe, dt, da = advance()
+            fe += dfe
+            tried += dt
+            acc += da
+            if fe >= next_pt:
+                trace.append((fe, _trace_point(g, sysm, kind, leaflet, n_bins, bin_width)))
+                next_pt += every
+        except M.MembxError as ex:   # e.g. a box the barostat shrank below three list radii
+            stopped = f"stopped at {fe} FE: {ex}"
+            break
     wall = time.perf_counter() - t0
     g.close()
-    return dict(method=method, trace=trace, accepted=acc, tried=tried, works=works, wall_s=wall)
+    return dict(method=method, trace=trace, accepted=acc, tried=tried, works=works, wall_s=wall,
+                stopped=stopped)
 
 
 def experiment(seed, fe_total, every, thermostat="langevin", equil=EQUIL):
@@ -182,7 +196,7 @@ def experiment(seed, fe_total, every, thermostat="langevin", equil=EQUIL):
         r = run(method, sysm, fe_total, every, thermostat=thermostat, equil=equil)
         x = np.array([p[0] for p in r["trace"]], dtype=np.float64)
         y = np.array([p[1] for p in r["trace"]], dtype=np.float64)
-        entry = {"fe": x.tolist(), "max_g": y.tolist(),
+        entry = {"fe": x.tolist(), "max_g": y.tolist(), "stopped": r["stopped"],
                  "accepted": r["accepted"], "tried": r["tried"], "wall_s": r["wall_s"]}
         if method == "mdas":
             entry["acceptance_from_work"] = acceptance_from_work(r["works"], kT)
@@ -251,7 +265,8 @@ def main(argv=None):
     ap.add_argument("--every", type=int, default=4000, help="force evaluations between g(r) samples")
     ap.add_argument("--seed", type=int, default=None, help="first seed (default: the mix workload's)")
     ap.add_argument("--repeats", type=int, default=1, help="independent runs, seeds seed, seed + 1, ...")
-    ap.add_argument("--thermostat", choices=["langevin", "vrescale"], default="langevin")
+    ap.add_argument("--thermostat", choices=["langevin", "vrescale", "npt"], default="langevin",
+                    help="npt: velocity rescaling and the semi-isotropic barostat (the paper's ensemble)")
     ap.add_argument("--equil", type=int, default=EQUIL, help="uncounted MD steps before each run")
     ap.add_argument("--combine", nargs="+", metavar="JSON",
                     help="no runs: summarise the repeats of earlier outputs of this program")
