@@ -55,11 +55,14 @@ __device__ __forceinline__ int block_scan(int v, int* sh)
     return base + x - v;
 }
 
-// Cell starts (exclusive scan of the counts) and the extended grid: real
+// Cell starts (exclusive scan of the counts), then the extended grid: real
 // extended cells point into the slots, halo cells into the ghost range, laid
-// out by a scan of their source cells' counts.  Run by one work-group of BB
-// threads, each taking a contiguous segment, read LU_L values at a time with
-// all loads in flight.  The counts are cleared for the next rebuild.
+// out by a scan of their source cells' counts.  Each part is run by one
+// work-group of BB threads, each taking a contiguous segment, read LU_L
+// values at a time with all loads in flight: the cell starts by k_layout
+// (which also clears the counts for the next rebuild), the extended grid by
+// an extra work-group of k_scatter, next to the scatter that needs only the
+// cell starts.
 constexpr int LU_L = 8;
 
 __device__ __forceinline__ int load_cnt(const int* p) { return *p; }
@@ -93,6 +96,14 @@ __device__ void layout_cells(const Dev<R>& d)
         if (t == BB - 1) d.cell_start[d.ncell] = run;
     }
     __syncthreads();
+    for (int k = t; k < d.ncell; k += BB) d.cell_cnt[k] = 0;
+}
+
+template <typename R>
+__device__ void layout_ext(const Dev<R>& d)
+{
+    __shared__ int sh[BB / 64];
+    const int t = threadIdx.x;
     {
         const int per = (d.next + BB - 1) / BB;
         const int k0 = min(d.next, t * per), k1 = min(d.next, k0 + per);
@@ -144,7 +155,6 @@ __device__ void layout_cells(const Dev<R>& d)
             if (run > d.Gcap) atomicOr(&d.flags[FL_GHOST_OVF], 1);
         }
     }
-    for (int k = t; k < d.ncell; k += BB) d.cell_cnt[k] = 0;
 }
 
 // Bead -> cell, coordinates wrapped into [0, L).  Beads come in slot order,
@@ -206,11 +216,17 @@ __global__ __launch_bounds__(BB) void k_layout(Dev<R> d)
     layout_cells(d);
 }
 
-// Scatter beads to their places in their cells' slot ranges.
+// Scatter beads to their places in their cells' slot ranges (BB threads per
+// block); block 0, dispatched first as it is the longest, lays out the
+// extended grid instead.
 template <typename R>
-__global__ void k_scatter(Dev<R> d)
+__global__ __launch_bounds__(BB) void k_scatter(Dev<R> d)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0) {
+        layout_ext(d);
+        return;
+    }
+    const int i = (blockIdx.x - 1) * blockDim.x + threadIdx.x;
     if (i >= d.N) return;
     const int dst = d.cell_start[d.cell_t[i]] + d.cell_pos[i];
     d.posq_t[dst] = d.posq[i];
@@ -573,7 +589,7 @@ void launch_rebuild(const Dev<R>& d, hipStream_t st)
 {
     hipLaunchKernelGGL(k_bin<R>, dim3((d.N + BB - 1) / BB), dim3(BB), 0, st, d);
     hipLaunchKernelGGL(k_layout<R>, dim3(1), dim3(BB), 0, st, d);
-    hipLaunchKernelGGL(k_scatter<R>, GRID(d.N), 0, st, d);
+    hipLaunchKernelGGL(k_scatter<R>, dim3((d.N + BB - 1) / BB + 1), dim3(BB), 0, st, d);
     hipLaunchKernelGGL(k_place<R>, dim3(d.ncell), dim3(64), 0, st, d);
     hipLaunchKernelGGL(k_list<R>, dim3(d.ncell), dim3(LB), 0, st, d);
 }
