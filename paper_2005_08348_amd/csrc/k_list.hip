@@ -99,61 +99,57 @@ __device__ void layout_cells(const Dev<R>& d)
     for (int k = t; k < d.ncell; k += BB) d.cell_cnt[k] = 0;
 }
 
+// Halo cells of the extended grid (one work-group of BB threads): ghost
+// ranges laid out by a scan of their source cells' counts.  Only halo cells
+// read the counts; the real extended cells are written by the scatter blocks.
 template <typename R>
-__device__ void layout_ext(const Dev<R>& d)
+__device__ void layout_halo(const Dev<R>& d)
 {
     __shared__ int sh[BB / 64];
     const int t = threadIdx.x;
-    {
-        const int per = (d.next + BB - 1) / BB;
-        const int k0 = min(d.next, t * per), k1 = min(d.next, k0 + per);
-        int st[LU_L], n[LU_L];
-        unsigned halo = 0;
-        auto fetch = [&](int kb) {
-            halo = 0;
+    const int per = (d.next + BB - 1) / BB;
+    const int k0 = min(d.next, t * per), k1 = min(d.next, k0 + per);
+    int n[LU_L];
+    unsigned halo = 0;
+    auto fetch = [&](int kb) {
+        halo = 0;
+        int st[LU_L];
 #pragma unroll
-            for (int u = 0; u < LU_L; ++u) {
-                const int k = min(kb + u, k1 - 1);
-                int a[3];
-                ext_coords(k, d.ne, a);
-                const int src = ext_source(a, d.nc);
-                st[u] = d.cell_start[src];
-                n[u] = d.cell_start[src + 1];
-                if (a[0] == 0 || a[1] == 0 || a[2] == 0) halo |= 1u << u;
-            }
-#pragma unroll
-            for (int u = 0; u < LU_L; ++u) n[u] -= st[u];
-        };
-        int s = 0;
-        for (int kb = k0; kb < k1; kb += LU_L) {
-            fetch(kb);
-#pragma unroll
-            for (int u = 0; u < LU_L; ++u)
-                if (kb + u < k1 && ((halo >> u) & 1u)) s += n[u];
+        for (int u = 0; u < LU_L; ++u) {
+            const int k = kb + u;
+            int a[3];
+            ext_coords(min(k, k1 - 1), d.ne, a);
+            const bool h = k < k1 && (a[0] == 0 || a[1] == 0 || a[2] == 0);
+            const int src = ext_source(a, d.nc);
+            st[u] = h ? d.cell_start[src] : 0;
+            n[u] = h ? d.cell_start[src + 1] : 0;
+            if (h) halo |= 1u << u;
         }
-        int run = block_scan(s, sh);
-        for (int kb = k0; kb < k1; kb += LU_L) {
-            if (per > LU_L) fetch(kb);
 #pragma unroll
-            for (int u = 0; u < LU_L; ++u) {
-                const int k = kb + u;
-                if (k >= k1) break;
-                if ((halo >> u) & 1u) {
-                    d.ext_start[k] = d.N + run;
-                    d.ext_cnt[k] = run >= d.Gcap ? 0 : min(n[u], d.Gcap - run);
-                    d.ext_scan[k] = run;          // ghost offset of this halo cell
-                    run += n[u];
-                } else {
-                    d.ext_start[k] = st[u];
-                    d.ext_cnt[k] = n[u];
-                    d.ext_scan[k] = -1;
-                }
-            }
+        for (int u = 0; u < LU_L; ++u) n[u] -= st[u];
+    };
+    int s = 0;
+    for (int kb = k0; kb < k1; kb += LU_L) {
+        fetch(kb);
+#pragma unroll
+        for (int u = 0; u < LU_L; ++u) s += n[u];
+    }
+    int run = block_scan(s, sh);
+    for (int kb = k0; kb < k1; kb += LU_L) {
+        if (per > LU_L) fetch(kb);
+#pragma unroll
+        for (int u = 0; u < LU_L; ++u) {
+            if (!((halo >> u) & 1u)) continue;
+            const int k = kb + u;
+            d.ext_start[k] = d.N + run;
+            d.ext_cnt[k] = run >= d.Gcap ? 0 : min(n[u], d.Gcap - run);
+            d.ext_scan[k] = run;          // ghost offset of this halo cell
+            run += n[u];
         }
-        if (t == BB - 1) {
-            *d.n_ghost = min(run, d.Gcap);
-            if (run > d.Gcap) atomicOr(&d.flags[FL_GHOST_OVF], 1);
-        }
+    }
+    if (t == BB - 1) {
+        *d.n_ghost = min(run, d.Gcap);
+        if (run > d.Gcap) atomicOr(&d.flags[FL_GHOST_OVF], 1);
     }
 }
 
@@ -217,16 +213,28 @@ __global__ __launch_bounds__(BB) void k_layout(Dev<R> d)
 }
 
 // Scatter beads to their places in their cells' slot ranges (BB threads per
-// block); block 0, dispatched first as it is the longest, lays out the
-// extended grid instead.
+// block), and point the real extended cells at their slots; block 0,
+// dispatched first as it is the longest, lays out the halo cells instead.
 template <typename R>
 __global__ __launch_bounds__(BB) void k_scatter(Dev<R> d)
 {
     if (blockIdx.x == 0) {
-        layout_ext(d);
+        layout_halo(d);
         return;
     }
-    const int i = (blockIdx.x - 1) * blockDim.x + threadIdx.x;
+    const int g = (blockIdx.x - 1) * blockDim.x + threadIdx.x;
+    const int stride = (gridDim.x - 1) * blockDim.x;
+    for (int k = g; k < d.next; k += stride) {
+        int a[3];
+        ext_coords(k, d.ne, a);
+        if (a[0] == 0 || a[1] == 0 || a[2] == 0) continue;
+        const int src = ext_source(a, d.nc);
+        const int st = d.cell_start[src];
+        d.ext_start[k] = st;
+        d.ext_cnt[k] = d.cell_start[src + 1] - st;
+        d.ext_scan[k] = -1;
+    }
+    const int i = g;
     if (i >= d.N) return;
     const int dst = d.cell_start[d.cell_t[i]] + d.cell_pos[i];
     d.posq_t[dst] = d.posq[i];
