@@ -263,7 +263,8 @@ int32_t membx_set_tuning(membx_sys* sys, double skin, int32_t rebuild_interval,
                          int32_t lanes_per_bead, double skin_inner, int32_t prune_interval);
 
 /* Autotune skin, rebuild interval, lanes per bead and the inner list by
- * timing short runs of n_steps (<= 0: 200) from the current state.
+ * timing short runs from the current state: per candidate, n_steps
+ * (<= 0: 200) untimed, then the fastest of three timed runs of n_steps.
  * Candidates: skin from 0.2 nm to skin_max (at most what the current box
  * allows, box >= 3 (r_cut + skin)) in steps of 0.1 nm, lanes per
  * bead 4 and 8, prune interval 1 (no inner list), 2, 3 and 4.  A pilot run
@@ -271,7 +272,7 @@ int32_t membx_set_tuning(membx_sys* sys, double skin, int32_t rebuild_interval,
  * (interval << 1/gamma) displacements grow linearly with time, so the
  * rebuild interval is the largest that keeps every bead within 0.8 skin/2,
  * and the inner buffer the smallest that keeps it within 0.8 delta/2 over a
- * prune interval.  A candidate is rejected if, in its timed run, a bead went
+ * prune interval.  A candidate is rejected if, in its timed runs, a bead went
  * beyond 0.9 skin/2 or beyond delta/2.  Positions, velocities, kinds and
  * random-number counters are restored afterwards; forces are recomputed and
  * the list is rebuilt.  Writes the chosen values and leaves the system

@@ -124,7 +124,8 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
 {
     __shared__ V4<R> tf[MAXCLS * MAXCLS];
     __shared__ V4<R> te[EN ? MAXCLS * MAXCLS : 1];
-    const int gid = blockIdx.x * WG + threadIdx.x;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int gid = blk * WG + threadIdx.x;
     const int i = gid / LPB, s = gid % LPB;
     const bool valid = i < d.N;
     const int ii = valid ? i : 0;
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
     // block's bead t (forces handed over through LDS), so that the
     // integrator runs on full waves instead of one lane per bead
     constexpr int NBB = WG / LPB;
-    const int ib = blockIdx.x * NBB + threadIdx.x;
+    const int ib = blk * NBB + threadIdx.x;
     const bool integ = FUSE && threadIdx.x < NBB && ib < d.N;
     for (int t = threadIdx.x; t < MAXCLS * MAXCLS; t += WG) {
         tf[t] = d.tabF[t];
@@ -321,7 +322,7 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
         if (threadIdx.x < 16) {
             double acc = 0.0;
             for (int ww = 0; ww < WG / 64; ++ww) acc += sh[threadIdx.x][ww];
-            part[16 * blockIdx.x + threadIdx.x] = acc;
+            part[16 * blk + threadIdx.x] = acc;
         }
     }
 }

@@ -404,7 +404,7 @@ __global__ __launch_bounds__(LB) void k_list(Dev<R> d)
     __shared__ __align__(8) unsigned short hits[LB * HP];
     __shared__ int off[28], jst[27], cod[27];
     __shared__ int cnt[LB];
-    const int cell = blockIdx.x;
+    const int cell = xcd_block(blockIdx.x, gridDim.x);
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
     const int Kc = d.Kcap;
     const int s0 = d.cell_start[cell], ni = d.cell_start[cell + 1] - s0;

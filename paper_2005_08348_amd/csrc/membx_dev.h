@@ -25,6 +25,18 @@ enum { ST_LANGEVIN = 0, ST_SWAP_DRAW = 1, ST_SWAP_ACCEPT = 2, ST_MDAS_SELECT = 3
 enum { FL_LIST_OVF = 0, FL_SKIN = 1, FL_GHOST_OVF = 2, FL_NONFINITE = 3, FL_AFF_OVF = 4,
        FL_REBUILDS = 5, FL_SKIN_IN = 6, NFLAGS = 8 };
 
+// The 8 XCDs of the chip take work-groups round-robin by id, each with its
+// own L2.  xcd_block(b, n) renumbers work-group b of n so that every XCD
+// runs one contiguous range of logical blocks (a slab of neighbouring
+// cells), so that its coordinate gathers stay in its own L2.  A bijection
+// of [0, n).
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_block(int b, int n)
+{
+    const int x = b % NXCD, l = b / NXCD, per = n / NXCD, rem = n % NXCD;
+    return x < rem ? x * (per + 1) + l : rem * (per + 1) + (x - rem) * per + l;
+}
+
 // device counters (int64)
 enum { CT_STEP = 0, CT_BATCH = 1, CT_CYCLE = 2, CT_MDAS_ACC = 3, NCTR = 4 };
 
