@@ -298,8 +298,9 @@ def main():
                           "batch_plus_2_steps_ms": 1e3 * tsw / nb,
                           "trials_per_s": nb * len(r["du"]) / tsw}
         # ---- the paper's thermostat: velocity rescaling, tau_t 1 ps,
-        # membrane and solvent in two coupling groups (not fused with the
-        # force pass: four launches per step instead of one)
+        # membrane and solvent in two coupling groups (three launches per
+        # step instead of one: the update with the previous step's factors,
+        # the force pass with the closing half-kick, the factors)
         log("[bench] velocity-rescaling leg")
         groups = [1 if k.name == "W" else 0 for k in c1.kinds]
         t_lang = 2.0 * gm.energies(check=False)["kinetic"] / (3 * c1.n_beads * S.KB)

@@ -108,19 +108,23 @@ __device__ __forceinline__ double wave_sum(double v)
 // energies: partial[16 * block] = {lj, rf, pairs, bond, angle, kinetic,
 // list entries, pair virial (3, both directions), bonded virial (3),
 // m v_a^2 (3)}.
-// FUSE: the lane that owns bead i's force also moves the bead through the
+// FUSE 1: the lane that owns bead i's force also moves the bead through the
 // next BAOAB step (its own force is all that step needs), writing the new
 // coordinates to pos_out (the other coordinate buffer: the neighbours' old
 // coordinates are still being read) and the velocity to vel_out.
+// FUSE 2 (velocity rescaling): it makes the step's closing half-kick
+// v += kick F / m instead and writes the block's kinetic energies and bead
+// counts of the two coupling groups to part[4 * block .. + 3], the input of
+// the thermostat's factors.
 // LIST: 0 walk the Verlet list; 1 walk the inner list; 2 walk the Verlet
 // list and rewrite the inner list from it (dynamic pruning): lane s of bead i
 // keeps its entries within r_cut + delta, in order, as its own entries
 // s, s + LPB, ... of the inner list, with its own count, and the bead's
 // coordinates become the reference for the inner list's displacement check.
-template <typename R, int LPB, bool EN, bool FUSE, int LIST>
+template <typename R, int LPB, bool EN, int FUSE, int LIST>
 __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, R kick,
                                            long long step_off, V4<R>* pos_out, V4<R>* vel_out,
-                                           int stats)
+                                           int stats, VrBuf vr)
 {
     __shared__ V4<R> tf[MAXCLS * MAXCLS];
     __shared__ V4<R> te[EN ? MAXCLS * MAXCLS : 1];
@@ -154,12 +158,12 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
         const int n1 = valid ? d.ncnt[i] : 0;
         m1n = n1 > s ? (n1 - s + LPB - 1) / LPB : 0;
     }
-    // FUSE: after the forces, thread t < WG / LPB of the block integrates the
+    // FUSE 1, 2: after the forces, thread t < WG / LPB of the block integrates the
     // block's bead t (forces handed over through LDS), so that the
     // integrator runs on full waves instead of one lane per bead
     constexpr int NBB = WG / LPB;
     const int ib = blk * NBB + threadIdx.x;
-    const bool integ = FUSE && threadIdx.x < NBB && ib < d.N;
+    const bool integ = FUSE != 0 && threadIdx.x < NBB && ib < d.N;
     for (int t = threadIdx.x; t < MAXCLS * MAXCLS; t += WG) {
         tf[t] = d.tabF[t];
         if (EN) te[t] = d.tabE[t];
@@ -252,7 +256,8 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
     // during the walk)
     BeadPre<R> pre{};
     V4<R> pb{};
-    if (integ) {
+    if (FUSE == 2 && integ) pb = d.vel[ib];   // the kick's velocity
+    if (FUSE == 1 && integ) {
         pb = d.posq[ib];
         pre = bead_pre(d, ib, LIST == 1);
         if (LIST == 2) pre.xri = pb;   // this pass makes the bead's coordinates the reference
@@ -288,8 +293,40 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
     }
     if (!EN) {
         const bool own = valid && s == 0;
-        if (!FUSE) {
+        if constexpr (FUSE == 0) {
             if (own) d.frc[i] = V4<R>{ fx, fy, fz, (R)0 };
+        } else if constexpr (FUSE == 2) {
+            __shared__ V4<R> fk[NBB];
+            __shared__ double sk[4][WG / 64];
+            if (own) {
+                const V4<R> f{ fx, fy, fz, (R)0 };
+                d.frc[i] = f;
+                fk[threadIdx.x / LPB] = f;
+            }
+            __syncthreads();
+            double q[4] = { 0.0, 0.0, 0.0, 0.0 };   // K of group 0, 1; beads of group 0, 1
+            if (integ) {
+                V4<R> v = pb;
+                const V4<R> f = fk[threadIdx.x];
+                v.x += kick * v.w * f.x; v.y += kick * v.w * f.y; v.z += kick * v.w * f.z;
+                d.vel[ib] = v;
+                const double k2 =
+                    0.5 * ((double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z) / (double)v.w;
+                const bool g1 = vr_group(d, vr, ib) != 0;
+                q[0] = g1 ? 0.0 : k2; q[1] = g1 ? k2 : 0.0;
+                q[2] = g1 ? 0.0 : 1.0; q[3] = g1 ? 1.0 : 0.0;
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double x = wave_sum(q[c]);
+                if ((threadIdx.x & 63) == 0) sk[c][threadIdx.x >> 6] = x;
+            }
+            __syncthreads();
+            if (threadIdx.x < 4) {
+                double t = 0.0;
+                for (int w = 0; w < WG / 64; ++w) t += sk[threadIdx.x][w];
+                part[4 * blk + threadIdx.x] = t;
+            }
         } else {
             __shared__ V4<R> fsh[NBB];
             if (LIST == 2 && valid) {
@@ -362,13 +399,13 @@ __global__ void k_energy_final(const double* __restrict__ p, int nb, double* __r
 }
 
 // ----------------------------------------------------------------- launch
-template <typename R, int LPB, bool EN, bool FUSE, int LIST>
+template <typename R, int LPB, bool EN, int FUSE, int LIST>
 static void nb_launch(const Dev<R>& d, double* part, R kick, long long step_off, V4<R>* pos_out,
-                      V4<R>* vel_out, int stats, hipStream_t st)
+                      V4<R>* vel_out, int stats, hipStream_t st, VrBuf vr = VrBuf{})
 {
     int nthr = d.N * LPB;
     hipLaunchKernelGGL((k_nb<R, LPB, EN, FUSE, LIST>), dim3((nthr + WG - 1) / WG), dim3(WG), 0, st, d,
-                       part, kick, step_off, pos_out, vel_out, stats);
+                       part, kick, step_off, pos_out, vel_out, stats, vr);
 }
 
 // forces (energy=false) or energies into part (energy=true), Verlet list;
@@ -377,14 +414,14 @@ template <typename R>
 int launch_nonbonded(const Dev<R>& d, int lpb, bool energy, double* part, hipStream_t st)
 {
     switch (lpb * 2 + (energy ? 1 : 0)) {
-    case 2: nb_launch<R, 1, false, false, 0>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
-    case 3: nb_launch<R, 1, true, false, 0>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
-    case 4: nb_launch<R, 2, false, false, 0>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
-    case 5: nb_launch<R, 2, true, false, 0>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
-    case 8: nb_launch<R, 4, false, false, 0>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
-    case 9: nb_launch<R, 4, true, false, 0>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
-    case 16: nb_launch<R, 8, false, false, 0>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
-    case 17: nb_launch<R, 8, true, false, 0>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
+    case 2: nb_launch<R, 1, false, 0, 0>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
+    case 3: nb_launch<R, 1, true, 0, 0>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
+    case 4: nb_launch<R, 2, false, 0, 0>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
+    case 5: nb_launch<R, 2, true, 0, 0>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
+    case 8: nb_launch<R, 4, false, 0, 0>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
+    case 9: nb_launch<R, 4, true, 0, 0>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
+    case 16: nb_launch<R, 8, false, 0, 0>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
+    case 17: nb_launch<R, 8, true, 0, 0>(d, part, 0, 0, nullptr, nullptr, 0, st); break;
     default: break;
     }
     return (d.N * lpb + WG - 1) / WG;
@@ -397,7 +434,7 @@ template <typename R>
 void launch_nonbonded_fused(const Dev<R>& d, int lpb, int list, R kick, long long step_off,
                             V4<R>* pos_out, V4<R>* vel_out, int stats, hipStream_t st)
 {
-#define NBF(L, M) nb_launch<R, L, false, true, M>(d, nullptr, kick, step_off, pos_out, vel_out, stats, st)
+#define NBF(L, M) nb_launch<R, L, false, 1, M>(d, nullptr, kick, step_off, pos_out, vel_out, stats, st)
     switch (lpb * 4 + list) {
     case 4: case 5: case 6: NBF(1, 0); break;
     case 8: NBF(2, 0); break;
@@ -414,12 +451,30 @@ void launch_nonbonded_fused(const Dev<R>& d, int lpb, int list, R kick, long lon
 #undef NBF
 }
 
+// forces followed by velocity rescaling's closing half-kick with the block
+// sums of the kinetic energies (see k_nb, FUSE 2); returns the blocks, i.e.
+// the partials written to vr.part
+template <typename R>
+int launch_nonbonded_kick(const Dev<R>& d, int lpb, const VrBuf& vr, R kick, hipStream_t st)
+{
+    switch (lpb) {
+    case 1: nb_launch<R, 1, false, 2, 0>(d, vr.part, kick, 0, nullptr, nullptr, 0, st, vr); break;
+    case 2: nb_launch<R, 2, false, 2, 0>(d, vr.part, kick, 0, nullptr, nullptr, 0, st, vr); break;
+    case 4: nb_launch<R, 4, false, 2, 0>(d, vr.part, kick, 0, nullptr, nullptr, 0, st, vr); break;
+    case 8: nb_launch<R, 8, false, 2, 0>(d, vr.part, kick, 0, nullptr, nullptr, 0, st, vr); break;
+    default: return 0;
+    }
+    return (d.N * lpb + WG - 1) / WG;
+}
+
 void launch_energy_final(const double* p, int nb, double* out, hipStream_t st)
 {
     hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, st, p, nb, out);
 }
 
 template int launch_nonbonded<float>(const Dev<float>&, int, bool, double*, hipStream_t);
+template int launch_nonbonded_kick<float>(const Dev<float>&, int, const VrBuf&, float, hipStream_t);
+template int launch_nonbonded_kick<double>(const Dev<double>&, int, const VrBuf&, double, hipStream_t);
 template int launch_nonbonded<double>(const Dev<double>&, int, bool, double*, hipStream_t);
 template void launch_nonbonded_fused<float>(const Dev<float>&, int, int, float, long long,
                                             V4<float>*, V4<float>*, int, hipStream_t);

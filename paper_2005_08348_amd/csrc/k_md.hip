@@ -147,16 +147,11 @@ void launch_import(const Dev<R>& d, V4<R>* dst, const double* in, hipStream_t st
 // multiplied by alpha = sqrt(K' / K), with the sign of the new velocity
 // component along the old one, R1 + sqrt(c Nf K / ((1 - c) Kt)).  Random
 // words: Philox stream 5, counter = step index, block (group << 16) for R1
-// and (group << 16) + 1 + t for the t-th attempt of the gamma sampler.  Two
-// launches per step beyond the force pass: half-kick with per-block group
-// sums, one wave for the two factors (float64 throughout); the scaling rides
-// on the next step's update.
-
-template <typename R>
-__device__ __forceinline__ int vr_group(const Dev<R>& d, const VrBuf& vr, int i)
-{
-    return vr.kgroup[d.mol_kind[vr.bmol[d.orig[i]]]];
-}
+// and (group << 16) + 1 + t for the t-th attempt of the gamma sampler.  The
+// half-kick with per-block group sums runs in the force pass itself (k_nb,
+// FUSE 2) or, after an MDAS segment's alchemical forces, in k_kick_ke; then
+// one wave draws the two factors (float64 throughout); the scaling rides on
+// the next step's update.
 
 template <typename R>
 __global__ __launch_bounds__(WG) void k_kick_ke(Dev<R> d, VrBuf vr, R kick)
@@ -228,21 +223,28 @@ __device__ double vr_factor(uint64_t seed, int g, double K, double nf, double kT
 
 // one wave: group sums over the blocks (fixed order), then lanes 0 and 1
 // draw the factors of groups 0 and 1
+// one work-group: the block partials summed (a force pass leaves up to
+// 8 N / 256 of them), then threads 0 and 1 draw the factors
 template <typename R>
-__global__ __launch_bounds__(64) void k_vr_alpha(Dev<R> d, VrBuf vr, int nblk, long long step_off,
+__global__ __launch_bounds__(WG) void k_vr_alpha(Dev<R> d, VrBuf vr, int nblk, long long step_off,
                                                  double c)
 {
-    const int l = threadIdx.x;
+    const int t = threadIdx.x;
     double q[4] = { 0.0, 0.0, 0.0, 0.0 };
-    for (int b = l; b < nblk; b += 64)
+    for (int b = t; b < nblk; b += WG)
 #pragma unroll
         for (int k = 0; k < 4; ++k) q[k] += vr.part[4 * b + k];
+    __shared__ double sw[4][WG / 64];
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 4; ++k) {
         for (int o = 32; o > 0; o >>= 1) q[k] += __shfl_xor(q[k], o, 64);
-    if (l < 2) {
-        const double K = l ? q[1] : q[0], nf = 3.0 * (l ? q[3] : q[2]);
-        vr.alpha[l] = vr_factor(d.seed, l, K, nf, d.kTd, c, d.ctr[CT_STEP] + step_off);
+        if ((t & 63) == 0) sw[k][t >> 6] = q[k];
+    }
+    __syncthreads();
+    if (t < 2) {
+        double K = 0.0, nb = 0.0;
+        for (int w = 0; w < WG / 64; ++w) { K += sw[t][w]; nb += sw[2 + t][w]; }
+        vr.alpha[t] = vr_factor(d.seed, t, K, 3.0 * nb, d.kTd, c, d.ctr[CT_STEP] + step_off);
     }
 }
 
@@ -331,13 +333,18 @@ __global__ __launch_bounds__(WG) void k_vr_kick_drift(Dev<R> d, VrBuf vr, R kick
 // closing half-kick with the group sums, then the factors of the step; the
 // scaling itself runs in the next step's update (k_vr_kick_drift) or, after
 // the last step of a sequence, in k_vr_scale (launch_vr_scale)
+// kicked_blocks > 0: the force pass already made the half-kick and wrote
+// that many block partials
 template <typename R>
 void launch_vrescale(const Dev<R>& d, const VrBuf& vr, R kick, long long step_off, double c,
-                     hipStream_t st)
+                     int kicked_blocks, hipStream_t st)
 {
-    const int nb = (d.N + WG - 1) / WG;
-    hipLaunchKernelGGL(k_kick_ke<R>, dim3(nb), dim3(WG), 0, st, d, vr, kick);
-    hipLaunchKernelGGL(k_vr_alpha<R>, dim3(1), dim3(64), 0, st, d, vr, nb, step_off, c);
+    int nb = kicked_blocks;
+    if (nb <= 0) {
+        nb = (d.N + WG - 1) / WG;
+        hipLaunchKernelGGL(k_kick_ke<R>, dim3(nb), dim3(WG), 0, st, d, vr, kick);
+    }
+    hipLaunchKernelGGL(k_vr_alpha<R>, dim3(1), dim3(WG), 0, st, d, vr, nb, step_off, c);
 }
 template <typename R>
 void launch_vr_scale(const Dev<R>& d, const VrBuf& vr, hipStream_t st)
@@ -354,7 +361,7 @@ void launch_vr_kick_drift(const Dev<R>& d, const VrBuf& vr, R kick, long long st
 
 #define INST(R)                                                                      \
     template void launch_vrescale<R>(const Dev<R>&, const VrBuf&, R, long long, double, \
-                                     hipStream_t);                                   \
+                                     int, hipStream_t);                              \
     template void launch_vr_scale<R>(const Dev<R>&, const VrBuf&, hipStream_t);      \
     template void launch_baro<R>(const Dev<R>&, const double*, double*, double, double, double, \
                                  double, double, hipStream_t);                       \

@@ -234,6 +234,13 @@ template <typename R> struct Dev {
     double* eout;    // final energies
 };
 
+// coupling group (0/1) of the bead in slot i under velocity rescaling
+template <typename R>
+__device__ __forceinline__ int vr_group(const Dev<R>& d, const VrBuf& vr, int i)
+{
+    return vr.kgroup[d.mol_kind[vr.bmol[d.orig[i]]]];
+}
+
 // Exchange moves (batched MC-MD trials and MDAS pair selection) and the
 // sparse alchemical force / energy difference machinery.
 constexpr int SEL_C0 = 1024;     // candidates of the first selection chunk

@@ -28,7 +28,9 @@ void launch_energy_final(const double*, int, double*, hipStream_t);
 template <typename R> void launch_kick_drift(const Dev<R>&, R, long long, int, hipStream_t);
 template <typename R> void launch_kick(const Dev<R>&, R, long long, hipStream_t);
 template <typename R>
-void launch_vrescale(const Dev<R>&, const VrBuf&, R, long long, double, hipStream_t);
+void launch_vrescale(const Dev<R>&, const VrBuf&, R, long long, double, int, hipStream_t);
+template <typename R>
+int launch_nonbonded_kick(const Dev<R>&, int, const VrBuf&, R, hipStream_t);
 template <typename R> void launch_vr_scale(const Dev<R>&, const VrBuf&, hipStream_t);
 template <typename R>
 void launch_baro(const Dev<R>&, const double*, double*, double, double, double, double, double,
@@ -586,7 +588,7 @@ static size_t layout(membx_sys* s, Dev<R>& d, Mv& m, char* base)
     d.ctr = a.take<long long>(NCTR);
     s->nbe_blocks = (N * 8 + WG - 1) / WG;
     s->bd_blocks = ((int)h.bmols.size() + 63) / 64;
-    s->ke_blocks = (N + WG - 1) / WG;
+    s->ke_blocks = (8 * N + WG - 1) / WG;   // blocks of a force pass at 8 lanes per bead
     d.red = a.take<double>(16 * (size_t)s->nbe_blocks);
     d.eout = a.take<double>(16);
     s->xbuf = a.take<double>(3 * (size_t)N);
@@ -792,9 +794,15 @@ static void steps_seq(membx_sys* s, long long n, const Alch* alch, bool launch =
             moved = true;
         } else {
             if (launch) {
-                forces<R>(s, rebuilt);
-                if (alch) alch_terms<R>(s, rebuilt, alch->lam);
-                if (vr) launch_vrescale<R>(d, s->vr, h, k, vr_c, s->st);
+                if (vr && !alch && !s->timing) {
+                    // forces and the closing half-kick in one pass
+                    const int nbk = launch_nonbonded_kick<R>(d, s->h.lpb, s->vr, h, s->st);
+                    launch_vrescale<R>(d, s->vr, h, k, vr_c, nbk, s->st);
+                } else {
+                    forces<R>(s, rebuilt);
+                    if (alch) alch_terms<R>(s, rebuilt, alch->lam);
+                    if (vr) launch_vrescale<R>(d, s->vr, h, k, vr_c, 0, s->st);
+                }
             }
             if (s->sp >= 0) s->sp++;
         }
