@@ -242,7 +242,7 @@ def main():
         "max_displacement_nm": e2["max_displacement"],
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": traffic,
-                     "kernel": f"k_nb<float,{tun['lanes_per_bead']},false,true,{list_kind}> "
+                     "kernel": f"k_nb<float,{tun['lanes_per_bead']},false,1,{list_kind}> "
                                "(nonbonded + bonded forces + next step's B-A-O-A)",
                      "launches_timed": NB_LAUNCHES, "mean_launch_ms": nb_ms,
                      "flop_per_launch": nb_flops,

@@ -61,6 +61,26 @@ def test_vrescale_fp64_c0(oracle_mod, c0_relaxed, tau):
     g.close()
 
 
+@pytest.mark.parametrize("lpb", [1, 2, 4, 8])
+def test_vrescale_fp64_c0_lanes(oracle_mod, c0_relaxed, lpb):
+    """The closing half-kick and the group sums inside the force pass, at
+    every lane count per bead (one set of block sums per work-group)."""
+    m = _membx()
+    g = m.System(c0_relaxed, precision="fp64")
+    g.set_tuning(0.3, 5, lpb)
+    o = oracle_mod.Oracle(c0_relaxed)
+    g.set_ensemble(1, tau_t=0.1, kind_group=GROUPS)
+    o.set_ensemble(1, tau_t=0.1, kind_group=GROUPS)
+    for _ in range(4):
+        g.md_step(5)
+    o.md_step(20)
+    sg, so = g.state(), o.state()
+    assert sg["step"] == so["step"] == 20
+    assert _pos_err(sg["pos"], so["pos"], c0_relaxed.box) < 1e-7
+    assert np.abs(sg["vel"] - so["vel"]).max() < 1e-6
+    g.close()
+
+
 def test_vrescale_mixed_c0(oracle_mod, c0_relaxed):
     m = _membx()
     g = m.System(c0_relaxed, precision="mixed", rebuild_interval=5)
