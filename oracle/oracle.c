@@ -988,8 +988,9 @@ void o_md_step(osys* s, int nsteps)
 }
 
 /* Capped steepest descent: each bead moves by alpha F_i, shortened to at most
- * `cap` nm.  Used only to relax synthetic start structures.  Parity unpinned:
- * no test pins it and no GPU result is compared with it. */
+ * `cap` nm.  Used only to relax synthetic start structures.  Pinned by the
+ * LJ minimum at 2^(1/6) sigma of an isolated pair, a lone bond relaxing to
+ * b0 and the exact cap from an overlap; no GPU result is compared with it. */
 void o_minimize(osys* s, int n_iter, double alpha, double cap)
 {
     double e[4];

@@ -807,3 +807,56 @@ def test_soft_core_path_end_states(oracle_mod, name):
         assert np.array_equal(lin["pairs"], sc["pairs"])
         assert abs(sc["work"] - (ub - ua)) < 1e-8 * max(1.0, abs(ua))
         assert abs(sc["work"] - lin["work"]) < 1e-8 * max(1.0, abs(ua))
+
+
+# ---------------------------------------------------------------- minimizer
+def _pair_system(r, eps_nn=5.0, bonded=False):
+    """Two beads of type N at distance r along x in a 6 nm box: two one-bead
+    molecules (LJ between them), or one two-bead molecule whose beads are
+    bonded with b0 = 0.47 nm, k = 1250 kJ/mol/nm^2 (LJ excluded)."""
+    eps = np.zeros((S.N_TYPES, S.N_TYPES))
+    eps[S.TYPE_N, S.TYPE_N] = eps_nn
+    pos = [[2.0, 3.0, 3.0], [2.0 + r, 3.0, 3.0]]
+    if bonded:
+        k = S.Kind("B", [S.TYPE_N, S.TYPE_N], [0.0, 0.0], [(0, 1, 0.47, 1250.0)], [], -1)
+        return S.custom("pair", [k], [0], pos, [6.0, 6.0, 6.0], eps)
+    k = S.Kind("P", [S.TYPE_N], [0.0], [], [], -1)
+    return S.custom("pair", [k], [0, 0], pos, [6.0, 6.0, 6.0], eps)
+
+
+def _sep(o):
+    p = o.state()["pos"]
+    return float(np.linalg.norm(p[1] - p[0]))
+
+
+@pytest.mark.parametrize("r0", [0.45, 0.6, 0.9])
+def test_minimize_lj_pair_reaches_lj_minimum(oracle_mod, r0):
+    """Capped steepest descent on two LJ beads stops where the 12-6 force
+    vanishes, r = 2^(1/6) sigma (the potential shift at the cutoff is a
+    constant and moves no minimum), from either side."""
+    o = oracle_mod.Oracle(_pair_system(r0))
+    o.minimize(400, alpha=1e-4, cap=0.01)
+    assert abs(_sep(o) - 2.0 ** (1.0 / 6.0) * S.SIGMA) < 1e-9
+    e = o.energy_forces()
+    assert np.abs(e["force"]).max() < 1e-6
+    vc = 4.0 * 5.0 * ((S.SIGMA / RC) ** 12 - (S.SIGMA / RC) ** 6)
+    assert abs(e["lj"] - (-5.0 - vc)) < 1e-9   # the well depth, shifted at r_c
+
+
+def test_minimize_bond_reaches_rest_length(oracle_mod):
+    """A harmonic bond alone (its pair is excluded from LJ) relaxes to b0."""
+    o = oracle_mod.Oracle(_pair_system(0.55, bonded=True))
+    o.minimize(400, alpha=1e-4, cap=0.01)
+    assert abs(_sep(o) - 0.47) < 1e-9
+
+
+def test_minimize_step_cap(oracle_mod):
+    """From a deep overlap every bead moves by exactly the cap, along the
+    force: one iteration separates the pair by 2 cap."""
+    s = _pair_system(0.3)
+    r0 = float(np.linalg.norm(s.pos[1] - s.pos[0]))
+    o = oracle_mod.Oracle(s)
+    o.minimize(1, alpha=1e-4, cap=0.01)
+    p = o.state()["pos"]
+    assert abs(_sep(o) - (r0 + 0.02)) < 1e-12
+    assert abs(p[0][1] - 3.0) < 1e-12 and abs(p[1][2] - 3.0) < 1e-12
