@@ -255,8 +255,8 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
     // force reduction (loaded here, not up front, to keep registers free
     // during the walk)
     BeadPre<R> pre{};
-    V4<R> pb{};
-    if (FUSE == 2 && integ) pb = d.vel[ib];   // the kick's velocity
+    V4<R> pb{}, vk{};
+    if (FUSE == 2 && integ) vk = d.vel[ib];   // the closing half-kick's velocity
     if (FUSE == 1 && integ) {
         pb = d.posq[ib];
         pre = bead_pre(d, ib, LIST == 1);
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
             __syncthreads();
             double q[4] = { 0.0, 0.0, 0.0, 0.0 };   // K of group 0, 1; beads of group 0, 1
             if (integ) {
-                V4<R> v = pb;
+                V4<R> v = vk;
                 const V4<R> f = fk[threadIdx.x];
                 v.x += kick * v.w * f.x; v.y += kick * v.w * f.y; v.z += kick * v.w * f.z;
                 d.vel[ib] = v;
