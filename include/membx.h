@@ -273,7 +273,10 @@ int32_t membx_set_tuning(membx_sys* sys, double skin, int32_t rebuild_interval,
  * rebuild interval is the largest that keeps every bead within 0.8 skin/2,
  * and the inner buffer the smallest that keeps it within 0.8 delta/2 over a
  * prune interval.  A candidate is rejected if, in its timed runs, a bead went
- * beyond 0.9 skin/2 or beyond delta/2.  Positions, velocities, kinds and
+ * beyond 0.9 skin/2 or beyond delta/2.  Candidates whose list build had to
+ * re-test a crowded cell's candidates (a lane's hit buffer overflowed) are
+ * chosen only if every candidate did: that path grows as a fresh system
+ * equilibrates.  Positions, velocities, kinds and
  * random-number counters are restored afterwards; forces are recomputed and
  * the list is rebuilt.  Writes the chosen values and leaves the system
  * tuned.  E_DEVICE. */

@@ -569,6 +569,7 @@ __global__ __launch_bounds__(LB) void k_list(Dev<R> d)
                                 d.nbr[ibase + nbr_koff(k0 + k + u, d.lpb_shift)] = e4[u];
                     }
                 } else {
+                    atomicOr(&d.flags[FL_HIT_OVF], 1);
                     int mm = 0;
                     for (int u = 0; u < nu; ++u) {
                         const int c = q + u * Q;
