@@ -25,6 +25,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define O_KB 0.00831446261815324      /* kJ/mol/K */
 #define O_FELEC 138.935458            /* kJ mol^-1 nm e^-2, 1/(4 pi eps0) */
@@ -64,6 +67,7 @@ typedef struct {
     /* scratch */
     int *mk_tmp;
     double *f_tmp;
+    double *f_slab;          /* per-slab force buffers of the nonbonded loop */
     /* ensemble: 0 Langevin BAOAB, 1 velocity Verlet + stochastic velocity
      * rescaling of two coupling groups */
     int ensemble;
@@ -267,7 +271,7 @@ void o_destroy(osys* s)
     void* p[] = { s->kn, s->koff, s->ktype, s->kfam, s->kq, s->km, s->knb, s->kboff,
                   s->bi, s->bj, s->bb0, s->bk, s->kna, s->kaoff, s->ai, s->aj, s->ak,
                   s->acos0, s->akk, s->mkind, s->mfirst, s->bmol, s->bloc, s->nexcl,
-                  s->excl, s->c6, s->c12, s->x, s->v, s->f, s->mk_tmp, s->f_tmp, s->region };
+                  s->excl, s->c6, s->c12, s->x, s->v, s->f, s->mk_tmp, s->f_tmp, s->region, s->f_slab };
     for (size_t i = 0; i < sizeof(p) / sizeof(p[0]); ++i) free(p[i]);
     free(s);
 }
@@ -391,12 +395,45 @@ static void grid_free(cgrid* g) { free(g->head); free(g->next); }
  * path, otherwise the all-pairs path is used. */
 typedef void (*pair_fn)(osys* s, int i, int j, const double d[3], double r2, void* ctx);
 
+static int cells_usable(const osys* s, double cut, int use_cells)
+{
+    int ok = use_cells;
+    for (int a = 0; a < 3; ++a) if (s->box[a] < 3.0 * cut) ok = 0;
+    return ok;
+}
+
+/* The pairs whose first bead lies in the cells cx in [cx0, cx1) of grid g. */
+static void for_pairs_slab(osys* s, const cgrid* g, double cut2, int cx0, int cx1, pair_fn fn,
+                           void* ctx)
+{
+    for (int cx = cx0; cx < cx1; ++cx)
+    for (int cy = 0; cy < g->nc[1]; ++cy)
+    for (int cz = 0; cz < g->nc[2]; ++cz) {
+        int c = (cx * g->nc[1] + cy) * g->nc[2] + cz;
+        for (int i = g->head[c]; i >= 0; i = g->next[i]) {
+            for (int ox = -1; ox <= 1; ++ox)
+            for (int oy = -1; oy <= 1; ++oy)
+            for (int oz = -1; oz <= 1; ++oz) {
+                int nx = (cx + ox + g->nc[0]) % g->nc[0];
+                int ny = (cy + oy + g->nc[1]) % g->nc[1];
+                int nz = (cz + oz + g->nc[2]) % g->nc[2];
+                int cn = (nx * g->nc[1] + ny) * g->nc[2] + nz;
+                for (int j = g->head[cn]; j >= 0; j = g->next[j]) {
+                    if (j <= i) continue;
+                    double d[3];
+                    min_image(s, &s->x[3 * i], &s->x[3 * j], d);
+                    double r2 = dist2(d);
+                    if (r2 < cut2 && !excluded(s, i, j)) fn(s, i, j, d, r2, ctx);
+                }
+            }
+        }
+    }
+}
+
 static void for_pairs(osys* s, double cut, int use_cells, pair_fn fn, void* ctx)
 {
     double cut2 = cut * cut;
-    int cells_ok = use_cells;
-    for (int a = 0; a < 3; ++a) if (s->box[a] < 3.0 * cut) cells_ok = 0;
-    if (!cells_ok) {
+    if (!cells_usable(s, cut, use_cells)) {
         for (int i = 0; i < s->n; ++i)
             for (int j = i + 1; j < s->n; ++j) {
                 double d[3];
@@ -408,28 +445,7 @@ static void for_pairs(osys* s, double cut, int use_cells, pair_fn fn, void* ctx)
     }
     cgrid g;
     grid_build(s, cut, &g);
-    for (int cx = 0; cx < g.nc[0]; ++cx)
-    for (int cy = 0; cy < g.nc[1]; ++cy)
-    for (int cz = 0; cz < g.nc[2]; ++cz) {
-        int c = (cx * g.nc[1] + cy) * g.nc[2] + cz;
-        for (int i = g.head[c]; i >= 0; i = g.next[i]) {
-            for (int ox = -1; ox <= 1; ++ox)
-            for (int oy = -1; oy <= 1; ++oy)
-            for (int oz = -1; oz <= 1; ++oz) {
-                int nx = (cx + ox + g.nc[0]) % g.nc[0];
-                int ny = (cy + oy + g.nc[1]) % g.nc[1];
-                int nz = (cz + oz + g.nc[2]) % g.nc[2];
-                int cn = (nx * g.nc[1] + ny) * g.nc[2] + nz;
-                for (int j = g.head[cn]; j >= 0; j = g.next[j]) {
-                    if (j <= i) continue;
-                    double d[3];
-                    min_image(s, &s->x[3 * i], &s->x[3 * j], d);
-                    double r2 = dist2(d);
-                    if (r2 < cut2 && !excluded(s, i, j)) fn(s, i, j, d, r2, ctx);
-                }
-            }
-        }
-    }
+    for_pairs_slab(s, &g, cut2, 0, g.nc[0], fn, ctx);
     grid_free(&g);
 }
 
@@ -498,15 +514,63 @@ static void bonded(const osys* s, const int* mk, double* f, double* eb, double* 
 
 /* Energies and forces for molecule kinds mk.  e = {lj, rf, bond, angle}.
  * use_cells selects the cell-list pair loop (identical pair set). */
+/* The cell path visits the pairs in O_NSLAB slabs of cells along x, each
+ * with its own energy sums and force buffer, and adds the slabs in slab
+ * order: the result is the same whether the slabs run one after another or
+ * on several threads (OpenMP, when the oracle is built with it). */
+#define O_NSLAB 16
 static long energy_forces(osys* s, const int* mk, double* f, double e[4], int use_cells)
 {
     if (f) memset(f, 0, sizeof(double) * 3 * s->n);
-    nb_ctx c = { mk, f, 0.0, 0.0, 0 };
-    for_pairs(s, s->rc, use_cells, nb_pair, &c);
     double eb, ea;
+    if (!cells_usable(s, s->rc, use_cells)) {
+        nb_ctx c = { mk, f, 0.0, 0.0, 0 };
+        for_pairs(s, s->rc, 0, nb_pair, &c);
+        bonded(s, mk, f, &eb, &ea);
+        e[0] = c.elj; e[1] = c.erf; e[2] = eb; e[3] = ea;
+        return c.npairs;
+    }
+    cgrid g;
+    grid_build(s, s->rc, &g);
+    const size_t n3 = 3 * (size_t)s->n;
+    if (f && !s->f_slab) s->f_slab = (double*)malloc(sizeof(double) * n3 * O_NSLAB);
+    nb_ctx c[O_NSLAB];
+    const double rc2 = s->rc * s->rc;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) if (s->n >= 20000)
+#endif
+    for (int k = 0; k < O_NSLAB; ++k) {
+        double* fk = f ? s->f_slab + n3 * k : NULL;
+        if (fk) memset(fk, 0, sizeof(double) * n3);
+        c[k].mk = mk; c[k].f = fk; c[k].elj = 0.0; c[k].erf = 0.0; c[k].npairs = 0;
+        for_pairs_slab(s, &g, rc2, k * g.nc[0] / O_NSLAB, (k + 1) * g.nc[0] / O_NSLAB, nb_pair,
+                       &c[k]);
+    }
+    grid_free(&g);
+    long np = 0;
+    double elj = 0.0, erf = 0.0;
+    for (int k = 0; k < O_NSLAB; ++k) {
+        elj += c[k].elj; erf += c[k].erf; np += c[k].npairs;
+        if (f)
+            for (size_t q = 0; q < n3; ++q) f[q] += s->f_slab[n3 * k + q];
+    }
     bonded(s, mk, f, &eb, &ea);
-    e[0] = c.elj; e[1] = c.erf; e[2] = eb; e[3] = ea;
-    return c.npairs;
+    e[0] = elj; e[1] = erf; e[2] = eb; e[3] = ea;
+    return np;
+}
+
+/* Number of threads the slabs of the nonbonded loop and the sampled forces
+ * may use (1 without OpenMP); n <= 0 leaves the current setting.  Returns
+ * the setting in force. */
+int o_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 /* public: energies/forces of the current state.  out_e = {lj, rf, bond,
@@ -598,6 +662,11 @@ void o_virial(osys* s, double* w, int use_cells)
 void o_forces_on(osys* s, int nsel, const int* sel, double* fout, double* near_cut)
 {
     double rc2 = s->rc * s->rc;
+    int maxkn = 1;
+    for (int k = 0; k < s->nk; ++k) if (s->kn[k] > maxkn) maxkn = s->kn[k];
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4) if ((double)nsel * s->n >= 1e7)
+#endif
     for (int q = 0; q < nsel; ++q) {
         int i = sel[q];
         double fx = 0, fy = 0, fz = 0, nc = 1e300;
@@ -616,7 +685,7 @@ void o_forces_on(osys* s, int nsel, const int* sel, double* fout, double* near_c
         }
         /* bonded terms touching bead i: evaluate its molecule's terms */
         int m = s->bmol[i], k = s->mkind[m], f0 = s->mfirst[m];
-        double* fm = s->f_tmp;
+        double* fm = (double*)malloc(sizeof(double) * 3 * maxkn);
         int nb = s->kn[k];
         memset(fm, 0, sizeof(double) * 3 * nb);
         for (int b = 0; b < s->knb[k]; ++b) {
@@ -650,6 +719,7 @@ void o_forces_on(osys* s, int nsel, const int* sel, double* fout, double* near_c
         fout[3 * q + 1] = fy + fm[3 * lb + 1];
         fout[3 * q + 2] = fz + fm[3 * lb + 2];
         if (near_cut) near_cut[q] = nc;
+        free(fm);
     }
 }
 
@@ -781,6 +851,24 @@ static double force_eval(osys* s, const int* mk_b, double lam, double* f)
     s->n_fe++;
     for (int i = 0; i < 3 * s->n; ++i) f[i] = (1.0 - lam) * s->f_tmp[i] + lam * f[i];
     return (1.0 - lam) * (e[0] + e[1] + e[2] + e[3]) + lam * (eb[0] + eb[1] + eb[2] + eb[3]);
+}
+
+/* U(lambda) and F(lambda) = -grad U(lambda) of the MDAS path in force (the
+ * linear coupling of Eq. 2, or the soft-core path of Eq. 4) for exchanging
+ * the given pairs, at the current coordinates: what the dynamics of an
+ * alchemical trajectory feel at coupling lambda (not counted as an FE). */
+double o_hybrid_energy_forces(osys* s, int n_pairs, const int* pairs, double lam, double* f)
+{
+    int* mk_b = (int*)malloc(sizeof(int) * s->nm);
+    memcpy(mk_b, s->mkind, sizeof(int) * s->nm);
+    for (int p = 0; p < n_pairs; ++p) {
+        int X = pairs[2 * p], Y = pairs[2 * p + 1];
+        mk_b[X] = s->mkind[Y]; mk_b[Y] = s->mkind[X];
+    }
+    double u = force_eval(s, mk_b, lam, f);
+    s->n_fe--;
+    free(mk_b);
+    return u;
 }
 
 /* Refresh the stored forces for the current state (needed after set_state). */
@@ -1292,13 +1380,9 @@ void o_pair_histogram(const osys* s, int kind, int po4, const int* leaflet, int 
         for (int b = a + 1; b < s->nm; ++b) {
             if (s->mkind[b] != kind || leaflet[b] != leaflet[a]) continue;
             const int ib = s->mfirst[b] + po4;
-            double dx = s->x[3 * ia] - s->x[3 * ib];
-            double dy = s->x[3 * ia + 1] - s->x[3 * ib + 1];
-            if (dx > 0.5 * s->box[0]) dx -= s->box[0];
-            else if (dx < -0.5 * s->box[0]) dx += s->box[0];
-            if (dy > 0.5 * s->box[1]) dy -= s->box[1];
-            else if (dy < -0.5 * s->box[1]) dy += s->box[1];
-            const double d2 = dx * dx + dy * dy;
+            double d[3];
+            min_image(s, &s->x[3 * ia], &s->x[3 * ib], d);
+            const double d2 = d[0] * d[0] + d[1] * d[1];
             int k = (int)(sqrt(d2) / w);
             while (k > 0 && bin_edge2(k, w) > d2) --k;
             while (bin_edge2(k + 1, w) <= d2) ++k;

@@ -27,11 +27,13 @@ _i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
 
 
 def build(force=False):
-    """Compile oracle.c with gcc (plain -O2, no FMA contraction)."""
+    """Compile oracle.c with gcc (plain -O2, no FMA contraction; OpenMP runs
+    the slabs of the nonbonded loop and the sampled forces on several
+    threads, with results independent of the thread count)."""
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
         return LIB
     tmp = LIB + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+    cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-fopenmp",
            "-shared", "-o", tmp, SRC, "-lm"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
@@ -100,8 +102,17 @@ def lib():
         L.o_gauss3.argtypes = [_u32p, _f64p]
         L.o_pair_term.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_double,
                                   C.c_double, _f64p]
+        L.o_hybrid_energy_forces.argtypes = [C.c_void_p, C.c_int, _i32p, C.c_double, _f64p]
+        L.o_hybrid_energy_forces.restype = C.c_double
+        L.o_threads.argtypes = [C.c_int]
+        L.o_threads.restype = C.c_int
         _lib = L
     return _lib
+
+
+def threads(n=0):
+    """threads of the oracle's parallel loops (n <= 0: query only)"""
+    return lib().o_threads(int(n))
 
 
 def philox(ctr, key):
@@ -214,6 +225,14 @@ class Oracle:
         """U at lambda on the soft-core path for exchanging pairs [(X, Y), ...]"""
         pr = _i32(pairs)
         return lib().o_sc_energy(self.h, len(pr) // 2, pr, float(lam))
+
+    def hybrid_energy_forces(self, pairs, lam):
+        """U(lambda) and F(lambda) on the MDAS path in force (linear, or
+        soft-core after set_mdas_path(1)) for exchanging pairs [(X, Y), ...]"""
+        pr = _i32(pairs)
+        f = np.zeros(3 * self.n)
+        u = lib().o_hybrid_energy_forces(self.h, len(pr) // 2, pr, float(lam), f)
+        return u, f.reshape(-1, 3)
 
     def box(self):
         b = np.zeros(3)
