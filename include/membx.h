@@ -218,6 +218,19 @@ int32_t membx_mdas_cycle(membx_sys* sys, int32_t n_pairs, int32_t k_increments,
  * E_LIST_OVERFLOW when the device flagged it since the last call. */
 int32_t membx_energies(membx_sys* sys, membx_energy* out);
 
+/* membx_energies for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results (bit for bit), with the energy
+ * pass's block partials and final sums in a file-scope device array of the
+ * library (8 MiB, one per device, held until the process ends) instead of
+ * the system's arena.  Allocates nothing.  Systems whose partials need more
+ * than the array (16 doubles per 256 lanes of the pass, 16 final sums) get
+ * E_NOMEM.  Every call on a device shares that device's array: calls that
+ * overlap on one device (from several threads or streams) race; the array
+ * needs no clearing, as each call overwrites what it reads.
+ * Synchronizes.  Errors as membx_energies, plus E_NOMEM. */
+int32_t membx_energies_noalloc(membx_sys* sys, membx_energy* out);
+
 /* Copy the state out in bead-id order (any pointer may be NULL).
  * counters = {step, batch, cycle}.  Synchronizes. */
 int32_t membx_get_state(membx_sys* sys, double* pos, double* vel, int32_t* mol_kind,

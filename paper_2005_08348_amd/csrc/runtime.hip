@@ -10,6 +10,7 @@
 #include <deque>
 #include <iterator>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -469,6 +470,7 @@ struct membx_sys {
     Dev<double> dd;
     Mv mv;
     hipStream_t st = nullptr, user = nullptr;
+    int device = 0;          // device current at creation
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     int since = 0;           // steps since the last rebuild
     long long step = 0, batch = 0, cycle = 0, fe = 0, n_rebuilds = 0;
@@ -1274,6 +1276,7 @@ int32_t membx_sys_create(const membx_desc* desc, void* dev_arena, uint64_t arena
     if (s->mixed()) layout<float>(s, s->df, s->mv, base);
     else layout<double>(s, s->dd, s->mv, base);
     s->user = (hipStream_t)hip_stream;
+    if (hipGetDevice(&s->device) != hipSuccess) { delete s; return MEMBX_E_DEVICE; }
     if (hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&s->ev_out, hipEventDisableTiming) != hipSuccess) {
@@ -1411,15 +1414,26 @@ static void reset_disp(membx_sys* s)
     launch_fill_i32(d.flags + FL_HIT_OVF, 0, 1, s->st);
 }
 
+// Block partials of the energy pass: 16 doubles per work-group it launches.
+static size_t energy_partials(const membx_sys* s)
+{
+    return 16 * (((size_t)s->h.N * s->h.lpb + WG - 1) / WG);
+}
+
+// part: the energy pass's block partials (energy_partials(s) doubles), eout:
+// their 16 final sums; the arena's buffers unless the caller brings others
 template <typename R>
-static int32_t energies_impl(membx_sys* s, membx_energy* out)
+static int32_t energies_impl(membx_sys* s, membx_energy* out, double* part = nullptr,
+                             double* eout = nullptr)
 {
     Dev<R>& d = dev<R>(s);
-    int nnb = launch_nonbonded<R>(d, s->h.lpb, true, d.red, s->st);
-    launch_energy_final(d.red, nnb, d.eout, s->st);
+    if (!part) part = d.red;
+    if (!eout) eout = d.eout;
+    int nnb = launch_nonbonded<R>(d, s->h.lpb, true, part, s->st);
+    launch_energy_final(part, nnb, eout, s->st);
     double e[16];
     int fl[NFLAGS];
-    HCK(hipMemcpyAsync(e, d.eout, sizeof(double) * 13, hipMemcpyDeviceToHost, s->st));
+    HCK(hipMemcpyAsync(e, eout, sizeof(double) * 13, hipMemcpyDeviceToHost, s->st));
     int32_t rc = read_flags(s, fl);
     if (rc) return rc;
     membx_energy E{};
@@ -1454,6 +1468,61 @@ int32_t membx_energies(membx_sys* s, membx_energy* out)
     int32_t rc = begin(s);
     if (rc) return rc;
     rc = DISPATCH(s, energies_impl, s, out);
+    int32_t rc2 = end(s);
+    return rc ? rc : rc2;
+}
+
+// ------------------------------------------------------ allocation-free energies
+// Scratch of membx_energies_noalloc: the energy pass's block partials and
+// their final sums live in this file-scope device array instead of the
+// system's arena.  Each device holds its own copy until the process ends;
+// host code reaches it only through the address hipGetSymbolAddress gives
+// on that device (the array's name is a host-side stand-in).
+constexpr size_t NOALLOC_DOUBLES = (size_t)1 << 20;   // 8 MiB
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+constexpr int NOALLOC_MAXDEV = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch[NOALLOC_MAXDEV];
+
+// Address of the scratch array on device dev, looked up once per device
+// with that device current.
+static int32_t scratch_on(membx_sys* s, int dev, double** out)
+{
+    if (dev < 0 || dev >= NOALLOC_MAXDEV) return fail(s, MEMBX_E_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        int cur = 0;
+        if (hipGetDevice(&cur) != hipSuccess) return fail(s, MEMBX_E_DEVICE, "hipGetDevice failed");
+        if (cur != dev && hipSetDevice(dev) != hipSuccess)
+            return fail(s, MEMBX_E_DEVICE, "hipSetDevice failed");
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p)
+            return fail(s, MEMBX_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                               hipGetErrorString(e));
+        g_scratch[dev] = (double*)p;
+    }
+    *out = g_scratch[dev];
+    return MEMBX_OK;
+}
+
+int32_t membx_energies_noalloc(membx_sys* s, membx_energy* out)
+{
+    if (!s) return MEMBX_E_INVAL;
+    const size_t need = energy_partials(s) + 16;
+    if (need > NOALLOC_DOUBLES)
+        return fail(s, MEMBX_E_NOMEM, "system too large for the allocation-free energy scratch (" +
+                                          std::to_string(need * 8) + " bytes needed, " +
+                                          std::to_string(NOALLOC_DOUBLES * 8) + " available)");
+    double* sp = nullptr;
+    int32_t rc = scratch_on(s, s->device, &sp);
+    if (rc) return rc;
+    rc = begin(s);
+    if (rc) return rc;
+    double* part = sp;
+    double* eout = sp + energy_partials(s);
+    rc = s->mixed() ? energies_impl<float>(s, out, part, eout) : energies_impl<double>(s, out, part, eout);
     int32_t rc2 = end(s);
     return rc ? rc : rc2;
 }

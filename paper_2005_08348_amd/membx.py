@@ -112,6 +112,7 @@ def lib():
             "membx_mc_swap_trials": ([vp, i32, C.POINTER(i32), C.POINTER(i32), vp], i32),
             "membx_mdas_cycle": ([vp, i32, i32, i32, C.POINTER(dp), C.POINTER(i32), vp], i32),
             "membx_energies": ([vp, C.POINTER(Energy)], i32),
+            "membx_energies_noalloc": ([vp, C.POINTER(Energy)], i32),
             "membx_get_state": ([vp, vp, vp, vp, vp], i32),
             "membx_set_state": ([vp, vp, vp, vp, vp], i32),
             "membx_forces": ([vp, vp], i32),
