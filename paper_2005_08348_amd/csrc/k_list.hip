@@ -2,8 +2,9 @@
 // Verlet neighbour list.
 //
 // Layout.  Beads live in "slots" sorted by cell (cells of edge >= r_cut +
-// skin, at least three per axis, z fastest), and within a cell by bead id,
-// so the order is deterministic.  Coordinates stay in [0, L) up to the drift
+// skin, at least three per axis, z fastest), and within a cell by z, then
+// bead id, so the order is deterministic and a bead's neighbours in a cell
+// are nearby slots.  Coordinates stay in [0, L) up to the drift
 // since the last rebuild.  Periodic images need no per-pair image
 // arithmetic: the top cell layer of each axis is copied, shifted by -L
 // (exact in floating point because x >= L/2), into a halo layer below 0
@@ -244,15 +245,24 @@ __global__ __launch_bounds__(BB) void k_scatter(Dev<R> d)
     d.alch_t[dst] = d.alch[i];
 }
 
-// One wave per cell: the cell's beads in bead-id order (a bead's rank is the
-// number of the cell's beads with a smaller id) moved to their final slots,
+// One wave per cell: the cell's beads in (z, bead id) order (a bead's rank is
+// the number of the cell's beads with a smaller key) moved to their final slots,
 // and their periodic images written to the halo cells this cell sources (the
 // bead of rank r is image r of each); each bead records its images with
 // their shift codes for the integrator.
+// Sort key of a bead within its cell: the z coordinate's float32 bits (z is
+// wrapped into [0, L), so the bits order like the values) above the bead id.
+template <typename R>
+__device__ __forceinline__ unsigned long long zkey(R z, int id)
+{
+    const float zf = (float)z;
+    return ((unsigned long long)(unsigned)__float_as_int(zf) << 32) | (unsigned)id;
+}
+
 template <typename R>
 __global__ __launch_bounds__(64) void k_place(Dev<R> d)
 {
-    __shared__ int ids[256];
+    __shared__ unsigned long long keys[256];
     const int cell = blockIdx.x, l = threadIdx.x;
     const int b = d.cell_start[cell], n = d.cell_start[cell + 1] - b;
     const int cz = cell % d.nc[2], cy = (cell / d.nc[2]) % d.nc[1], cx = cell / (d.nc[2] * d.nc[1]);
@@ -261,13 +271,17 @@ __global__ __launch_bounds__(64) void k_place(Dev<R> d)
     for (int m0 = 0; m0 < n; m0 += 64) {
         const int m = m0 + l;
         const int o = m < n ? d.orig_t[b + m] : 0x7fffffff;
+        // the key: the wrapped z coordinate (non-negative, so its bits order
+        // like the values) then the bead id; a strict total order
+        const unsigned long long key =
+            m < n ? zkey(d.posq_t[b + m].z, o) : ~0ull;
         int r = 0;
         for (int c0 = 0; c0 < n; c0 += 256) {
             const int nn = min(256, n - c0);
             __syncthreads();
-            for (int k = l; k < nn; k += 64) ids[k] = d.orig_t[b + c0 + k];
+            for (int k = l; k < nn; k += 64) keys[k] = zkey(d.posq_t[b + c0 + k].z, d.orig_t[b + c0 + k]);
             __syncthreads();
-            for (int k = 0; k < nn; ++k) r += ids[k] < o ? 1 : 0;
+            for (int k = 0; k < nn; ++k) r += keys[k] < key ? 1 : 0;
         }
         if (m >= n) continue;
         const int p = b + m, s = b + r;
