@@ -27,7 +27,9 @@ PEAK_HBM = 8.0e12         # MI355X HBM3E B/s
 FLOP_PAIR_F = 31          # algorithmic flops per in-cutoff pair, forces only
 CALIB_BYTES = 512 << 20   # plain copy used to scale the HBM byte counters
 NB_LAUNCHES = 200         # graph-replayed launches for the kernel duration
-KERNEL_SOURCES = ("paper_2005_08348_amd/csrc/k_force.hip", "paper_2005_08348_amd/csrc/membx_dev.h")
+# the force pass and the list layout it walks (cell order, lane interleave)
+KERNEL_SOURCES = ("paper_2005_08348_amd/csrc/k_force.hip", "paper_2005_08348_amd/csrc/membx_dev.h",
+                  "paper_2005_08348_amd/csrc/k_list.hip")
 
 
 def kernel_source_sha():
@@ -127,28 +129,28 @@ def cpu_baseline(sysm, target_s=10.0):
                 one_thread=r_one, host_cpus=os.cpu_count(), cpu_model=cpu_model())
 
 
-def serving_leg(n_jobs, budget=2 << 30):
-    """Serving: n_jobs bilayers with N log-uniform in [1.4k, 250k] beads, each
-    relaxed (100 steepest-descent steps) at admission, then 4 cycles of 50 MD
-    steps and 20 MDAS cycles (8 pairs, K 50, M 1), all
-    submitted at once to a server whose arena budget forces admission to
-    wait for finished jobs."""
+def _serve(jobs, req, budget, arrivals=None, one_at_a_time=False):
+    """Run jobs through one server.  arrivals: submit times (s from the
+    start; None: all at once); one_at_a_time: each job is submitted when the
+    previous one finished (sequential reference)."""
     import numpy as np
     import torch
     from paper_2005_08348_amd import membx as M
-    from paper_2005_08348_amd import systems as S
-    log(f"[bench] serving leg: building {n_jobs} jobs")
-    jobs = S.serving_jobs(48)[:n_jobs]
-    req = dict(minimize_iters=100, md_cycles=4, md_steps=50, mdas_cycles=20, mdas_pairs=8,
-               mdas_k=50, mdas_m=1)
     srv = M.Server(budget)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for s in jobs:
-        srv.submit(s, **req)
-    done, max_wait, max_res = [], 0, 0
+    done, max_wait, max_res, nxt = [], 0, 0, 0
     last = t0
     while len(done) < len(jobs):
+        now = time.perf_counter() - t0
+        if one_at_a_time:
+            if nxt == len(done) and nxt < len(jobs):
+                srv.submit(jobs[nxt], **req)
+                nxt += 1
+        else:
+            while nxt < len(jobs) and (arrivals is None or arrivals[nxt] <= now):
+                srv.submit(jobs[nxt], **req)
+                nxt += 1
         res, nres, nwait = srv.poll()
         done += res
         max_wait, max_res = max(max_wait, nwait), max(max_res, nres)
@@ -157,21 +159,62 @@ def serving_leg(n_jobs, budget=2 << 30):
             log(f"[bench] serving: {len(done)}/{len(jobs)} jobs done")
     wall = time.perf_counter() - t0
     cyc = srv.cycle_times()
+    cpairs = srv.cycle_pairs()
     srv.close()
     bad = [r for r in done if r["status"] != 0]
     steps = sum(r["md_steps"] for r in done)
-    pair_int = sum(r["pairs_in_cutoff"] * r["md_steps"] for r in done)
+    pair_int = sum(r["pair_interactions"] for r in done)
     turn = np.array([r["finish_s"] - r["submit_s"] for r in done])
+    wait = np.array([r["admit_s"] - r["submit_s"] for r in done])
     return {"jobs": len(done), "failed": len(bad), "budget_bytes": budget,
-            "beads_total": int(sum(s.n_beads for s in jobs)),
             "max_resident": max_res, "max_waiting": max_wait,
             "wall_s": wall, "jobs_per_s": len(done) / wall,
             "md_steps_per_s": steps / wall,
-            "pair_interactions_per_s_est": pair_int / wall,
+            # measured: each cycle's in-cutoff pair count (energy pass at the
+            # cycle's end) times its MD steps, summed over all cycles
+            "pair_interactions_per_s": pair_int / wall,
+            "pair_interactions_cycle_sum_check": bool(abs(float(cpairs.sum()) - pair_int) < 0.5),
+            "device_s_sum": float(cyc.sum()) / 1e3,
             "cycle_ms_p50": float(np.percentile(cyc, 50)), "cycle_ms_p99": float(np.percentile(cyc, 99)),
             "turnaround_s_p50": float(np.percentile(turn, 50)),
             "turnaround_s_p99": float(np.percentile(turn, 99)),
+            "admission_wait_s_p50": float(np.percentile(wait, 50)),
+            "admission_wait_s_p99": float(np.percentile(wait, 99)),
             "mdas_accepted": int(sum(r["mdas_accepted"] for r in done))}
+
+
+def serving_leg(n_jobs, budget=2 << 30):
+    """Serving: n_jobs bilayers with N log-uniform in [1.4k, 250k] beads, each
+    relaxed (100 steepest-descent steps) at admission, then 4 cycles of 50 MD
+    steps and 20 MDAS cycles (8 pairs, K 50, M 1), every cycle closed by a
+    pair count.  Three runs of the same jobs through a server whose arena
+    budget makes admission wait for finished jobs: one job at a time (the
+    sequential capacity), Poisson arrivals at 0.8 x that capacity (seeded),
+    and all jobs at once (the burst)."""
+    import numpy as np
+    from paper_2005_08348_amd import systems as S
+    log(f"[bench] serving leg: building {n_jobs} jobs")
+    jobs = S.serving_jobs(48)[:n_jobs]
+    req = dict(minimize_iters=100, md_cycles=4, md_steps=50, mdas_cycles=20, mdas_pairs=8,
+               mdas_k=50, mdas_m=1, count_pairs=True)
+    _serve(jobs[:2], req, budget)                     # first admissions: code objects, graphs
+    log("[bench] serving: sequential")
+    seq = _serve(jobs, req, budget, one_at_a_time=True)
+    rate = 0.8 * seq["jobs_per_s"]
+    arrivals = np.cumsum(np.random.default_rng(200508348).exponential(1.0 / rate, size=len(jobs)))
+    log(f"[bench] serving: Poisson arrivals at {rate:.2f} jobs/s")
+    poi = _serve(jobs, req, budget, arrivals=arrivals)
+    poi["arrival_rate_jobs_per_s"] = rate
+    poi["last_arrival_s"] = float(arrivals[-1])
+    log("[bench] serving: burst")
+    burst = _serve(jobs, req, budget)
+    return {"jobs": len(jobs), "beads_total": int(sum(s.n_beads for s in jobs)),
+            "request": req, "sequential": seq, "poisson_0.8x": poi, "burst": burst,
+            # share of the sequential run's wall time outside the cycles'
+            # device time (admission with upload and minimiser, host polls,
+            # launch gaps, closing queries): the most a persistent kernel
+            # that keeps the cycles' arithmetic could recover there
+            "sequential_outside_cycles_share": 1.0 - seq["device_s_sum"] / seq["wall_s"]}
 
 
 def main():

@@ -43,7 +43,9 @@ extern "C" {
 #define MEMBX_E_NOMEM          2  /* arena too small                          */
 #define MEMBX_E_DEVICE         3  /* HIP runtime error                        */
 #define MEMBX_E_LIST_OVERFLOW  4  /* neighbour list or ghost capacity exceeded */
-#define MEMBX_E_NONFINITE      5  /* non-finite energy                        */
+                                  /* (sticky: the handle's results are void;  */
+                                  /* the message names the capacity needed)   */
+#define MEMBX_E_NONFINITE      5  /* non-finite energy or input state         */
 #define MEMBX_E_STATE          6  /* call not valid in the current state      */
 #define MEMBX_E_SKIN           7  /* a bead moved more than skin/2 between    */
                                   /* list rebuilds (pairs may have been lost) */
@@ -145,6 +147,13 @@ typedef struct membx_energy {
     double  pressure[3];          /* P_aa = (mv2 + virial) / V, bar: the    */
                                   /* pressure the paper's barostat couples  */
                                   /* to (Methods)                           */
+    int64_t list_retests;         /* 1 if a list build since the list       */
+                                  /* geometry last changed (creation,       */
+                                  /* membx_set_tuning, a box rescale) had a */
+                                  /* lane whose LDS hit buffer overflowed,  */
+                                  /* so that it tested its candidates again */
+                                  /* while writing: a slower path giving    */
+                                  /* the same list; else 0                  */
 } membx_energy;
 
 /* One admitted exchange trial of a batch. */
@@ -237,7 +246,13 @@ int32_t membx_get_state(membx_sys* sys, double* pos, double* vel, int32_t* mol_k
                         int64_t* counters);
 
 /* Replace the state (any pointer may be NULL); rebuilds the neighbour list
- * and re-evaluates the forces.  Synchronizes. */
+ * and re-evaluates the forces.  Coordinates are wrapped into the box.  With
+ * the counters of membx_get_state, restoring a state taken right after a
+ * list rebuild (a step count that is a multiple of rebuild_interval since
+ * creation or the last retune) continues bit for bit as the run it was taken
+ * from.  Synchronizes.  Errors (the state is left unchanged): E_NONFINITE
+ * for a non-finite coordinate or velocity, E_INVAL for a kind outside the
+ * molecule's family or a negative counter. */
 int32_t membx_set_state(membx_sys* sys, const double* pos, const double* vel,
                         const int32_t* mol_kind, const int64_t* counters);
 
@@ -417,6 +432,11 @@ typedef struct membx_request {
     int32_t mdas_pairs;           /* pairs per MDAS cycle (1..max_pairs)    */
     int32_t mdas_k;               /* lambda increments per MDAS cycle       */
     int32_t mdas_m;               /* MD steps per increment                 */
+    int32_t count_pairs;          /* 1: each cycle ends with an energy pass */
+                                  /* (about one force pass) whose count of  */
+                                  /* pairs within r_cut, times the cycle's  */
+                                  /* MD steps, is the cycle's pair          */
+                                  /* interactions; 0: not counted           */
 } membx_request;
 
 typedef struct membx_job_result {
@@ -432,6 +452,9 @@ typedef struct membx_job_result {
     int64_t fe_count;             /* force evaluations                      */
     int64_t pairs_in_cutoff;      /* at the end of the job                  */
     double  potential;            /* final potential energy, kJ/mol         */
+    int64_t pair_interactions;    /* sum over cycles of the pair count at   */
+                                  /* the cycle's end times its MD steps     */
+                                  /* (count_pairs), else -1                 */
 } membx_job_result;
 
 /* Create a server over a device arena of arena_bytes (owned by the caller,
@@ -455,6 +478,12 @@ int32_t membx_server_poll(membx_server* srv, membx_job_result* out, int32_t cap,
 /* Device times (ms) of every cycle completed since creation, in completion
  * order: up to cap values, *n = total count.  E_INVAL. */
 int32_t membx_server_cycle_times(membx_server* srv, float* out, int64_t cap, int64_t* n);
+
+/* Pair interactions of every cycle completed since creation (as
+ * membx_job_result.pair_interactions; -1 for a job without count_pairs), in
+ * the order of membx_server_cycle_times: up to cap values, *n = total count.
+ * E_INVAL. */
+int32_t membx_server_cycle_pairs(membx_server* srv, double* out, int64_t cap, int64_t* n);
 
 /* Wait for and release every resident job (their results are dropped). */
 int32_t membx_server_destroy(membx_server* srv);

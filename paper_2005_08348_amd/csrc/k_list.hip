@@ -176,11 +176,11 @@ __global__ __launch_bounds__(BB) void k_bin(Dev<R> d)
             R x = *c[a];
             if (x >= d.L[a]) x -= d.L[a];        // exact (Sterbenz) for x in [L, 2L]
             else if (x < (R)0) x += d.L[a];
-            if (!(x >= (R)0 && x < d.L[a])) {     // far outside (set_state, minimizer)
-                double xd = (double)*c[a];
-                xd -= d.Ld[a] * floor(xd / d.Ld[a]);
+            if (!(x >= (R)0 && x < d.L[a])) {     // far outside (minimizer, a blown-up run)
+                double xd = fmod((double)*c[a], d.Ld[a]);   // exact, in (-L, L); NaN stays NaN
+                if (xd < 0.0) xd += d.Ld[a];
                 x = (R)xd;
-                if (!(x < d.L[a])) x = (R)0;
+                if (!(x >= (R)0 && x < d.L[a])) x = (R)0;   // NaN, or rounded up to L
             }
             *c[a] = x;
             const int ci = (int)(x * d.inv_edge[a]);
@@ -599,7 +599,10 @@ __global__ __launch_bounds__(LB) void k_list(Dev<R> d)
         if (act && q == 0) {
             d.nseg0[i] = 0;
             d.ncnt[i] = min(kb, Kc);
-            if (kb > Kc) atomicOr(&d.flags[FL_LIST_OVF], 1);
+            if (kb > Kc) {
+                atomicOr(&d.flags[FL_LIST_OVF], 1);
+                atomicMax(&d.flags[FL_LIST_NEED], kb);
+            }
         }
     }
 }

@@ -23,9 +23,11 @@ enum { ST_LANGEVIN = 0, ST_SWAP_DRAW = 1, ST_SWAP_ACCEPT = 2, ST_MDAS_SELECT = 3
 // FL_SKIN counts (bead, step) events beyond skin/2 since the last reset;
 // FL_SKIN_IN the same for the inner list (beyond delta/2 since its prune);
 // FL_HIT_OVF: a list-build lane overflowed its hit buffer and took the
-// slower re-test path since the last reset (not an error)
+// slower re-test path since the last reset (not an error);
+// FL_LIST_NEED: the largest entry count a bead needed when FL_LIST_OVF was
+// raised (the capacity that would have held its list)
 enum { FL_LIST_OVF = 0, FL_SKIN = 1, FL_GHOST_OVF = 2, FL_NONFINITE = 3, FL_AFF_OVF = 4,
-       FL_REBUILDS = 5, FL_SKIN_IN = 6, FL_HIT_OVF = 7, NFLAGS = 8 };
+       FL_REBUILDS = 5, FL_SKIN_IN = 6, FL_HIT_OVF = 7, FL_LIST_NEED = 8, NFLAGS = 9 };
 
 // The 8 XCDs of the chip take work-groups round-robin by id, each with its
 // own L2.  xcd_block(b, n) renumbers work-group b of n so that every XCD

@@ -1235,8 +1235,14 @@ static int32_t read_flags(membx_sys* s, int* fl)
 
 static int32_t flag_status(membx_sys* s, const int* fl)
 {
-    if (fl[FL_LIST_OVF] || fl[FL_GHOST_OVF] || fl[FL_AFF_OVF])
-        return fail(s, MEMBX_E_LIST_OVERFLOW, "neighbour list / ghost / affected-set capacity exceeded");
+    if (fl[FL_LIST_OVF])
+        return fail(s, MEMBX_E_LIST_OVERFLOW,
+                    "neighbour list capacity exceeded: a bead needed " + std::to_string(fl[FL_LIST_NEED]) +
+                    " entries, list_capacity is " + std::to_string(s->h.Kcap) +
+                    "; recreate the system with a larger list_capacity (or a smaller skin) and "
+                    "restore the last state taken before this error");
+    if (fl[FL_GHOST_OVF] || fl[FL_AFF_OVF])
+        return fail(s, MEMBX_E_LIST_OVERFLOW, "ghost-image / affected-set capacity exceeded");
     if (fl[FL_SKIN]) return fail(s, MEMBX_E_SKIN, "a bead moved more than skin/2 between rebuilds");
     if (fl[FL_SKIN_IN])
         return fail(s, MEMBX_E_SKIN, "a bead moved more than skin_inner/2 between inner-list prunes");
@@ -1457,6 +1463,7 @@ static int32_t energies_impl(membx_sys* s, membx_energy* out, double* part = nul
         if (rc2) return rc2;
         E.max_displacement = dm;
     }
+    E.list_retests = fl[FL_HIT_OVF] ? 1 : 0;
     if (out) *out = E;
     if (!std::isfinite(E.total)) return fail(s, MEMBX_E_NONFINITE, "non-finite energy");
     return flag_status(s, fl);
@@ -1568,13 +1575,29 @@ static int32_t set_state_impl(membx_sys* s, const double* pos, const double* vel
     Host& h = s->h;
     size_t nb = sizeof(double) * 3 * d.N;
     std::vector<double> tmp;
+    for (size_t q = 0; q < 3 * (size_t)d.N; ++q)
+        if ((pos && !std::isfinite(pos[q])) || (vel && !std::isfinite(vel[q])))
+            return fail(s, MEMBX_E_NONFINITE, "non-finite coordinate or velocity (bead " +
+                        std::to_string(q / 3) + "); the state is unchanged");
+    if (mol_kind)
+        for (int m = 0; m < h.nm; ++m) {
+            int k = mol_kind[m], k0 = h.mol_kind0[m];
+            if (k < 0 || k >= h.nk || h.kn[k] != h.kn[k0] ||
+                (k != k0 && (h.fam_of_kind[k] < 0 || h.fam_of_kind[k] != h.fam_of_kind[k0])))
+                return fail(s, MEMBX_E_INVAL, "mol_kind must keep each molecule in its family");
+        }
+    if (counters && (counters[0] < 0 || counters[1] < 0 || counters[2] < 0))
+        return fail(s, MEMBX_E_INVAL, "negative counter");
     if (pos) {
         tmp.assign(pos, pos + 3 * (size_t)d.N);
         for (int i = 0; i < d.N; ++i)
             for (int a = 0; a < 3; ++a) {
                 double& v = tmp[3 * i + a];
-                if (!(v >= 0.0 && v < h.box[a])) v -= h.box[a] * std::floor(v / h.box[a]);
-                if (!(v < h.box[a])) v = 0.0;
+                if (!(v >= 0.0 && v < h.box[a])) {
+                    v = std::fmod(v, h.box[a]);          // exact, in (-L, L)
+                    if (v < 0.0) v += h.box[a];
+                }
+                if (!(v >= 0.0 && v < h.box[a])) v = 0.0;   // v + L rounded up to L
             }
         HCK(hipMemcpyAsync(s->xbuf, tmp.data(), nb, hipMemcpyHostToDevice, s->st));
         launch_import<R>(d, d.posq, s->xbuf, s->st);
@@ -1587,12 +1610,6 @@ static int32_t set_state_impl(membx_sys* s, const double* pos, const double* vel
     }
     std::vector<int> cls;
     if (mol_kind) {
-        for (int m = 0; m < h.nm; ++m) {
-            int k = mol_kind[m], k0 = h.mol_kind0[m];
-            if (k < 0 || k >= h.nk || h.kn[k] != h.kn[k0] ||
-                (k != k0 && (h.fam_of_kind[k] < 0 || h.fam_of_kind[k] != h.fam_of_kind[k0])))
-                return fail(s, MEMBX_E_INVAL, "mol_kind must keep each molecule in its family");
-        }
         cls.resize(d.N);
         for (int m = 0; m < h.nm; ++m)
             for (int b = 0; b < h.kn[mol_kind[m]]; ++b)
@@ -2180,7 +2197,23 @@ struct SrvJob {
     std::deque<int> inflight;     // event slots of cycles in flight
     int next_slot = 0;
     std::vector<float> cyc;
+    // pair counting (request.count_pairs): energy-pass sums of each slot's
+    // cycle land in pinned host memory, read when the cycle's event is done
+    double* sums = nullptr;       // SRV_DEPTH x 16 doubles
+    int64_t slot_steps[SRV_DEPTH] = {};
+    int64_t pair_int = 0;
 };
+
+// Energy pass at the end of a cycle: its sums (in-cutoff pair count at
+// index 5) are copied to host slot memory on the job's stream.
+template <typename R>
+static void srv_count_pairs(membx_sys* s, double* host)
+{
+    Dev<R>& d = dev<R>(s);
+    const int nnb = launch_nonbonded<R>(d, s->h.lpb, true, d.red, s->st);
+    launch_energy_final(d.red, nnb, d.eout, s->st);
+    (void)hipMemcpyAsync(host, d.eout, sizeof(double) * 13, hipMemcpyDeviceToHost, s->st);
+}
 
 }  // namespace
 
@@ -2192,6 +2225,7 @@ struct membx_server {
     std::vector<SrvJob*> active;
     std::deque<membx_job_result> finished;
     std::vector<float> cycles;
+    std::vector<double> cycle_pairs;       // pair interactions of each cycle (-1: not counted)
     int64_t next_id = 1;
     std::chrono::steady_clock::time_point t0;
     std::string err;
@@ -2264,7 +2298,8 @@ int32_t membx_server_submit(membx_server* v, const membx_desc* desc, const membx
     if (rq->minimize_iters < 0 || rq->md_cycles < 0 || rq->mdas_cycles < 0 ||
         rq->md_cycles + rq->mdas_cycles <= 0 ||
         (rq->md_cycles > 0 && rq->md_steps < 1) ||
-        (rq->mdas_cycles > 0 && (rq->mdas_pairs < 1 || rq->mdas_k < 1 || rq->mdas_m < 0))) {
+        (rq->mdas_cycles > 0 && (rq->mdas_pairs < 1 || rq->mdas_k < 1 || rq->mdas_m < 0)) ||
+        (rq->count_pairs != 0 && rq->count_pairs != 1)) {
         v->err = "bad request";
         return MEMBX_E_INVAL;
     }
@@ -2317,6 +2352,9 @@ static int32_t srv_admit(membx_server* v, SrvJob* j)
         if (hipEventCreateWithFlags(&j->ev[q][0], hipEventDisableSystemFence) != hipSuccess ||
             hipEventCreate(&j->ev[q][1]) != hipSuccess)
             return MEMBX_E_DEVICE;
+    if (j->rq.count_pairs &&
+        hipHostMalloc((void**)&j->sums, sizeof(double) * 16 * SRV_DEPTH, hipHostMallocDefault) != hipSuccess)
+        return MEMBX_E_DEVICE;
     membx_desc dsc{};
     dsc.pos = j->pos.data();
     dsc.vel = j->vel.empty() ? nullptr : j->vel.data();
@@ -2332,11 +2370,18 @@ static int32_t srv_issue(SrvJob* j)
     j->next_slot = (j->next_slot + 1) % SRV_DEPTH;
     if (hipEventRecord(j->ev[slot][0], s->st) != hipSuccess) return MEMBX_E_DEVICE;
     int32_t rc;
-    if (j->issued < j->rq.md_cycles)
+    if (j->issued < j->rq.md_cycles) {
         rc = membx_md_step(s, j->rq.md_steps);
-    else
+        j->slot_steps[slot] = j->rq.md_steps;
+    } else {
         rc = membx_mdas_cycle(s, j->rq.mdas_pairs, j->rq.mdas_k, j->rq.mdas_m, nullptr, nullptr, nullptr);
+        j->slot_steps[slot] = (int64_t)j->rq.mdas_k * j->rq.mdas_m;
+    }
     if (rc) return rc;
+    if (j->sums) {
+        if (s->mixed()) srv_count_pairs<float>(s, j->sums + 16 * slot);
+        else srv_count_pairs<double>(s, j->sums + 16 * slot);
+    }
     if (hipEventRecord(j->ev[slot][1], s->st) != hipSuccess) return MEMBX_E_DEVICE;
     j->inflight.push_back(slot);
     j->issued++;
@@ -2352,6 +2397,7 @@ static void srv_free_job(membx_server* v, SrvJob* j)
                 if (j->ev[q][e]) (void)hipEventDestroy(j->ev[q][e]);
         srv_release(v, j->off, j->span);
     }
+    if (j->sums) (void)hipHostFree(j->sums);
     membx_sys_destroy(j->s);
     delete j;
 }
@@ -2368,6 +2414,7 @@ static void srv_close(membx_server* v, SrvJob* j)
     r.cycle_ms_p50 = pct(j->cyc, 0.50);
     r.cycle_ms_p99 = pct(j->cyc, 0.99);
     r.cycle_ms_max = pct(j->cyc, 1.0);
+    r.pair_interactions = j->sums ? j->pair_int : -1;
     if (j->status == MEMBX_OK) {
         membx_energy e{};
         int32_t rc = membx_energies(j->s, &e);
@@ -2402,6 +2449,13 @@ int32_t membx_server_poll(membx_server* v, membx_job_result* out, int32_t cap, i
             (void)hipEventElapsedTime(&ms, j->ev[slot][0], j->ev[slot][1]);
             j->cyc.push_back(ms);
             v->cycles.push_back(ms);
+            if (j->sums) {
+                const int64_t pairs = (int64_t)std::llround(j->sums[16 * slot + 5]);
+                j->pair_int += pairs * j->slot_steps[slot];
+                v->cycle_pairs.push_back((double)pairs * (double)j->slot_steps[slot]);
+            } else {
+                v->cycle_pairs.push_back(-1.0);
+            }
             j->inflight.pop_front();
             j->done++;
         }
@@ -2454,6 +2508,15 @@ int32_t membx_server_cycle_times(membx_server* v, float* out, int64_t cap, int64
     const int64_t m = std::min<int64_t>(cap, (int64_t)v->cycles.size());
     for (int64_t q = 0; q < m; ++q) out[q] = v->cycles[q];
     if (n) *n = (int64_t)v->cycles.size();
+    return MEMBX_OK;
+}
+
+int32_t membx_server_cycle_pairs(membx_server* v, double* out, int64_t cap, int64_t* n)
+{
+    if (!v || cap < 0 || (cap > 0 && !out)) return MEMBX_E_INVAL;
+    const int64_t m = std::min<int64_t>(cap, (int64_t)v->cycle_pairs.size());
+    for (int64_t q = 0; q < m; ++q) out[q] = v->cycle_pairs[q];
+    if (n) *n = (int64_t)v->cycle_pairs.size();
     return MEMBX_OK;
 }
 

@@ -64,13 +64,15 @@ class Energy(C.Structure):
                 ("cycle", C.c_int64), ("n_rebuilds", C.c_int64),
                 ("n_skin_violations", C.c_int64),
                 ("max_displacement", C.c_double), ("n_list_entries", C.c_int64),
-                ("virial", C.c_double * 3), ("mv2", C.c_double * 3), ("pressure", C.c_double * 3)]
+                ("virial", C.c_double * 3), ("mv2", C.c_double * 3), ("pressure", C.c_double * 3),
+                ("list_retests", C.c_int64)]
 
 
 class Request(C.Structure):
     _fields_ = [("minimize_iters", C.c_int32),
                 ("md_cycles", C.c_int32), ("md_steps", C.c_int32), ("mdas_cycles", C.c_int32),
-                ("mdas_pairs", C.c_int32), ("mdas_k", C.c_int32), ("mdas_m", C.c_int32)]
+                ("mdas_pairs", C.c_int32), ("mdas_k", C.c_int32), ("mdas_m", C.c_int32),
+                ("count_pairs", C.c_int32)]
 
 
 class JobResult(C.Structure):
@@ -79,7 +81,8 @@ class JobResult(C.Structure):
                 ("submit_s", C.c_double), ("admit_s", C.c_double), ("finish_s", C.c_double),
                 ("cycle_ms_p50", C.c_double), ("cycle_ms_p99", C.c_double),
                 ("cycle_ms_max", C.c_double), ("md_steps", C.c_int64), ("fe_count", C.c_int64),
-                ("pairs_in_cutoff", C.c_int64), ("potential", C.c_double)]
+                ("pairs_in_cutoff", C.c_int64), ("potential", C.c_double),
+                ("pair_interactions", C.c_int64)]
 
 
 class Trial(C.Structure):
@@ -136,6 +139,7 @@ def lib():
             "membx_server_poll": ([vp, C.POINTER(JobResult), i32, C.POINTER(i32), C.POINTER(i32),
                                    C.POINTER(i32)], i32),
             "membx_server_cycle_times": ([vp, C.POINTER(C.c_float), i64, C.POINTER(i64)], i32),
+            "membx_server_cycle_pairs": ([vp, C.POINTER(C.c_double), i64, C.POINTER(i64)], i32),
             "membx_server_destroy": ([vp], i32),
             "membx_server_last_error": ([vp], C.c_char_p),
             "membx_last_error": ([vp], C.c_char_p),
@@ -473,9 +477,10 @@ class Server:
             raise MembxError(rc, lib().membx_server_last_error(self.h).decode())
 
     def submit(self, system, minimize_iters=100, md_cycles=4, md_steps=50, mdas_cycles=20,
-               mdas_pairs=8, mdas_k=50, mdas_m=1, precision="mixed", **tuning):
+               mdas_pairs=8, mdas_k=50, mdas_m=1, count_pairs=False, precision="mixed", **tuning):
         b = _DescBuilder(system, MIXED if precision == "mixed" else FP64, *_tuning(tuning))
-        rq = Request(minimize_iters, md_cycles, md_steps, mdas_cycles, mdas_pairs, mdas_k, mdas_m)
+        rq = Request(minimize_iters, md_cycles, md_steps, mdas_cycles, mdas_pairs, mdas_k, mdas_m,
+                     int(bool(count_pairs)))
         jid = C.c_int64()
         self._err(lib().membx_server_submit(self.h, C.byref(b.desc), C.byref(rq), C.byref(jid)))
         return int(jid.value)
@@ -493,6 +498,13 @@ class Server:
         buf = (C.c_float * max(1, n.value))()
         self._err(lib().membx_server_cycle_times(self.h, buf, n.value, C.byref(n)))
         return np.frombuffer(buf, dtype=np.float32, count=n.value).copy()
+
+    def cycle_pairs(self):
+        n = C.c_int64()
+        self._err(lib().membx_server_cycle_pairs(self.h, None, 0, C.byref(n)))
+        buf = (C.c_double * max(1, n.value))()
+        self._err(lib().membx_server_cycle_pairs(self.h, buf, n.value, C.byref(n)))
+        return np.frombuffer(buf, dtype=np.float64, count=n.value).copy()
 
     def close(self):
         if getattr(self, "h", None):

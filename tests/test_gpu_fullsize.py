@@ -74,6 +74,39 @@ def test_forces_c1_sampled_aged_list(oracle_mod, c1, prec, tun):
     g.close()
 
 
+def _pair_codes(p, n):
+    """pairs (i, j), either order, as sorted int64 codes min*n + max"""
+    p = np.sort(np.asarray(p, dtype=np.int64), axis=1)
+    return np.sort(p[:, 0] * n + p[:, 1])
+
+
+@pytest.mark.parametrize("tun", [BENCH_TUNING, BENCH_TUNING_B], ids=["skin0.4", "skin0.3"])
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_pairset_c1_bench_tunings(oracle_mod, c1, prec, tun):
+    """The list the force pass reads, built at both tunings the bench runs
+    (4 lanes per bead) on the 95,876-bead bilayer after 30 steps, is the set
+    of pairs within r_cut + skin of the oracle's cell search at the same
+    coordinates, exactly.  At skin 0.4 nm a lane finds more hits than its
+    LDS buffer holds, so the build takes its re-test path there; the test
+    checks that this path ran and gave the same set."""
+    m = _membx()
+    g = _aged(m, c1, prec, **tun)
+    st = g.state()
+    ps = g.pairset()
+    retests = g.energies()["list_retests"]
+    o = oracle_mod.Oracle(c1)
+    o.set_state(pos=st["pos"], vel=st["vel"], mol_kind=st["mol_kind"])
+    ref = o.pairset(c1.rc + tun["skin"])
+    a, b = _pair_codes(ps, c1.n_beads), _pair_codes(ref, c1.n_beads)
+    print(f"{prec} skin {tun['skin']}: {len(a)} pairs listed, {len(b)} in the oracle's "
+          f"set, re-test path {'taken' if retests else 'not taken'}")
+    assert len(np.unique(a)) == len(a)
+    assert np.array_equal(a, b)
+    if tun["skin"] >= 0.4:
+        assert retests == 1
+    g.close()
+
+
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
 def test_energies_c1_full(oracle_mod, c1, prec):
     m = _membx()
@@ -111,6 +144,30 @@ def test_md_c1_short_horizon_fp64(oracle_mod, c1, tun):
     g.close()
 
 
+def test_md_c1_short_horizon_mixed(oracle_mod, c1):
+    """Mixed-precision trajectory at the bench's tuning (skin 0.4 nm, list
+    rebuilt every 7 steps, force pass fused with the integrator) over 9 steps
+    from a float32-representable state stays within 1e-4 nm of the float64
+    oracle's: float32 coordinates in a 36 nm box round at 2e-6 nm per
+    update, force errors are 1e-5 relative, and over 0.18 ps neither is
+    amplified by more than a small factor."""
+    m = _membx()
+    g = m.System(c1, precision="mixed", **BENCH_TUNING)
+    g.minimize(50)
+    st = g.state()
+    o = oracle_mod.Oracle(c1)
+    o.set_state(pos=st["pos"], vel=st["vel"], mol_kind=st["mol_kind"])
+    g.md_step(9)
+    o.md_step(9)
+    d = g.state()["pos"] - o.state()["pos"]
+    d -= c1.box * np.rint(d / c1.box)
+    dv = g.state()["vel"] - o.state()["vel"]
+    print("mixed C1 9 steps: max |dx| %.2e nm, max |dv| %.2e nm/ps" % (np.abs(d).max(), np.abs(dv).max()))
+    assert np.abs(d).max() < 1e-4
+    assert np.abs(dv).max() < 1e-2
+    g.close()
+
+
 def test_forces_c3_sampled_mixed(oracle_mod):
     """1,140,504-bead bilayer (the MDAS workload), 2,000 sampled beads."""
     m = _membx()
@@ -133,6 +190,40 @@ def test_mdas_frozen_c3(oracle_mod):
     assert np.array_equal(rg["pairs"], ro["pairs"])
     assert abs(rg["work"] - ro["work"]) < 1e-6
     assert rg["accept"] == ro["accept"]
+    g.close()
+
+
+# The tuning the autotuner picked for the MDAS leg on this bilayer.
+C3_TUNING = dict(skin=0.4, rebuild_interval=6, lanes_per_bead=8)
+
+
+def test_mdas_cycle_c3_bench_config_mixed(oracle_mod):
+    """MDAS as the bench runs it on the 1,140,504-bead bilayer: 32 pairs,
+    M = 1, mixed precision, its tuning, from the state the bench starts from
+    (60 minimiser iterations, 20 MD steps).  K = 8 increments, not the
+    bench's 50: every increment runs the same steps, and the oracle takes
+    about 7 s per increment on 8 host threads (one hybrid MD step and the
+    two end-state energies at 1.1M beads), so K = 50 would hold the GPU for
+    six minutes.  Identical pairs and decision; work within 5e-2 kJ/mol
+    (the C1 cycle's 2e-2 for 4 pairs, scaled to the larger set of changed
+    interactions)."""
+    m = _membx()
+    c3 = S.make("c3")
+    g = m.System(c3, precision="mixed", **C3_TUNING)
+    g.minimize(60)
+    g.md_step(20)
+    st = g.state()
+    o = oracle_mod.Oracle(c3)
+    o.set_state(pos=st["pos"], vel=st["vel"], mol_kind=st["mol_kind"],
+                counters=[st["step"], st["batch"], st["cycle"]])
+    rg = g.mdas_cycle(32, 8, 1)
+    ro = o.mdas_cycle(32, 8, 1)
+    assert np.array_equal(rg["pairs"], ro["pairs"])
+    print("C3 MDAS 32 pairs K=8: work gpu %.6f oracle %.6f, accept %d/%d"
+          % (rg["work"], ro["work"], rg["accept"], ro["accept"]))
+    assert abs(rg["work"] - ro["work"]) < 5e-2
+    assert rg["accept"] == ro["accept"]
+    assert np.array_equal(g.state()["mol_kind"], o.state()["mol_kind"])
     g.close()
 
 

@@ -48,21 +48,27 @@ def test_jobs_alone_equal_jobs_in_a_mix():
     jobs = [S.serving_job(j, n, 200508348100 + j) for j, n in enumerate((1500, 3000, 2200, 4000))]
     req = dict(minimize_iters=100, md_cycles=2, md_steps=20, mdas_cycles=2, mdas_pairs=4,
                mdas_k=5, mdas_m=1)
-    alone = []
+    alone, pair_int = [], []
     for s in jobs:
         g = M.System(s, precision="mixed")
         g.minimize(req["minimize_iters"], 1e-4, 0.01)
+        pi = 0
         for _ in range(req["md_cycles"]):
             g.md_step(req["md_steps"])
+            pi += g.energies()["n_pairs_in_cutoff"] * req["md_steps"]
         for _ in range(req["mdas_cycles"]):
             g.mdas_cycle(req["mdas_pairs"], req["mdas_k"], req["mdas_m"], results=False)
+            pi += g.energies()["n_pairs_in_cutoff"] * req["mdas_k"] * req["mdas_m"]
         e = g.energies()
         alone.append((e["potential"], e["step"], e["n_pairs_in_cutoff"]))
+        pair_int.append(pi)
         g.close()
     sizes = [M.arena_bytes(s, precision="mixed") for s in jobs]
     budget = int(max(sizes) * 1.6) + 4096        # at most two of these fit at once
     srv = M.Server(budget)
-    ids = [srv.submit(s, **req) for s in jobs]
+    # every other job counts its pair interactions per cycle (an extra
+    # energy pass that must leave the trajectory untouched)
+    ids = [srv.submit(s, count_pairs=(q % 2 == 0), **req) for q, s in enumerate(jobs)]
     done, max_wait = {}, 0
     for _ in range(200000):
         res, nres, nwait = srv.poll()
@@ -73,8 +79,9 @@ def test_jobs_alone_equal_jobs_in_a_mix():
             break
     assert len(done) == len(jobs)
     assert max_wait >= 1, "the budget should have forced queueing"
-    for jid, s, (pot, steps, pairs) in zip(ids, jobs, alone):
+    for q, (jid, s, (pot, steps, pairs)) in enumerate(zip(ids, jobs, alone)):
         r = done[jid]
+        assert r["pair_interactions"] == (pair_int[q] if q % 2 == 0 else -1)
         assert r["status"] == 0
         assert r["n_cycles"] == req["md_cycles"] + req["mdas_cycles"]
         assert r["potential"] == pot
@@ -82,4 +89,7 @@ def test_jobs_alone_equal_jobs_in_a_mix():
         assert r["pairs_in_cutoff"] == pairs
         assert r["cycle_ms_p50"] > 0
     assert len(srv.cycle_times()) == len(jobs) * 4
+    cp = srv.cycle_pairs()
+    assert len(cp) == len(jobs) * 4
+    assert cp[cp >= 0].sum() == sum(pair_int[q] for q in range(0, len(jobs), 2))
     srv.close()
