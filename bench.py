@@ -32,6 +32,14 @@ KERNEL_SOURCES = ("paper_2005_08348_amd/csrc/k_force.hip", "paper_2005_08348_amd
                   "paper_2005_08348_amd/csrc/k_list.hip")
 
 
+WORKLOAD = {
+    "c1": "bilayer 4096 lipids (A:B:C 1639:1638:819) + 50000 W, 95876 beads, box 36.2x36.2x10 nm, "
+          "LJ+RF r_c 1.1 nm, Langevin BAOAB dt 20 fs",
+    "c3": "bilayer 49152 lipids (A:B:C:D 30:30:20:20) + 590000 W, 1140504 beads, "
+          "box 125.4x125.4x11 nm, LJ+RF r_c 1.1 nm, Langevin BAOAB dt 20 fs",
+}
+
+
 def kernel_source_sha():
     import hashlib
     h = hashlib.sha256()
@@ -233,6 +241,9 @@ def main():
     ap.add_argument("--skin", type=float, default=0.5)
     ap.add_argument("--skin-inner", type=float, default=0.15)
     ap.add_argument("--prune", type=int, default=3, help="force passes per inner-list prune")
+    ap.add_argument("--system", choices=["c1", "c3"], default="c1",
+                    help="system of the main timed region (c3, the 1,140,504-bead MDAS bilayer, "
+                         "for kernel profiles; use with --no-legs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -246,8 +257,8 @@ def main():
     sync = torch.cuda.synchronize
     K, W = args.steps, args.warmup
 
-    log("[bench] building c1 (95,876 beads)")
-    c1 = S.make("c1")
+    log(f"[bench] building {args.system}")
+    c1 = S.make(args.system)
     tun = dict(skin=args.skin, rebuild_interval=args.rebuild, lanes_per_bead=args.lpb,
                skin_inner=args.skin_inner, prune_interval=args.prune)
     g = gpu_system(c1, "mixed", **tun)
@@ -295,7 +306,7 @@ def main():
     achieved = nb_flops / (nb_ms * 1e-3)
     list_kind = 1 if tun["prune_interval"] > 1 else 0
     traffic = measured_traffic(tun["lanes_per_bead"], list_kind, tun["skin"],
-                               tun["skin_inner"] if list_kind else 0.0)
+                               tun["skin_inner"] if list_kind else 0.0) if args.system == "c1" else None
     result = {
         "metric": "MD steps/s & pair-interactions/s (FP32-mixed vs FP64); swap trials/s",
         "value": steps_s,
@@ -304,9 +315,7 @@ def main():
         "ms_per_step": 1e3 * t_main / K,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 (f64 energies)", "data": "synthetic",
-        "config": {"workload": "bilayer 4096 lipids (A:B:C 1639:1638:819) + 50000 W, "
-                               "95876 beads, box 36.2x36.2x10 nm, LJ+RF r_c 1.1 nm, "
-                               "Langevin BAOAB dt 20 fs",
+        "config": {"workload": WORKLOAD[args.system],
                    "n_beads": c1.n_beads, "precision": "mixed",
                    "skin_nm": tun["skin"], "rebuild_interval": tun["rebuild_interval"],
                    "lanes_per_bead": tun["lanes_per_bead"],

@@ -346,6 +346,36 @@ int32_t membx_set_exchange_regions(membx_sys* sys, int32_t mode, const int32_t* 
 int32_t membx_set_barostat(membx_sys* sys, int32_t nst, double p_ref_bar, double compressibility,
                            double tau_p);
 
+/* Pressure coupling of membx_md_step by the paper's own barostat (Methods:
+ * semi-isotropic Parrinello-Rahman, 1 bar, tau_p 12 ps; Parrinello and
+ * Rahman, J. Appl. Phys. 52, 7182, 1981) for a rectangular box.  Positions
+ * are r = L s (s scaled coordinates) and the integrator's velocities are
+ * peculiar, u_a = L_a ds_a/dt; the extended energy
+ *   H = sum m |u|^2 / 2 + U + P0 V + (W / 2) sum_a (dL_a/dt)^2
+ * gives W d2L_a/dt2 = V (P_aa - P0) / L_a (P_aa = (mv2_a + virial_a) / V as
+ * in membx_energy; x and y both driven by (P_xx + P_yy) / 2), and a move of
+ * the box at fixed s scales r_a by L'_a / L_a and u_a by L_a / L'_a.  Box
+ * mass W = 3 tau_p^2 L_max / (4 pi^2 compressibility), L_max the longest
+ * edge at this call, fixed afterwards.  After every MD step whose index is
+ * a multiple of nst (t = nst dt): dL_a/dt += t V (P_aa - P0) / (W L_a), then
+ * L'_a = L_a + t dL_a/dt with coordinates and velocities scaled; the list is
+ * rebuilt and the forces refreshed.  Without a thermostat (Langevin gamma =
+ * 0) H is conserved to first order in t.  The box velocity starts at zero.
+ * Replaces membx_set_barostat's coupling (and vice versa); nst <= 0: off.
+ * Units and errors as membx_set_barostat; E_NONFINITE from membx_md_step if
+ * the pressure or the new box is not finite and positive. */
+int32_t membx_set_barostat_pr(membx_sys* sys, int32_t nst, double p_ref_bar,
+                              double compressibility, double tau_p);
+
+/* Parrinello-Rahman box state: if set_box_vel (host, [3] nm/ps) is not
+ * NULL, the box velocity is replaced first (for a restart from membx_
+ * get_state, membx_get_box and this call's output); box_vel (may be NULL)
+ * receives the box velocity, h_box (may be NULL) the box's terms of the
+ * conserved energy, P0 V + (W / 2) sum_a (dL_a/dt)^2 in kJ/mol.  E_INVAL,
+ * E_NONFINITE (a non-finite set_box_vel, nothing changed). */
+int32_t membx_barostat_state(membx_sys* sys, const double* set_box_vel, double* box_vel,
+                             double* h_box);
+
 /* Lambda path of MDAS cycles.  path 0 (default): linear in the end-state
  * energies, U(lambda) = (1 - lambda) U_A + lambda U_B (Eq. 2), forces from
  * one pass plus lambda (F_B - F_A).  path 1: the soft-core path of Eq. 4

@@ -32,6 +32,7 @@
 #define O_KB 0.00831446261815324      /* kJ/mol/K */
 #define O_FELEC 138.935458            /* kJ mol^-1 nm e^-2, 1/(4 pi eps0) */
 #define O_MAXEXCL 8
+#define O_PI 3.14159265358979323846
 
 /* random stream ids (fourth counter word) */
 enum { ST_LANGEVIN = 0, ST_SWAP_DRAW = 1, ST_SWAP_ACCEPT = 2,
@@ -77,9 +78,12 @@ typedef struct {
      * region of X, 2 in the other region */
     int xmode;
     int* region;             /* [nm] 0 or 1 */
-    /* semi-isotropic pressure coupling every baro_nst steps (0: off) */
-    int baro_nst;
+    /* semi-isotropic pressure coupling every baro_nst steps (0: off):
+     * baro_kind 0 stochastic cell rescaling, 1 Parrinello-Rahman */
+    int baro_nst, baro_kind;
     double p_ref, kappa, tau_p;   /* kJ mol^-1 nm^-3, its inverse, ps */
+    double box_v[3];              /* Parrinello-Rahman box velocity, nm/ps */
+    double w_box;                 /* Parrinello-Rahman box mass, amu */
     /* MDAS lambda path: 0 linear in the end-state energies (Eq. 2),
      * 1 soft-core LJ of the changed beads (Eq. 4, shift sc_delta nm^2) */
     int mdas_path;
@@ -1059,10 +1063,85 @@ static void couple_pressure(osys* s)
     s->n_fe--;                        /* a refresh, not a step */
 }
 
+/* Parrinello-Rahman pressure coupling, the paper's barostat (Methods;
+ * Parrinello and Rahman, J. Appl. Phys. 52, 7182 (1981)), for a box that
+ * stays rectangular, semi-isotropic.  Positions are r = L s (s scaled
+ * coordinates, L the box lengths) and the integrator's velocities are the
+ * peculiar ones, u_a = L_a ds_a/dt.  The extended Hamiltonian
+ *   H = sum_i m_i |u_i|^2 / 2 + U + P0 V + (W / 2) sum_a (dL_a/dt)^2
+ * gives W d2L_a/dt2 = V (P_aa - P0) / L_a with P_aa V = sum_i m_i u_ia^2 + W_aa
+ * (the pressure tensor of o_virial), and du_a/dt = F_a / m - (dL_a/dt / L_a) u_a:
+ * a change of L_a at fixed s scales r_a by L'_a / L_a and u_a by L_a / L'_a.
+ * Semi-isotropic: x and y are both driven by (P_xx + P_yy) / 2, which for a
+ * box with L_x = L_y is the same Hamiltonian with L_x = L_y held equal.  Box
+ * mass: W = 3 tau_p^2 L_max / (4 pi^2 beta) with beta the compressibility
+ * and L_max the longest edge when the coupling is switched on (the usual
+ * choice, under which a system of compressibility beta swings with period
+ * tau_p), held fixed so that H is conserved without a thermostat.
+ * Discretisation, every nst steps (t = nst dt), after the step that ends the
+ * interval: the box velocity takes the impulse of the whole interval at the
+ * current pressure, dL_a/dt += t V (P_aa - P0) / (W L_a), then the box moves
+ * L'_a = L_a + t dL_a/dt with r and u scaled as above, and the forces of the
+ * new configuration are evaluated.  The particles step at fixed box in
+ * between.  H is conserved to first order in t (tests pin its convergence). */
+static void couple_pr(osys* s)
+{
+    double w[9];
+    o_virial(s, w, 1);
+    const double V = s->box[0] * s->box[1] * s->box[2];
+    const double t = s->baro_nst * s->dt;
+    double p[3];
+    for (int a = 0; a < 3; ++a) p[a] = (w[3 + a] + w[a]) / V;
+    const double pxy = 0.5 * (p[0] + p[1]);
+    const double drive[3] = { pxy - s->p_ref, pxy - s->p_ref, p[2] - s->p_ref };
+    double mu[3];
+    for (int a = 0; a < 3; ++a) {
+        s->box_v[a] += t * V * drive[a] / (s->w_box * s->box[a]);
+        mu[a] = (s->box[a] + t * s->box_v[a]) / s->box[a];
+    }
+    for (int i = 0; i < s->n; ++i)
+        for (int a = 0; a < 3; ++a) {
+            s->x[3 * i + a] *= mu[a];
+            s->v[3 * i + a] /= mu[a];
+        }
+    for (int a = 0; a < 3; ++a) s->box[a] *= mu[a];
+    force_eval(s, NULL, 0.0, s->f);   /* forces of the new configuration */
+    s->n_fe--;                        /* a refresh, not a step */
+}
+
 void o_set_barostat(osys* s, int nst, double p_ref, double kappa, double tau_p)
 {
     s->baro_nst = nst > 0 ? nst : 0;
+    s->baro_kind = 0;
     s->p_ref = p_ref; s->kappa = kappa; s->tau_p = tau_p;
+}
+
+/* Parrinello-Rahman coupling every nst steps (0: off); p_ref in
+ * kJ mol^-1 nm^-3, beta in its inverse, tau_p in ps.  The box velocity
+ * starts at zero and W is fixed from the current box. */
+void o_set_barostat_pr(osys* s, int nst, double p_ref, double beta, double tau_p)
+{
+    s->baro_nst = nst > 0 ? nst : 0;
+    s->baro_kind = 1;
+    s->p_ref = p_ref; s->kappa = beta; s->tau_p = tau_p;
+    double lmax = fmax(s->box[0], fmax(s->box[1], s->box[2]));
+    s->w_box = 3.0 * tau_p * tau_p * lmax / (4.0 * O_PI * O_PI * beta);
+    for (int a = 0; a < 3; ++a) s->box_v[a] = 0.0;
+}
+
+/* Box velocity (nm/ps, may be NULL) and the box's terms of the conserved
+ * Parrinello-Rahman energy, P0 V + (W / 2) sum_a (dL_a/dt)^2 (kJ/mol). */
+double o_barostat_state(const osys* s, double* box_v)
+{
+    if (box_v) for (int a = 0; a < 3; ++a) box_v[a] = s->box_v[a];
+    double k = 0.0;
+    for (int a = 0; a < 3; ++a) k += 0.5 * s->w_box * s->box_v[a] * s->box_v[a];
+    return s->p_ref * s->box[0] * s->box[1] * s->box[2] + k;
+}
+
+void o_set_box_velocity(osys* s, const double* box_v)
+{
+    for (int a = 0; a < 3; ++a) s->box_v[a] = box_v[a];
 }
 
 void o_get_box(const osys* s, double* box) { for (int a = 0; a < 3; ++a) box[a] = s->box[a]; }
@@ -1071,7 +1150,10 @@ void o_md_step(osys* s, int nsteps)
 {
     for (int t = 0; t < nsteps; ++t) {
         md_one(s, NULL, 0.0);
-        if (s->baro_nst > 0 && s->step % s->baro_nst == 0) couple_pressure(s);
+        if (s->baro_nst > 0 && s->step % s->baro_nst == 0) {
+            if (s->baro_kind == 1) couple_pr(s);
+            else couple_pressure(s);
+        }
     }
 }
 

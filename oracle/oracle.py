@@ -90,6 +90,10 @@ def lib():
         L.o_set_exchange_regions.argtypes = [C.c_void_p, C.c_int, _i32p]
         L.o_virial.argtypes = [C.c_void_p, _f64p, C.c_int]
         L.o_set_barostat.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_double]
+        L.o_set_barostat_pr.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_double]
+        L.o_barostat_state.argtypes = [C.c_void_p, _f64p]
+        L.o_barostat_state.restype = C.c_double
+        L.o_set_box_velocity.argtypes = [C.c_void_p, _f64p]
         L.o_get_box.argtypes = [C.c_void_p, _f64p]
         L.o_sc_lj.argtypes = [C.c_double] * 6 + [_f64p]
         L.o_sc_energy.argtypes = [C.c_void_p, C.c_int, _i32p, C.c_double]
@@ -216,6 +220,21 @@ class Oracle:
         """semi-isotropic stochastic cell rescaling every nst MD steps (0: off);
         pressure in bar, compressibility in 1/bar, tau_p in ps"""
         lib().o_set_barostat(self.h, int(nst), p_ref_bar / BAR, compressibility * BAR, tau_p)
+
+    def set_barostat_pr(self, nst, p_ref_bar=1.0, compressibility=3e-4, tau_p=12.0):
+        """semi-isotropic Parrinello-Rahman coupling every nst MD steps (0:
+        off); pressure in bar, compressibility in 1/bar, tau_p in ps; the box
+        velocity starts at zero"""
+        lib().o_set_barostat_pr(self.h, int(nst), p_ref_bar / BAR, compressibility * BAR, tau_p)
+
+    def barostat_state(self):
+        """(box velocity [3] nm/ps, P0 V + W/2 |dL/dt|^2 in kJ/mol)"""
+        bv = np.zeros(3)
+        h = lib().o_barostat_state(self.h, bv)
+        return bv, h
+
+    def set_box_velocity(self, bv):
+        lib().o_set_box_velocity(self.h, _f64(bv))
 
     def set_mdas_path(self, path, delta=0.05):
         """MDAS lambda path: 0 linear (Eq. 2), 1 soft-core LJ (Eq. 4, delta nm^2)"""

@@ -297,6 +297,25 @@ __global__ __launch_bounds__(WG) void k_scale_pos(Dev<R> d, double mx, double my
     d.posq[i] = p;
 }
 
+// peculiar velocities divided by the box stretch per axis (a Parrinello-
+// Rahman box move at fixed scaled coordinates and their momenta)
+template <typename R>
+__global__ __launch_bounds__(WG) void k_unscale_vel(Dev<R> d, double mx, double my, double mz)
+{
+    const int i = blockIdx.x * WG + threadIdx.x;
+    if (i >= d.N) return;
+    V4<R> v = d.vel[i];
+    v.x = (R)((double)v.x / mx); v.y = (R)((double)v.y / my); v.z = (R)((double)v.z / mz);
+    d.vel[i] = v;
+}
+
+template <typename R>
+void launch_unscale_vel(const Dev<R>& d, const double* mu, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_unscale_vel<R>, dim3((d.N + WG - 1) / WG), dim3(WG), 0, st, d, mu[0], mu[1],
+                       mu[2]);
+}
+
 template <typename R>
 void launch_baro(const Dev<R>& d, const double* eout, double* mu, double p0, double kappa,
                  double tau_p, double t, double vol, hipStream_t st)
@@ -366,6 +385,7 @@ void launch_vr_kick_drift(const Dev<R>& d, const VrBuf& vr, R kick, long long st
     template void launch_baro<R>(const Dev<R>&, const double*, double*, double, double, double, \
                                  double, double, hipStream_t);                       \
     template void launch_scale_pos<R>(const Dev<R>&, const double*, hipStream_t);    \
+    template void launch_unscale_vel<R>(const Dev<R>&, const double*, hipStream_t);  \
     template void launch_vr_kick_drift<R>(const Dev<R>&, const VrBuf&, R, long long, int, \
                                           hipStream_t);                              \
     template void launch_kick_drift<R>(const Dev<R>&, R, long long, int, hipStream_t); \

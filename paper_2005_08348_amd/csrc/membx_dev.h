@@ -30,15 +30,29 @@ enum { FL_LIST_OVF = 0, FL_SKIN = 1, FL_GHOST_OVF = 2, FL_NONFINITE = 3, FL_AFF_
        FL_REBUILDS = 5, FL_SKIN_IN = 6, FL_HIT_OVF = 7, FL_LIST_NEED = 8, NFLAGS = 9 };
 
 // The 8 XCDs of the chip take work-groups round-robin by id, each with its
-// own L2.  xcd_block(b, n) renumbers work-group b of n so that every XCD
-// runs one contiguous range of logical blocks (a slab of neighbouring
-// cells), so that its coordinate gathers stay in its own L2.  A bijection
+// own L2, and an XCD deals its work-groups round-robin to its 32 CUs.
+// xcd_block(b, n) renumbers work-group b of n so that every XCD runs one
+// contiguous range of logical blocks (a slab of neighbouring cells), whose
+// coordinate gathers stay in its own L2, and within it every CU a
+// contiguous sub-range, so that the work-groups resident on a CU share
+// neighbourhoods in its L1 (measured on the 95,876-bead bilayer: force pass
+// 20.2 -> 19.9 us at skin 0.3 nm, 23.0 -> 21.9 us at 0.4 nm).  A bijection
 // of [0, n).
 constexpr int NXCD = 8;
+constexpr int CU_PER_XCD = 32;
+__device__ __forceinline__ int split_rr(int b, int n, int k)
+{
+    // work-group b of n dealt round-robin to k units; unit b % k runs the
+    // (b / k)-th block of its own contiguous range
+    const int x = b % k, l = b / k, per = n / k, rem = n % k;
+    return x < rem ? x * (per + 1) + l : rem * (per + 1) + (x - rem) * per + l;
+}
 __device__ __forceinline__ int xcd_block(int b, int n)
 {
-    const int x = b % NXCD, l = b / NXCD, per = n / NXCD, rem = n % NXCD;
-    return x < rem ? x * (per + 1) + l : rem * (per + 1) + (x - rem) * per + l;
+    const int x = b % NXCD, per = n / NXCD, rem = n % NXCD;
+    const int nx = x < rem ? per + 1 : per;
+    const int base = x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per;
+    return base + split_rr(b / NXCD, nx, CU_PER_XCD);
 }
 
 // device counters (int64)
@@ -250,7 +264,7 @@ __device__ __forceinline__ int vr_group(const Dev<R>& d, const VrBuf& vr, int i)
 constexpr int SEL_C0 = 1024;     // candidates of the first selection chunk
 constexpr int SEL_CMAX = 8192;   // largest selection chunk
 constexpr int SEL_CAPC = 64;     // earlier conflicting candidates listed per candidate
-constexpr int SEL_LDS = 16384;   // conflict-list entries one chunk may resolve
+constexpr int SEL_LDS = 61440;   // conflict-list entries one chunk may resolve (120 KB of LDS)
 constexpr int MAXMC = 2 * MAXCH; // changed beads per trial
 // selection state words
 enum { SEL_ADM = 0, SEL_NEXT = 1, SEL_DONE = 2, SEL_EPC = 3, SEL_STAMP = 4, SEL_NSEL = 8 };

@@ -37,6 +37,7 @@ template <typename R>
 void launch_baro(const Dev<R>&, const double*, double*, double, double, double, double, double,
                  hipStream_t);
 template <typename R> void launch_scale_pos(const Dev<R>&, const double*, hipStream_t);
+template <typename R> void launch_unscale_vel(const Dev<R>&, const double*, hipStream_t);
 template <typename R>
 void launch_vr_kick_drift(const Dev<R>&, const VrBuf&, R, long long, int, hipStream_t);
 template <typename R> void launch_sd_step(const Dev<R>&, double, double, hipStream_t);
@@ -141,6 +142,10 @@ struct Host {
     // compressibility (its inverse), tau_p (ps)
     int baro_nst = 0;
     double p_ref = 0.0, kappa = 0.0, tau_p = 0.0;
+    // 0 stochastic cell rescaling; 1 Parrinello-Rahman with box velocity
+    // box_v (nm/ps) and box mass w_box (amu)
+    int baro_kind = 0;
+    double box_v[3] = { 0.0, 0.0, 0.0 }, w_box = 0.0;
     // MDAS lambda path: 0 linear (Eq. 2), 1 soft-core LJ (Eq. 4), shift (nm^2)
     int mdas_path = 0;
     double sc_delta = 0.05;
@@ -919,10 +924,34 @@ template <typename R>
 static int32_t couple_pressure(membx_sys* s)
 {
     Dev<R>& d = dev<R>(s);
-    const Host& h = s->h;
+    Host& h = s->h;
     const int nnb = launch_nonbonded<R>(d, h.lpb, true, d.red, s->st);
     launch_energy_final(d.red, nnb, d.eout, s->st);
     const double vol = h.box[0] * h.box[1] * h.box[2];
+    if (h.baro_kind == 1) {
+        // Parrinello-Rahman: the box velocity takes the interval's impulse at
+        // the current pressure tensor (x and y: the mean of P_xx and P_yy),
+        // the box moves with it; coordinates scale with the box, peculiar
+        // velocities against it (host arithmetic in float64)
+        double e[13];
+        HCK(hipMemcpyAsync(e, d.eout, sizeof(e), hipMemcpyDeviceToHost, s->st));
+        HCK(hipStreamSynchronize(s->st));
+        const double t = h.baro_nst * h.dt;
+        double p[3];
+        for (int a = 0; a < 3; ++a) p[a] = (e[10 + a] + e[7 + a]) / vol;
+        const double pxy = 0.5 * (p[0] + p[1]);
+        const double drive[3] = { pxy - h.p_ref, pxy - h.p_ref, p[2] - h.p_ref };
+        double mu[3];
+        for (int a = 0; a < 3; ++a) {
+            h.box_v[a] += t * vol * drive[a] / (h.w_box * h.box[a]);
+            mu[a] = (h.box[a] + t * h.box_v[a]) / h.box[a];
+        }
+        if (!(std::isfinite(mu[0]) && std::isfinite(mu[1]) && std::isfinite(mu[2]) &&
+              mu[0] > 0.0 && mu[1] > 0.0 && mu[2] > 0.0))
+            return fail(s, MEMBX_E_NONFINITE, "non-finite pressure or box");
+        launch_unscale_vel<R>(d, mu, s->st);
+        return rescale_box<R>(s, mu);
+    }
     launch_baro<R>(d, d.eout, d.eout + 13, h.p_ref, h.kappa, h.tau_p, h.baro_nst * h.dt, vol, s->st);
     double mu[3];
     HCK(hipMemcpyAsync(mu, d.eout + 13, sizeof(mu), hipMemcpyDeviceToHost, s->st));
@@ -2023,9 +2052,47 @@ int32_t membx_set_barostat(membx_sys* s, int32_t nst, double p_ref_bar, double c
                      std::isfinite(compressibility) && std::isfinite(tau_p)))
         return fail(s, MEMBX_E_INVAL, "barostat needs finite p_ref, compressibility > 0, tau_p > 0");
     s->h.baro_nst = nst > 0 ? nst : 0;
+    s->h.baro_kind = 0;
     s->h.p_ref = p_ref_bar / BAR;
     s->h.kappa = compressibility * BAR;
     s->h.tau_p = tau_p;
+    return MEMBX_OK;
+}
+
+int32_t membx_set_barostat_pr(membx_sys* s, int32_t nst, double p_ref_bar, double compressibility,
+                              double tau_p)
+{
+    if (!s) return MEMBX_E_INVAL;
+    if (nst > 0 && !(std::isfinite(p_ref_bar) && compressibility > 0.0 && tau_p > 0.0 &&
+                     std::isfinite(compressibility) && std::isfinite(tau_p)))
+        return fail(s, MEMBX_E_INVAL, "barostat needs finite p_ref, compressibility > 0, tau_p > 0");
+    Host& h = s->h;
+    h.baro_nst = nst > 0 ? nst : 0;
+    h.baro_kind = 1;
+    h.p_ref = p_ref_bar / BAR;
+    h.kappa = compressibility * BAR;
+    h.tau_p = tau_p;
+    const double lmax = std::max(h.box[0], std::max(h.box[1], h.box[2]));
+    h.w_box = 3.0 * tau_p * tau_p * lmax / (4.0 * M_PI * M_PI * h.kappa);
+    for (int a = 0; a < 3; ++a) h.box_v[a] = 0.0;
+    return MEMBX_OK;
+}
+
+int32_t membx_barostat_state(membx_sys* s, const double* set_box_vel, double* box_vel, double* h_box)
+{
+    if (!s) return MEMBX_E_INVAL;
+    Host& h = s->h;
+    if (set_box_vel) {
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(set_box_vel[a])) return fail(s, MEMBX_E_NONFINITE, "non-finite box velocity");
+        for (int a = 0; a < 3; ++a) h.box_v[a] = set_box_vel[a];
+    }
+    if (box_vel) for (int a = 0; a < 3; ++a) box_vel[a] = h.box_v[a];
+    if (h_box) {
+        double k = 0.0;
+        for (int a = 0; a < 3; ++a) k += 0.5 * h.w_box * h.box_v[a] * h.box_v[a];
+        *h_box = h.p_ref * h.box[0] * h.box[1] * h.box[2] + k;
+    }
     return MEMBX_OK;
 }
 

@@ -129,6 +129,8 @@ def lib():
             "membx_set_ensemble": ([vp, i32, dp, vp], i32),
             "membx_set_exchange_regions": ([vp, i32, vp], i32),
             "membx_set_barostat": ([vp, i32, dp, dp, dp], i32),
+            "membx_set_barostat_pr": ([vp, i32, dp, dp, dp], i32),
+            "membx_barostat_state": ([vp, vp, vp, C.POINTER(dp)], i32),
             "membx_get_box": ([vp, vp], i32),
             "membx_set_mdas_path": ([vp, i32, dp], i32),
             "membx_kernel_timing": ([vp, i32], i32),
@@ -381,6 +383,20 @@ class System:
         """semi-isotropic pressure coupling every nst MD steps (0: off)"""
         _check(lib().membx_set_barostat(self.h, int(nst), float(p_ref_bar), float(compressibility),
                                         float(tau_p)), self.h)
+
+    def set_barostat_pr(self, nst, p_ref_bar=1.0, compressibility=3e-4, tau_p=12.0):
+        """semi-isotropic Parrinello-Rahman coupling every nst MD steps (0: off)"""
+        _check(lib().membx_set_barostat_pr(self.h, int(nst), float(p_ref_bar), float(compressibility),
+                                           float(tau_p)), self.h)
+
+    def barostat_state(self, set_box_vel=None):
+        """(box velocity [3] nm/ps, P0 V + W/2 |dL/dt|^2 kJ/mol); set_box_vel
+        replaces the box velocity first"""
+        bv, hb = np.zeros(3), C.c_double()
+        sv = None if set_box_vel is None else np.ascontiguousarray(set_box_vel, dtype=np.float64)
+        _check(lib().membx_barostat_state(self.h, None if sv is None else sv.ctypes.data_as(C.c_void_p),
+                                          bv.ctypes.data_as(C.c_void_p), C.byref(hb)), self.h)
+        return bv, hb.value
 
     def set_mdas_path(self, path, delta=0.05):
         """MDAS lambda path: 0 linear (Eq. 2), 1 soft-core LJ (Eq. 4, delta nm^2)"""

@@ -22,8 +22,11 @@ does: one per MD step, per exchange trial and per MDAS step (a frozen MDAS
 cycle, M = 0, counts one).  With ``--thermostat vrescale`` every sampler
 integrates with the paper's thermostat (velocity rescaling, tau_t = 1 ps,
 membrane and solvent coupled separately) instead of Langevin dynamics, and
-``--thermostat npt`` adds the semi-isotropic barostat at 1 bar (tau_p 12 ps):
-the paper's ensemble;
+``--thermostat npt`` adds the overdamped semi-isotropic barostat at 1 bar
+(tau_p 12 ps), and ``--thermostat paper`` is the paper's ensemble: 335 K,
+velocity rescaling and the semi-isotropic Parrinello-Rahman barostat (1 bar,
+tau_p 12 ps), switched on after the uncounted equilibration, which runs
+under the overdamped barostat;
 ``--repeats`` runs independent seeds and summarises the halfway speed-ups
 (mean and standard deviation over the runs); ``--combine`` summarises the
 repeats of several earlier outputs together.
@@ -111,6 +114,7 @@ N_BINS = 45      # up to 4.5 nm
 # synthetic start melts within them, while lateral diffusion (~0.1 nm in that
 # time) leaves the stripes in place, so the traces follow demixing only
 EQUIL = 20000
+PAPER_T = 335.0  # K, the temperature of the paper's runs (Methods)
 # the halfway metric needs the start clearly above the mixed level: max[g] of
 # 100 lipids per leaflet scatters by about 0.1 between samples
 MIN_GAP = 0.2
@@ -133,12 +137,16 @@ def run(method, sysm, fe_total, every, kind=S.KIND_D, n_bins=N_BINS, bin_width=B
     from . import membx as M
     leaflet = sysm.meta["leaflet"]
     g = M.System(sysm, precision=precision)
-    if thermostat in ("vrescale", "npt"):
+    if thermostat in ("vrescale", "npt", "paper"):
         g.set_ensemble(1, tau_t=1.0, kind_group=[1 if k.name == "W" else 0 for k in sysm.kinds])
     if thermostat == "npt":   # and the semi-isotropic barostat at 1 bar
         g.set_barostat(10, p_ref_bar=1.0, compressibility=3e-4, tau_p=12.0)
+    if thermostat == "paper":   # overdamped towards 1 bar while equilibrating
+        g.set_barostat(10, p_ref_bar=1.0, compressibility=3e-4, tau_p=1.0)
     g.minimize(100)
     g.md_step(max(equil, 200))           # thermalise (not counted)
+    if thermostat == "paper":   # then the paper's Parrinello-Rahman coupling
+        g.set_barostat_pr(10, p_ref_bar=1.0, compressibility=3e-4, tau_p=12.0)
     fe, trace, works, acc, tried = 0, [], [], 0, 0
     trace.append((0, _trace_point(g, sysm, kind, leaflet, n_bins, bin_width)))
     next_pt = every
@@ -184,10 +192,13 @@ def experiment(seed, fe_total, every, thermostat="langevin", equil=EQUIL):
     """MD, MC-MD and MDAS from the striped start of one seed, with the mixed
     level from the randomly mixed start of the same seed."""
     sysm = S.make("mix", seed=seed)
+    if thermostat == "paper":
+        sysm.temperature = PAPER_T
     kT = S.KB * sysm.temperature
     out = {"seed": int(sysm.seed), "runs": {}}
     # the level of a uniformly mixed membrane: the same lipids randomly mixed
     mixed = S.make("mix", seed=seed, demix=False)
+    mixed.temperature = sysm.temperature
     ref = run("md", mixed, max(fe_total // 10, 4 * every), every, thermostat=thermostat, equil=equil)
     y_mixed = float(np.mean([p[1] for p in ref["trace"]]))
     out["mixed_level"] = y_mixed
@@ -265,8 +276,8 @@ def main(argv=None):
     ap.add_argument("--every", type=int, default=4000, help="force evaluations between g(r) samples")
     ap.add_argument("--seed", type=int, default=None, help="first seed (default: the mix workload's)")
     ap.add_argument("--repeats", type=int, default=1, help="independent runs, seeds seed, seed + 1, ...")
-    ap.add_argument("--thermostat", choices=["langevin", "vrescale", "npt"], default="langevin",
-                    help="npt: velocity rescaling and the semi-isotropic barostat (the paper's ensemble)")
+    ap.add_argument("--thermostat", choices=["langevin", "vrescale", "npt", "paper"], default="langevin",
+                    help="vrescale: velocity rescaling; npt: plus the overdamped barostat; paper: 335 K, velocity rescaling and Parrinello-Rahman (the paper's ensemble)")
     ap.add_argument("--equil", type=int, default=EQUIL, help="uncounted MD steps before each run")
     ap.add_argument("--combine", nargs="+", metavar="JSON",
                     help="no runs: summarise the repeats of earlier outputs of this program")
