@@ -81,6 +81,8 @@ typedef struct {
     /* semi-isotropic pressure coupling every baro_nst steps (0: off):
      * baro_kind 0 stochastic cell rescaling, 1 Parrinello-Rahman */
     int baro_nst, baro_kind;
+    /* ktopo[k1 * nk + k2]: kinds k1 and k2 differ in their bonded terms */
+    int* ktopo;
     double p_ref, kappa, tau_p;   /* kJ mol^-1 nm^-3, its inverse, ps */
     double box_v[3];              /* Parrinello-Rahman box velocity, nm/ps */
     double w_box;                 /* Parrinello-Rahman box mass, amu */
@@ -220,6 +222,22 @@ osys* o_create(int nk, const int* kn, const int* ktype, const double* kq,
         s->acos0[a] = cos(ath0_deg[a] * (3.14159265358979323846 / 180.0));
         s->akk[a] = akk[a];
     }
+    s->ktopo = (int*)xcalloc((size_t)nk * nk, sizeof(int));
+    for (int k1 = 0; k1 < nk; ++k1)
+        for (int k2 = 0; k2 < nk; ++k2) {
+            int dif = s->knb[k1] != s->knb[k2] || s->kna[k1] != s->kna[k2];
+            for (int b = 0; !dif && b < s->knb[k1]; ++b) {
+                int p = s->kboff[k1] + b, q = s->kboff[k2] + b;
+                dif = s->bi[p] != s->bi[q] || s->bj[p] != s->bj[q] || s->bb0[p] != s->bb0[q] ||
+                      s->bk[p] != s->bk[q];
+            }
+            for (int a = 0; !dif && a < s->kna[k1]; ++a) {
+                int p = s->kaoff[k1] + a, q = s->kaoff[k2] + a;
+                dif = s->ai[p] != s->ai[q] || s->aj[p] != s->aj[q] || s->ak[p] != s->ak[q] ||
+                      s->acos0[p] != s->acos0[q] || s->akk[p] != s->akk[q];
+            }
+            s->ktopo[k1 * nk + k2] = dif;
+        }
     s->nm = nm;
     s->mkind = (int*)xcalloc(nm, sizeof(int));
     s->region = (int*)xcalloc(nm, sizeof(int));
@@ -233,15 +251,26 @@ osys* o_create(int nk, const int* kn, const int* ktype, const double* kq,
     s->bmol = (int*)xcalloc(n, sizeof(int));
     s->bloc = (int*)xcalloc(n, sizeof(int));
     set_bead_tables(s);
-    /* exclusions: beads joined by a bond of their molecule (nrexcl = 1) */
+    /* exclusions: beads joined by a bond of their molecule (nrexcl = 1).
+     * A molecule of a swap family whose kinds differ in their bonds (a
+     * topology-changing exchange) excludes the pairs bonded in any kind of
+     * the family, so that its nonbonded pair set does not depend on its
+     * current kind. */
     s->nexcl = (int*)xcalloc(n, sizeof(int));
     s->excl = (int*)xcalloc((size_t)n * O_MAXEXCL, sizeof(int));
     for (int m = 0; m < nm; ++m) {
-        int k = s->mkind[m], f0 = s->mfirst[m];
-        for (int b = 0; b < s->knb[k]; ++b) {
-            int i = f0 + s->bi[s->kboff[k] + b], j = f0 + s->bj[s->kboff[k] + b];
-            if (s->nexcl[i] < O_MAXEXCL) s->excl[(size_t)i * O_MAXEXCL + s->nexcl[i]++] = j;
-            if (s->nexcl[j] < O_MAXEXCL) s->excl[(size_t)j * O_MAXEXCL + s->nexcl[j]++] = i;
+        int k0 = s->mkind[m], f0 = s->mfirst[m];
+        for (int k = 0; k < nk; ++k) {
+            if (k != k0 && (s->kfam[k0] < 0 || s->kfam[k] != s->kfam[k0])) continue;
+            for (int b = 0; b < s->knb[k]; ++b) {
+                int i = f0 + s->bi[s->kboff[k] + b], j = f0 + s->bj[s->kboff[k] + b];
+                int dup = 0;
+                for (int e = 0; e < s->nexcl[i]; ++e)
+                    if (s->excl[(size_t)i * O_MAXEXCL + e] == j) dup = 1;
+                if (dup) continue;
+                if (s->nexcl[i] < O_MAXEXCL) s->excl[(size_t)i * O_MAXEXCL + s->nexcl[i]++] = j;
+                if (s->nexcl[j] < O_MAXEXCL) s->excl[(size_t)j * O_MAXEXCL + s->nexcl[j]++] = i;
+            }
         }
     }
     s->nt = nt;
@@ -275,7 +304,8 @@ void o_destroy(osys* s)
     void* p[] = { s->kn, s->koff, s->ktype, s->kfam, s->kq, s->km, s->knb, s->kboff,
                   s->bi, s->bj, s->bb0, s->bk, s->kna, s->kaoff, s->ai, s->aj, s->ak,
                   s->acos0, s->akk, s->mkind, s->mfirst, s->bmol, s->bloc, s->nexcl,
-                  s->excl, s->c6, s->c12, s->x, s->v, s->f, s->mk_tmp, s->f_tmp, s->region, s->f_slab };
+                  s->excl, s->c6, s->c12, s->x, s->v, s->f, s->mk_tmp, s->f_tmp, s->region, s->f_slab,
+                  s->ktopo };
     for (size_t i = 0; i < sizeof(p) / sizeof(p[0]); ++i) free(p[i]);
     free(s);
 }
@@ -774,7 +804,8 @@ void o_sc_lj(double c6, double c12, double r2, double mu, double delta, double r
  * keeps its plain terms; a pair with a changed bead takes the A-state LJ at
  * mu = 1 - lambda and the B-state LJ at mu = lambda, both soft-core, and the
  * reaction field of the charge product (1 - lambda) q_i q_j |A + lambda
- * q_i q_j |B.  Bonded terms are those of the family, common to both states.
+ * q_i q_j |B.  Bonded terms are (1 - lambda) U_A + lambda U_B (the same
+ * terms in both states unless the exchange changes the topology).
  * U_0 = U_A and U_1 = U_B exactly. */
 typedef struct { const int* mk_b; const char* chg; double lam; double* f; double u; } sc_ctx;
 
@@ -814,10 +845,24 @@ static double sc_energy_forces(osys* s, const int* mk_b, double lam, double* f)
     if (f) memset(f, 0, sizeof(double) * 3 * s->n);
     sc_ctx c = { mk_b, chg, lam, f, 0.0 };
     for_pairs(s, s->rc, 1, sc_pair, &c);
-    double eb, ea;
-    bonded(s, s->mkind, f, &eb, &ea);
+    double eb, ea, ub = 0.0;
+    int topo = 0;
+    for (int m = 0; m < s->nm; ++m) topo |= s->ktopo[s->mkind[m] * s->nk + mk_b[m]];
+    if (!topo || lam == 0.0 || lam == 1.0) {
+        bonded(s, lam == 0.0 ? s->mkind : mk_b, f, &eb, &ea);
+        ub = eb + ea;
+    } else {
+        double* fb = f ? (double*)calloc((size_t)3 * s->n, sizeof(double)) : NULL;
+        bonded(s, s->mkind, fb, &eb, &ea);
+        ub += (1.0 - lam) * (eb + ea);
+        if (f) for (int q = 0; q < 3 * s->n; ++q) { f[q] += (1.0 - lam) * fb[q]; fb[q] = 0.0; }
+        bonded(s, mk_b, fb, &eb, &ea);
+        ub += lam * (eb + ea);
+        if (f) for (int q = 0; q < 3 * s->n; ++q) f[q] += lam * fb[q];
+        free(fb);
+    }
     free(chg);
-    return c.u + eb + ea;
+    return c.u + ub;
 }
 
 /* U at lambda on the soft-core path for exchanging the given pairs */
@@ -1240,9 +1285,34 @@ static int draw_pair(const osys* s, const uint32_t w[4], int* X, int* Y)
     return 1;
 }
 
-/* U(after) - U(before) for exchanging the kinds of molecules X and Y,
- * summed over the pair terms that involve a changed bead (bonded terms do
- * not change because the kinds of a family share their topology). */
+/* Bonded energy of molecule m if it had kind k, at the current coordinates. */
+static double mol_bonded_energy(const osys* s, int m, int k)
+{
+    double Eb = 0.0, Ea = 0.0;
+    int f0 = s->mfirst[m];
+    for (int b = 0; b < s->knb[k]; ++b) {
+        int bb = s->kboff[k] + b;
+        double d[3];
+        min_image(s, &s->x[3 * (f0 + s->bi[bb])], &s->x[3 * (f0 + s->bj[bb])], d);
+        double dr = sqrt(dist2(d)) - s->bb0[bb];
+        Eb += 0.5 * s->bk[bb] * dr * dr;
+    }
+    for (int t = 0; t < s->kna[k]; ++t) {
+        int aa = s->kaoff[k] + t;
+        double u[3], w[3];
+        min_image(s, &s->x[3 * (f0 + s->ai[aa])], &s->x[3 * (f0 + s->aj[aa])], u);
+        min_image(s, &s->x[3 * (f0 + s->ak[aa])], &s->x[3 * (f0 + s->aj[aa])], w);
+        double cth = (u[0] * w[0] + u[1] * w[1] + u[2] * w[2]) / (sqrt(dist2(u)) * sqrt(dist2(w)));
+        double dc = cth - s->acos0[aa];
+        Ea += 0.5 * s->akk[aa] * dc * dc;
+    }
+    return Eb + Ea;
+}
+
+/* U(after) - U(before) for exchanging the kinds of molecules X and Y: the
+ * pair terms that involve a changed bead, plus, when the kinds differ in
+ * their bonded terms (a topology-changing exchange), the bonded energies of
+ * X and Y in their new kinds minus those in their old ones. */
 static double delta_u_pair(osys* s, int X, int Y)
 {
     int kx = s->mkind[X], ky = s->mkind[Y];
@@ -1274,6 +1344,9 @@ static double delta_u_pair(osys* s, int X, int Y)
             du += (v1a + v1b) - (v0a + v0b);
         }
     }
+    if (s->ktopo[kx * s->nk + ky])
+        du += (mol_bonded_energy(s, X, ky) + mol_bonded_energy(s, Y, kx))
+            - (mol_bonded_energy(s, X, kx) + mol_bonded_energy(s, Y, ky));
     return du;
 }
 

@@ -688,6 +688,7 @@ __global__ void k_trial_accept(Dev<R> d, Mv m)
     int MC = m.maxcht;
     double du = 0.0;
     for (int q = 0; q < m.r_nb[a]; ++q) du += m.du_bead[a * MC + q];
+    du += m.du_bond[a];
     uint4 w = draw(d.seed, (uint32_t)m.r_draw[a], d.ctr[CT_BATCH], ST_SWAP_ACCEPT);
     double u = u53(w.x, w.y);
     int acc = u < exp(-du / d.kTd);
@@ -703,8 +704,10 @@ __global__ void k_du_total(Dev<R> d, Mv m, double* out)
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     int MC = m.maxcht;
     double s = 0.0;
-    for (int a = 0; a < m.r_n[0]; ++a)
+    for (int a = 0; a < m.r_n[0]; ++a) {
         for (int q = 0; q < m.r_nb[a]; ++q) s += m.du_bead[a * MC + q];
+        s += m.du_bond[a];
+    }
     *out = s;
 }
 
@@ -939,6 +942,174 @@ __global__ void k_dlam(Dev<R> d, Mv m, R dl)
     d.frc[i] = f;
 }
 
+// ------------------------------------------- topology-changing exchanges
+// An exchange between kinds whose bonded terms differ changes the bonded
+// energy and forces of both molecules.  In float64, from the stored
+// coordinates, with the bonded partners' minimum-image separation taken as
+// in the force pass (the coordinate beyond half a box shifted by L first).
+__device__ __forceinline__ double sep_d(double xi, double xj, double L)
+{
+    double dx = xi - xj;
+    if (dx > 0.5 * L) dx = (xi - L) - xj;
+    else if (dx < -0.5 * L) dx = xi - (xj - L);
+    return dx;
+}
+
+// Bonded energy of molecule mol as kind k at the current coordinates; with
+// f, its forces are added to f[local bead][axis] times sgn.
+template <typename R>
+__device__ double mol_bonded(const Dev<R>& d, int mol, int k, double (*f)[3], double sgn)
+{
+    const int f0 = d.mol_first[mol];
+    double u = 0.0;
+    for (int q = 0; q < d.kb_n[k]; ++q) {
+        const int bq = d.kb_off[k] + q;
+        const int li = d.b_ij[2 * bq], lj = d.b_ij[2 * bq + 1];
+        const V4<R> pi = d.posq[d.inv[f0 + li]], pj = d.posq[d.inv[f0 + lj]];
+        const double dx = sep_d(pi.x, pj.x, d.Ld[0]), dy = sep_d(pi.y, pj.y, d.Ld[1]),
+                     dz = sep_d(pi.z, pj.z, d.Ld[2]);
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        const double kk = (double)d.b_par[2 * bq + 1], dr = r - (double)d.b_par[2 * bq];
+        u += 0.5 * kk * dr * dr;
+        if (f) {
+            const double fs = -kk * dr / r * sgn;
+            f[li][0] += fs * dx; f[li][1] += fs * dy; f[li][2] += fs * dz;
+            f[lj][0] -= fs * dx; f[lj][1] -= fs * dy; f[lj][2] -= fs * dz;
+        }
+    }
+    for (int q = 0; q < d.ka_n[k]; ++q) {
+        const int aq = d.ka_off[k] + q;
+        const int li = d.a_ijk[3 * aq], lj = d.a_ijk[3 * aq + 1], lk = d.a_ijk[3 * aq + 2];
+        const V4<R> pi = d.posq[d.inv[f0 + li]], pj = d.posq[d.inv[f0 + lj]],
+                    pk = d.posq[d.inv[f0 + lk]];
+        const double u3[3] = { sep_d(pi.x, pj.x, d.Ld[0]), sep_d(pi.y, pj.y, d.Ld[1]),
+                               sep_d(pi.z, pj.z, d.Ld[2]) };
+        const double w3[3] = { sep_d(pk.x, pj.x, d.Ld[0]), sep_d(pk.y, pj.y, d.Ld[1]),
+                               sep_d(pk.z, pj.z, d.Ld[2]) };
+        const double uu = u3[0] * u3[0] + u3[1] * u3[1] + u3[2] * u3[2];
+        const double ww = w3[0] * w3[0] + w3[1] * w3[1] + w3[2] * w3[2];
+        const double nuw = sqrt(uu) * sqrt(ww);
+        const double cth = (u3[0] * w3[0] + u3[1] * w3[1] + u3[2] * w3[2]) / nuw;
+        const double kk = (double)d.a_par[2 * aq + 1], dc = cth - (double)d.a_par[2 * aq];
+        u += 0.5 * kk * dc * dc;
+        if (f) {
+            const double pre = -kk * dc * sgn;
+            for (int a = 0; a < 3; ++a) {
+                const double dci = w3[a] / nuw - cth * u3[a] / uu;
+                const double dck = u3[a] / nuw - cth * w3[a] / ww;
+                f[li][a] += pre * dci;
+                f[lk][a] += pre * dck;
+                f[lj][a] -= pre * (dci + dck);
+            }
+        }
+    }
+    return u;
+}
+
+// du_bond[a] = scale (U_bonded(after) - U_bonded(before)) of trial a: X and
+// Y in each other's kinds minus in their own (zero unless the kinds differ
+// in their bonded terms).  One thread per trial.
+template <typename R>
+__global__ void k_bond_du(Dev<R> d, Mv m, double scale)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= m.T) return;
+    double du = 0.0;
+    if (a < m.r_n[0]) {
+        const int X = m.r_x[a], Y = m.r_y[a];
+        const int kx = d.mol_kind[X], ky = d.mol_kind[Y];
+        if (d.ktopo[kx * d.nk + ky])
+            du = scale * ((mol_bonded(d, X, ky, nullptr, 0.0) + mol_bonded(d, Y, kx, nullptr, 0.0)) -
+                          (mol_bonded(d, X, kx, nullptr, 0.0) + mol_bonded(d, Y, ky, nullptr, 0.0)));
+    }
+    m.du_bond[a] = du;
+}
+
+// F_new - F_old of the bonded terms on the beads of each side of a trial
+// (thread 2 a + side: X, Y), kept in dfb and added to the stored forces
+// times scale; with only_accepted, trials that were not accepted are left
+// alone.  Zero unless the kinds differ in their bonded terms.
+template <typename R>
+__global__ void k_bond_dforce(Dev<R> d, Mv m, double scale, int only_accepted)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int a = e >> 1, side = e & 1;
+    if (a >= m.r_n[0]) return;
+    if (only_accepted && !m.r_acc[a]) return;
+    const int X = m.r_x[a], Y = m.r_y[a];
+    const int mol = side ? Y : X, other = side ? X : Y;
+    const int kold = d.mol_kind[mol], knew = d.mol_kind[other];
+    double f[MAXKN_TOPO][3];
+    for (int l = 0; l < MAXKN_TOPO; ++l) f[l][0] = f[l][1] = f[l][2] = 0.0;
+    const bool topo = d.ktopo[kold * d.nk + knew] != 0;
+    if (topo) {
+        mol_bonded(d, mol, knew, f, 1.0);
+        mol_bonded(d, mol, kold, f, -1.0);
+    }
+    double* out = m.dfb + (size_t)e * MAXKN_TOPO * 3;
+    const int f0 = d.mol_first[mol], n = d.kn[kold];
+    for (int l = 0; l < MAXKN_TOPO; ++l) {
+        out[3 * l] = f[l][0]; out[3 * l + 1] = f[l][1]; out[3 * l + 2] = f[l][2];
+        if (topo && l < n && scale != 0.0) {
+            const int sl = d.inv[f0 + l];
+            V4<R> g = d.frc[sl];
+            g.x = (R)((double)g.x + scale * f[l][0]);
+            g.y = (R)((double)g.y + scale * f[l][1]);
+            g.z = (R)((double)g.z + scale * f[l][2]);
+            d.frc[sl] = g;
+        }
+    }
+}
+
+// F += dl (F_B - F_A) of the bonded terms (an MDAS lambda increment).
+template <typename R>
+__global__ void k_bond_dlam(Dev<R> d, Mv m, double dl)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int a = e >> 1, side = e & 1;
+    if (a >= m.r_n[0]) return;
+    const int mol = side ? m.r_y[a] : m.r_x[a];
+    const int f0 = d.mol_first[mol], n = min(d.kn[d.mol_kind[mol]], MAXKN_TOPO);
+    const double* in = m.dfb + (size_t)e * MAXKN_TOPO * 3;
+    for (int l = 0; l < n; ++l) {
+        const int sl = d.inv[f0 + l];
+        V4<R> g = d.frc[sl];
+        g.x = (R)((double)g.x + dl * in[3 * l]);
+        g.y = (R)((double)g.y + dl * in[3 * l + 1]);
+        g.z = (R)((double)g.z + dl * in[3 * l + 2]);
+        d.frc[sl] = g;
+    }
+}
+
+// After accepted exchanges between kinds with different bonded terms: the
+// molecules' bonded records (bead-id order) and their slot-ordered copies
+// rewritten from their new kinds' templates (run after the commit).
+template <typename R>
+__global__ void k_bt_refresh(Dev<R> d, Mv m, int mode)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int a = e >> 1, side = e & 1;
+    if (a >= m.r_n[0]) return;
+    const bool acc = mode == 0 ? (m.r_acc[a] != 0) : (m.md[2] != 0.0);
+    if (!acc) return;
+    const int X = m.r_x[a], Y = m.r_y[a];
+    const int mol = side ? Y : X;
+    const int k = d.mol_kind[mol], ko = d.mol_kind[side ? X : Y];
+    if (!d.ktopo[k * d.nk + ko]) return;
+    const int f0 = d.mol_first[mol];
+    for (int l = 0; l < d.kn[k]; ++l) {
+        const int b = f0 + l, sl = d.inv[b];
+        for (int t = 0; t < MAXBT; ++t) {
+            const int4 tp = d.ktpl[(size_t)(d.kbead_off[k] + l) * MAXBT + t];
+            const bool on = tp.x >= 0;
+            const int p1 = on ? f0 + tp.y : b, p2 = on && tp.z >= 0 ? f0 + tp.z : -1;
+            d.bt[(size_t)b * MAXBT + t] = make_int4(on ? tp.x : -1, p1, p2, on ? tp.w : 0);
+            d.bslot[(size_t)sl * MAXBT + t] =
+                make_int4(on ? tp.x : -1, d.inv[p1], p2 >= 0 ? d.inv[p2] : sl, on ? tp.w : 0);
+        }
+    }
+}
+
 // Apply accepted exchanges: new classes and molecule kinds.
 template <typename R>
 __global__ void k_commit(Dev<R> d, Mv m, int mode)
@@ -1155,6 +1326,31 @@ void launch_dlam(const Dev<R>& d, const Mv& m, R dl, hipStream_t st)
 }
 
 template <typename R>
+void launch_bond_du(const Dev<R>& d, const Mv& m, double scale, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bond_du<R>, dim3((m.T + 255) / 256), dim3(256), 0, st, d, m, scale);
+}
+
+template <typename R>
+void launch_bond_dforce(const Dev<R>& d, const Mv& m, double scale, int only_accepted, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bond_dforce<R>, dim3((2 * m.T + 63) / 64), dim3(64), 0, st, d, m, scale,
+                       only_accepted);
+}
+
+template <typename R>
+void launch_bond_dlam(const Dev<R>& d, const Mv& m, double dl, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bond_dlam<R>, dim3((2 * m.T + 63) / 64), dim3(64), 0, st, d, m, dl);
+}
+
+template <typename R>
+void launch_bt_refresh(const Dev<R>& d, const Mv& m, int mode, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bt_refresh<R>, dim3((2 * m.T + 63) / 64), dim3(64), 0, st, d, m, mode);
+}
+
+template <typename R>
 void launch_commit(const Dev<R>& d, const Mv& m, int mode, int T, hipStream_t st)
 {
     int n = T * m.maxcht;
@@ -1200,6 +1396,10 @@ void launch_kcnt(const Dev<R>& d, const Mv& m, int kind, hipStream_t st)
     template void launch_scdu<R>(const Dev<R>&, const Mv&, int, double, double, double,    \
                                  hipStream_t);                                            \
     template void launch_commit<R>(const Dev<R>&, const Mv&, int, int, hipStream_t);      \
+    template void launch_bond_du<R>(const Dev<R>&, const Mv&, double, hipStream_t);       \
+    template void launch_bond_dforce<R>(const Dev<R>&, const Mv&, double, int, hipStream_t); \
+    template void launch_bond_dlam<R>(const Dev<R>&, const Mv&, double, hipStream_t);     \
+    template void launch_bt_refresh<R>(const Dev<R>&, const Mv&, int, hipStream_t);       \
     template void launch_mdas_accept<R>(const Dev<R>&, const Mv&, hipStream_t);           \
     template void launch_snapshot<R>(const Dev<R>&, const Mv&, int, hipStream_t);         \
     template void launch_kcnt<R>(const Dev<R>&, const Mv&, int, hipStream_t);

@@ -242,6 +242,15 @@ template <typename R> struct Dev {
     int* bt_off;
     int4* bt;
     R* bt_par;       // (b0, k) or (cos theta0, k)
+    // topology-changing exchanges (kinds of one family with different
+    // bonded terms): topo != 0; ktopo[k1 * nk + k2] marks such kind pairs;
+    // the bonded terms then sit MAXBT per bead (bt_off[b] = b MAXBT) and are
+    // rewritten from the per-kind templates ktpl[(kbead_off[k] + l) MAXBT
+    // + t] = {role, partner 1, partner 2 (-1: none), parameter} in local
+    // bead indices when a molecule changes kind
+    int topo;
+    int* ktopo;
+    int4* ktpl;
     // tables
     V4<R>* tabF;
     V4<R>* tabE;
@@ -266,6 +275,7 @@ constexpr int SEL_CMAX = 8192;   // largest selection chunk
 constexpr int SEL_CAPC = 64;     // earlier conflicting candidates listed per candidate
 constexpr int SEL_LDS = 61440;   // conflict-list entries one chunk may resolve (120 KB of LDS)
 constexpr int MAXMC = 2 * MAXCH; // changed beads per trial
+constexpr int MAXKN_TOPO = 16;   // beads per molecule in a topology-changing family
 // selection state words
 enum { SEL_ADM = 0, SEL_NEXT = 1, SEL_DONE = 2, SEL_EPC = 3, SEL_STAMP = 4, SEL_NSEL = 8 };
 constexpr int HBW = 4;           // entries per hash bucket
@@ -321,6 +331,11 @@ struct Mv {
     int* aff_list;       // [aff_cap]
     int* aff_n;          // [1]
     int aff_cap;
+    // bonded part of an exchange that changes the topology: dU per trial
+    // (scaled as the caller asks; zero otherwise) and F_B - F_A on the
+    // beads of each exchanged molecule ([T][2][MAXKN_TOPO][3])
+    double* du_bond;     // [T]
+    double* dfb;
     // MDAS
     double* md;          // [8]: work, dU, accept, u
     // snapshot of the per-slot state

@@ -63,6 +63,10 @@ template <typename R>
 void launch_scdu(const Dev<R>&, const Mv&, int, double, double, double, hipStream_t);
 template <typename R> void launch_dlam(const Dev<R>&, const Mv&, R, hipStream_t);
 template <typename R> void launch_commit(const Dev<R>&, const Mv&, int, int, hipStream_t);
+template <typename R> void launch_bond_du(const Dev<R>&, const Mv&, double, hipStream_t);
+template <typename R> void launch_bond_dforce(const Dev<R>&, const Mv&, double, int, hipStream_t);
+template <typename R> void launch_bond_dlam(const Dev<R>&, const Mv&, double, hipStream_t);
+template <typename R> void launch_bt_refresh(const Dev<R>&, const Mv&, int, hipStream_t);
 void launch_work(double*, double, hipStream_t);
 template <typename R> void launch_mdas_accept(const Dev<R>&, const Mv&, hipStream_t);
 template <typename R> void launch_snapshot(const Dev<R>&, const Mv&, int, hipStream_t);
@@ -118,6 +122,10 @@ struct Host {
     std::vector<int> bt_off;            // per-bead bonded terms (CSR over bead ids)
     std::vector<int> bt;                // 4 ints per entry
     std::vector<double> bt_par;         // 2 per parameter set
+    // topology-changing families: per-kind-pair flags, per-kind-bead record
+    // templates (4 ints each, MAXBT per kind bead); bt is then MAXBT per bead
+    int topo = 0;
+    std::vector<int> ktopo, ktpl;
     std::vector<int> sw_list, fam_off, fam_mem, fam_of_kind, chg_n, chg_loc;
     int nfam = 0, maxch = 0, fam_stride = 1;
     // exchange regions (leaflets) and the partner rule (0 anywhere, 1 within
@@ -328,6 +336,29 @@ Status check_desc(const membx_desc* d, Host& h)
     return { MEMBX_OK, "" };
 }
 
+// Bonded records at MAXBT per bead (bt_off[b] = b MAXBT), rewritten from
+// the kind templates for the given molecule kinds (topology-changing
+// families: a molecule's records follow its current kind).
+static void bt_from_kinds(Host& h, const std::vector<int>& kinds)
+{
+    h.bt.assign((size_t)h.N * MAXBT * 4, 0);
+    h.bt_off.assign(h.N + 1, 0);
+    for (int b = 0; b <= h.N; ++b) h.bt_off[b] = b * MAXBT;
+    for (int m = 0; m < h.nm; ++m) {
+        const int k = kinds[m], f0 = h.mol_first[m];
+        for (int l = 0; l < h.kn[k]; ++l)
+            for (int t = 0; t < MAXBT; ++t) {
+                const int* tp = &h.ktpl[((size_t)(h.kbead_off[k] + l) * MAXBT + t) * 4];
+                int* r = &h.bt[((size_t)(f0 + l) * MAXBT + t) * 4];
+                const bool on = tp[0] >= 0;
+                r[0] = on ? tp[0] : -1;
+                r[1] = on ? f0 + tp[1] : f0 + l;
+                r[2] = on && tp[2] >= 0 ? f0 + tp[2] : -1;
+                r[3] = on ? tp[3] : 0;
+            }
+    }
+}
+
 Status derive(const membx_desc* d, Host& h)
 {
     // classes: distinct (type, charge) pairs over all kinds
@@ -347,10 +378,14 @@ Status derive(const membx_desc* d, Host& h)
     // exclusions: beads joined by a bond (nrexcl = 1)
     h.excl.assign((size_t)h.N * MAXEXCL, -1);
     std::vector<int> nex(h.N, 0);
+    // (a molecule of a swap family excludes the pairs bonded in any kind of
+    // the family, so that its nonbonded pairs do not depend on its kind)
     for (int m = 0; m < h.nm; ++m) {
-        int k = h.mol_kind0[m], f0 = h.mol_first[m];
-        if (h.kb_n[k] > 0 || h.ka_n[k] > 0) h.bmols.push_back(m);
-        for (int q = 0; q < h.kb_n[k]; ++q) {
+        int k0 = h.mol_kind0[m], f0 = h.mol_first[m];
+        if (h.kb_n[k0] > 0 || h.ka_n[k0] > 0) h.bmols.push_back(m);
+        for (int k = 0; k < h.nk; ++k) {
+          if (k != k0 && (h.kfam[k0] < 0 || h.kfam[k] != h.kfam[k0] || h.kn[k] != h.kn[k0])) continue;
+          for (int q = 0; q < h.kb_n[k]; ++q) {
             int bq = h.kb_off[k] + q;
             int i = f0 + h.b_ij[2 * bq], j = f0 + h.b_ij[2 * bq + 1];
             bool dup = false;
@@ -360,6 +395,7 @@ Status derive(const membx_desc* d, Host& h)
                 return { MEMBX_E_INVAL, "a bead has more than 8 bonded partners" };
             h.excl[(size_t)i * MAXEXCL + nex[i]++] = j;
             h.excl[(size_t)j * MAXEXCL + nex[j]++] = i;
+          }
         }
     }
     // swap families
@@ -374,28 +410,35 @@ Status derive(const membx_desc* d, Host& h)
             h.fam_of_kind[k] = fid[h.kfam[k]];
         }
     h.nfam = (int)fid.size();
-    // kinds of one family: same size, topology and masses
+    // kinds of one family: same number of beads and masses; their bonded
+    // terms may differ (a topology-changing exchange, then at most
+    // MAXKN_TOPO beads per molecule)
+    h.ktopo.assign((size_t)h.nk * h.nk, 0);
     for (int a = 0; a < h.nk; ++a)
         for (int b = 0; b < h.nk; ++b) {
             if (h.fam_of_kind[a] < 0 || h.fam_of_kind[a] != h.fam_of_kind[b] || a >= b) continue;
-            if (h.kn[a] != h.kn[b] || h.kb_n[a] != h.kb_n[b] || h.ka_n[a] != h.ka_n[b])
-                return { MEMBX_E_INVAL, "kinds of one swap family differ in topology" };
-            for (int q = 0; q < h.kb_n[a]; ++q)
-                for (int c = 0; c < 2; ++c)
-                    if (h.b_ij[2 * (h.kb_off[a] + q) + c] != h.b_ij[2 * (h.kb_off[b] + q) + c] ||
-                        h.b_par[2 * (h.kb_off[a] + q) + c] != h.b_par[2 * (h.kb_off[b] + q) + c])
-                        return { MEMBX_E_INVAL, "kinds of one swap family differ in bonds" };
-            for (int q = 0; q < h.ka_n[a]; ++q) {
-                for (int c = 0; c < 3; ++c)
-                    if (h.a_ijk[3 * (h.ka_off[a] + q) + c] != h.a_ijk[3 * (h.ka_off[b] + q) + c])
-                        return { MEMBX_E_INVAL, "kinds of one swap family differ in angles" };
-                for (int c = 0; c < 2; ++c)
-                    if (h.a_par[2 * (h.ka_off[a] + q) + c] != h.a_par[2 * (h.ka_off[b] + q) + c])
-                        return { MEMBX_E_INVAL, "kinds of one swap family differ in angles" };
-            }
+            if (h.kn[a] != h.kn[b])
+                return { MEMBX_E_INVAL, "kinds of one swap family differ in their number of beads" };
             for (int q = 0; q < h.kn[a]; ++q)
                 if (h.bm[h.kbead_off[a] + q] != h.bm[h.kbead_off[b] + q])
                     return { MEMBX_E_INVAL, "kinds of one swap family differ in masses" };
+            bool dif = h.kb_n[a] != h.kb_n[b] || h.ka_n[a] != h.ka_n[b];
+            for (int q = 0; !dif && q < h.kb_n[a]; ++q)
+                for (int c = 0; c < 2; ++c)
+                    dif |= h.b_ij[2 * (h.kb_off[a] + q) + c] != h.b_ij[2 * (h.kb_off[b] + q) + c] ||
+                           h.b_par[2 * (h.kb_off[a] + q) + c] != h.b_par[2 * (h.kb_off[b] + q) + c];
+            for (int q = 0; !dif && q < h.ka_n[a]; ++q) {
+                for (int c = 0; c < 3; ++c)
+                    dif |= h.a_ijk[3 * (h.ka_off[a] + q) + c] != h.a_ijk[3 * (h.ka_off[b] + q) + c];
+                for (int c = 0; c < 2; ++c)
+                    dif |= h.a_par[2 * (h.ka_off[a] + q) + c] != h.a_par[2 * (h.ka_off[b] + q) + c];
+            }
+            if (dif) {
+                if (h.kn[a] > MAXKN_TOPO)
+                    return { MEMBX_E_INVAL, "a topology-changing swap family has more than 16 beads per molecule" };
+                h.ktopo[(size_t)a * h.nk + b] = h.ktopo[(size_t)b * h.nk + a] = 1;
+                h.topo = 1;
+            }
         }
     h.fam_off.assign(h.nfam + 1, 0);
     std::vector<std::vector<int>> mem(h.nfam);
@@ -459,6 +502,36 @@ Status derive(const membx_desc* d, Host& h)
         }
         if (h.bt.empty()) h.bt.assign(4, 0);
         if (h.bt_par.empty()) h.bt_par.assign(2, 0.0);
+        // per-kind templates in local bead indices (same construction)
+        const int nkb = (int)h.btype.size();
+        h.ktpl.assign((size_t)std::max(nkb, 1) * MAXBT * 4, 0);
+        std::vector<int> cnt(std::max(nkb, 1), 0);
+        auto put = [&](int k, int l, int role, int p1, int p2, int par) -> bool {
+            const int kb = h.kbead_off[k] + l;
+            if (cnt[kb] >= MAXBT) return false;
+            int* r = &h.ktpl[((size_t)kb * MAXBT + cnt[kb]++) * 4];
+            r[0] = role; r[1] = p1; r[2] = p2; r[3] = par;
+            return true;
+        };
+        bool ok = true;
+        for (int k = 0; k < h.nk; ++k) {
+            for (int q = 0; q < h.kb_n[k]; ++q) {
+                int bq = h.kb_off[k] + q, i = h.b_ij[2 * bq], j = h.b_ij[2 * bq + 1];
+                ok &= put(k, i, 0, j, -1, bq);
+                ok &= put(k, j, 1, i, -1, bq);
+            }
+            for (int q = 0; q < h.ka_n[k]; ++q) {
+                int aq = h.ka_off[k] + q;
+                int i = h.a_ijk[3 * aq], j = h.a_ijk[3 * aq + 1], l = h.a_ijk[3 * aq + 2];
+                ok &= put(k, i, 2, j, l, nbp + aq);
+                ok &= put(k, l, 2, j, i, nbp + aq);
+                ok &= put(k, j, 3, i, l, nbp + aq);
+            }
+        }
+        if (!ok) return { MEMBX_E_INVAL, "a bead takes part in more than 8 bonded terms" };
+        for (int kb = 0; kb < nkb; ++kb)
+            for (int t = cnt[kb]; t < MAXBT; ++t) h.ktpl[((size_t)kb * MAXBT + t) * 4] = -1;
+        if (h.topo) bt_from_kinds(h, h.mol_kind0);
     }
     h.aff_cap = std::max(h.T_cap, h.P_cap) * 2 * h.maxch * (h.Kcap + 1);
     h.aff_cap = std::min(h.aff_cap, h.N);
@@ -590,6 +663,9 @@ static size_t layout(membx_sys* s, Dev<R>& d, Mv& m, char* base)
     d.bt_off = a.take<int>(h.bt_off.size());
     d.bt = a.take<int4>(h.bt.size() / 4);
     d.bt_par = a.take<R>(h.bt_par.size());
+    d.topo = h.topo;
+    d.ktopo = a.take<int>((size_t)h.nk * h.nk);
+    d.ktpl = a.take<int4>(h.ktpl.size() / 4);
     d.tabF = a.take<V4<R>>(MAXCLS * MAXCLS); d.tabE = a.take<V4<R>>(MAXCLS * MAXCLS);
     d.flags = a.take<int>(NFLAGS);
     d.ctr = a.take<long long>(NCTR);
@@ -660,6 +736,8 @@ static size_t layout(membx_sys* s, Dev<R>& d, Mv& m, char* base)
     m.r_nb = a.take<int>(T); m.r_bead = a.take<int>(T * MC); m.r_cls = a.take<int>(T * MC);
     m.r_pos = a.take<double>(3 * (size_t)T * MC);
     m.du_bead = a.take<double>(T * MC);
+    m.du_bond = a.take<double>(T);
+    m.dfb = a.take<double>((size_t)2 * T * MAXKN_TOPO * 3);
     m.aff_flag = a.take<int>(N);
     m.aff_cap = h.aff_cap;
     m.aff_list = a.take<int>(h.aff_cap);
@@ -750,12 +828,18 @@ static void alch_terms(membx_sys* s, bool rebuilt, double lam)
         launch_aff_clear<R>(d, m, s->st);
         launch_aff_build<R>(d, m, 0, T, s->st);
     }
+    const bool topo = s->h.topo != 0;
     if (s->h.mdas_path == 1) {   // force pass (A) + F_sc(lam) - F_sc(0)
         launch_scforce<R>(d, m, 0.0, lam, s->h.sc_delta, s->st);
+        if (topo) launch_bond_dforce<R>(d, m, lam, 0, s->st);   // + lam (F_B - F_A) bonded
         return;
     }
     launch_dforce<R>(d, m, (R)lam, s->st);
     launch_du<R>(d, m, T, s->st);
+    if (topo) {
+        launch_bond_dforce<R>(d, m, lam, 0, s->st);
+        launch_bond_du<R>(d, m, 1.0, s->st);
+    }
     launch_du_total<R>(d, m, m.md + 1, s->st);
 }
 
@@ -998,15 +1082,19 @@ static void swap_seq(membx_sys* s, int n_trials)
     Dev<R>& d = dev<R>(s);
     Mv& m = s->mv;
     int T = m.T;
+    const bool topo = s->h.topo != 0;
     launch_select<R>(d, m, n_trials, 64 * n_trials, 0, s->st);
     launch_mark<R>(d, m, 0, T, s->st);
     launch_ghost_update<R>(d, s->st);
     launch_du<R>(d, m, T, s->st);
+    if (topo) launch_bond_du<R>(d, m, 1.0, s->st);   // bonded part of dU
     launch_trial_accept<R>(d, m, T, s->st);
     launch_unmark<R>(d, m, 1, T, s->st);
     launch_aff_build<R>(d, m, 1, T, s->st);
     launch_dforce<R>(d, m, (R)1, s->st);
+    if (topo) launch_bond_dforce<R>(d, m, 1.0, 1, s->st);   // accepted: bonded F_new - F_old
     launch_commit<R>(d, m, 0, T, s->st);
+    if (topo) launch_bt_refresh<R>(d, m, 0, s->st);
     launch_aff_clear<R>(d, m, s->st);
     kcnt_all<R>(s);
     launch_ghost_update<R>(d, s->st);
@@ -1056,10 +1144,17 @@ static int32_t mdas(membx_sys* s, int P, int K, int M)
     launch_fill_i32((int*)m.md, 0, 16, st);
     launch_ghost_update<R>(d, st);
     const bool sc = s->h.mdas_path == 1;
+    const bool topo = s->h.topo != 0;
     if (!sc) {
         launch_dforce<R>(d, m, (R)0, st);
         launch_du<R>(d, m, T, st);
+        if (topo) {
+            launch_bond_dforce<R>(d, m, 0.0, 0, st);
+            launch_bond_du<R>(d, m, 1.0, st);
+        }
         launch_du_total<R>(d, m, m.md + 1, st);
+    } else if (topo) {
+        launch_bond_dforce<R>(d, m, 0.0, 0, st);   // F_B - F_A bonded at the start
     }
     double lam = 0.0;
     for (int k = 1; k <= K; ++k) {
@@ -1073,18 +1168,22 @@ static int32_t mdas(membx_sys* s, int P, int K, int M)
         double dl = lam_new - lam;
         if (sc) {   // w += U_sc(lam_new) - U_sc(lam) at x; forces follow lambda
             launch_scdu<R>(d, m, T, lam, lam_new, s->h.sc_delta, st);
+            if (topo) launch_bond_du<R>(d, m, dl, st);   // bonded terms: linear in lambda
             launch_du_total<R>(d, m, m.md + 1, st);
             launch_work(m.md, 1.0, st);
             launch_scforce<R>(d, m, lam, lam_new, s->h.sc_delta, st);
+            if (topo) launch_bond_dlam<R>(d, m, dl, st);
         } else {
             launch_work(m.md, dl, st);
             launch_dlam<R>(d, m, (R)dl, st);
+            if (topo) launch_bond_dlam<R>(d, m, dl, st);
         }
         lam = lam_new;
     }
     if (M == 0) s->fe += 1;
     launch_mdas_accept<R>(d, m, st);
     launch_commit<R>(d, m, 1, T, st);
+    if (topo) launch_bt_refresh<R>(d, m, 1, st);
     launch_aff_clear<R>(d, m, st);
     launch_snapshot<R>(d, m, 1, st);
     rebuild<R>(s);
@@ -1192,6 +1291,14 @@ static int32_t upload(membx_sys* s, const membx_desc* desc)
     UP(d.bt_off, h.bt_off);
     UP(d.bt, h.bt);
     UP(d.bt_par, btpar);
+    UP(d.ktopo, h.ktopo);
+    UP(d.ktpl, h.ktpl);
+    {
+        std::vector<double> z((size_t)2 * m.T * MAXKN_TOPO * 3, 0.0);
+        HCK(hipMemcpyAsync(m.du_bond, z.data(), sizeof(double) * m.T, hipMemcpyHostToDevice, st));
+        HCK(hipMemcpyAsync(m.dfb, z.data(), sizeof(double) * z.size(), hipMemcpyHostToDevice, st));
+        HCK(hipStreamSynchronize(st));
+    }
     UP(d.tabF, tf);
     UP(d.tabE, te);
     UP(d.flags, zeros_flags);
@@ -1644,6 +1751,10 @@ static int32_t set_state_impl(membx_sys* s, const double* pos, const double* vel
             for (int b = 0; b < h.kn[mol_kind[m]]; ++b)
                 cls[h.mol_first[m] + b] = h.kcls[h.kbead_off[mol_kind[m]] + b];
         HCK(hipMemcpyAsync(d.mol_kind, mol_kind, sizeof(int) * d.nm, hipMemcpyHostToDevice, s->st));
+        if (h.topo) {   // bonded records follow the molecules' new kinds
+            bt_from_kinds(h, std::vector<int>(mol_kind, mol_kind + h.nm));
+            HCK(hipMemcpyAsync(d.bt, h.bt.data(), sizeof(int) * h.bt.size(), hipMemcpyHostToDevice, s->st));
+        }
         HCK(hipMemcpyAsync(s->ibuf, cls.data(), sizeof(int) * d.N, hipMemcpyHostToDevice, s->st));
         launch_set_classes(d.posq, s->mixed() ? 1 : 0, s->ibuf, d.orig, d.N, s->st);
         kcnt_all<R>(s);

@@ -20,6 +20,8 @@ Kinds: A is a 12-bead saturated lipid (NC3 +1, PO4 -1, GL1, GL2, two 4-bead
 tails); B is A with the third bead of each tail unsaturated; D is A with a -1
 head charge; C is an 8-bead sterol-like molecule; W is one water bead.
 A, B and D form swap family 0 (identical topology); C and W never swap.
+``topo`` (C0's shape) puts A and S12, the sterol padded to 12 bead slots
+with four dummy beads, in one family: a topology-changing exchange.
 
 Coordinates lie in [0, L) per axis and are rounded to float32-representable
 values, as are the box lengths and velocities, so that a float32 and a
@@ -36,13 +38,16 @@ import numpy as np
 # 2 C (saturated tail, sterol ring/tail), 3 U (unsaturated tail), 4 W (water).
 TYPE_Q, TYPE_N, TYPE_C, TYPE_U, TYPE_W = 0, 1, 2, 3, 4
 N_TYPES = 5
+# a bead with no Lennard-Jones interaction (a sixth type, only in systems
+# with topology-changing exchanges, whose epsilon row and column are zero)
+TYPE_DUMMY = 5
 EPS_LEVELS = (5.6, 5.0, 4.5, 4.0, 3.5, 3.1, 2.7, 2.3, 2.0)  # kJ/mol
 SIGMA = 0.47  # nm
 MASS = 72.0  # amu
 KB = 0.00831446261815324  # kJ/mol/K (used only to draw initial velocities)
 
 SEEDS = {"c0": 200508348000, "c1": 200508348001, "c2": 200508348002,
-         "c3": 200508348003, "mix": 200508348010}
+         "c3": 200508348003, "mix": 200508348010, "topo": 200508348020}
 PO4 = 1   # bead index of the phosphate in the lipid kinds A, B and D
 
 
@@ -137,6 +142,22 @@ def sterol_kind():
     angles = [(0, 1, 3, 180.0, 25.0), (1, 3, 5, 180.0, 25.0),
               (3, 5, 6, 180.0, 25.0), (5, 6, 7, 180.0, 25.0)]
     return Kind("C", types, charges, bonds, angles, -1)
+
+
+def sterol12_kind(family=0):
+    """The sterol padded to the lipids' 12 bead slots for a topology-changing
+    exchange family with them: slots 0-7 the sterol, slots 8-11 dummy beads
+    (type TYPE_DUMMY: no Lennard-Jones, no charge) held by a chain of bonds
+    from slot 3, the way the lipid's second tail hangs from its GL2.  In an
+    exchange with a lipid the dummies become a tail and four lipid beads
+    become sterol beads or vanish."""
+    st = sterol_kind()
+    types = list(st.types) + [TYPE_DUMMY] * 4
+    charges = list(st.charges) + [0.0] * 4
+    bonds = list(st.bonds) + [(3, 8, 0.47, 1250.0), (8, 9, 0.47, 1250.0),
+                              (9, 10, 0.47, 1250.0), (10, 11, 0.47, 1250.0)]
+    angles = list(st.angles) + [(8, 9, 10, 180.0, 25.0), (9, 10, 11, 180.0, 25.0)]
+    return Kind("S12", types, charges, bonds, angles, family)
 
 
 def water_kind():
@@ -324,6 +345,19 @@ def make(config, seed=None, **kw):
     if config == "c3":
         return bilayer("c3", 24576, [0.3, 0.3, 0.2, 0.2], 590000, 125.4, 11.0,
                        SEEDS["c3"] if seed is None else seed, **kw)
+    if config == "topo":
+        # topology-changing exchanges: C0's shape with lipid A and the
+        # 12-slot sterol S12 in one swap family (S12 takes kind slot 1)
+        kinds = standard_kinds()
+        kinds[KIND_B] = sterol12_kind()
+        s = bilayer("topo", 32, [0.5, 0.5], 640, 4.53, 9.0,
+                    SEEDS["topo"] if seed is None else seed, kinds=kinds,
+                    lipid_kinds=[KIND_A, KIND_B], **kw)
+        eps = np.zeros((N_TYPES + 1, N_TYPES + 1))
+        eps[:N_TYPES, :N_TYPES] = s.eps
+        s.eps = eps
+        s.sigma = np.full((N_TYPES + 1, N_TYPES + 1), SIGMA)
+        return s
     if config == "mix":
         # the paper's mixing test in shape: 400 lipids, 1:1 of a neutral lipid
         # (A) and its anionic twin (D, head charge -1), water, far-from-mixed
@@ -368,6 +402,43 @@ def custom(name, kinds, mol_kind, pos, box, eps, vel=None, seed=1, **kw):
                sigma=np.full(np.asarray(eps).shape, SIGMA), seed=seed)
     for k, v in kw.items():
         setattr(s, k, v)
+    return s
+
+
+def topo_exchange_toy(nmol=216, box=4.8, seed=13):
+    """A fluid of three-bead molecules of two kinds in one swap family whose
+    bonded terms differ (a topology-changing exchange with moderate energy
+    changes, so that exchanges are accepted): P is a chain h-s-t (bonds
+    0.47 nm, 1250 kJ/mol/nm^2, an angle at s) with s and t of type C; Q has
+    s and t of type U, bonds of 0.50 nm and 800 kJ/mol/nm^2 and no angle."""
+    kp = Kind("P", [TYPE_N, TYPE_C, TYPE_C], [0.0, 0.0, 0.0],
+              [(0, 1, 0.47, 1250.0), (1, 2, 0.47, 1250.0)], [(0, 1, 2, 180.0, 25.0)], 0)
+    kq = Kind("Q", [TYPE_N, TYPE_U, TYPE_U], [0.0, 0.0, 0.0],
+              [(0, 1, 0.50, 800.0), (1, 2, 0.50, 800.0)], [], 0)
+    eps = np.full((N_TYPES + 1, N_TYPES + 1), 3.5)
+    eps[TYPE_C, TYPE_C] = 4.5
+    eps[TYPE_C, TYPE_U] = eps[TYPE_U, TYPE_C] = 4.0
+    eps[TYPE_N, TYPE_C] = eps[TYPE_C, TYPE_N] = 3.1
+    eps[TYPE_N, TYPE_U] = eps[TYPE_U, TYPE_N] = 4.0
+    eps[TYPE_DUMMY, :] = 0.0
+    eps[:, TYPE_DUMMY] = 0.0
+    rng = np.random.default_rng(seed)
+    n = int(math.ceil(nmol ** (1 / 3)))
+    a = box / n
+    pts = [(i, j, k) for i in range(n) for j in range(n) for k in range(n)][:nmol]
+    pos = []
+    for p in pts:
+        hd = (np.array(p) + 0.2) * a
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        pos += [hd, hd + 0.47 * u, hd + 0.94 * u]
+    pos = np.mod(np.array(pos), box)
+    mk = np.array([i % 2 for i in range(nmol)], dtype=np.int32)
+    masses = np.full(3 * nmol, MASS)
+    sig = np.sqrt(KB * 323.0 / masses)
+    vel = rng.standard_normal(pos.shape) * sig[:, None]
+    s = custom("topo_toy", [kp, kq], mk, pos, [box] * 3, eps, vel=vel, seed=seed)
+    s.sigma = np.full(eps.shape, SIGMA)
     return s
 
 

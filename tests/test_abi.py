@@ -35,13 +35,17 @@ def test_descriptor_validation():
         M.arena_bytes(bad)
     with pytest.raises(M.MembxError):
         M.arena_bytes(s, lanes_per_bead=3)
-    # a family whose kinds differ in topology is rejected
+    # a family whose kinds differ in their number of beads is rejected (the
+    # 8-bead sterol beside the 12-bead lipids) ...
     k = S.standard_kinds()
     k[S.KIND_C].family = 0
     bad = s.copy()
     bad.kinds = k
     with pytest.raises(M.MembxError):
         M.arena_bytes(bad)
+    # ... one whose kinds differ only in bonded terms (the sterol padded to
+    # 12 slots with dummy beads) is a topology-changing family, accepted
+    assert M.arena_bytes(S.make("topo")) > 0
 
 
 def test_no_cpu_fallback():

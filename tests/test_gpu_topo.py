@@ -1,0 +1,182 @@
+"""Topology-changing exchanges (kinds of one swap family whose bonded terms
+differ; the soft-core path of Eq. 4 for beads that appear and vanish) on the
+GPU against the float64 oracle.
+
+Systems: the ``topo`` bilayer (lipid A and S12, the sterol padded to 12
+slots with four dummy beads: exchanges change bead classes, make dummies
+appear and vanish and change every bonded term of both molecules, with
+energy changes of 1e3 to 1e8 kJ/mol) and ``topo_exchange_toy`` (three-bead
+molecules whose kinds differ in bond lengths and constants and in an angle,
+so that exchanges are accepted).
+
+Tolerances: as for same-topology exchanges, made relative where the energy
+changes are large: dU within 1e-10 (float64) / 1e-6 (mixed) of max(1, |dU|)
+plus the absolute 1e-8 / 5e-4 kJ/mol; MDAS work within 1e-6 / 2e-2 kJ/mol
+(toy) or 1e-10 of |w| (frozen cycles on the bilayer); positions after the
+exchanges within 1e-7 nm (float64) / 1e-4 nm (mixed).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2005_08348_amd import systems as S
+
+pytestmark = pytest.mark.gpu
+
+KB = 0.00831446261815324
+
+
+def _membx():
+    from paper_2005_08348_amd import membx
+    return membx
+
+
+def _relaxed(oracle_mod, s, iters):
+    o = oracle_mod.Oracle(s)
+    o.minimize(iters)
+    r = s.copy()
+    r.pos = o.state()["pos"].astype(np.float32).astype(np.float64) % s.box
+    r.pos = np.where(r.pos >= s.box, 0.0, r.pos)
+    return r
+
+
+@pytest.fixture(scope="module")
+def topo(oracle_mod):
+    return _relaxed(oracle_mod, S.make("topo"), 100)
+
+
+@pytest.fixture(scope="module")
+def toy(oracle_mod):
+    return _relaxed(oracle_mod, S.topo_exchange_toy(), 50)
+
+
+def _pos_err(a, b, box):
+    d = a - b
+    d -= box * np.rint(d / box)
+    return np.abs(d).max()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_topo_bilayer_energies_and_forces(oracle_mod, topo, prec):
+    """Exclusions are the union over the family's kinds on both sides."""
+    m = _membx()
+    g = m.System(topo, precision=prec)
+    o = oracle_mod.Oracle(topo)
+    ref = o.energy_forces()
+    e = g.energies()
+    tot_abs = abs(ref["lj"]) + abs(ref["rf"]) + abs(ref["bond"]) + abs(ref["angle"])
+    tol = 1e-10 if prec == "fp64" else 2e-6
+    for k in ["lj", "rf", "bond", "angle"]:
+        assert abs(e[k] - ref[k]) <= tol * tot_abs, (k, e[k], ref[k])
+    assert e["n_pairs_in_cutoff"] == ref["n_pairs"]
+    f, fr = g.forces(), ref["force"]
+    frms = math.sqrt((fr ** 2).sum(axis=1).mean())
+    err = np.linalg.norm(f - fr, axis=1) / np.maximum(np.linalg.norm(fr, axis=1), frms)
+    assert err.max() < (1e-9 if prec == "fp64" else 1e-4), err.max()
+    g.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_topo_bilayer_exchange_energies(oracle_mod, topo, prec):
+    """Batches of A <-> S12 trials: the bonded part of dU (the sterol's ring
+    and the dummies' chain against the lipid's bonds) included."""
+    m = _membx()
+    g = m.System(topo, precision=prec)
+    o = oracle_mod.Oracle(topo)
+    for _ in range(2):
+        rg, ro = g.swap_trials(4), o.swap_batch(4)
+        assert list(rg["draw"]) == list(ro["draw"])
+        assert list(rg["X"]) == list(ro["X"]) and list(rg["Y"]) == list(ro["Y"])
+        rel, ab = (1e-10, 1e-8) if prec == "fp64" else (1e-6, 5e-4)
+        for a, b in zip(rg["du"], ro["du"]):
+            assert abs(a - b) <= rel * max(1.0, abs(b)) + ab, (a, b)
+        assert np.abs(ro["du"]).max() > 1e3
+        assert list(rg["accept"]) == list(ro["accept"])
+        g.set_state(mol_kind=o.state()["mol_kind"])
+    g.close()
+
+
+@pytest.mark.parametrize("path", [0, 1])
+def test_topo_bilayer_frozen_mdas(oracle_mod, topo, path):
+    """A frozen cycle (K = 1, M = 0) exchanging two A/S12 pairs: the work is
+    U_B - U_A on both paths, dummies and bonded terms included."""
+    m = _membx()
+    g = m.System(topo, precision="fp64")
+    o = oracle_mod.Oracle(topo)
+    if path == 1:
+        g.set_mdas_path(1, 0.05)
+        o.set_mdas_path(1, 0.05)
+    rg, ro = g.mdas_cycle(2, 1, 0), o.mdas_cycle(2, 1, 0)
+    assert np.array_equal(rg["pairs"], ro["pairs"])
+    assert abs(rg["work"] - ro["work"]) <= 1e-10 * max(1.0, abs(ro["work"])), (rg["work"], ro["work"])
+    assert rg["accept"] == ro["accept"]
+    g.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_topo_toy_exchanges_then_dynamics(oracle_mod, toy, prec):
+    """Accepted exchanges change the molecules' bonded terms: the stored
+    forces are updated (bonded F_new - F_old) and the bonded records
+    rewritten, so the dynamics that follow match the oracle's."""
+    m = _membx()
+    g = m.System(toy, precision=prec, rebuild_interval=4)
+    o = oracle_mod.Oracle(toy)
+    kT = KB * toy.temperature
+    n_acc = 0
+    for _ in range(4):
+        g.md_step(3)
+        o.md_step(3)
+        rg, ro = g.swap_trials(8), o.swap_batch(8)
+        assert list(rg["X"]) == list(ro["X"]) and list(rg["Y"]) == list(ro["Y"])
+        tol = 1e-8 if prec == "fp64" else 5e-4
+        assert np.abs(rg["du"] - ro["du"]).max() < tol
+        for a, b, u, du in zip(rg["accept"], ro["accept"], ro["u"], ro["du"]):
+            if a != b:
+                assert abs(math.log(u) + du / kT) < tol / kT
+        n_acc += int(np.count_nonzero(ro["accept"]))
+        if list(rg["accept"]) != list(ro["accept"]):
+            g.set_state(mol_kind=o.state()["mol_kind"])
+    assert n_acc >= 4
+    assert np.array_equal(g.state()["mol_kind"], o.state()["mol_kind"])
+    g.md_step(6)
+    o.md_step(6)
+    err = _pos_err(g.state()["pos"], o.state()["pos"], toy.box)
+    print(prec, "accepted", n_acc, "pos err %.2e" % err)
+    assert err < (1e-7 if prec == "fp64" else 1e-4)
+    # the stored forces after the incremental updates equal a fresh
+    # evaluation with bonded records rebuilt from the kinds
+    st = g.state()
+    g2 = m.System(toy, precision=prec, rebuild_interval=4)
+    g2.set_state(pos=st["pos"], vel=st["vel"], mol_kind=st["mol_kind"],
+                 counters=[st["step"], st["batch"], st["cycle"]])
+    fa, fb = g.forces(), g2.forces()
+    frms = math.sqrt((fb ** 2).sum(axis=1).mean())
+    assert np.abs(fa - fb).max() < (1e-9 if prec == "fp64" else 1e-4) * max(frms, 1.0)
+    g.close()
+    g2.close()
+
+
+@pytest.mark.parametrize("path", [0, 1])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_topo_toy_mdas(oracle_mod, toy, path, prec):
+    """MDAS cycles (2 pairs, K = 5, M = 2) on both paths: bonded terms
+    mixed linearly along lambda in the forces and the work."""
+    m = _membx()
+    g = m.System(toy, precision=prec, rebuild_interval=4)
+    o = oracle_mod.Oracle(toy)
+    if path == 1:
+        g.set_mdas_path(1, 0.05)
+        o.set_mdas_path(1, 0.05)
+    for _ in range(3):
+        rg, ro = g.mdas_cycle(2, 5, 2), o.mdas_cycle(2, 5, 2)
+        assert np.array_equal(rg["pairs"], ro["pairs"])
+        tol = 1e-6 if prec == "fp64" else 2e-2
+        assert abs(rg["work"] - ro["work"]) < tol, (rg["work"], ro["work"])
+        assert rg["accept"] == ro["accept"]
+        g.md_step(2)
+        o.md_step(2)
+    err = _pos_err(g.state()["pos"], o.state()["pos"], toy.box)
+    assert err < (1e-7 if prec == "fp64" else 1e-3), err
+    g.close()
+
