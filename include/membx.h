@@ -60,9 +60,16 @@ extern "C" {
  * used by Martini, V = k/2 (cos(theta) - cos(theta0))^2 (paper, Methods:
  * Martini 2.2).  Beads joined by a bond do not interact through the
  * nonbonded terms.  Kinds of one swap family (swap_family >= 0) must have the
- * same bead count and bonded topology; an exchange move changes only bead
- * types and charges (paper, Theory: "We do not modify coordinates, only the
- * corresponding potential parameters").  swap_family < 0: never exchanged. */
+ * same bead count and masses; an exchange changes the potential parameters
+ * of the two molecules, not their coordinates (paper, Theory).  Kinds of a
+ * family that differ in their bonded terms make a topology-changing
+ * exchange (at most 16 beads per molecule): a kind with fewer real beads
+ * fills its slots with dummy beads (a type with no Lennard-Jones and no
+ * charge, held by bonds), whose appearing and vanishing the soft-core path
+ * of membx_set_mdas_path handles (paper, Eq. 4); a family molecule then
+ * excludes from the nonbonded terms the pairs bonded in any kind of its
+ * family, and its bonded terms follow its current kind (mixed linearly in
+ * lambda along an MDAS trajectory).  swap_family < 0: never exchanged. */
 typedef struct membx_kind {
     int32_t n_beads;
     const int32_t* bead_type;     /* [n_beads] in [0, n_types)            */
