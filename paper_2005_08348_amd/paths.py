@@ -7,9 +7,10 @@ from the same relaxed start, once per path, and reports the acceptance,
 the mean and spread of the work, and the acceptance estimated from the
 works.  The paper applies the soft-core form to its atomistic runs only.
 
-    python -m paper_2005_08348_amd.paths [--cycles 400] [--systems mix c1]
+    python -m paper_2005_08348_amd.paths [--cycles 400] [--systems mix c1 toy]
 
-prints one JSON line.
+prints one JSON line.  ``toy`` is the topology-changing exchange fluid
+(``systems.topo_exchange_toy``: the two kinds differ in their bonded terms).
 """
 from __future__ import annotations
 
@@ -54,7 +55,10 @@ def main(argv=None):
     out = {"mdas": "1 pair, K = 50, M = 1, 50 MD steps between cycles", "delta_nm2": 0.05,
            "runs": {}}
     for name in args.systems:
-        sysm = S.make(name, demix=False) if name == "mix" else S.make(name)
+        if name == "toy":
+            sysm = S.topo_exchange_toy()
+        else:
+            sysm = S.make(name, demix=False) if name == "mix" else S.make(name)
         for path in (0, 1):
             print(f"[paths] {name} path {path}", file=sys.stderr, flush=True)
             out["runs"].setdefault(name, []).append(run(sysm, path, args.cycles))
