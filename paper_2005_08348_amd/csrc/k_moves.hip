@@ -406,6 +406,7 @@ __device__ __forceinline__ int block1024_excl_scan(int v, int* s_w, int* total)
 // admitted candidates in draw order up to the number still wanted.  A
 // candidate whose list is incomplete, or does not fit, ends the chunk there:
 // the next chunk starts with its draw.
+static_assert(SEL_CMAX <= SEL_LDS, "the admitted list of a chunk reuses the conflict-list LDS");
 template <typename R>
 __global__ __launch_bounds__(1024) void k_sel_resolve(Dev<R> d, Mv m, int n_want, int draw_cap,
                                                       int mode, int ck)
@@ -513,24 +514,33 @@ __global__ __launch_bounds__(1024) void k_sel_resolve(Dev<R> d, Mv m, int n_want
         __syncthreads();
         if (!s_chg[r % 3]) break;
     }
-    // admitted candidates in draw order
+    // admitted candidates in draw order (rank), listed in LDS (the conflict
+    // lists are no longer read), then written out one (trial, changed bead)
+    // per thread: the hash inserts of a trial's beads run side by side
     int nin = 0;
 #pragma unroll
     for (int k = 0; k < PER; ++k) nin += (k < per && nst[k] == 1) ? 1 : 0;
     int rank = block1024_excl_scan(nin, s_red + 32, s_red + 48);
     const int total = s_red[48];
     const int need = n_want - adm;
+    const int nadm_c = total < need ? total : need;   // admitted in this chunk
+    short* adm_t = lst;                               // [nadm_c] <= ck <= SEL_LDS
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int t = t0 + k;
         if (k < per && nst[k] == 1) {
             if (rank < need) {
-                sel_admit(d, m, mode, adm + rank, base + t, m.c_x[t], m.c_y[t], m.c_nb[t],
-                          m.c_bead + t * MC, m.c_cls + t * MC, m.c_pos + 3 * t * MC, 0, 1, stamp);
+                adm_t[rank] = (short)t;
                 if (rank == need - 1) s_stop = t;
             }
             ++rank;
         }
+    }
+    __syncthreads();
+    for (int w = tid; w < nadm_c * MC; w += 1024) {
+        const int a = w / MC, q = w - a * MC, t = adm_t[a];
+        sel_admit(d, m, mode, adm + a, base + t, m.c_x[t], m.c_y[t], m.c_nb[t], m.c_bead + t * MC,
+                  m.c_cls + t * MC, m.c_pos + 3 * t * MC, q, MC, stamp);
     }
     __syncthreads();
     if (tid == 0) {
