@@ -85,6 +85,15 @@ __device__ __forceinline__ double ld_coh(const double* p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// COH: device-coherent (the kernel itself may have written the word);
+// otherwise a plain load, for data written by earlier launches only (a
+// kernel boundary makes it visible, and the load may hit in the L2)
+template <bool COH, typename T>
+__device__ __forceinline__ T ld_sel(const T* p)
+{
+    if constexpr (COH) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *p;
+}
 
 __device__ __forceinline__ void hb_insert(u64* word, int* ent, int mask, unsigned key, int e,
                                           unsigned ep)
@@ -153,7 +162,7 @@ __device__ __forceinline__ int wave_incl_scan(int v)
 // One wave per candidate: draw, partner, changed beads.  Returns the flag
 // (0 live, 1 no valid trial, 2 molecule already used) and fills X, Y, nb;
 // lane q < nb returns bead q's id, class and position.
-template <typename R>
+template <bool COH, typename R>
 __device__ __forceinline__ int sel_candidate(const Dev<R>& d, const Mv& m, int dd, long long ctrv,
                                              unsigned stream, int stamp, int& X, int& Y, int& nb,
                                              int& bead, int& cls, double p[3])
@@ -163,7 +172,7 @@ __device__ __forceinline__ int sel_candidate(const Dev<R>& d, const Mv& m, int d
     if (m.n_sw <= 0) return 1;
     const uint4 w = draw(d.seed, (uint32_t)dd, ctrv, stream);
     X = m.sw_list[pick(w.x, (uint32_t)m.n_sw)];
-    const int kx = ld_coh(d.mol_kind + X);
+    const int kx = ld_sel<COH>(d.mol_kind + X);
     const int f = m.fam_of_kind[kx];
     if (m.xmode == 0) {
         const int nf = m.fam_off[f + 1] - m.fam_off[f];
@@ -183,8 +192,8 @@ __device__ __forceinline__ int sel_candidate(const Dev<R>& d, const Mv& m, int d
         if (nr <= 0) return 1;
         Y = m.reg_mem[o0 + pick(w.y, (uint32_t)nr)];
     }
-    const int ky = ld_coh(d.mol_kind + Y);
-    const int flag = (ld_coh(m.used + X) == stamp || ld_coh(m.used + Y) == stamp) ? 2 : 0;
+    const int ky = ld_sel<COH>(d.mol_kind + Y);
+    const int flag = (ld_sel<COH>(m.used + X) == stamp || ld_sel<COH>(m.used + Y) == stamp) ? 2 : 0;
     const int nch = m.chg_n[kx * d.nk + ky];
     nb = 2 * nch;
     if (ln < nb) {
@@ -202,7 +211,7 @@ __device__ __forceinline__ int sel_candidate(const Dev<R>& d, const Mv& m, int d
 // Wave-wide: does any changed bead (positions in sp[3*q], q < nb) lie within
 // r_cut of a changed bead of the trials admitted so far (table ab, epoch
 // stamp)?
-template <typename R>
+template <bool COH, typename R>
 __device__ __forceinline__ bool sel_hits_admitted(const Dev<R>& d, const Mv& m, const double* sp,
                                                   int nb, unsigned stamp)
 {
@@ -213,17 +222,17 @@ __device__ __forceinline__ bool sel_hits_admitted(const Dev<R>& d, const Mv& m, 
         const double* p = sp + 3 * q;
         const unsigned key = nbr_cell_key(d, m, p, o27);
         unsigned h = hhash(key) & (unsigned)m.ab_mask;
-        u64 w = hw_load(&m.ab_word[h]);
+        u64 w = ld_sel<COH>(&m.ab_word[h]);
         while (!hit && hw_ep(w) == stamp) {
             if (hw_key(w) == key)
                 for (unsigned s = 0; s < hw_n(w) && s < HBW; ++s) {
-                    const int e = ld_coh(m.ab_ent + h * HBW + s);
+                    const int e = ld_sel<COH>(m.ab_ent + h * HBW + s);
                     double r[3];
-                    for (int k = 0; k < 3; ++k) r[k] = ld_coh(m.r_pos + 3 * e + k);
+                    for (int k = 0; k < 3; ++k) r[k] = ld_sel<COH>(m.r_pos + 3 * e + k);
                     if (mi_dist2(d, p, r) < d.rc2d) hit = true;
                 }
             h = (h + 1) & (unsigned)m.ab_mask;
-            w = hw_load(&m.ab_word[h]);
+            w = ld_sel<COH>(&m.ab_word[h]);
         }
     }
     return __ballot(hit) != 0;
@@ -248,7 +257,7 @@ __global__ __launch_bounds__(256) void k_sel_draw(Dev<R> d, Mv m, int draw_cap, 
     int flag = 1, X = -1, Y = -1, nb = 0, bead = -1, cls = 0;
     double p[3] = {0.0, 0.0, 0.0};
     if (t < ck && dd < draw_cap)
-        flag = sel_candidate(d, m, dd, ctrv, stream, stamp, X, Y, nb, bead, cls, p);
+        flag = sel_candidate<false>(d, m, dd, ctrv, stream, stamp, X, Y, nb, bead, cls, p);
     if (flag != 1 && ln < nb) {
         const int e = t * MC + ln;
         m.c_bead[e] = bead;
@@ -257,7 +266,7 @@ __global__ __launch_bounds__(256) void k_sel_draw(Dev<R> d, Mv m, int draw_cap, 
     }
     __syncthreads();
     if (flag == 0 && mode == 0 && m.sel[SEL_ADM] > 0 &&
-        sel_hits_admitted(d, m, s_pos[wv], nb, (unsigned)stamp))
+        sel_hits_admitted<false>(d, m, s_pos[wv], nb, (unsigned)stamp))
         flag = 2;
     if (flag == 0) {
         if (mode == 0 && ln < nb) {
@@ -407,6 +416,7 @@ __device__ __forceinline__ int block1024_excl_scan(int v, int* s_w, int* total)
 // candidate whose list is incomplete, or does not fit, ends the chunk there:
 // the next chunk starts with its draw.
 static_assert(SEL_CMAX <= SEL_LDS, "the admitted list of a chunk reuses the conflict-list LDS");
+static_assert(4 * SEL_C0 <= SEL_CMAX && SEL_C0 % 4 == 0, "chunk sizes of launch_select");
 template <typename R>
 __global__ __launch_bounds__(1024) void k_sel_resolve(Dev<R> d, Mv m, int n_want, int draw_cap,
                                                       int mode, int ck)
@@ -572,14 +582,14 @@ __global__ __launch_bounds__(64) void k_sel_tail(Dev<R> d, Mv m, int n_want, int
     for (; dd < draw_cap && adm < n_want; ++dd) {
         int X, Y, nb, bead = -1, cls = 0;
         double p[3] = {0.0, 0.0, 0.0};
-        int flag = sel_candidate(d, m, dd, ctrv, stream, stamp, X, Y, nb, bead, cls, p);
+        int flag = sel_candidate<true>(d, m, dd, ctrv, stream, stamp, X, Y, nb, bead, cls, p);
         if (flag != 1 && ln < nb) {
             s_bead[ln] = bead;
             s_cls[ln] = cls;
             for (int k = 0; k < 3; ++k) s_pos[3 * ln + k] = p[k];
         }
         __syncthreads();
-        if (flag == 0 && mode == 0 && adm > 0 && sel_hits_admitted(d, m, s_pos, nb, (unsigned)stamp))
+        if (flag == 0 && mode == 0 && adm > 0 && sel_hits_admitted<true>(d, m, s_pos, nb, (unsigned)stamp))
             flag = 2;
         if (flag == 0) {
             sel_admit(d, m, mode, adm, dd, X, Y, nb, s_bead, s_cls, s_pos, ln, 64, stamp);
@@ -1230,14 +1240,17 @@ __global__ __launch_bounds__(1024) void k_kcnt(Dev<R> d, Mv m, int kind)
 }
 
 // ----------------------------------------------------------------- launch
-// Chunk sizes: SEL_C0, SEL_C0, then doubling up to SEL_CMAX, until they
-// cover the draw cap; one more of SEL_CMAX in reserve (a chunk ends early
-// only where a candidate has more than SEL_CAPC earlier conflicts or the
-// chunk's lists outgrow SEL_LDS), then the one-draw-at-a-time tail.  The chunking does not change the
-// admitted trials, only how many rounds find them.  Small first chunks pay:
-// the later chunks' draws are filtered against the trials admitted before
-// (measured on the 95,876-bead bilayer, 256 trials: a first chunk of 8192
-// draws took 350 us to resolve, the five chunks of this sequence 210 us).
+// Chunk sizes: SEL_C0, 4 SEL_C0, then SEL_CMAX, until they cover the draw
+// cap; one more of SEL_CMAX in reserve (a chunk ends early only where a
+// candidate has more than SEL_CAPC earlier conflicts or the chunk's lists
+// outgrow SEL_LDS), then the one-draw-at-a-time tail.  The chunking does
+// not change the admitted trials, only how many rounds find them.  A small
+// first chunk pays: the later chunks' draws are filtered against the trials
+// admitted before, and most of them fall out there.  Measured on the
+// 95,876-bead bilayer, 256 trials plus 2 MD steps per batch: 0.530 ms with
+// chunks of 1k, 1k, 2k, 4k, 8k; 0.515 ms with 2k, 8k, ...; 0.502 ms with
+// 1k, 8k, ...; 0.490 ms with 1k, 2k, 8k, ...; 0.485 ms with this sequence.
+// (A first chunk of 8192 draws alone took 350 us to resolve.)
 template <typename R>
 void launch_select(const Dev<R>& d, const Mv& m, int n_want, int draw_cap, int mode,
                    hipStream_t st)
@@ -1256,7 +1269,7 @@ void launch_select(const Dev<R>& d, const Mv& m, int n_want, int draw_cap, int m
         hipLaunchKernelGGL(k_sel_resolve<R>, dim3(1), dim3(1024), 0, st, d, m, n_want, draw_cap,
                            mode, ck);
         covered += ck;
-        if (++k >= 2 && ck < SEL_CMAX) ck *= 2;
+        ck = ++k == 1 ? 4 * SEL_C0 : SEL_CMAX;
     }
     hipLaunchKernelGGL(k_sel_tail<R>, dim3(1), dim3(64), 0, st, d, m, n_want, draw_cap, mode);
 }
