@@ -59,16 +59,33 @@ __device__ __forceinline__ int block_scan(int v, int* sh)
 // Cell starts (exclusive scan of the counts), then the extended grid: real
 // extended cells point into the slots, halo cells into the ghost range, laid
 // out by a scan of their source cells' counts.  Each part is run by one
-// work-group of BB threads, each taking a contiguous segment, read LU_L
-// values at a time with all loads in flight: the cell starts by k_layout
-// (which also clears the counts for the next rebuild), the extended grid by
-// an extra work-group of k_scatter, next to the scatter that needs only the
-// cell starts.
-constexpr int LU_L = 8;
+// work-group of BB threads, each taking a contiguous segment whose loads
+// are all in flight at once (up to LU values per thread; longer segments in
+// batches, read twice): the cell starts by k_layout (which also clears the
+// counts for the next rebuild), the halo cells by an extra work-group of
+// k_scatter, next to the scatter that needs only the cell starts.  LU is
+// chosen per system at launch (8, or 64 and 16 for large grids): a batch
+// wider than the segment costs instructions on small grids, a narrow one
+// costs round trips on large ones.
 
-__device__ __forceinline__ int load_cnt(const int* p) { return *p; }
+// Halo cells in increasing extended index: the layer a0 = 0 (ne1 ne2 cells),
+// then per a0 >= 1 the row a1 = 0 (ne2 cells) and the cells a1 >= 1, a2 = 0
+// (ne1 - 1 cells).
+__host__ __device__ __forceinline__ int halo_count(const int ne[3])
+{
+    return ne[1] * ne[2] + (ne[0] - 1) * (ne[2] + ne[1] - 1);
+}
+__device__ __forceinline__ int halo_ext(int h, const int ne[3])
+{
+    const int l0 = ne[1] * ne[2];
+    if (h < l0) return h;
+    const int g = ne[2] + ne[1] - 1, hh = h - l0;
+    const int a0 = 1 + hh / g, r = hh - (a0 - 1) * g;
+    const int a1 = r < ne[2] ? 0 : r - ne[2] + 1, a2 = r < ne[2] ? r : 0;
+    return (a0 * ne[1] + a1) * ne[2] + a2;
+}
 
-template <typename R>
+template <typename R, int LU_L>
 __device__ void layout_cells(const Dev<R>& d)
 {
     __shared__ int sh[BB / 64];
@@ -80,7 +97,7 @@ __device__ void layout_cells(const Dev<R>& d)
         int s = 0;
         for (int kb = k0; kb < k1; kb += LU_L) {
 #pragma unroll
-            for (int u = 0; u < LU_L; ++u) v[u] = kb + u < k1 ? load_cnt(d.cell_cnt + kb + u) : 0;
+            for (int u = 0; u < LU_L; ++u) v[u] = kb + u < k1 ? d.cell_cnt[kb + u] : 0;
 #pragma unroll
             for (int u = 0; u < LU_L; ++u) s += v[u];
         }
@@ -88,7 +105,7 @@ __device__ void layout_cells(const Dev<R>& d)
         for (int kb = k0; kb < k1; kb += LU_L) {
             if (per > LU_L) {   // segment longer than one batch: load again
 #pragma unroll
-                for (int u = 0; u < LU_L; ++u) v[u] = kb + u < k1 ? load_cnt(d.cell_cnt + kb + u) : 0;
+                for (int u = 0; u < LU_L; ++u) v[u] = kb + u < k1 ? d.cell_cnt[kb + u] : 0;
             }
 #pragma unroll
             for (int u = 0; u < LU_L; ++u)
@@ -101,47 +118,48 @@ __device__ void layout_cells(const Dev<R>& d)
 }
 
 // Halo cells of the extended grid (one work-group of BB threads): ghost
-// ranges laid out by a scan of their source cells' counts.  Only halo cells
-// read the counts; the real extended cells are written by the scatter blocks.
-template <typename R>
+// ranges laid out by a scan of their source cells' counts, in increasing
+// extended index.  Only halo cells are visited; the real extended cells are
+// written by the scatter blocks.
+template <typename R, int LU_H>
 __device__ void layout_halo(const Dev<R>& d)
 {
     __shared__ int sh[BB / 64];
     const int t = threadIdx.x;
-    const int per = (d.next + BB - 1) / BB;
-    const int k0 = min(d.next, t * per), k1 = min(d.next, k0 + per);
-    int n[LU_L];
-    unsigned halo = 0;
+    const int nh = halo_count(d.ne);
+    const int per = (nh + BB - 1) / BB;
+    const int k0 = min(nh, t * per), k1 = min(nh, k0 + per);
+    int n[LU_H];
     auto fetch = [&](int kb) {
-        halo = 0;
-        int st[LU_L];
+        int st[LU_H];
 #pragma unroll
-        for (int u = 0; u < LU_L; ++u) {
-            const int k = kb + u;
-            int a[3];
-            ext_coords(min(k, k1 - 1), d.ne, a);
-            const bool h = k < k1 && (a[0] == 0 || a[1] == 0 || a[2] == 0);
-            const int src = ext_source(a, d.nc);
-            st[u] = h ? d.cell_start[src] : 0;
-            n[u] = h ? d.cell_start[src + 1] : 0;
-            if (h) halo |= 1u << u;
+        for (int u = 0; u < LU_H; ++u) {
+            st[u] = 0;
+            n[u] = 0;
+            if (kb + u < k1) {
+                int a[3];
+                ext_coords(halo_ext(kb + u, d.ne), d.ne, a);
+                const int src = ext_source(a, d.nc);
+                st[u] = d.cell_start[src];
+                n[u] = d.cell_start[src + 1];
+            }
         }
 #pragma unroll
-        for (int u = 0; u < LU_L; ++u) n[u] -= st[u];
+        for (int u = 0; u < LU_H; ++u) n[u] -= st[u];
     };
     int s = 0;
-    for (int kb = k0; kb < k1; kb += LU_L) {
+    for (int kb = k0; kb < k1; kb += LU_H) {
         fetch(kb);
 #pragma unroll
-        for (int u = 0; u < LU_L; ++u) s += n[u];
+        for (int u = 0; u < LU_H; ++u) s += n[u];
     }
     int run = block_scan(s, sh);
-    for (int kb = k0; kb < k1; kb += LU_L) {
-        if (per > LU_L) fetch(kb);
+    for (int kb = k0; kb < k1; kb += LU_H) {
+        if (per > LU_H) fetch(kb);
 #pragma unroll
-        for (int u = 0; u < LU_L; ++u) {
-            if (!((halo >> u) & 1u)) continue;
-            const int k = kb + u;
+        for (int u = 0; u < LU_H; ++u) {
+            if (kb + u >= k1) continue;
+            const int k = halo_ext(kb + u, d.ne);
             d.ext_start[k] = d.N + run;
             d.ext_cnt[k] = run >= d.Gcap ? 0 : min(n[u], d.Gcap - run);
             d.ext_scan[k] = run;          // ghost offset of this halo cell
@@ -207,20 +225,20 @@ __global__ __launch_bounds__(BB) void k_bin(Dev<R> d)
     }
 }
 
-template <typename R>
+template <typename R, int LU>
 __global__ __launch_bounds__(BB) void k_layout(Dev<R> d)
 {
-    layout_cells(d);
+    layout_cells<R, LU>(d);
 }
 
 // Scatter beads to their places in their cells' slot ranges (BB threads per
 // block), and point the real extended cells at their slots; block 0,
 // dispatched first as it is the longest, lays out the halo cells instead.
-template <typename R>
+template <typename R, int LU>
 __global__ __launch_bounds__(BB) void k_scatter(Dev<R> d)
 {
     if (blockIdx.x == 0) {
-        layout_halo(d);
+        layout_halo<R, LU>(d);
         return;
     }
     const int g = (blockIdx.x - 1) * blockDim.x + threadIdx.x;
@@ -614,8 +632,15 @@ template <typename R>
 void launch_rebuild(const Dev<R>& d, hipStream_t st)
 {
     hipLaunchKernelGGL(k_bin<R>, dim3((d.N + BB - 1) / BB), dim3(BB), 0, st, d);
-    hipLaunchKernelGGL(k_layout<R>, dim3(1), dim3(BB), 0, st, d);
-    hipLaunchKernelGGL(k_scatter<R>, dim3((d.N + BB - 1) / BB + 1), dim3(BB), 0, st, d);
+    // segment lengths of the two single-work-group scans
+    const int per_c = (d.ncell + BB - 1) / BB;
+    const int per_h = (halo_count(d.ne) + BB - 1) / BB;
+    if (per_c <= 8) hipLaunchKernelGGL((k_layout<R, 8>), dim3(1), dim3(BB), 0, st, d);
+    else hipLaunchKernelGGL((k_layout<R, 64>), dim3(1), dim3(BB), 0, st, d);
+    if (per_h <= 8)
+        hipLaunchKernelGGL((k_scatter<R, 8>), dim3((d.N + BB - 1) / BB + 1), dim3(BB), 0, st, d);
+    else
+        hipLaunchKernelGGL((k_scatter<R, 16>), dim3((d.N + BB - 1) / BB + 1), dim3(BB), 0, st, d);
     hipLaunchKernelGGL(k_place<R>, dim3(d.ncell), dim3(64), 0, st, d);
     hipLaunchKernelGGL(k_list<R>, dim3(d.ncell), dim3(LB), 0, st, d);
 }
