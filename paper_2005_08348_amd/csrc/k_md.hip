@@ -33,6 +33,36 @@ __global__ __launch_bounds__(WG) void k_kick(Dev<R> d, R kick, long long nsteps)
 
 __global__ void k_add_ctr(long long* ctr, int which, long long n) { ctr[which] += n; }
 
+// The boundary between two MDAS segments (Eq. 3's increments, Langevin) in
+// one pass, the operations of k_kick, k_work, k_dlam and k_kick_drift in
+// that order: the closing half-kick of the last step at lambda, the work
+// increment w += dlw dU (md[0], md[1]; thread 0), the affected beads'
+// forces moved to the next lambda (F += dl (F_B - F_A)), and the opening
+// B-A-O-A of the next segment's first step (step counter + step_off; the
+// step counter itself advances at the cycle's last closing kick).
+template <typename R>
+__global__ __launch_bounds__(WG) void k_alch_bridge(Dev<R> d, const int* __restrict__ aff_flag,
+                                                    double* md, R kick, R dl, double dlw,
+                                                    long long step_off)
+{
+    const int i = blockIdx.x * WG + threadIdx.x;
+    if (i == 0) md[0] += dlw * md[1];
+    float e2 = 0.f, e2_in = 0.f;
+    if (i < d.N) {
+        BeadPre<R> pre = bead_pre(d, i, false);
+        V4<R> f = d.frc[i];
+        pre.v.x += kick * pre.v.w * f.x; pre.v.y += kick * pre.v.w * f.y;
+        pre.v.z += kick * pre.v.w * f.z;
+        if (aff_flag[i]) {
+            const V4<R> g = d.dfrc[i];
+            f.x += dl * g.x; f.y += dl * g.y; f.z += dl * g.z;
+            d.frc[i] = f;
+        }
+        e2 = baoab_bead(d, i, d.posq[i], pre, f, kick, step_off, d.posq, d.vel, false, e2_in);
+    }
+    disp_stats(d, e2, e2_in, i < d.N);
+}
+
 // capped steepest-descent step: x += s * alpha F, |s alpha F| <= cap
 template <typename R>
 __global__ void k_sd_step(Dev<R> d, double alpha, double cap)
@@ -112,6 +142,13 @@ void launch_kick_drift(const Dev<R>& d, R kick, long long step_off, int chk_in, 
 {
     hipLaunchKernelGGL(k_kick_drift<R>, dim3((d.N + WG - 1) / WG), dim3(WG), 0, st, d, kick,
                        step_off, chk_in);
+}
+template <typename R>
+void launch_alch_bridge(const Dev<R>& d, const int* aff_flag, double* md, R kick, R dl, double dlw,
+                        long long step_off, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_alch_bridge<R>, dim3((d.N + WG - 1) / WG), dim3(WG), 0, st, d, aff_flag, md,
+                       kick, dl, dlw, step_off);
 }
 template <typename R>
 void launch_kick(const Dev<R>& d, R kick, long long nsteps, hipStream_t st)
@@ -390,6 +427,8 @@ void launch_vr_kick_drift(const Dev<R>& d, const VrBuf& vr, R kick, long long st
                                           hipStream_t);                              \
     template void launch_kick_drift<R>(const Dev<R>&, R, long long, int, hipStream_t); \
     template void launch_kick<R>(const Dev<R>&, R, long long, hipStream_t);                    \
+    template void launch_alch_bridge<R>(const Dev<R>&, const int*, double*, R, R, double, long long, \
+                                        hipStream_t);                                          \
     template void launch_sd_step<R>(const Dev<R>&, double, double, hipStream_t);     \
     template void launch_export<R>(const Dev<R>&, const V4<R>*, double*, hipStream_t); \
     template void launch_import<R>(const Dev<R>&, V4<R>*, const double*, hipStream_t);

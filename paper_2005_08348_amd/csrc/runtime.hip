@@ -27,6 +27,8 @@ template <typename R>
 void launch_nonbonded_fused(const Dev<R>&, int, int, R, long long, V4<R>*, V4<R>*, int, hipStream_t);
 void launch_energy_final(const double*, int, double*, hipStream_t);
 template <typename R> void launch_kick_drift(const Dev<R>&, R, long long, int, hipStream_t);
+template <typename R>
+void launch_alch_bridge(const Dev<R>&, const int*, double*, R, R, double, long long, hipStream_t);
 template <typename R> void launch_kick(const Dev<R>&, R, long long, hipStream_t);
 template <typename R>
 void launch_vrescale(const Dev<R>&, const VrBuf&, R, long long, double, int, hipStream_t);
@@ -816,6 +818,12 @@ static void swap_coords(membx_sys* s)
 
 struct Alch {
     double lam;
+    // Langevin segments of a cycle chained by k_alch_bridge: the segment's
+    // step counters start at base (the closing kicks of earlier segments did
+    // not advance the step counter), its opening update ran in the bridge
+    // (open = false) and its closing half-kick runs there too (close = false)
+    long long base = 0;
+    bool open = true, close = true;
 };
 
 template <typename R>
@@ -862,7 +870,9 @@ static void steps_seq(membx_sys* s, long long n, const Alch* alch, bool launch =
         if (!moved && launch) {
             const int chk = (inner && s->sp >= 0) ? 1 : 0;
             if (vr && k > 0) launch_vr_kick_drift<R>(d, s->vr, h, k, chk, s->st);
-            else launch_kick_drift<R>(d, (k == 0 || vr) ? h : full, k, chk, s->st);
+            else if (!(alch && k == 0 && !alch->open))
+                launch_kick_drift<R>(d, (k == 0 || vr) ? h : full, (alch ? alch->base : 0) + k, chk,
+                                     s->st);
         }
         moved = false;
         bool rebuilt = false;
@@ -903,7 +913,8 @@ static void steps_seq(membx_sys* s, long long n, const Alch* alch, bool launch =
             if (n > 0) launch_vr_scale<R>(d, s->vr, s->st);
             launch_add_ctr(d.ctr, CT_STEP, n, s->st);
         } else {
-            launch_kick<R>(d, h, n, s->st);
+            if (!alch) launch_kick<R>(d, h, n, s->st);
+            else if (alch->close) launch_kick<R>(d, h, alch->base + n, s->st);
         }
     }
 }
@@ -1156,17 +1167,30 @@ static int32_t mdas(membx_sys* s, int P, int K, int M)
     } else if (topo) {
         launch_bond_dforce<R>(d, m, 0.0, 0, st);   // F_B - F_A bonded at the start
     }
+    // Langevin, linear path: a segment's closing half-kick, the work
+    // increment, the move of the forces to the next lambda and the next
+    // segment's opening update run as one pass (the same operations)
+    const bool bridge = !sc && !topo && M > 0 && s->h.ensemble == 0;
+    long long base = 0;
     double lam = 0.0;
     for (int k = 1; k <= K; ++k) {
         if (M > 0) {
             Alch a{ lam };
+            if (bridge) {
+                a.base = base;
+                a.open = k == 1;
+                a.close = k == K;
+            }
             steps_seq<R>(s, M, &a);
             s->step += M;
             s->fe += M;
         }
         double lam_new = (double)k / (double)K;
         double dl = lam_new - lam;
-        if (sc) {   // w += U_sc(lam_new) - U_sc(lam) at x; forces follow lambda
+        if (bridge && k < K) {
+            launch_alch_bridge<R>(d, m.aff_flag, m.md, (R)(0.5 * s->h.dt), (R)dl, dl, base + M, st);
+            base += M;
+        } else if (sc) {   // w += U_sc(lam_new) - U_sc(lam) at x; forces follow lambda
             launch_scdu<R>(d, m, T, lam, lam_new, s->h.sc_delta, st);
             if (topo) launch_bond_du<R>(d, m, dl, st);   // bonded terms: linear in lambda
             launch_du_total<R>(d, m, m.md + 1, st);
