@@ -719,16 +719,29 @@ __global__ void k_trial_accept(Dev<R> d, Mv m)
 
 // Total dU over every admitted change (MDAS: U_B - U_A at the current x).
 template <typename R>
-__global__ void k_du_total(Dev<R> d, Mv m, double* out)
+__global__ __launch_bounds__(64) void k_du_total(Dev<R> d, Mv m, double* out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int MC = m.maxcht;
+    // one wave: lane a sums trial a's bead terms and bonded change in bead
+    // order (the trials' loads all in flight), then lane 0 adds the trials
+    // in order, 64 at a time
+    __shared__ double part[64];
+    const int ln = threadIdx.x, MC = m.maxcht, n = m.r_n[0];
     double s = 0.0;
-    for (int a = 0; a < m.r_n[0]; ++a) {
-        for (int q = 0; q < m.r_nb[a]; ++q) s += m.du_bead[a * MC + q];
-        s += m.du_bond[a];
+    for (int a0 = 0; a0 < n; a0 += 64) {
+        const int a = a0 + ln;
+        double p = 0.0;
+        if (a < n) {
+            const int nb = m.r_nb[a];
+            for (int q = 0; q < nb; ++q) p += m.du_bead[a * MC + q];
+            p += m.du_bond[a];
+        }
+        part[ln] = p;
+        __syncthreads();
+        if (ln == 0)
+            for (int k = 0; k < 64 && a0 + k < n; ++k) s += part[k];
+        __syncthreads();
     }
-    *out = s;
+    if (ln == 0) *out = s;
 }
 
 // Affected set: the marked beads and every bead in their neighbour lists.
@@ -1196,11 +1209,28 @@ __device__ void kcnt_list(const Dev<R>& d, const int* __restrict__ mem, int nf, 
                           int* oth)
 {
     __shared__ int part[1024];
+    // a thread's segment (up to KU molecules) in chunks of KC loads in flight
+    constexpr int KU = 48, KC = 16;
     const int t = threadIdx.x;
     const int per = (nf + 1023) / 1024;
     const int b = t * per, e = min(nf, b + per);
     int s = 0;
-    for (int k = b; k < e; ++k) s += d.mol_kind[mem[k]] == kind;
+    unsigned long long same = 0;
+    if (per <= KU) {
+#pragma unroll
+        for (int c0 = 0; c0 < KU; c0 += KC) {
+            if (b + c0 >= e) break;
+            int mk[KC];
+#pragma unroll
+            for (int u = 0; u < KC; ++u) mk[u] = b + c0 + u < e ? mem[b + c0 + u] : -1;
+#pragma unroll
+            for (int u = 0; u < KC; ++u)
+                if (mk[u] >= 0 && d.mol_kind[mk[u]] == kind) same |= 1ull << (c0 + u);
+        }
+        s = __popcll(same);
+    } else {
+        for (int k = b; k < e; ++k) s += d.mol_kind[mem[k]] == kind;
+    }
     __syncthreads();   // part may still be read by a previous call
     part[t] = s;
     __syncthreads();
@@ -1211,12 +1241,31 @@ __device__ void kcnt_list(const Dev<R>& d, const int* __restrict__ mem, int nf, 
         __syncthreads();
     }
     int run = part[t] - s;
-    for (int k = b; k < e; ++k) {
-        const int mm = mem[k];
-        const bool same = d.mol_kind[mm] == kind;
-        out[k] = run;
-        if (!same) oth[k - run] = mm;   // members of other kinds, ascending
-        run += same;
+    if (per <= KU) {
+#pragma unroll
+        for (int c0 = 0; c0 < KU; c0 += KC) {
+            if (b + c0 >= e) break;
+            int mk[KC];
+#pragma unroll
+            for (int u = 0; u < KC; ++u) mk[u] = b + c0 + u < e ? mem[b + c0 + u] : -1;
+#pragma unroll
+            for (int u = 0; u < KC; ++u) {
+                if (b + c0 + u < e) {
+                    const bool sm = (same >> (c0 + u)) & 1ull;
+                    out[b + c0 + u] = run;
+                    if (!sm) oth[b + c0 + u - run] = mk[u];   // members of other kinds, ascending
+                    run += sm ? 1 : 0;
+                }
+            }
+        }
+    } else {
+        for (int k = b; k < e; ++k) {
+            const int mm = mem[k];
+            const bool sm = d.mol_kind[mm] == kind;
+            out[k] = run;
+            if (!sm) oth[k - run] = mm;
+            run += sm;
+        }
     }
     if (t == 1023) out[nf] = part[1023];
 }
@@ -1224,8 +1273,9 @@ __device__ void kcnt_list(const Dev<R>& d, const int* __restrict__ mem, int nf, 
 // Kind counts of one kind over its family, and (within-region exchanges)
 // over each region of the family.
 template <typename R>
-__global__ __launch_bounds__(1024) void k_kcnt(Dev<R> d, Mv m, int kind)
+__global__ __launch_bounds__(1024) void k_kcnt(Dev<R> d, Mv m, int kind0)
 {
+    const int kind = kind0 + blockIdx.x;   // one work-group per kind
     const int f = m.fam_of_kind[kind];
     if (f < 0) return;
     const int f0 = m.fam_off[f], nf = m.fam_off[f + 1] - f0;
@@ -1398,9 +1448,10 @@ void launch_snapshot(const Dev<R>& d, const Mv& m, int restore, hipStream_t st)
 }
 
 template <typename R>
-void launch_kcnt(const Dev<R>& d, const Mv& m, int kind, hipStream_t st)
+void launch_kcnt(const Dev<R>& d, const Mv& m, int kind0, int nkinds, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_kcnt<R>, dim3(1), dim3(1024), 0, st, d, m, kind);
+    if (nkinds <= 0) return;
+    hipLaunchKernelGGL(k_kcnt<R>, dim3(nkinds), dim3(1024), 0, st, d, m, kind0);
 }
 
 #define INSTM(R)                                                                         \
@@ -1425,7 +1476,7 @@ void launch_kcnt(const Dev<R>& d, const Mv& m, int kind, hipStream_t st)
     template void launch_bt_refresh<R>(const Dev<R>&, const Mv&, int, hipStream_t);       \
     template void launch_mdas_accept<R>(const Dev<R>&, const Mv&, hipStream_t);           \
     template void launch_snapshot<R>(const Dev<R>&, const Mv&, int, hipStream_t);         \
-    template void launch_kcnt<R>(const Dev<R>&, const Mv&, int, hipStream_t);
+    template void launch_kcnt<R>(const Dev<R>&, const Mv&, int, int, hipStream_t);
 INSTM(float)
 INSTM(double)
 

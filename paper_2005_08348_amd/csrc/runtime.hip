@@ -72,7 +72,7 @@ template <typename R> void launch_bt_refresh(const Dev<R>&, const Mv&, int, hipS
 void launch_work(double*, double, hipStream_t);
 template <typename R> void launch_mdas_accept(const Dev<R>&, const Mv&, hipStream_t);
 template <typename R> void launch_snapshot(const Dev<R>&, const Mv&, int, hipStream_t);
-template <typename R> void launch_kcnt(const Dev<R>&, const Mv&, int, hipStream_t);
+template <typename R> void launch_kcnt(const Dev<R>&, const Mv&, int, int, hipStream_t);
 void launch_set_classes(void* posq, int prec, const int* cls_by_bead, const int* orig, int N,
                         hipStream_t st);
 }  // namespace mbx
@@ -1083,8 +1083,8 @@ static void refresh_forces(membx_sys* s)
 template <typename R>
 static void kcnt_all(membx_sys* s)
 {
-    for (int k = 0; k < s->h.nk; ++k)
-        if (s->h.fam_of_kind[k] >= 0) launch_kcnt<R>(dev<R>(s), s->mv, k, s->st);
+    // one work-group per kind (kinds outside every swap family return at once)
+    launch_kcnt<R>(dev<R>(s), s->mv, 0, s->h.nk, s->st);
 }
 
 template <typename R>
