@@ -241,6 +241,9 @@ def main():
     ap.add_argument("--skin", type=float, default=0.5)
     ap.add_argument("--skin-inner", type=float, default=0.15)
     ap.add_argument("--prune", type=int, default=3, help="force passes per inner-list prune")
+    ap.add_argument("--mdas-cycles", type=int, default=0,
+                    help="also time this many MDAS cycles (32 pairs, K = 50, M = 1) on the main "
+                         "system after its timed region (for kernel profiles of the cycle)")
     ap.add_argument("--system", choices=["c1", "c3"], default="c1",
                     help="system of the main timed region (c3, the 1,140,504-bead MDAS bilayer, "
                          "for kernel profiles; use with --no-legs)")
@@ -338,6 +341,13 @@ def main():
                      "slot_efficiency": (2 * pairs2 / slots) if slots else None,
                      "slot_tflops": slots * FLOP_PAIR_F / (nb_ms * 1e-3) / 1e12},
     }
+    if args.mdas_cycles > 0:
+        log(f"[bench] {args.mdas_cycles} MDAS cycles (32 pairs, K = 50, M = 1) on the main system")
+        g.mdas_cycle(32, 50, 1, results=False)
+        tcy = timed(lambda: [g.mdas_cycle(32, 50, 1, results=False)
+                             for _ in range(args.mdas_cycles)], sync)
+        result["mdas_main"] = {"pairs": 32, "k_increments": 50, "m_steps": 1,
+                               "cycles": args.mdas_cycles, "cycles_per_s": args.mdas_cycles / tcy}
     g.close()
     del g
     torch.cuda.empty_cache()

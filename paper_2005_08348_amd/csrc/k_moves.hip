@@ -627,6 +627,7 @@ template <typename R>
 __global__ void k_mark(Dev<R> d, Mv m, int mode)
 {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e == 0) *m.aff_n = 0;   // the affected set of these trials starts empty
     int MC = m.maxcht;
     int a = e / MC, q = e % MC;
     if (a >= m.r_n[0] || q >= m.r_nb[a]) return;
@@ -1357,9 +1358,11 @@ void launch_du_total(const Dev<R>& d, const Mv& m, double* out, hipStream_t st)
 }
 
 template <typename R>
-void launch_aff_build(const Dev<R>& d, const Mv& m, int only_accepted, int T, hipStream_t st)
+void launch_aff_build(const Dev<R>& d, const Mv& m, int only_accepted, int T, bool zero,
+                      hipStream_t st)
 {
-    hipLaunchKernelGGL(k_zero1, dim3(1), dim3(1), 0, st, m.aff_n);
+    // zero = false: k_mark of the same trials has emptied the set
+    if (zero) hipLaunchKernelGGL(k_zero1, dim3(1), dim3(1), 0, st, m.aff_n);
     hipLaunchKernelGGL(k_aff_mark<R>, dim3(T * m.maxcht), dim3(64), 0, st, d, m, only_accepted);
 }
 
@@ -1461,7 +1464,7 @@ void launch_kcnt(const Dev<R>& d, const Mv& m, int kind0, int nkinds, hipStream_
     template void launch_du<R>(const Dev<R>&, const Mv&, int, hipStream_t);               \
     template void launch_trial_accept<R>(const Dev<R>&, const Mv&, int, hipStream_t);     \
     template void launch_du_total<R>(const Dev<R>&, const Mv&, double*, hipStream_t);     \
-    template void launch_aff_build<R>(const Dev<R>&, const Mv&, int, int, hipStream_t);   \
+    template void launch_aff_build<R>(const Dev<R>&, const Mv&, int, int, bool, hipStream_t); \
     template void launch_aff_clear<R>(const Dev<R>&, const Mv&, hipStream_t);             \
     template void launch_dforce<R>(const Dev<R>&, const Mv&, R, hipStream_t);             \
     template void launch_dlam<R>(const Dev<R>&, const Mv&, R, hipStream_t);               \

@@ -56,7 +56,7 @@ template <typename R> void launch_unmark(const Dev<R>&, const Mv&, int, int, hip
 template <typename R> void launch_du(const Dev<R>&, const Mv&, int, hipStream_t);
 template <typename R> void launch_trial_accept(const Dev<R>&, const Mv&, int, hipStream_t);
 template <typename R> void launch_du_total(const Dev<R>&, const Mv&, double*, hipStream_t);
-template <typename R> void launch_aff_build(const Dev<R>&, const Mv&, int, int, hipStream_t);
+template <typename R> void launch_aff_build(const Dev<R>&, const Mv&, int, int, bool, hipStream_t);
 template <typename R> void launch_aff_clear(const Dev<R>&, const Mv&, hipStream_t);
 template <typename R> void launch_dforce(const Dev<R>&, const Mv&, R, hipStream_t);
 template <typename R>
@@ -834,7 +834,7 @@ static void alch_terms(membx_sys* s, bool rebuilt, double lam)
     int T = m.T;
     if (rebuilt) {   // the affected set follows the new slot order
         launch_aff_clear<R>(d, m, s->st);
-        launch_aff_build<R>(d, m, 0, T, s->st);
+        launch_aff_build<R>(d, m, 0, T, true, s->st);
     }
     const bool topo = s->h.topo != 0;
     if (s->h.mdas_path == 1) {   // force pass (A) + F_sc(lam) - F_sc(0)
@@ -1095,13 +1095,12 @@ static void swap_seq(membx_sys* s, int n_trials)
     int T = m.T;
     const bool topo = s->h.topo != 0;
     launch_select<R>(d, m, n_trials, 64 * n_trials, 0, s->st);
-    launch_mark<R>(d, m, 0, T, s->st);
-    launch_ghost_update<R>(d, s->st);
+    launch_mark<R>(d, m, 0, T, s->st);   // marks only: positions and classes (ghosts too) unchanged
     launch_du<R>(d, m, T, s->st);
     if (topo) launch_bond_du<R>(d, m, 1.0, s->st);   // bonded part of dU
     launch_trial_accept<R>(d, m, T, s->st);
     launch_unmark<R>(d, m, 1, T, s->st);
-    launch_aff_build<R>(d, m, 1, T, s->st);
+    launch_aff_build<R>(d, m, 1, T, false, s->st);
     launch_dforce<R>(d, m, (R)1, s->st);
     if (topo) launch_bond_dforce<R>(d, m, 1.0, 1, s->st);   // accepted: bonded F_new - F_old
     launch_commit<R>(d, m, 0, T, s->st);
@@ -1151,9 +1150,8 @@ static int32_t mdas(membx_sys* s, int P, int K, int M)
     launch_select<R>(d, m, P, 64 * P, 1, st);
     launch_snapshot<R>(d, m, 0, st);
     launch_mark<R>(d, m, 1, T, st);
-    launch_aff_build<R>(d, m, 0, T, st);
+    launch_aff_build<R>(d, m, 0, T, false, st);
     launch_fill_i32((int*)m.md, 0, 16, st);
-    launch_ghost_update<R>(d, st);
     const bool sc = s->h.mdas_path == 1;
     const bool topo = s->h.topo != 0;
     if (!sc) {
