@@ -328,7 +328,6 @@ __global__ __launch_bounds__(64) void k_place(Dev<R> d)
                 if (code & 4) y.z -= d.L[2];
                 d.posq[d.N + g] = y;
                 d.ghost_owner[g] = s;
-                d.ghost_code[g] = code;
                 d.orig_ext[d.N + g] = o;
                 d.glist[s * 8 + q] = g | (code << CODE_SHIFT);
             }
@@ -337,20 +336,6 @@ __global__ __launch_bounds__(64) void k_place(Dev<R> d)
     }
 }
 
-// Refresh ghost coordinates (and class) from their owners (after a change of
-// classes; the integrator refreshes them itself after a move).
-template <typename R>
-__global__ void k_ghost_update(Dev<R> d)
-{
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= *d.n_ghost) return;
-    int s = d.ghost_owner[g], code = d.ghost_code[g];
-    V4<R> p = d.posq[s];
-    if (code & 1) p.x -= d.L[0];
-    if (code & 2) p.y -= d.L[1];
-    if (code & 4) p.z -= d.L[2];
-    d.posq[d.N + g] = p;
-}
 
 // ---------------------------------------------------------------- list
 // exact float64 predicate d^2 < (r_cut + skin)^2, evaluated as
@@ -645,15 +630,8 @@ void launch_rebuild(const Dev<R>& d, hipStream_t st)
     hipLaunchKernelGGL(k_list<R>, dim3(d.ncell), dim3(LB), 0, st, d);
 }
 
-template <typename R>
-void launch_ghost_update(const Dev<R>& d, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_ghost_update<R>, GRID(d.Gcap), 0, st, d);
-}
 
 template void launch_rebuild<float>(const Dev<float>&, hipStream_t);
 template void launch_rebuild<double>(const Dev<double>&, hipStream_t);
-template void launch_ghost_update<float>(const Dev<float>&, hipStream_t);
-template void launch_ghost_update<double>(const Dev<double>&, hipStream_t);
 
 }  // namespace mbx

@@ -635,18 +635,6 @@ __global__ void k_mark(Dev<R> d, Mv m, int mode)
     d.alch[s] = m.r_cls[a * MC + q] | ((mode == 0 ? a : 0) << 8);
 }
 
-// Clear the marks (all admitted trials, or only the rejected ones).
-template <typename R>
-__global__ void k_unmark(Dev<R> d, Mv m, int only_rejected)
-{
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    int MC = m.maxcht;
-    int a = e / MC, q = e % MC;
-    if (a >= m.r_n[0] || q >= m.r_nb[a]) return;
-    if (only_rejected && m.r_acc[a]) return;
-    d.alch[d.inv[m.r_bead[a * MC + q]]] = -1;
-}
-
 __device__ __forceinline__ int owner_of(const int* ghost_owner, int N, int j)
 {
     return j < N ? j : ghost_owner[j - N];
@@ -716,6 +704,9 @@ __global__ void k_trial_accept(Dev<R> d, Mv m)
     m.r_du[a] = du;
     m.r_u[a] = u;
     m.r_acc[a] = acc;
+    // a rejected trial's marks are cleared here; the accepted ones by the commit
+    if (!acc)
+        for (int q = 0; q < m.r_nb[a]; ++q) d.alch[d.inv[m.r_bead[a * MC + q]]] = -1;
 }
 
 // Total dU over every admitted change (MDAS: U_B - U_A at the current x).
@@ -1165,6 +1156,22 @@ __global__ void k_commit(Dev<R> d, Mv m, int mode)
         V4<R> p = d.posq[s];
         p.w = cls_to<R>(m.r_cls[a * MC + q]);
         d.posq[s] = p;
+        // the bead's periodic images take the new class too (their record:
+        // entries g | code << CODE_SHIFT, -1 unused, the second half read only
+        // when the first is full)
+        const int4* gl = reinterpret_cast<const int4*>(d.glist) + 2 * s;
+        const int4 g0 = gl[0];
+        int ge[8] = { g0.x, g0.y, g0.z, g0.w, -1, -1, -1, -1 };
+        if (g0.w != -1) {
+            const int4 g1 = gl[1];
+            ge[4] = g1.x; ge[5] = g1.y; ge[6] = g1.z; ge[7] = g1.w;
+        }
+        for (int k = 0; k < 8 && ge[k] != -1; ++k) {
+            const int g = d.N + (ge[k] & JMASK);
+            V4<R> pg = d.posq[g];
+            pg.w = p.w;
+            d.posq[g] = pg;
+        }
     }
     d.alch[s] = -1;
 }
@@ -1274,8 +1281,10 @@ __device__ void kcnt_list(const Dev<R>& d, const int* __restrict__ mem, int nf, 
 // Kind counts of one kind over its family, and (within-region exchanges)
 // over each region of the family.
 template <typename R>
-__global__ __launch_bounds__(1024) void k_kcnt(Dev<R> d, Mv m, int kind0)
+__global__ __launch_bounds__(1024) void k_kcnt(Dev<R> d, Mv m, int kind0, int batch_done)
 {
+    // batch_done: this launch closes an exchange batch, whose counter it advances
+    if (batch_done && blockIdx.x == 0 && threadIdx.x == 0) d.ctr[CT_BATCH] += 1;
     const int kind = kind0 + blockIdx.x;   // one work-group per kind
     const int f = m.fam_of_kind[kind];
     if (f < 0) return;
@@ -1332,12 +1341,6 @@ void launch_mark(const Dev<R>& d, const Mv& m, int mode, int T, hipStream_t st)
     hipLaunchKernelGGL(k_mark<R>, dim3((n + 255) / 256), dim3(256), 0, st, d, m, mode);
 }
 
-template <typename R>
-void launch_unmark(const Dev<R>& d, const Mv& m, int only_rejected, int T, hipStream_t st)
-{
-    int n = T * m.maxcht;
-    hipLaunchKernelGGL(k_unmark<R>, dim3((n + 255) / 256), dim3(256), 0, st, d, m, only_rejected);
-}
 
 template <typename R>
 void launch_du(const Dev<R>& d, const Mv& m, int T, hipStream_t st)
@@ -1451,16 +1454,15 @@ void launch_snapshot(const Dev<R>& d, const Mv& m, int restore, hipStream_t st)
 }
 
 template <typename R>
-void launch_kcnt(const Dev<R>& d, const Mv& m, int kind0, int nkinds, hipStream_t st)
+void launch_kcnt(const Dev<R>& d, const Mv& m, int kind0, int nkinds, int batch_done, hipStream_t st)
 {
     if (nkinds <= 0) return;
-    hipLaunchKernelGGL(k_kcnt<R>, dim3(nkinds), dim3(1024), 0, st, d, m, kind0);
+    hipLaunchKernelGGL(k_kcnt<R>, dim3(nkinds), dim3(1024), 0, st, d, m, kind0, batch_done);
 }
 
 #define INSTM(R)                                                                         \
     template void launch_select<R>(const Dev<R>&, const Mv&, int, int, int, hipStream_t); \
     template void launch_mark<R>(const Dev<R>&, const Mv&, int, int, hipStream_t);        \
-    template void launch_unmark<R>(const Dev<R>&, const Mv&, int, int, hipStream_t);      \
     template void launch_du<R>(const Dev<R>&, const Mv&, int, hipStream_t);               \
     template void launch_trial_accept<R>(const Dev<R>&, const Mv&, int, hipStream_t);     \
     template void launch_du_total<R>(const Dev<R>&, const Mv&, double*, hipStream_t);     \
@@ -1479,7 +1481,7 @@ void launch_kcnt(const Dev<R>& d, const Mv& m, int kind0, int nkinds, hipStream_
     template void launch_bt_refresh<R>(const Dev<R>&, const Mv&, int, hipStream_t);       \
     template void launch_mdas_accept<R>(const Dev<R>&, const Mv&, hipStream_t);           \
     template void launch_snapshot<R>(const Dev<R>&, const Mv&, int, hipStream_t);         \
-    template void launch_kcnt<R>(const Dev<R>&, const Mv&, int, int, hipStream_t);
+    template void launch_kcnt<R>(const Dev<R>&, const Mv&, int, int, int, hipStream_t);
 INSTM(float)
 INSTM(double)
 

@@ -203,8 +203,7 @@ template <typename R> struct Dev {
     int* ext_start;  // [next]
     int* ext_cnt;    // [next]
     int* ext_scan;   // [next + 1]
-    int* ghost_owner;
-    int* ghost_code;
+    int* ghost_owner;  // [Gcap] slot whose image each ghost is
     int* n_ghost;    // [1]
     int* glist;      // [N * 8] their ghost indices | code << 29, -1 unused
     int* orig_ext;   // [N + Gcap] bead id of each slot or ghost image

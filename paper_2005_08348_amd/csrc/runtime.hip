@@ -21,7 +21,6 @@
 namespace mbx {
 // launchers (defined in the kernel translation units)
 template <typename R> void launch_rebuild(const Dev<R>&, hipStream_t);
-template <typename R> void launch_ghost_update(const Dev<R>&, hipStream_t);
 template <typename R> int launch_nonbonded(const Dev<R>&, int, bool, double*, hipStream_t);
 template <typename R>
 void launch_nonbonded_fused(const Dev<R>&, int, int, R, long long, V4<R>*, V4<R>*, int, hipStream_t);
@@ -52,7 +51,6 @@ void launch_copy(void*, const void*, size_t, hipStream_t);
 void launch_add_ctr(long long*, int, long long, hipStream_t);
 template <typename R> void launch_select(const Dev<R>&, const Mv&, int, int, int, hipStream_t);
 template <typename R> void launch_mark(const Dev<R>&, const Mv&, int, int, hipStream_t);
-template <typename R> void launch_unmark(const Dev<R>&, const Mv&, int, int, hipStream_t);
 template <typename R> void launch_du(const Dev<R>&, const Mv&, int, hipStream_t);
 template <typename R> void launch_trial_accept(const Dev<R>&, const Mv&, int, hipStream_t);
 template <typename R> void launch_du_total(const Dev<R>&, const Mv&, double*, hipStream_t);
@@ -72,7 +70,7 @@ template <typename R> void launch_bt_refresh(const Dev<R>&, const Mv&, int, hipS
 void launch_work(double*, double, hipStream_t);
 template <typename R> void launch_mdas_accept(const Dev<R>&, const Mv&, hipStream_t);
 template <typename R> void launch_snapshot(const Dev<R>&, const Mv&, int, hipStream_t);
-template <typename R> void launch_kcnt(const Dev<R>&, const Mv&, int, int, hipStream_t);
+template <typename R> void launch_kcnt(const Dev<R>&, const Mv&, int, int, int, hipStream_t);
 void launch_set_classes(void* posq, int prec, const int* cls_by_bead, const int* orig, int N,
                         hipStream_t st);
 }  // namespace mbx
@@ -641,7 +639,7 @@ static size_t layout(membx_sys* s, Dev<R>& d, Mv& m, char* base)
     d.cell_start = a.take<int>(h.ncell_cap + 1);
     d.ext_start = a.take<int>(h.next_cap); d.ext_cnt = a.take<int>(h.next_cap);
     d.ext_scan = a.take<int>(2 * h.next_cap + 2);
-    d.ghost_owner = a.take<int>(h.Gcap); d.ghost_code = a.take<int>(h.Gcap);
+    d.ghost_owner = a.take<int>(h.Gcap);
     d.n_ghost = a.take<int>(1);
     d.glist = a.take<int>(8 * (size_t)N);
     d.orig_ext = a.take<int>(N + h.Gcap);
@@ -1081,10 +1079,11 @@ static void refresh_forces(membx_sys* s)
 }
 
 template <typename R>
-static void kcnt_all(membx_sys* s)
+static void kcnt_all(membx_sys* s, bool batch_done = false)
 {
-    // one work-group per kind (kinds outside every swap family return at once)
-    launch_kcnt<R>(dev<R>(s), s->mv, 0, s->h.nk, s->st);
+    // one work-group per kind (kinds outside every swap family return at once);
+    // batch_done: the same launch advances the exchange-batch counter
+    launch_kcnt<R>(dev<R>(s), s->mv, 0, s->h.nk, batch_done ? 1 : 0, s->st);
 }
 
 template <typename R>
@@ -1098,17 +1097,14 @@ static void swap_seq(membx_sys* s, int n_trials)
     launch_mark<R>(d, m, 0, T, s->st);   // marks only: positions and classes (ghosts too) unchanged
     launch_du<R>(d, m, T, s->st);
     if (topo) launch_bond_du<R>(d, m, 1.0, s->st);   // bonded part of dU
-    launch_trial_accept<R>(d, m, T, s->st);
-    launch_unmark<R>(d, m, 1, T, s->st);
+    launch_trial_accept<R>(d, m, T, s->st);   // also clears the rejected trials' marks
     launch_aff_build<R>(d, m, 1, T, false, s->st);
     launch_dforce<R>(d, m, (R)1, s->st);
     if (topo) launch_bond_dforce<R>(d, m, 1.0, 1, s->st);   // accepted: bonded F_new - F_old
-    launch_commit<R>(d, m, 0, T, s->st);
+    launch_commit<R>(d, m, 0, T, s->st);   // classes of the beads and their images
     if (topo) launch_bt_refresh<R>(d, m, 0, s->st);
     launch_aff_clear<R>(d, m, s->st);
-    kcnt_all<R>(s);
-    launch_ghost_update<R>(d, s->st);
-    launch_add_ctr(d.ctr, CT_BATCH, 1, s->st);
+    kcnt_all<R>(s, true);
 }
 
 template <typename R>
@@ -1208,9 +1204,8 @@ static int32_t mdas(membx_sys* s, int P, int K, int M)
     if (topo) launch_bt_refresh<R>(d, m, 1, st);
     launch_aff_clear<R>(d, m, st);
     launch_snapshot<R>(d, m, 1, st);
-    rebuild<R>(s);
+    rebuild<R>(s);   // writes the periodic images too
     kcnt_all<R>(s);
-    launch_ghost_update<R>(d, st);
     launch_add_ctr(d.ctr, CT_CYCLE, 1, st);
     s->cycle++;
     return MEMBX_OK;
