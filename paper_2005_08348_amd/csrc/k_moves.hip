@@ -786,27 +786,44 @@ __global__ __launch_bounds__(WG) void k_dforce(Dev<R> d, Mv m, R scale)
         const int mk = d.alch[i];
         const int ci2 = mk >= 0 ? (mk & 0xff) : ci;
         const int n1 = d.ncnt[i];
-        for (int k = s; k < n1; k += 8) {
-            int en = d.nbr[nbr_index(i, k, d.Kcap, d.lpb)];
-            int j = en & JMASK, code = (int)((unsigned)en >> CODE_SHIFT);
-                int o = owner_of(d.ghost_owner, d.N, j);
-            int mj = d.alch[o];
-            if (mk < 0 && mj < 0) continue;
-            V4<R> pj = d.posq[j];
-            int cj = cls_of<R>(d.posq[o].w);
-            int cj2 = mj >= 0 ? (mj & 0xff) : cj;
-            R xs = (code & 1) ? pi.x - d.L[0] : pi.x;
-            R ys = (code & 2) ? pi.y - d.L[1] : pi.y;
-            R zs = (code & 4) ? pi.z - d.L[2] : pi.z;
-            R dx = xs - pj.x, dy = ys - pj.y, dz = zs - pj.z;
-            R r2 = dx * dx + dy * dy + dz * dz;
-            if (!(r2 < d.rc2)) continue;
-            R rinv = rsq_m<R>(r2), rinv2 = rinv * rinv, rinv6 = rinv2 * rinv2 * rinv2;
-            V4<R> p1 = d.tabF[ci2 * MAXCLS + cj2], p0 = d.tabF[ci * MAXCLS + cj];
-            R f1 = (p1.y * rinv6 - p1.x) * (rinv6 * rinv2) + (p1.z * (rinv * rinv2) - p1.w);
-            R f0 = (p0.y * rinv6 - p0.x) * (rinv6 * rinv2) + (p0.z * (rinv * rinv2) - p0.w);
-            R fs = f1 - f0;
-            fx += fs * dx; fy += fs * dy; fz += fs * dz;
+        // KB entries per lane at a time: entries, then owners, then marks,
+        // each with all its loads in flight (most pairs have no mark and
+        // stop there)
+        constexpr int KB = 4;
+        for (int kb = s; kb < n1; kb += 8 * KB) {
+            int ent[KB], own[KB], mrk[KB];
+#pragma unroll
+            for (int b = 0; b < KB; ++b) {
+                const int k = kb + 8 * b;
+                ent[b] = k < n1 ? d.nbr[nbr_index(i, k, d.Kcap, d.lpb)] : 0;
+            }
+#pragma unroll
+            for (int b = 0; b < KB; ++b)
+                own[b] = kb + 8 * b < n1 ? owner_of(d.ghost_owner, d.N, ent[b] & JMASK) : 0;
+#pragma unroll
+            for (int b = 0; b < KB; ++b) mrk[b] = kb + 8 * b < n1 ? d.alch[own[b]] : -1;
+#pragma unroll
+            for (int b = 0; b < KB; ++b) {
+                if (kb + 8 * b >= n1) continue;
+                const int en = ent[b], o = own[b], mj = mrk[b];
+                int j = en & JMASK, code = (int)((unsigned)en >> CODE_SHIFT);
+                if (mk < 0 && mj < 0) continue;
+                V4<R> pj = d.posq[j];
+                int cj = cls_of<R>(d.posq[o].w);
+                int cj2 = mj >= 0 ? (mj & 0xff) : cj;
+                R xs = (code & 1) ? pi.x - d.L[0] : pi.x;
+                R ys = (code & 2) ? pi.y - d.L[1] : pi.y;
+                R zs = (code & 4) ? pi.z - d.L[2] : pi.z;
+                R dx = xs - pj.x, dy = ys - pj.y, dz = zs - pj.z;
+                R r2 = dx * dx + dy * dy + dz * dz;
+                if (!(r2 < d.rc2)) continue;
+                R rinv = rsq_m<R>(r2), rinv2 = rinv * rinv, rinv6 = rinv2 * rinv2 * rinv2;
+                V4<R> p1 = d.tabF[ci2 * MAXCLS + cj2], p0 = d.tabF[ci * MAXCLS + cj];
+                R f1 = (p1.y * rinv6 - p1.x) * (rinv6 * rinv2) + (p1.z * (rinv * rinv2) - p1.w);
+                R f0 = (p0.y * rinv6 - p0.x) * (rinv6 * rinv2) + (p0.z * (rinv * rinv2) - p0.w);
+                R fs = f1 - f0;
+                fx += fs * dx; fy += fs * dy; fz += fs * dz;
+            }
         }
     }
 #pragma unroll
@@ -872,27 +889,42 @@ __global__ __launch_bounds__(WG) void k_scforce(Dev<R> d, Mv m, double lam_from,
         const int mk = d.alch[i];
         const int ci2 = mk >= 0 ? (mk & 0xff) : ci;
         const int n1 = d.ncnt[i];
-        for (int k = s; k < n1; k += 8) {
-            const int en = d.nbr[nbr_index(i, k, d.Kcap, d.lpb)];
-            const int j = en & JMASK, code = (int)((unsigned)en >> CODE_SHIFT);
-            const int o = owner_of(d.ghost_owner, d.N, j);
-            const int mj = d.alch[o];
-            if (mk < 0 && mj < 0) continue;
-            const V4<R> pj = d.posq[j];
-            const int cj = cls_of<R>(d.posq[o].w);
-            const int cj2 = mj >= 0 ? (mj & 0xff) : cj;
-            const R xs = (code & 1) ? pi.x - d.L[0] : pi.x;
-            const R ys = (code & 2) ? pi.y - d.L[1] : pi.y;
-            const R zs = (code & 4) ? pi.z - d.L[2] : pi.z;
-            const double dx = (double)xs - (double)pj.x, dy = (double)ys - (double)pj.y,
-                         dz = (double)zs - (double)pj.z;
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            if (!(r2 < d.rc2d)) continue;
-            double v1, f1, v0, f0;
-            sc_pair_d(d, ci, cj, ci2, cj2, r2, lam_to, delta, v1, f1);
-            sc_pair_d(d, ci, cj, ci2, cj2, r2, lam_from, delta, v0, f0);
-            const double fs = f1 - f0;
-            fx += fs * dx; fy += fs * dy; fz += fs * dz;
+        // entries, owners and marks KB at a time per lane, as in k_dforce
+        constexpr int KB = 4;
+        for (int kb = s; kb < n1; kb += 8 * KB) {
+            int ent[KB], own[KB], mrk[KB];
+#pragma unroll
+            for (int b = 0; b < KB; ++b) {
+                const int k = kb + 8 * b;
+                ent[b] = k < n1 ? d.nbr[nbr_index(i, k, d.Kcap, d.lpb)] : 0;
+            }
+#pragma unroll
+            for (int b = 0; b < KB; ++b)
+                own[b] = kb + 8 * b < n1 ? owner_of(d.ghost_owner, d.N, ent[b] & JMASK) : 0;
+#pragma unroll
+            for (int b = 0; b < KB; ++b) mrk[b] = kb + 8 * b < n1 ? d.alch[own[b]] : -1;
+#pragma unroll
+            for (int b = 0; b < KB; ++b) {
+                if (kb + 8 * b >= n1) continue;
+                const int en = ent[b], o = own[b], mj = mrk[b];
+                const int j = en & JMASK, code = (int)((unsigned)en >> CODE_SHIFT);
+                if (mk < 0 && mj < 0) continue;
+                const V4<R> pj = d.posq[j];
+                const int cj = cls_of<R>(d.posq[o].w);
+                const int cj2 = mj >= 0 ? (mj & 0xff) : cj;
+                const R xs = (code & 1) ? pi.x - d.L[0] : pi.x;
+                const R ys = (code & 2) ? pi.y - d.L[1] : pi.y;
+                const R zs = (code & 4) ? pi.z - d.L[2] : pi.z;
+                const double dx = (double)xs - (double)pj.x, dy = (double)ys - (double)pj.y,
+                             dz = (double)zs - (double)pj.z;
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                if (!(r2 < d.rc2d)) continue;
+                double v1, f1, v0, f0;
+                sc_pair_d(d, ci, cj, ci2, cj2, r2, lam_to, delta, v1, f1);
+                sc_pair_d(d, ci, cj, ci2, cj2, r2, lam_from, delta, v0, f0);
+                const double fs = f1 - f0;
+                fx += fs * dx; fy += fs * dy; fz += fs * dz;
+            }
         }
     }
 #pragma unroll
