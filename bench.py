@@ -409,9 +409,10 @@ def main():
             result["swap"]["mixed_speedup_vs_fp64"] = (result["swap"]["trials_per_s"] /
                                                        result["fp64"]["swap"]["trials_per_s"])
         # ---- the paper's thermostat: velocity rescaling, tau_t 1 ps,
-        # membrane and solvent in two coupling groups (three launches per
-        # step instead of one: the update with the previous step's factors,
-        # the force pass with the closing half-kick, the factors)
+        # membrane and solvent in two coupling groups (two launches per
+        # step instead of one: the update, which draws and applies the
+        # previous step's factors, and the force pass with the closing
+        # half-kick and the kinetic-energy sums)
         log("[bench] velocity-rescaling leg")
         groups = [1 if k.name == "W" else 0 for k in c1.kinds]
         t_lang = 2.0 * gm.energies(check=False)["kinetic"] / (3 * c1.n_beads * S.KB)

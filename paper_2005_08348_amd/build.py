@@ -46,7 +46,9 @@ def build(verbose=False):
     with ThreadPoolExecutor(max_workers=min(len(SOURCES), 8)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-o", tmp, *objs]
+    # -z defs: an entry point whose kernel launcher is missing fails here,
+    # not when the library is loaded on the GPU host
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-Wl,-z,defs", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed\n{r.stdout}\n{r.stderr}")

@@ -186,9 +186,10 @@ void launch_import(const Dev<R>& d, V4<R>* dst, const double* in, hipStream_t st
 // words: Philox stream 5, counter = step index, block (group << 16) for R1
 // and (group << 16) + 1 + t for the t-th attempt of the gamma sampler.  The
 // half-kick with per-block group sums runs in the force pass itself (k_nb,
-// FUSE 2) or, after an MDAS segment's alchemical forces, in k_kick_ke; then
-// one wave draws the two factors (float64 throughout); the scaling rides on
-// the next step's update.
+// FUSE 2) or, after an MDAS segment's alchemical forces, in k_kick_ke; every
+// work-group of the next step's update (or of k_vr_scale after the last
+// step) sums those partials and draws the two factors itself (float64
+// throughout; all draw the same), then scales its beads' velocities.
 
 template <typename R>
 __global__ __launch_bounds__(WG) void k_kick_ke(Dev<R> d, VrBuf vr, R kick)
@@ -258,13 +259,15 @@ __device__ double vr_factor(uint64_t seed, int g, double K, double nf, double kT
     return (r1 + sqrt(c * nf * K / ((1.0 - c) * kt)) < 0.0) ? -al : al;
 }
 
-// one wave: group sums over the blocks (fixed order), then lanes 0 and 1
-// draw the factors of groups 0 and 1
-// one work-group: the block partials summed (a force pass leaves up to
-// 8 N / 256 of them), then threads 0 and 1 draw the factors
+// The step's two factors from the nblk block partials of its closing
+// half-kick: sums in a fixed order (strided over the work-group's threads,
+// then its waves), then threads 0 and 1 draw the factors of groups 0 and 1
+// into al (LDS).  Every thread of the work-group calls it; each work-group
+// of the update that applies the factors runs it itself, so no separate
+// launch waits between the force pass and the update.
 template <typename R>
-__global__ __launch_bounds__(WG) void k_vr_alpha(Dev<R> d, VrBuf vr, int nblk, long long step_off,
-                                                 double c)
+__device__ __forceinline__ void vr_factors_wg(const Dev<R>& d, const VrBuf& vr, int nblk,
+                                              long long fstep, double c, double* al)
 {
     const int t = threadIdx.x;
     double q[4] = { 0.0, 0.0, 0.0, 0.0 };
@@ -281,16 +284,22 @@ __global__ __launch_bounds__(WG) void k_vr_alpha(Dev<R> d, VrBuf vr, int nblk, l
     if (t < 2) {
         double K = 0.0, nb = 0.0;
         for (int w = 0; w < WG / 64; ++w) { K += sw[t][w]; nb += sw[2 + t][w]; }
-        vr.alpha[t] = vr_factor(d.seed, t, K, 3.0 * nb, d.kTd, c, d.ctr[CT_STEP] + step_off);
+        al[t] = vr_factor(d.seed, t, K, 3.0 * nb, d.kTd, c, d.ctr[CT_STEP] + fstep);
+        if (blockIdx.x == 0) vr.alpha[t] = al[t];   // the last factors, for the record
     }
+    __syncthreads();
 }
 
+// the last step's factors applied after a sequence of steps
 template <typename R>
-__global__ __launch_bounds__(WG) void k_vr_scale(Dev<R> d, VrBuf vr)
+__global__ __launch_bounds__(WG) void k_vr_scale(Dev<R> d, VrBuf vr, int nblk, long long fstep,
+                                                 double c)
 {
+    __shared__ double al[2];
+    vr_factors_wg(d, vr, nblk, fstep, c, al);
     const int i = blockIdx.x * WG + threadIdx.x;
     if (i >= d.N) return;
-    const double a = vr.alpha[vr_group(d, vr, i)];
+    const double a = al[vr_group(d, vr, i)];
     V4<R> v = d.vel[i];
     v.x = (R)(a * (double)v.x); v.y = (R)(a * (double)v.y); v.z = (R)(a * (double)v.z);
     d.vel[i] = v;
@@ -367,16 +376,19 @@ void launch_scale_pos(const Dev<R>& d, const double* mu, hipStream_t st)
 }
 
 // the previous step's scaling folded into this step's B-A-O-A (the O part is
-// off under this thermostat): v <- alpha_g v, then the kick and drifts
+// off under this thermostat): v <- alpha_g v, then the kick and drifts; the
+// factors come from that step's nblk block partials (counter: step fstep)
 template <typename R>
 __global__ __launch_bounds__(WG) void k_vr_kick_drift(Dev<R> d, VrBuf vr, R kick, long long step_off,
-                                                      int chk_in)
+                                                      int chk_in, int nblk, long long fstep, double c)
 {
+    __shared__ double al[2];
+    vr_factors_wg(d, vr, nblk, fstep, c, al);
     const int i = blockIdx.x * WG + threadIdx.x;
     float e2 = 0.f, e2_in = 0.f;
     if (i < d.N) {
         BeadPre<R> pre = bead_pre(d, i, chk_in != 0);
-        const double a = vr.alpha[vr_group(d, vr, i)];
+        const double a = al[vr_group(d, vr, i)];
         pre.v.x = (R)(a * (double)pre.v.x);
         pre.v.y = (R)(a * (double)pre.v.y);
         pre.v.z = (R)(a * (double)pre.v.z);
@@ -386,45 +398,42 @@ __global__ __launch_bounds__(WG) void k_vr_kick_drift(Dev<R> d, VrBuf vr, R kick
     disp_stats(d, e2, e2_in, i < d.N);
 }
 
-// closing half-kick with the group sums, then the factors of the step; the
-// scaling itself runs in the next step's update (k_vr_kick_drift) or, after
-// the last step of a sequence, in k_vr_scale (launch_vr_scale)
-// kicked_blocks > 0: the force pass already made the half-kick and wrote
-// that many block partials
+// closing half-kick with the group sums (after an MDAS segment's alchemical
+// forces; otherwise the force pass makes it, FUSE 2); returns the number of
+// block partials.  The factors are drawn where they are applied
+// (k_vr_kick_drift of the next step, or k_vr_scale after the last).
 template <typename R>
-void launch_vrescale(const Dev<R>& d, const VrBuf& vr, R kick, long long step_off, double c,
-                     int kicked_blocks, hipStream_t st)
+int launch_kick_ke(const Dev<R>& d, const VrBuf& vr, R kick, hipStream_t st)
 {
-    int nb = kicked_blocks;
-    if (nb <= 0) {
-        nb = (d.N + WG - 1) / WG;
-        hipLaunchKernelGGL(k_kick_ke<R>, dim3(nb), dim3(WG), 0, st, d, vr, kick);
-    }
-    hipLaunchKernelGGL(k_vr_alpha<R>, dim3(1), dim3(WG), 0, st, d, vr, nb, step_off, c);
+    const int nb = (d.N + WG - 1) / WG;
+    hipLaunchKernelGGL(k_kick_ke<R>, dim3(nb), dim3(WG), 0, st, d, vr, kick);
+    return nb;
 }
 template <typename R>
-void launch_vr_scale(const Dev<R>& d, const VrBuf& vr, hipStream_t st)
+void launch_vr_scale(const Dev<R>& d, const VrBuf& vr, int nblk, long long fstep, double c,
+                     hipStream_t st)
 {
-    hipLaunchKernelGGL(k_vr_scale<R>, dim3((d.N + WG - 1) / WG), dim3(WG), 0, st, d, vr);
+    hipLaunchKernelGGL(k_vr_scale<R>, dim3((d.N + WG - 1) / WG), dim3(WG), 0, st, d, vr, nblk, fstep,
+                       c);
 }
 template <typename R>
 void launch_vr_kick_drift(const Dev<R>& d, const VrBuf& vr, R kick, long long step_off, int chk_in,
-                          hipStream_t st)
+                          int nblk, long long fstep, double c, hipStream_t st)
 {
     hipLaunchKernelGGL(k_vr_kick_drift<R>, dim3((d.N + WG - 1) / WG), dim3(WG), 0, st, d, vr, kick,
-                       step_off, chk_in);
+                       step_off, chk_in, nblk, fstep, c);
 }
 
 #define INST(R)                                                                      \
-    template void launch_vrescale<R>(const Dev<R>&, const VrBuf&, R, long long, double, \
-                                     int, hipStream_t);                              \
-    template void launch_vr_scale<R>(const Dev<R>&, const VrBuf&, hipStream_t);      \
+    template int launch_kick_ke<R>(const Dev<R>&, const VrBuf&, R, hipStream_t);     \
+    template void launch_vr_scale<R>(const Dev<R>&, const VrBuf&, int, long long, double, \
+                                     hipStream_t);                                   \
     template void launch_baro<R>(const Dev<R>&, const double*, double*, double, double, double, \
                                  double, double, hipStream_t);                       \
     template void launch_scale_pos<R>(const Dev<R>&, const double*, hipStream_t);    \
     template void launch_unscale_vel<R>(const Dev<R>&, const double*, hipStream_t);  \
-    template void launch_vr_kick_drift<R>(const Dev<R>&, const VrBuf&, R, long long, int, \
-                                          hipStream_t);                              \
+    template void launch_vr_kick_drift<R>(const Dev<R>&, const VrBuf&, R, long long, int, int, \
+                                          long long, double, hipStream_t);           \
     template void launch_kick_drift<R>(const Dev<R>&, R, long long, int, hipStream_t); \
     template void launch_kick<R>(const Dev<R>&, R, long long, hipStream_t);                    \
     template void launch_alch_bridge<R>(const Dev<R>&, const int*, double*, R, R, double, long long, \

@@ -30,17 +30,19 @@ template <typename R>
 void launch_alch_bridge(const Dev<R>&, const int*, double*, R, R, double, long long, hipStream_t);
 template <typename R> void launch_kick(const Dev<R>&, R, long long, hipStream_t);
 template <typename R>
-void launch_vrescale(const Dev<R>&, const VrBuf&, R, long long, double, int, hipStream_t);
+int launch_kick_ke(const Dev<R>&, const VrBuf&, R, hipStream_t);
 template <typename R>
 int launch_nonbonded_kick(const Dev<R>&, int, const VrBuf&, R, hipStream_t);
-template <typename R> void launch_vr_scale(const Dev<R>&, const VrBuf&, hipStream_t);
+template <typename R>
+void launch_vr_scale(const Dev<R>&, const VrBuf&, int, long long, double, hipStream_t);
 template <typename R>
 void launch_baro(const Dev<R>&, const double*, double*, double, double, double, double, double,
                  hipStream_t);
 template <typename R> void launch_scale_pos(const Dev<R>&, const double*, hipStream_t);
 template <typename R> void launch_unscale_vel(const Dev<R>&, const double*, hipStream_t);
 template <typename R>
-void launch_vr_kick_drift(const Dev<R>&, const VrBuf&, R, long long, int, hipStream_t);
+void launch_vr_kick_drift(const Dev<R>&, const VrBuf&, R, long long, int, int, long long, double,
+                          hipStream_t);
 template <typename R> void launch_sd_step(const Dev<R>&, double, double, hipStream_t);
 template <typename R> void launch_export(const Dev<R>&, const V4<R>*, double*, hipStream_t);
 template <typename R> void launch_import(const Dev<R>&, V4<R>*, const double*, hipStream_t);
@@ -864,10 +866,11 @@ static void steps_seq(membx_sys* s, long long n, const Alch* alch, bool launch =
     const double vr_c = vr ? std::exp(-s->h.dt / s->h.tau_t) : 1.0;
     if (alch) s->sp = -1;   // MDAS segments walk the Verlet list; no inner bookkeeping
     bool moved = false;   // the previous force pass already moved the beads
+    int vr_nblk = 0;      // block partials of the last closing half-kick (its factors pending)
     for (long long k = 0; k < n; ++k) {
         if (!moved && launch) {
             const int chk = (inner && s->sp >= 0) ? 1 : 0;
-            if (vr && k > 0) launch_vr_kick_drift<R>(d, s->vr, h, k, chk, s->st);
+            if (vr && k > 0) launch_vr_kick_drift<R>(d, s->vr, h, k, chk, vr_nblk, k - 1, vr_c, s->st);
             else if (!(alch && k == 0 && !alch->open))
                 launch_kick_drift<R>(d, (k == 0 || vr) ? h : full, (alch ? alch->base : 0) + k, chk,
                                      s->st);
@@ -894,13 +897,12 @@ static void steps_seq(membx_sys* s, long long n, const Alch* alch, bool launch =
         } else {
             if (launch) {
                 if (vr && !alch && !s->timing) {
-                    // forces and the closing half-kick in one pass
-                    const int nbk = launch_nonbonded_kick<R>(d, s->h.lpb, s->vr, h, s->st);
-                    launch_vrescale<R>(d, s->vr, h, k, vr_c, nbk, s->st);
+                    // forces and the closing half-kick with its block partials in one pass
+                    vr_nblk = launch_nonbonded_kick<R>(d, s->h.lpb, s->vr, h, s->st);
                 } else {
                     forces<R>(s, rebuilt);
                     if (alch) alch_terms<R>(s, rebuilt, alch->lam);
-                    if (vr) launch_vrescale<R>(d, s->vr, h, k, vr_c, 0, s->st);
+                    if (vr) vr_nblk = launch_kick_ke<R>(d, s->vr, h, s->st);
                 }
             }
             if (s->sp >= 0) s->sp++;
@@ -908,7 +910,7 @@ static void steps_seq(membx_sys* s, long long n, const Alch* alch, bool launch =
     }
     if (launch) {
         if (vr) {
-            if (n > 0) launch_vr_scale<R>(d, s->vr, s->st);
+            if (n > 0) launch_vr_scale<R>(d, s->vr, vr_nblk, n - 1, vr_c, s->st);
             launch_add_ctr(d.ctr, CT_STEP, n, s->st);
         } else {
             if (!alch) launch_kick<R>(d, h, n, s->st);
