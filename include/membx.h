@@ -119,7 +119,8 @@ typedef struct membx_desc {
                                   /* skin                                   */
     int32_t rebuild_interval;     /* steps between list rebuilds (def. 5)   */
     int32_t lanes_per_bead;       /* 1, 2, 4 or 8 (default 8)               */
-    int32_t list_capacity;        /* neighbour slots per bead (default auto) */
+    int32_t list_capacity;        /* neighbour slots per bead (default auto; */
+                                  /* rounded up to a multiple of 8)         */
     int32_t max_trials;           /* largest exchange batch (default 256)   */
     int32_t max_pairs;            /* largest MDAS pair count (default 64)   */
     /* dynamic pruning: every prune_interval force passes of plain MD the

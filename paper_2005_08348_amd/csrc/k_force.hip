@@ -185,22 +185,17 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
     int mmax = m1n;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) mmax = max(mmax, __shfl_xor(mmax, o, 64));
-    auto compute = [&](int m0, const int* jj, auto nbt) {
+    // one batch of pairs; SH: some entry of the wave carries a periodic
+    // code, so bead i is shifted down by L along the code's axes (exact:
+    // it sits in the upper half of the box there); the common case takes
+    // bead i as it is
+    auto pairs = [&](int m0, const int* jj, const V4<R>* q, auto nbt, auto shx) {
         constexpr int NB = decltype(nbt)::value;
-        V4<R> q[NB];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) q[b] = P[m0 + b < m1n ? (jj[b] & JMASK) : ii];
-        // i-image shifts: decoded only in waves that hold a shifted entry
-        bool shifted = false;
-#pragma unroll
-        for (int b = 0; b < NB; ++b)
-            shifted |= (m0 + b < m1n) && ((unsigned)jj[b] >> CODE_SHIFT) != 0u;
-        const bool wave_shift = __ballot(shifted) != 0ull;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const bool live = m0 + b < m1n;
             R xs = pi.x, ys = pi.y, zs = pi.z;
-            if (wave_shift) {
+            if (decltype(shx)::value) {
                 const int code = live ? (int)((unsigned)jj[b] >> CODE_SHIFT) : 0;
                 if (code & 1) xs -= d.L[0];
                 if (code & 2) ys -= d.L[1];
@@ -209,10 +204,10 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
             const R dx = xs - q[b].x, dy = ys - q[b].y, dz = zs - q[b].z;
             const R r2 = dx * dx + dy * dy + dz * dz;
             if (LIST == 2 && live && r2 < d.rin2) nb_out[(size_t)(nkeep++) * 64] = jj[b];
-            // unused slots hold the bead itself (r2 = 0): masked, kept off rsq(0)
+            // unused slots hold the bead itself (r2 = 0): rsq gives inf and
+            // the terms inf or NaN, which the selects below drop
             const bool in = live && r2 < d.rc2;
-            const R r2s = in ? r2 : (R)1;
-            const R rinv = rsq<R>(r2s);
+            const R rinv = rsq<R>(r2);
             const R rinv2 = rinv * rinv;
             const R rinv6 = rinv2 * rinv2 * rinv2;
             const V4<R> p = rowF[cls_of<R>(q[b].w)];
@@ -224,7 +219,7 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
             if (EN) {
                 const V4<R> e = rowE[cls_of<R>(q[b].w)];
                 const R vlj = (e.y * rinv6 - e.x) * rinv6 - e.w;
-                const R vrf = e.z * (rinv + d.krf * r2s - d.crf);
+                const R vrf = e.z * (rinv + d.krf * r2 - d.crf);
                 if (in) {
                     elj += (double)vlj;
                     erf += (double)vrf;
@@ -236,11 +231,36 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
             }
         }
     };
+    // coordinates by 32-bit byte offset (slots < 2^27, checked at creation):
+    // the shift code's bits fall off the top of the shifted entry
+    constexpr int PSH = sizeof(V4<R>) == 16 ? 4 : 5;
+    const char* __restrict__ Pc = reinterpret_cast<const char*>(P);
+    auto compute = [&](int m0, const int* jj, auto nbt) {
+        constexpr int NB = decltype(nbt)::value;
+        V4<R> q[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const unsigned o = (unsigned)(m0 + b < m1n ? jj[b] : ii) << PSH;
+            q[b] = *reinterpret_cast<const V4<R>*>(Pc + o);
+        }
+        bool shifted = false;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) shifted |= (m0 + b < m1n) && (unsigned)jj[b] > (unsigned)JMASK;
+        if (__ballot(shifted) != 0ull) pairs(m0, jj, q, nbt, std::true_type{});
+        else pairs(m0, jj, q, nbt, std::false_type{});
+    };
     auto batch = [&](int m0, auto nbt) {
         constexpr int NB = decltype(nbt)::value;
         int jj[NB];
+        if constexpr (NB == B) {
+            // full batches end at mmax <= mcap: no clamp, one base address
+            const int* __restrict__ nbm = nb + (size_t)m0 * 64;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) jj[b] = nb[(size_t)min(m0 + b, mcap - 1) * 64];
+            for (int b = 0; b < NB; ++b) jj[b] = nbm[b * 64];
+        } else {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) jj[b] = nb[(size_t)min(m0 + b, mcap - 1) * 64];
+        }
         compute(m0, jj, nbt);
     };
     int m0 = 0;

@@ -317,7 +317,8 @@ Status check_desc(const membx_desc* d, Host& h)
     set_grid(h, h.skin_max);
     double vol = h.box[0] * h.box[1] * h.box[2];
     double rho = h.N / vol;
-    if (d->list_capacity > 0) h.Kcap = d->list_capacity;
+    // a multiple of 8: the list is tiled in rows of 64 / lanes_per_bead beads
+    if (d->list_capacity > 0) h.Kcap = (d->list_capacity + 7) / 8 * 8;
     else {
         double exp_n = rho * 4.0 / 3.0 * M_PI * rl * rl * rl;
         h.Kcap = (int)std::ceil((exp_n * 1.8 + 24) / 8.0) * 8;
@@ -326,7 +327,10 @@ Status check_desc(const membx_desc* d, Host& h)
     if (h.Kcap > 512) return { MEMBX_E_INVAL, "list capacity above 512 per bead (lower skin or density)" };
     double gfrac = (1.0 + 1.0 / h.nc[0]) * (1.0 + 1.0 / h.nc[1]) * (1.0 + 1.0 / h.nc[2]) - 1.0;
     h.Gcap = (int)(h.N * gfrac * 1.6) + 4096;
-    if ((long long)h.N + h.Gcap >= (1LL << CODE_SHIFT)) return { MEMBX_E_INVAL, "too many beads" };
+    // list entries hold slots below 2^29, and the force pass addresses the
+    // coordinates of a slot by a 32-bit byte offset (32 bytes per slot)
+    if ((long long)h.N + h.Gcap >= (1LL << 27))
+        return { MEMBX_E_INVAL, "too many beads (beads plus periodic images >= 2^27)" };
     set_grid(h, h.skin);
     // exchange hash (cells >= r_cut)
     h.hcells = 1;
