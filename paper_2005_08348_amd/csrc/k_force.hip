@@ -324,28 +324,40 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
                 fk[threadIdx.x / LPB] = f;
             }
             __syncthreads();
-            double q[4] = { 0.0, 0.0, 0.0, 0.0 };   // K of group 0, 1; beads of group 0, 1
-            if (integ) {
-                V4<R> v = vk;
-                const V4<R> f = fk[threadIdx.x];
-                v.x += kick * v.w * f.x; v.y += kick * v.w * f.y; v.z += kick * v.w * f.z;
-                d.vel[ib] = v;
-                const double k2 =
-                    0.5 * ((double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z) / (double)v.w;
-                const bool g1 = vr_group(d, vr, ib) != 0;
-                q[0] = g1 ? 0.0 : k2; q[1] = g1 ? k2 : 0.0;
-                q[2] = g1 ? 0.0 : 1.0; q[3] = g1 ? 1.0 : 0.0;
-            }
+            // only the first NIW waves integrate (thread t < NBB takes bead t)
+            constexpr int NIW = (NBB + 63) / 64;
+            if (threadIdx.x < NIW * 64) {   // wave-uniform
+                double q[4] = { 0.0, 0.0, 0.0, 0.0 };   // K of group 0, 1; beads of group 0, 1
+                if (integ) {
+                    V4<R> v = vk;
+                    const V4<R> f = fk[threadIdx.x];
+                    v.x += kick * v.w * f.x; v.y += kick * v.w * f.y; v.z += kick * v.w * f.z;
+                    d.vel[ib] = v;
+                    const double k2 =
+                        0.5 * ((double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z) / (double)v.w;
+                    const bool g1 = vr_group(d, vr, ib) != 0;
+                    q[0] = g1 ? 0.0 : k2; q[1] = g1 ? k2 : 0.0;
+                    q[2] = g1 ? 0.0 : 1.0; q[3] = g1 ? 1.0 : 0.0;
+                }
+                // butterfly sums: every lane holds the wave's totals
+                double x[4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const double x = wave_sum(q[c]);
-                if ((threadIdx.x & 63) == 0) sk[c][threadIdx.x >> 6] = x;
+                for (int c = 0; c < 4; ++c) x[c] = wave_sum(q[c]);
+                const int l = threadIdx.x & 63;
+                if constexpr (NIW == 1) {
+                    if (l < 4) part[4 * blk + l] = l == 0 ? x[0] : l == 1 ? x[1] : l == 2 ? x[2] : x[3];
+                } else {
+                    if (l == 0)
+                        for (int c = 0; c < 4; ++c) sk[c][threadIdx.x >> 6] = x[c];
+                }
             }
-            __syncthreads();
-            if (threadIdx.x < 4) {
-                double t = 0.0;
-                for (int w = 0; w < WG / 64; ++w) t += sk[threadIdx.x][w];
-                part[4 * blk + threadIdx.x] = t;
+            if constexpr (NIW > 1) {
+                __syncthreads();
+                if (threadIdx.x < 4) {
+                    double t = 0.0;
+                    for (int w = 0; w < NIW; ++w) t += sk[threadIdx.x][w];
+                    part[4 * blk + threadIdx.x] = t;
+                }
             }
         } else {
             __shared__ V4<R> fsh[NBB];
@@ -363,7 +375,7 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
             if (integ)
                 e2 = baoab_bead(d, ib, pb, pre, fsh[threadIdx.x], kick, step_off, pos_out, vel_out,
                                 LIST != 0, e2_in);
-            if (stats) disp_stats(d, e2, e2_in, integ);
+            if (stats) disp_stats_lead<(NBB + 63) / 64>(d, e2, e2_in, integ);
         }
     } else {
         __shared__ double sh[16][WG / 64];

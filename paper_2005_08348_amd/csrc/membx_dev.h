@@ -442,6 +442,38 @@ __device__ __forceinline__ void disp_stats(const Dev<R>& d, float e2, float e2_i
     }
 }
 
+// disp_stats when only the block's first NIW waves hold counted beads (the
+// force pass that integrates: thread t < WG / lanes per bead takes bead t):
+// the other waves skip it, and with one such wave there is no barrier.
+template <int NIW, typename R>
+__device__ __forceinline__ void disp_stats_lead(const Dev<R>& d, float e2, float e2_in, bool counted)
+{
+    if constexpr (NIW >= WG / 64) {
+        disp_stats(d, e2, e2_in, counted);
+    } else {
+        __shared__ float s_m2[NIW];
+        float m2 = 0.f;
+        if (threadIdx.x < NIW * 64) {   // wave-uniform
+            const unsigned long long over = __ballot(counted && e2 > (float)d.skin_half2);
+            const unsigned long long over_in = __ballot(counted && e2_in > (float)d.in_half2);
+            m2 = counted ? e2 : 0.f;
+            for (int o = 32; o > 0; o >>= 1) m2 = fmaxf(m2, __shfl_xor(m2, o, 64));
+            if ((threadIdx.x & 63) == 0) {
+                if (over) atomicAdd(&d.flags[FL_SKIN], __popcll(over));
+                if (over_in) atomicAdd(&d.flags[FL_SKIN_IN], __popcll(over_in));
+                if (NIW > 1) s_m2[threadIdx.x >> 6] = m2;
+            }
+        }
+        if constexpr (NIW > 1) {
+            __syncthreads();
+            if (threadIdx.x == 0)
+                for (int w = 1; w < NIW; ++w) m2 = fmaxf(m2, s_m2[w]);
+        }
+        if (threadIdx.x == 0)
+            atomicMax(reinterpret_cast<int*>(d.dmax_part) + blockIdx.x, __float_as_int(m2));
+    }
+}
+
 // Entry k of slot i's neighbour list: beads are grouped by 64/lpb, and
 // within a group entries are interleaved in blocks of lpb.
 __host__ __device__ __forceinline__ size_t nbr_index(int i, int k, int Kcap, int lpb)
