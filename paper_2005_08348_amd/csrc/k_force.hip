@@ -121,10 +121,16 @@ __device__ __forceinline__ double wave_sum(double v)
 // keeps its entries within r_cut + delta, in order, as its own entries
 // s, s + LPB, ... of the inner list, with its own count, and the bead's
 // coordinates become the reference for the inner list's displacement check.
+// FUSE 3 (MDAS segment boundary, in place of the closing pass of a segment
+// and the next one's opening update): as FUSE 1, but the integrating thread
+// first adds lam (F_B - F_A) to an affected bead's force, makes the closing
+// half-kick with it, moves the force to lam + dl and makes the opening
+// B-A-O-A with that (kick = dt / 2); one thread adds the work increment
+// dlw dU.  The operations and their order are those of the separate passes.
 template <typename R, int LPB, bool EN, int FUSE, int LIST>
 __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, R kick,
                                            long long step_off, V4<R>* pos_out, V4<R>* vel_out,
-                                           int stats, VrBuf vr)
+                                           int stats, VrBuf vr, AlchK<R> ak)
 {
     __shared__ V4<R> tf[MAXCLS * MAXCLS];
     __shared__ V4<R> te[EN ? MAXCLS * MAXCLS : 1];
@@ -158,7 +164,7 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
         const int n1 = valid ? d.ncnt[i] : 0;
         m1n = n1 > s ? (n1 - s + LPB - 1) / LPB : 0;
     }
-    // FUSE 1, 2: after the forces, thread t < WG / LPB of the block integrates the
+    // FUSE 1, 2, 3: after the forces, thread t < WG / LPB of the block integrates the
     // block's bead t (forces handed over through LDS), so that the
     // integrator runs on full waves instead of one lane per bead
     constexpr int NBB = WG / LPB;
@@ -276,11 +282,21 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
     // during the walk)
     BeadPre<R> pre{};
     V4<R> pb{}, vk{};
-    if (FUSE == 2 && integ) vk = d.vel[ib];   // the closing half-kick's velocity
-    if (FUSE == 1 && integ) {
+    int grp = 0;   // coupling group of bead ib (a chain of four loads, in flight early)
+    if (FUSE == 2 && integ) {
+        vk = d.vel[ib];   // the closing half-kick's velocity
+        grp = vr_group(d, vr, ib);
+    }
+    int af = 0;
+    V4<R> gd{};   // FUSE 3: the bead's F_B - F_A
+    if ((FUSE == 1 || FUSE == 3) && integ) {
         pb = d.posq[ib];
         pre = bead_pre(d, ib, LIST == 1);
         if (LIST == 2) pre.xri = pb;   // this pass makes the bead's coordinates the reference
+        if (FUSE == 3) {
+            af = ak.aff_flag[ib];
+            if (af) gd = d.dfrc[ib];
+        }
     }
     // bonded records (lane s takes terms s, s + LPB, ... of its bead) and
     // their partners' coordinates
@@ -335,7 +351,7 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
                     d.vel[ib] = v;
                     const double k2 =
                         0.5 * ((double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z) / (double)v.w;
-                    const bool g1 = vr_group(d, vr, ib) != 0;
+                    const bool g1 = grp != 0;
                     q[0] = g1 ? 0.0 : k2; q[1] = g1 ? k2 : 0.0;
                     q[2] = g1 ? 0.0 : 1.0; q[3] = g1 ? 1.0 : 0.0;
                 }
@@ -367,14 +383,23 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
             }
             if (own) {
                 const V4<R> f{ fx, fy, fz, (R)0 };
-                d.frc[i] = f;
+                if (FUSE == 1) d.frc[i] = f;
                 fsh[threadIdx.x / LPB] = f;
             }
+            if (FUSE == 3 && blockIdx.x == 0 && threadIdx.x == 0) ak.md[0] += ak.dlw * ak.md[1];
             __syncthreads();
             float e2 = 0.f, e2_in = 0.f;
-            if (integ)
-                e2 = baoab_bead(d, ib, pb, pre, fsh[threadIdx.x], kick, step_off, pos_out, vel_out,
-                                LIST != 0, e2_in);
+            if (integ) {
+                V4<R> f = fsh[threadIdx.x];
+                if (FUSE == 3) {
+                    if (af) { f.x += ak.lam * gd.x; f.y += ak.lam * gd.y; f.z += ak.lam * gd.z; }
+                    pre.v.x += kick * pre.v.w * f.x; pre.v.y += kick * pre.v.w * f.y;
+                    pre.v.z += kick * pre.v.w * f.z;
+                    if (af) { f.x += ak.dl * gd.x; f.y += ak.dl * gd.y; f.z += ak.dl * gd.z; }
+                    d.frc[ib] = f;
+                }
+                e2 = baoab_bead(d, ib, pb, pre, f, kick, step_off, pos_out, vel_out, LIST != 0, e2_in);
+            }
             if (stats) disp_stats_lead<(NBB + 63) / 64>(d, e2, e2_in, integ);
         }
     } else {
@@ -433,11 +458,12 @@ __global__ void k_energy_final(const double* __restrict__ p, int nb, double* __r
 // ----------------------------------------------------------------- launch
 template <typename R, int LPB, bool EN, int FUSE, int LIST>
 static void nb_launch(const Dev<R>& d, double* part, R kick, long long step_off, V4<R>* pos_out,
-                      V4<R>* vel_out, int stats, hipStream_t st, VrBuf vr = VrBuf{})
+                      V4<R>* vel_out, int stats, hipStream_t st, VrBuf vr = VrBuf{},
+                      AlchK<R> ak = AlchK<R>{})
 {
     int nthr = d.N * LPB;
     hipLaunchKernelGGL((k_nb<R, LPB, EN, FUSE, LIST>), dim3((nthr + WG - 1) / WG), dim3(WG), 0, st, d,
-                       part, kick, step_off, pos_out, vel_out, stats, vr);
+                       part, kick, step_off, pos_out, vel_out, stats, vr, ak);
 }
 
 // forces (energy=false) or energies into part (energy=true), Verlet list;
@@ -499,11 +525,32 @@ int launch_nonbonded_kick(const Dev<R>& d, int lpb, const VrBuf& vr, R kick, hip
     return (d.N * lpb + WG - 1) / WG;
 }
 
+// MDAS segment boundary fused into the force pass (see k_nb, FUSE 3):
+// Verlet list, kick = dt / 2, the update written to pos_out
+template <typename R>
+void launch_nonbonded_alch(const Dev<R>& d, int lpb, R kick, long long step_off, V4<R>* pos_out,
+                           V4<R>* vel_out, const AlchK<R>& ak, hipStream_t st)
+{
+#define NBA(L) nb_launch<R, L, false, 3, 0>(d, nullptr, kick, step_off, pos_out, vel_out, 1, st, VrBuf{}, ak)
+    switch (lpb) {
+    case 1: NBA(1); break;
+    case 2: NBA(2); break;
+    case 4: NBA(4); break;
+    case 8: NBA(8); break;
+    default: break;
+    }
+#undef NBA
+}
+
 void launch_energy_final(const double* p, int nb, double* out, hipStream_t st)
 {
     hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, st, p, nb, out);
 }
 
+template void launch_nonbonded_alch<float>(const Dev<float>&, int, float, long long, V4<float>*,
+                                           V4<float>*, const AlchK<float>&, hipStream_t);
+template void launch_nonbonded_alch<double>(const Dev<double>&, int, double, long long, V4<double>*,
+                                            V4<double>*, const AlchK<double>&, hipStream_t);
 template int launch_nonbonded<float>(const Dev<float>&, int, bool, double*, hipStream_t);
 template int launch_nonbonded_kick<float>(const Dev<float>&, int, const VrBuf&, float, hipStream_t);
 template int launch_nonbonded_kick<double>(const Dev<double>&, int, const VrBuf&, double, hipStream_t);

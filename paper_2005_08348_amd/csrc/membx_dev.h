@@ -151,6 +151,16 @@ struct ObsBuf {
     unsigned long long* hist;  // [OBS_MAXBINS] pair counts
 };
 
+// Boundary between two MDAS segments fused into the force pass (linear
+// path, Langevin): the affected beads' force difference F_B - F_A (dfrc,
+// computed beforehand at the same coordinates) and the two lambdas' weights.
+template <typename R> struct AlchK {
+    const int* aff_flag;   // [N] nonzero: the bead's force depends on lambda
+    double* md;            // MDAS accumulators: md[0] += dlw md[1] (work)
+    R lam, dl;             // lambda of the closing step, increment to the next
+    double dlw;
+};
+
 // Stochastic velocity rescaling with two coupling groups: the group of a
 // bead is kgroup[kind of its molecule], so it follows exchanges of kinds.
 struct VrBuf {

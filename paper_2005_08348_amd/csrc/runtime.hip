@@ -24,6 +24,9 @@ template <typename R> void launch_rebuild(const Dev<R>&, hipStream_t);
 template <typename R> int launch_nonbonded(const Dev<R>&, int, bool, double*, hipStream_t);
 template <typename R>
 void launch_nonbonded_fused(const Dev<R>&, int, int, R, long long, V4<R>*, V4<R>*, int, hipStream_t);
+template <typename R>
+void launch_nonbonded_alch(const Dev<R>&, int, R, long long, V4<R>*, V4<R>*, const AlchK<R>&,
+                           hipStream_t);
 void launch_energy_final(const double*, int, double*, hipStream_t);
 template <typename R> void launch_kick_drift(const Dev<R>&, R, long long, int, hipStream_t);
 template <typename R>
@@ -828,6 +831,10 @@ struct Alch {
     // (open = false) and its closing half-kick runs there too (close = false)
     long long base = 0;
     bool open = true, close = true;
+    // the segment's last force pass also makes the boundary to the next
+    // segment (lambda + dl), in place of k_alch_bridge (k_nb, FUSE 3)
+    bool fuse_next = false;
+    double dl = 0.0;
 };
 
 template <typename R>
@@ -903,6 +910,16 @@ static void steps_seq(membx_sys* s, long long n, const Alch* alch, bool launch =
                 if (vr && !alch && !s->timing) {
                     // forces and the closing half-kick with its block partials in one pass
                     vr_nblk = launch_nonbonded_kick<R>(d, s->h.lpb, s->vr, h, s->st);
+                } else if (alch && alch->fuse_next && k + 1 == n) {
+                    // the affected beads' F_B - F_A and dU at these coordinates
+                    // first (the force update there adds 0), then forces, the
+                    // closing half-kick at lambda, the work increment and the
+                    // next segment's opening update in one pass
+                    alch_terms<R>(s, rebuilt, 0.0);
+                    Mv& m = s->mv;
+                    const AlchK<R> ak{ m.aff_flag, m.md, (R)alch->lam, (R)alch->dl, alch->dl };
+                    launch_nonbonded_alch<R>(d, s->h.lpb, h, alch->base + n, d.posq_alt, d.vel, ak, s->st);
+                    swap_coords<R>(s);
                 } else {
                     forces<R>(s, rebuilt);
                     if (alch) alch_terms<R>(s, rebuilt, alch->lam);
@@ -1171,24 +1188,29 @@ static int32_t mdas(membx_sys* s, int P, int K, int M)
     // increment, the move of the forces to the next lambda and the next
     // segment's opening update run as one pass (the same operations)
     const bool bridge = !sc && !topo && M > 0 && s->h.ensemble == 0;
+    // ... and that pass is the segment's last force pass (not under kernel timing)
+    const bool fbridge = bridge && !s->timing;
     long long base = 0;
     double lam = 0.0;
     for (int k = 1; k <= K; ++k) {
+        double lam_new = (double)k / (double)K;
+        double dl = lam_new - lam;
         if (M > 0) {
             Alch a{ lam };
             if (bridge) {
                 a.base = base;
                 a.open = k == 1;
                 a.close = k == K;
+                a.fuse_next = fbridge && k < K;
+                a.dl = dl;
             }
             steps_seq<R>(s, M, &a);
             s->step += M;
             s->fe += M;
         }
-        double lam_new = (double)k / (double)K;
-        double dl = lam_new - lam;
         if (bridge && k < K) {
-            launch_alch_bridge<R>(d, m.aff_flag, m.md, (R)(0.5 * s->h.dt), (R)dl, dl, base + M, st);
+            if (!fbridge)
+                launch_alch_bridge<R>(d, m.aff_flag, m.md, (R)(0.5 * s->h.dt), (R)dl, dl, base + M, st);
             base += M;
         } else if (sc) {   // w += U_sc(lam_new) - U_sc(lam) at x; forces follow lambda
             launch_scdu<R>(d, m, T, lam, lam_new, s->h.sc_delta, st);
