@@ -63,6 +63,33 @@ __global__ __launch_bounds__(WG) void k_alch_bridge(Dev<R> d, const int* __restr
     disp_stats(d, e2, e2_in, i < d.N);
 }
 
+// The same boundary on the soft-core path (Langevin): the operations of
+// k_kick, k_work (weight 1: the work increment is U_sc(lam') - U_sc(lam)),
+// k_scforce's update of the affected beads' forces (held in dsc in float64)
+// and k_kick_drift in that order.
+template <typename R>
+__global__ __launch_bounds__(WG) void k_sc_bridge(Dev<R> d, const int* __restrict__ aff_flag,
+                                                 const double* __restrict__ dsc, double* md, R kick,
+                                                 long long step_off)
+{
+    const int i = blockIdx.x * WG + threadIdx.x;
+    if (i == 0) md[0] += 1.0 * md[1];
+    float e2 = 0.f, e2_in = 0.f;
+    if (i < d.N) {
+        BeadPre<R> pre = bead_pre(d, i, false);
+        V4<R> f = d.frc[i];
+        pre.v.x += kick * pre.v.w * f.x; pre.v.y += kick * pre.v.w * f.y;
+        pre.v.z += kick * pre.v.w * f.z;
+        if (aff_flag[i]) {
+            const double* g = dsc + 4 * (size_t)i;
+            f.x = (R)((double)f.x + g[0]); f.y = (R)((double)f.y + g[1]); f.z = (R)((double)f.z + g[2]);
+            d.frc[i] = f;
+        }
+        e2 = baoab_bead(d, i, d.posq[i], pre, f, kick, step_off, d.posq, d.vel, false, e2_in);
+    }
+    disp_stats(d, e2, e2_in, i < d.N);
+}
+
 // capped steepest-descent step: x += s * alpha F, |s alpha F| <= cap
 template <typename R>
 __global__ void k_sd_step(Dev<R> d, double alpha, double cap)
@@ -142,6 +169,13 @@ void launch_kick_drift(const Dev<R>& d, R kick, long long step_off, int chk_in, 
 {
     hipLaunchKernelGGL(k_kick_drift<R>, dim3((d.N + WG - 1) / WG), dim3(WG), 0, st, d, kick,
                        step_off, chk_in);
+}
+template <typename R>
+void launch_sc_bridge(const Dev<R>& d, const int* aff_flag, const double* dsc, double* md, R kick,
+                      long long step_off, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sc_bridge<R>, dim3((d.N + WG - 1) / WG), dim3(WG), 0, st, d, aff_flag, dsc,
+                       md, kick, step_off);
 }
 template <typename R>
 void launch_alch_bridge(const Dev<R>& d, const int* aff_flag, double* md, R kick, R dl, double dlw,
@@ -436,6 +470,8 @@ void launch_vr_kick_drift(const Dev<R>& d, const VrBuf& vr, R kick, long long st
                                           long long, double, hipStream_t);           \
     template void launch_kick_drift<R>(const Dev<R>&, R, long long, int, hipStream_t); \
     template void launch_kick<R>(const Dev<R>&, R, long long, hipStream_t);                    \
+    template void launch_sc_bridge<R>(const Dev<R>&, const int*, const double*, double*, R,      \
+                                      long long, hipStream_t);                                 \
     template void launch_alch_bridge<R>(const Dev<R>&, const int*, double*, R, R, double, long long, \
                                         hipStream_t);                                          \
     template void launch_sd_step<R>(const Dev<R>&, double, double, hipStream_t);     \

@@ -875,7 +875,7 @@ __device__ __forceinline__ void sc_pair_d(const Dev<R>& d, int ci, int cj, int c
 // F += F_sc(lam_to) - F_sc(lam_from) on each affected bead (8 lanes per bead)
 template <typename R>
 __global__ __launch_bounds__(WG) void k_scforce(Dev<R> d, Mv m, double lam_from, double lam_to,
-                                                double delta)
+                                                double delta, int defer)
 {
     const int gid = blockIdx.x * WG + threadIdx.x;
     const int k0 = gid >> 3, s = gid & 7;
@@ -934,9 +934,13 @@ __global__ __launch_bounds__(WG) void k_scforce(Dev<R> d, Mv m, double lam_from,
         fz += __shfl_xor(fz, q);
     }
     if (valid && s == 0) {
-        V4<R> f = d.frc[i];
-        f.x = (R)((double)f.x + fx); f.y = (R)((double)f.y + fy); f.z = (R)((double)f.z + fz);
-        d.frc[i] = f;
+        if (defer) {   // applied by the segment boundary pass (k_sc_bridge)
+            m.dsc[4 * (size_t)i] = fx; m.dsc[4 * (size_t)i + 1] = fy; m.dsc[4 * (size_t)i + 2] = fz;
+        } else {
+            V4<R> f = d.frc[i];
+            f.x = (R)((double)f.x + fx); f.y = (R)((double)f.y + fy); f.z = (R)((double)f.z + fz);
+            d.frc[i] = f;
+        }
     }
 }
 
@@ -1416,11 +1420,11 @@ void launch_dforce(const Dev<R>& d, const Mv& m, R scale, hipStream_t st)
 
 template <typename R>
 void launch_scforce(const Dev<R>& d, const Mv& m, double lam_from, double lam_to, double delta,
-                    hipStream_t st)
+                    hipStream_t st, bool defer)
 {
     int n = m.aff_cap * 8;
     hipLaunchKernelGGL(k_scforce<R>, dim3((n + WG - 1) / WG), dim3(WG), 0, st, d, m, lam_from, lam_to,
-                       delta);
+                       delta, defer ? 1 : 0);
 }
 
 template <typename R>
@@ -1503,7 +1507,7 @@ void launch_kcnt(const Dev<R>& d, const Mv& m, int kind0, int nkinds, int batch_
     template void launch_dforce<R>(const Dev<R>&, const Mv&, R, hipStream_t);             \
     template void launch_dlam<R>(const Dev<R>&, const Mv&, R, hipStream_t);               \
     template void launch_scforce<R>(const Dev<R>&, const Mv&, double, double, double,      \
-                                    hipStream_t);                                         \
+                                    hipStream_t, bool);                                   \
     template void launch_scdu<R>(const Dev<R>&, const Mv&, int, double, double, double,    \
                                  hipStream_t);                                            \
     template void launch_commit<R>(const Dev<R>&, const Mv&, int, int, hipStream_t);      \

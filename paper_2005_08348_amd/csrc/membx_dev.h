@@ -347,6 +347,8 @@ struct Mv {
     double* dfb;
     // MDAS
     double* md;          // [8]: work, dU, accept, u
+    double* dsc;         // [4 N] soft-core force change of an affected bead between
+                         // two lambdas, held for the segment boundary pass
     // snapshot of the per-slot state
     void* snap_posq; void* snap_vel; void* snap_frc; int* snap_orig;
 };

@@ -31,6 +31,8 @@ void launch_energy_final(const double*, int, double*, hipStream_t);
 template <typename R> void launch_kick_drift(const Dev<R>&, R, long long, int, hipStream_t);
 template <typename R>
 void launch_alch_bridge(const Dev<R>&, const int*, double*, R, R, double, long long, hipStream_t);
+template <typename R>
+void launch_sc_bridge(const Dev<R>&, const int*, const double*, double*, R, long long, hipStream_t);
 template <typename R> void launch_kick(const Dev<R>&, R, long long, hipStream_t);
 template <typename R>
 int launch_kick_ke(const Dev<R>&, const VrBuf&, R, hipStream_t);
@@ -63,7 +65,7 @@ template <typename R> void launch_aff_build(const Dev<R>&, const Mv&, int, int, 
 template <typename R> void launch_aff_clear(const Dev<R>&, const Mv&, hipStream_t);
 template <typename R> void launch_dforce(const Dev<R>&, const Mv&, R, hipStream_t);
 template <typename R>
-void launch_scforce(const Dev<R>&, const Mv&, double, double, double, hipStream_t);
+void launch_scforce(const Dev<R>&, const Mv&, double, double, double, hipStream_t, bool = false);
 template <typename R>
 void launch_scdu(const Dev<R>&, const Mv&, int, double, double, double, hipStream_t);
 template <typename R> void launch_dlam(const Dev<R>&, const Mv&, R, hipStream_t);
@@ -752,6 +754,7 @@ static size_t layout(membx_sys* s, Dev<R>& d, Mv& m, char* base)
     m.aff_list = a.take<int>(h.aff_cap);
     m.aff_n = a.take<int>(1);
     m.md = a.take<double>(8);
+    m.dsc = a.take<double>((size_t)4 * N);
     m.snap_posq = a.take<V4<R>>(N);
     m.snap_vel = a.take<V4<R>>(N);
     m.snap_frc = a.take<V4<R>>(N);
@@ -1190,6 +1193,10 @@ static int32_t mdas(membx_sys* s, int P, int K, int M)
     const bool bridge = !sc && !topo && M > 0 && s->h.ensemble == 0;
     // ... and that pass is the segment's last force pass (not under kernel timing)
     const bool fbridge = bridge && !s->timing;
+    // soft-core path, Langevin: the closing half-kick, the work increment,
+    // the affected beads' force update (computed before, held in float64)
+    // and the next opening update in one pass (k_sc_bridge)
+    const bool scb = sc && !topo && M > 0 && s->h.ensemble == 0;
     long long base = 0;
     double lam = 0.0;
     for (int k = 1; k <= K; ++k) {
@@ -1197,7 +1204,7 @@ static int32_t mdas(membx_sys* s, int P, int K, int M)
         double dl = lam_new - lam;
         if (M > 0) {
             Alch a{ lam };
-            if (bridge) {
+            if (bridge || scb) {
                 a.base = base;
                 a.open = k == 1;
                 a.close = k == K;
@@ -1211,6 +1218,12 @@ static int32_t mdas(membx_sys* s, int P, int K, int M)
         if (bridge && k < K) {
             if (!fbridge)
                 launch_alch_bridge<R>(d, m.aff_flag, m.md, (R)(0.5 * s->h.dt), (R)dl, dl, base + M, st);
+            base += M;
+        } else if (scb && k < K) {
+            launch_scdu<R>(d, m, T, lam, lam_new, s->h.sc_delta, st);
+            launch_du_total<R>(d, m, m.md + 1, st);
+            launch_scforce<R>(d, m, lam, lam_new, s->h.sc_delta, st, true);
+            launch_sc_bridge<R>(d, m.aff_flag, m.dsc, m.md, (R)(0.5 * s->h.dt), base + M, st);
             base += M;
         } else if (sc) {   // w += U_sc(lam_new) - U_sc(lam) at x; forces follow lambda
             launch_scdu<R>(d, m, T, lam, lam_new, s->h.sc_delta, st);
