@@ -121,6 +121,8 @@ __device__ __forceinline__ double wave_sum(double v)
 // keeps its entries within r_cut + delta, in order, as its own entries
 // s, s + LPB, ... of the inner list, with its own count, and the bead's
 // coordinates become the reference for the inner list's displacement check.
+// stats: bit 0 the displacement bookkeeping; bit 1 (FUSE 1) the binning of
+// the list build that follows (k_bin's work, on the new coordinates).
 // FUSE 3 (MDAS segment boundary, in place of the closing pass of a segment
 // and the next one's opening update): as FUSE 1, but the integrating thread
 // first adds lam (F_B - F_A) to an affected bead's force, makes the closing
@@ -400,7 +402,16 @@ __global__ __launch_bounds__(WG) void k_nb(Dev<R> d, double* __restrict__ part, 
                 }
                 e2 = baoab_bead(d, ib, pb, pre, f, kick, step_off, pos_out, vel_out, LIST != 0, e2_in);
             }
-            if (stats) disp_stats_lead<(NBB + 63) / 64>(d, e2, e2_in, integ);
+            if (stats & 1) disp_stats_lead<(NBB + 63) / 64>(d, e2, e2_in, integ);
+            if (FUSE == 1 && (stats & 2) && threadIdx.x < (NBB + 63) / 64 * 64) {   // wave-uniform
+                int cell = -1;
+                if (integ) {
+                    V4<R> p = pos_out[ib];   // this thread's own store above
+                    cell = bin_cell(d, p);
+                    pos_out[ib] = p;
+                }
+                bin_place(d, ib, cell);
+            }
         }
     } else {
         __shared__ double sh[16][WG / 64];

@@ -172,57 +172,19 @@ __device__ void layout_halo(const Dev<R>& d)
     }
 }
 
-// Bead -> cell, coordinates wrapped into [0, L).  Beads come in slot order,
-// which is cell order up to the beads that changed cell since the last
-// rebuild, so the lanes of a wave form few runs of equal cells: the first
-// lane of each run reserves the run's places in its cell with one atomic, and
-// a bead's place in its cell (in arbitrary order across runs; the per-cell
-// sort fixes the final order) is the reserved base plus its offset in the
-// run.
+// Bead -> cell for every slot, coordinates wrapped into [0, L) (bin_cell,
+// bin_place); skipped when the force pass before the rebuild binned.
 template <typename R>
 __global__ __launch_bounds__(BB) void k_bin(Dev<R> d)
 {
     const int i = blockIdx.x * BB + threadIdx.x;
-    const int l = threadIdx.x & 63;
     int cell = -1;
     if (i < d.N) {
         V4<R> p = d.posq[i];
-        R* c[3] = { &p.x, &p.y, &p.z };
-        int cc[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            R x = *c[a];
-            if (x >= d.L[a]) x -= d.L[a];        // exact (Sterbenz) for x in [L, 2L]
-            else if (x < (R)0) x += d.L[a];
-            if (!(x >= (R)0 && x < d.L[a])) {     // far outside (minimizer, a blown-up run)
-                double xd = fmod((double)*c[a], d.Ld[a]);   // exact, in (-L, L); NaN stays NaN
-                if (xd < 0.0) xd += d.Ld[a];
-                x = (R)xd;
-                if (!(x >= (R)0 && x < d.L[a])) x = (R)0;   // NaN, or rounded up to L
-            }
-            *c[a] = x;
-            const int ci = (int)(x * d.inv_edge[a]);
-            cc[a] = ci < 0 ? 0 : (ci >= d.nc[a] ? d.nc[a] - 1 : ci);
-        }
+        cell = bin_cell(d, p);
         d.posq[i] = p;
-        cell = (cc[0] * d.nc[1] + cc[1]) * d.nc[2] + cc[2];
     }
-    const int prev = __shfl_up(cell, 1);
-    const bool head = l == 0 || prev != cell;
-    const unsigned long long hm = __ballot(head);
-    const unsigned long long upto = l == 63 ? ~0ull : ((2ull << l) - 1);   // lanes 0..l
-    const int h = 63 - __clzll((long long)(hm & upto));
-    const unsigned long long above = hm & ~upto;
-    int base = 0;
-    if (head && cell >= 0) {
-        const int len = (above ? __ffsll((long long)above) - 1 : 64) - l;
-        base = atomicAdd(&d.cell_cnt[cell], len);
-    }
-    base = __shfl(base, h);
-    if (cell >= 0) {
-        d.cell_t[i] = cell;
-        d.cell_pos[i] = base + l - h;
-    }
+    bin_place(d, i, cell);
 }
 
 template <typename R, int LU>
@@ -614,9 +576,9 @@ __global__ __launch_bounds__(LB) void k_list(Dev<R> d)
 #define GRID(n) dim3(((n) + WG - 1) / WG), dim3(WG)
 
 template <typename R>
-void launch_rebuild(const Dev<R>& d, hipStream_t st)
+void launch_rebuild(const Dev<R>& d, hipStream_t st, bool binned)
 {
-    hipLaunchKernelGGL(k_bin<R>, dim3((d.N + BB - 1) / BB), dim3(BB), 0, st, d);
+    if (!binned) hipLaunchKernelGGL(k_bin<R>, dim3((d.N + BB - 1) / BB), dim3(BB), 0, st, d);
     // segment lengths of the two single-work-group scans
     const int per_c = (d.ncell + BB - 1) / BB;
     const int per_h = (halo_count(d.ne) + BB - 1) / BB;
@@ -631,7 +593,7 @@ void launch_rebuild(const Dev<R>& d, hipStream_t st)
 }
 
 
-template void launch_rebuild<float>(const Dev<float>&, hipStream_t);
-template void launch_rebuild<double>(const Dev<double>&, hipStream_t);
+template void launch_rebuild<float>(const Dev<float>&, hipStream_t, bool);
+template void launch_rebuild<double>(const Dev<double>&, hipStream_t, bool);
 
 }  // namespace mbx

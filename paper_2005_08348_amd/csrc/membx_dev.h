@@ -454,6 +454,59 @@ __device__ __forceinline__ void disp_stats(const Dev<R>& d, float e2, float e2_i
     }
 }
 
+// Binning for the list build.  bin_cell: the cell of a bead, its
+// coordinates wrapped into [0, L) on the way.  bin_place (all 64 lanes of a
+// wave call it; cell -1: no bead): beads come in slot order, which is cell
+// order up to the beads that changed cell since the last rebuild, so the
+// lanes form few runs of equal cells; the first lane of each run reserves
+// the run's places in its cell with one atomic, and a bead's place in its
+// cell (arbitrary across runs; the per-cell sort fixes the final order) is
+// the reserved base plus its offset in the run.
+template <typename R>
+__device__ __forceinline__ int bin_cell(const Dev<R>& d, V4<R>& p)
+{
+    R* c[3] = { &p.x, &p.y, &p.z };
+    int cc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        R x = *c[a];
+        if (x >= d.L[a]) x -= d.L[a];        // exact (Sterbenz) for x in [L, 2L]
+        else if (x < (R)0) x += d.L[a];
+        if (!(x >= (R)0 && x < d.L[a])) {     // far outside (minimizer, a blown-up run)
+            double xd = fmod((double)*c[a], d.Ld[a]);   // exact, in (-L, L); NaN stays NaN
+            if (xd < 0.0) xd += d.Ld[a];
+            x = (R)xd;
+            if (!(x >= (R)0 && x < d.L[a])) x = (R)0;   // NaN, or rounded up to L
+        }
+        *c[a] = x;
+        const int ci = (int)(x * d.inv_edge[a]);
+        cc[a] = ci < 0 ? 0 : (ci >= d.nc[a] ? d.nc[a] - 1 : ci);
+    }
+    return (cc[0] * d.nc[1] + cc[1]) * d.nc[2] + cc[2];
+}
+
+template <typename R>
+__device__ __forceinline__ void bin_place(const Dev<R>& d, int i, int cell)
+{
+    const int l = threadIdx.x & 63;
+    const int prev = __shfl_up(cell, 1);
+    const bool head = l == 0 || prev != cell;
+    const unsigned long long hm = __ballot(head);
+    const unsigned long long upto = l == 63 ? ~0ull : ((2ull << l) - 1);   // lanes 0..l
+    const int h = 63 - __clzll((long long)(hm & upto));
+    const unsigned long long above = hm & ~upto;
+    int base = 0;
+    if (head && cell >= 0) {
+        const int len = (above ? __ffsll((long long)above) - 1 : 64) - l;
+        base = atomicAdd(&d.cell_cnt[cell], len);
+    }
+    base = __shfl(base, h);
+    if (cell >= 0) {
+        d.cell_t[i] = cell;
+        d.cell_pos[i] = base + l - h;
+    }
+}
+
 // disp_stats when only the block's first NIW waves hold counted beads (the
 // force pass that integrates: thread t < WG / lanes per bead takes bead t):
 // the other waves skip it, and with one such wave there is no barrier.

@@ -20,7 +20,7 @@
 
 namespace mbx {
 // launchers (defined in the kernel translation units)
-template <typename R> void launch_rebuild(const Dev<R>&, hipStream_t);
+template <typename R> void launch_rebuild(const Dev<R>&, hipStream_t, bool);
 template <typename R> int launch_nonbonded(const Dev<R>&, int, bool, double*, hipStream_t);
 template <typename R>
 void launch_nonbonded_fused(const Dev<R>&, int, int, R, long long, V4<R>*, V4<R>*, int, hipStream_t);
@@ -785,10 +785,10 @@ template <> Dev<double>& dev<double>(membx_sys* s) { return s->dd; }
 
 // ----------------------------------------------------------------- sequences
 template <typename R>
-static void rebuild(membx_sys* s)
+static void rebuild(membx_sys* s, bool binned = false)
 {
     Dev<R>& d = dev<R>(s);
-    launch_rebuild<R>(d, s->st);
+    launch_rebuild<R>(d, s->st, binned);
     s->since = 0;
     s->n_rebuilds++;
     s->sp = -1;   // slots reordered: the inner list must be rebuilt
@@ -880,6 +880,7 @@ static void steps_seq(membx_sys* s, long long n, const Alch* alch, bool launch =
     const double vr_c = vr ? std::exp(-s->h.dt / s->h.tau_t) : 1.0;
     if (alch) s->sp = -1;   // MDAS segments walk the Verlet list; no inner bookkeeping
     bool moved = false;   // the previous force pass already moved the beads
+    bool binned = false;  // ... and binned them for the rebuild that follows
     int vr_nblk = 0;      // block partials of the last closing half-kick (its factors pending)
     for (long long k = 0; k < n; ++k) {
         if (!moved && launch) {
@@ -892,10 +893,11 @@ static void steps_seq(membx_sys* s, long long n, const Alch* alch, bool launch =
         moved = false;
         bool rebuilt = false;
         if (++s->since >= s->h.R) {
-            if (launch) rebuild<R>(s);
+            if (launch) rebuild<R>(s, binned);
             else { s->since = 0; s->n_rebuilds++; s->sp = -1; }
             rebuilt = true;
         }
+        binned = false;
         if (!alch && !vr && s->fuse && !s->timing && k + 1 < n) {
             // forces of step k and B-A-O-A of step k + 1 in one pass, on the
             // inner list between prunes
@@ -904,8 +906,11 @@ static void steps_seq(membx_sys* s, long long n, const Alch* alch, bool launch =
                 if (s->sp < 0 || s->sp >= s->h.prune - 1) { list = 2; s->sp = 0; }
                 else { list = 1; s->sp++; }
             }
+            // the next step rebuilds: this pass also bins the new coordinates
+            binned = s->since + 1 >= s->h.R;
             if (launch)
-                launch_nonbonded_fused<R>(d, s->h.lpb, list, full, k + 1, d.posq_alt, d.vel, 1, s->st);
+                launch_nonbonded_fused<R>(d, s->h.lpb, list, full, k + 1, d.posq_alt, d.vel,
+                                          binned ? 3 : 1, s->st);
             swap_coords<R>(s);
             moved = true;
         } else {
