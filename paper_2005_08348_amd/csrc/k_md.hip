@@ -9,7 +9,8 @@ namespace mbx {
 // place; x at the last rebuild is compared to flag displacements beyond
 // skin/2.
 template <typename R>
-__global__ __launch_bounds__(WG) void k_kick_drift(Dev<R> d, R kick, long long step_off, int chk_in)
+__global__ __launch_bounds__(WG) void k_kick_drift(Dev<R> d, R kick, long long step_off, int chk_in,
+                                                   int bin)
 {
     const int i = blockIdx.x * WG + threadIdx.x;
     float e2 = 0.f, e2_in = 0.f;
@@ -17,6 +18,15 @@ __global__ __launch_bounds__(WG) void k_kick_drift(Dev<R> d, R kick, long long s
         e2 = baoab_bead(d, i, d.posq[i], bead_pre(d, i, chk_in != 0), d.frc[i], kick, step_off,
                         d.posq, d.vel, chk_in != 0, e2_in);
     disp_stats(d, e2, e2_in, i < d.N);
+    if (bin) {   // the rebuild that follows skips its binning
+        int cell = -1;
+        if (i < d.N) {
+            V4<R> p = d.posq[i];   // this thread's own store above
+            cell = bin_cell(d, p);
+            d.posq[i] = p;
+        }
+        bin_place(d, i, cell);
+    }
 }
 
 // closing half-kick of a run of steps; also advances the step counter
@@ -165,10 +175,11 @@ void launch_add_ctr(long long* ctr, int which, long long n, hipStream_t st)
 }
 
 template <typename R>
-void launch_kick_drift(const Dev<R>& d, R kick, long long step_off, int chk_in, hipStream_t st)
+void launch_kick_drift(const Dev<R>& d, R kick, long long step_off, int chk_in, hipStream_t st,
+                       int bin)
 {
     hipLaunchKernelGGL(k_kick_drift<R>, dim3((d.N + WG - 1) / WG), dim3(WG), 0, st, d, kick,
-                       step_off, chk_in);
+                       step_off, chk_in, bin);
 }
 template <typename R>
 void launch_sc_bridge(const Dev<R>& d, const int* aff_flag, const double* dsc, double* md, R kick,
@@ -414,7 +425,8 @@ void launch_scale_pos(const Dev<R>& d, const double* mu, hipStream_t st)
 // factors come from that step's nblk block partials (counter: step fstep)
 template <typename R>
 __global__ __launch_bounds__(WG) void k_vr_kick_drift(Dev<R> d, VrBuf vr, R kick, long long step_off,
-                                                      int chk_in, int nblk, long long fstep, double c)
+                                                      int chk_in, int nblk, long long fstep, double c,
+                                                      int bin)
 {
     __shared__ double al[2];
     vr_factors_wg(d, vr, nblk, fstep, c, al);
@@ -430,6 +442,15 @@ __global__ __launch_bounds__(WG) void k_vr_kick_drift(Dev<R> d, VrBuf vr, R kick
                         e2_in);
     }
     disp_stats(d, e2, e2_in, i < d.N);
+    if (bin) {   // the rebuild that follows skips its binning
+        int cell = -1;
+        if (i < d.N) {
+            V4<R> p = d.posq[i];   // this thread's own store above
+            cell = bin_cell(d, p);
+            d.posq[i] = p;
+        }
+        bin_place(d, i, cell);
+    }
 }
 
 // closing half-kick with the group sums (after an MDAS segment's alchemical
@@ -452,10 +473,10 @@ void launch_vr_scale(const Dev<R>& d, const VrBuf& vr, int nblk, long long fstep
 }
 template <typename R>
 void launch_vr_kick_drift(const Dev<R>& d, const VrBuf& vr, R kick, long long step_off, int chk_in,
-                          int nblk, long long fstep, double c, hipStream_t st)
+                          int nblk, long long fstep, double c, hipStream_t st, int bin)
 {
     hipLaunchKernelGGL(k_vr_kick_drift<R>, dim3((d.N + WG - 1) / WG), dim3(WG), 0, st, d, vr, kick,
-                       step_off, chk_in, nblk, fstep, c);
+                       step_off, chk_in, nblk, fstep, c, bin);
 }
 
 #define INST(R)                                                                      \
@@ -467,8 +488,8 @@ void launch_vr_kick_drift(const Dev<R>& d, const VrBuf& vr, R kick, long long st
     template void launch_scale_pos<R>(const Dev<R>&, const double*, hipStream_t);    \
     template void launch_unscale_vel<R>(const Dev<R>&, const double*, hipStream_t);  \
     template void launch_vr_kick_drift<R>(const Dev<R>&, const VrBuf&, R, long long, int, int, \
-                                          long long, double, hipStream_t);           \
-    template void launch_kick_drift<R>(const Dev<R>&, R, long long, int, hipStream_t); \
+                                          long long, double, hipStream_t, int);      \
+    template void launch_kick_drift<R>(const Dev<R>&, R, long long, int, hipStream_t, int); \
     template void launch_kick<R>(const Dev<R>&, R, long long, hipStream_t);                    \
     template void launch_sc_bridge<R>(const Dev<R>&, const int*, const double*, double*, R,      \
                                       long long, hipStream_t);                                 \

@@ -28,7 +28,7 @@ template <typename R>
 void launch_nonbonded_alch(const Dev<R>&, int, R, long long, V4<R>*, V4<R>*, const AlchK<R>&,
                            hipStream_t);
 void launch_energy_final(const double*, int, double*, hipStream_t);
-template <typename R> void launch_kick_drift(const Dev<R>&, R, long long, int, hipStream_t);
+template <typename R> void launch_kick_drift(const Dev<R>&, R, long long, int, hipStream_t, int = 0);
 template <typename R>
 void launch_alch_bridge(const Dev<R>&, const int*, double*, R, R, double, long long, hipStream_t);
 template <typename R>
@@ -47,7 +47,7 @@ template <typename R> void launch_scale_pos(const Dev<R>&, const double*, hipStr
 template <typename R> void launch_unscale_vel(const Dev<R>&, const double*, hipStream_t);
 template <typename R>
 void launch_vr_kick_drift(const Dev<R>&, const VrBuf&, R, long long, int, int, long long, double,
-                          hipStream_t);
+                          hipStream_t, int);
 template <typename R> void launch_sd_step(const Dev<R>&, double, double, hipStream_t);
 template <typename R> void launch_export(const Dev<R>&, const V4<R>*, double*, hipStream_t);
 template <typename R> void launch_import(const Dev<R>&, V4<R>*, const double*, hipStream_t);
@@ -885,10 +885,16 @@ static void steps_seq(membx_sys* s, long long n, const Alch* alch, bool launch =
     for (long long k = 0; k < n; ++k) {
         if (!moved && launch) {
             const int chk = (inner && s->sp >= 0) ? 1 : 0;
-            if (vr && k > 0) launch_vr_kick_drift<R>(d, s->vr, h, k, chk, vr_nblk, k - 1, vr_c, s->st);
-            else if (!(alch && k == 0 && !alch->open))
+            // this step rebuilds: the update also bins the new coordinates
+            const int bn = s->since + 1 >= s->h.R ? 1 : 0;
+            if (vr && k > 0) {
+                launch_vr_kick_drift<R>(d, s->vr, h, k, chk, vr_nblk, k - 1, vr_c, s->st, bn);
+                binned = bn != 0;
+            } else if (!(alch && k == 0 && !alch->open)) {
                 launch_kick_drift<R>(d, (k == 0 || vr) ? h : full, (alch ? alch->base : 0) + k, chk,
-                                     s->st);
+                                     s->st, bn);
+                binned = bn != 0;
+            }
         }
         moved = false;
         bool rebuilt = false;
