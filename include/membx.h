@@ -176,7 +176,9 @@ typedef struct membx_trial {
 typedef struct membx_sys membx_sys;
 
 /* Bytes of device memory a system needs (arena size for membx_sys_create).
- * Errors: E_INVAL for an invalid descriptor. */
+ * Errors: E_INVAL for an invalid descriptor, among them systems whose beads
+ * plus periodic-image capacity reach 2^27 slots (the force pass addresses a
+ * slot's coordinates by a 32-bit byte offset). */
 int32_t membx_sys_bytes(const membx_desc* desc, uint64_t* bytes);
 
 /* Build a system in `dev_arena` (device pointer, 256-byte aligned, at least
