@@ -54,3 +54,12 @@ def test_no_cpu_fallback():
         pytest.skip("GPU present")
     with pytest.raises(RuntimeError):
         M.System(S.make("c0"))
+
+
+def test_list_capacity_rounds_to_the_list_tiling():
+    """The neighbour list is tiled in rows of 64 / lanes_per_bead beads, so a
+    requested capacity is rounded up to a multiple of 8 entries: 97..104
+    give the arena of 104, and 105 a larger one."""
+    s = S.make("c0")
+    b = [M.arena_bytes(s, "mixed", list_capacity=k) for k in (97, 100, 104, 105)]
+    assert b[0] == b[1] == b[2] < b[3]
